@@ -222,11 +222,14 @@ def esdf_lookup(grid, origin, voxel, p):
     """Trilinear phi(p) from a (nz, ny, nx) grid of values at voxel centres.
 
     Continuous index u = (p - origin)/voxel - 1/2 per axis, clamped to [0, n-1];
-    base corner i0 = min(floor(u), n-2), fraction f = u - i0.
+    base corner i0 = min(floor(u), n-2), fraction f = u - i0.  A non-finite query
+    point has no distance: the result is nan there.
     """
     grid = np.asarray(grid, np.float64)
     nz, ny, nx = grid.shape
     p = np.asarray(p, np.float64)
+    bad = ~np.all(np.isfinite(p), axis=-1)
+    p = np.where(bad[..., None], 0.0, p)
     u = (p - np.asarray(origin, np.float64)) / voxel - 0.5
     n = np.array([nx, ny, nz])
     u = np.clip(u, 0.0, n - 1)
@@ -242,7 +245,7 @@ def esdf_lookup(grid, origin, voxel, p):
             for bx in (0, 1):
                 wx = fx if bx else 1.0 - fx
                 phi += wx * wy * wz * grid[iz + bz, iy + by, ix + bx]
-    return phi
+    return np.where(bad, np.nan, phi)
 
 
 def env_collision_cost(robot, centres, grid, origin, voxel, w_env, d_act):

@@ -515,3 +515,10 @@ def test_lambda_to_zero_selects_argmin_rollout():
     m = int(np.argmin(out["S"]))
     np.testing.assert_allclose(out["U_star"], inp.U_bar + inp.noise[m], atol=1e-12)
     assert out["ess"] == pytest.approx(1.0)
+
+
+def test_lookup_of_non_finite_point_is_nan():
+    grid = np.zeros((3, 3, 3))
+    p = np.array([[0.1, 0.1, 0.1], [np.nan, 0.1, 0.1], [0.1, np.inf, 0.1]])
+    got = O.esdf_lookup(grid, np.zeros(3), 0.1, p)
+    assert got[0] == 0.0 and np.isnan(got[1]) and np.isnan(got[2])
