@@ -1,0 +1,189 @@
+/*
+ * smpc.h -- C interface of libsmpc, a gfx950 (MI355X) implementation of one plan
+ * step of the sampling-based MPC planner of ParaMaP (arXiv:2512.22575, Sec. IV).
+ *
+ * One call of smpc_plan_step() performs one pass of the paper's Algorithm 1 for a
+ * 7-DoF arm and a given set of K sampled disturbance sequences of length H:
+ *
+ *   u_k^(m)  = ubar_k + eps_k^(m)                         (eq. 27)
+ *   roll out q_{k+1} = f(q_k, u_k) from (q0, qd0)         (eq. 7)
+ *   forward kinematics of all link frames                 (eq. 6)
+ *   S^(m) = l_f(T_H) + sum_{k<H} l(q_k, x_k, u_k)          (eq. 28, costs eqs. 16-25)
+ *   w^(m) = exp(-(S^(m) - S_min)/lambda) / Z               (eq. 29)
+ *   U*    = Ubar + sum_m w^(m) eps^(m)                     (eq. 30)
+ *
+ * Readings of points the paper leaves open, fixed by this interface:
+ *   - dynamics: semi-implicit Euler, qd_{k+1} = qd_k + u_k dt, q_{k+1} = q_k + qd_{k+1} dt;
+ *   - kinematics: modified DH, A_i = RotX(alpha_i) TransX(a_i) RotZ(q_i) TransZ(d_i),
+ *     base at the world origin, end effector = frame 7;
+ *   - running terms on (q_k, qd_k, u_k) for k = 0..H-1, terminal pose term on q_H;
+ *   - distance field: trilinear between voxel centres, query clamped to the grid;
+ *   - joint-limit tightening margin = limit_margin_frac * (max - min) (eq. 21);
+ *   - Q_k = diag(w_pose_t I3, w_pose_r I3), Q_H = diag(w_term_t I3, w_term_r I3);
+ *   - non-finite rollout costs get weight 0.
+ *
+ * Conventions
+ *   - All floating-point data are IEEE binary32 unless a field says double.
+ *   - "device" pointers are HIP device allocations on the context's device;
+ *     "host" data are read during the call and not retained.
+ *   - Every entry point validates its arguments on the host before any device
+ *     work is enqueued; on error nothing is enqueued and a negative status is
+ *     returned (details in smpc_last_error()).  No C++ exception crosses this ABI.
+ *   - A context is not thread-safe.  Plan steps issued on one stream run in
+ *     order; plan steps of one context must not run concurrently on different
+ *     streams (they share the context's workspace).
+ */
+#ifndef SMPC_H
+#define SMPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t smpc_status;
+
+enum {
+  SMPC_OK = 0,
+  SMPC_E_INVALID_ARG = -1, /* argument out of range, null pointer, non-finite value  */
+  SMPC_E_OOM = -2,         /* device workspace allocation failed                      */
+  SMPC_E_DEVICE = -3,      /* a HIP runtime call or kernel launch failed              */
+  SMPC_E_NUMERIC = -4,     /* every rollout cost is non-finite (reported in stats)    */
+  SMPC_E_UNSUPPORTED = -5  /* valid request outside what this build implements        */
+};
+
+#define SMPC_NDOF 7
+#define SMPC_MAX_H 64              /* horizon limit: one rollout fits one wavefront    */
+#define SMPC_SPHERES_PER_LINK 4    /* sphere slots per link                            */
+#define SMPC_MAX_SPHERES 28        /* 7 links x 4 slots                                */
+#define SMPC_MAX_PAIRS 378         /* 28 * 27 / 2                                      */
+
+enum { SMPC_GRID_F32 = 0, SMPC_GRID_F16 = 1 };
+
+typedef struct smpc_ctx smpc_ctx;
+
+/*
+ * Robot description (host memory, copied by smpc_set_robot).
+ *   a, d, alpha : modified-DH parameters; joint i (1-based) uses entry i-1 (eq. 6).
+ *   *_min/_max  : admissible ranges of q, qd and qdd (eqs. 21-22); min < max.
+ *   q_ref       : null-space reference posture (eq. 24).
+ *   spheres     : n_spheres collision spheres (Sec. IV-B-2, eq. 17); sphere s is
+ *                 rigidly attached to frame sphere_link[s] in 1..7, its centre is
+ *                 sphere_center[s] in that frame (metres), radius >= 0.  At most
+ *                 SMPC_SPHERES_PER_LINK spheres per link.
+ *   pairs       : n_pairs self-collision pairs (eq. 18), sphere indices i != j.
+ */
+typedef struct {
+  int32_t n_dof; /* must be SMPC_NDOF */
+  double a[SMPC_NDOF];
+  double d[SMPC_NDOF];
+  double alpha[SMPC_NDOF];
+  double q_min[SMPC_NDOF], q_max[SMPC_NDOF];
+  double qd_min[SMPC_NDOF], qd_max[SMPC_NDOF];
+  double qdd_min[SMPC_NDOF], qdd_max[SMPC_NDOF];
+  double q_ref[SMPC_NDOF];
+  int32_t n_spheres;
+  int32_t sphere_link[SMPC_MAX_SPHERES];
+  double sphere_center[SMPC_MAX_SPHERES][3];
+  double sphere_radius[SMPC_MAX_SPHERES];
+  int32_t n_pairs;
+  int32_t pairs[SMPC_MAX_PAIRS][2];
+} smpc_robot_desc;
+
+/* Cost weights (Sec. IV-B).  All finite and >= 0; limit_margin_frac in [0, 0.5). */
+typedef struct {
+  float w_pose_t, w_pose_r;  /* Q_k blocks, running pose cost (eq. 16)     */
+  float w_term_t, w_term_r;  /* Q_H blocks, terminal cost (eq. 25)          */
+  float w_env, d_act;        /* environment hinge weight and activation (m) */
+  float w_self;              /* self-collision hinge weight (eq. 20)        */
+  float w_q, w_qd, w_qdd;    /* joint-limit weights (eq. 22)                */
+  float limit_margin_frac;   /* tightening margin as a fraction of range    */
+  float w_smooth;            /* acceleration smoothness (eq. 23)            */
+  float w_ns;                /* null-space regularisation (eq. 24)          */
+} smpc_cost_weights;
+
+/*
+ * Signed distance grid phi (Sec. IV-B-2, eq. 17), device memory, metres.
+ * Layout: element (ix, iy, iz) at index (iz * ny + iy) * nx + ix (x fastest).
+ * origin is the corner of voxel (0,0,0); voxel centres are at
+ * origin + (i + 1/2) * voxel.  nx, ny, nz >= 2; total size < 2^31 bytes.
+ */
+typedef struct {
+  const void* data;
+  int32_t nx, ny, nz;
+  int32_t dtype; /* SMPC_GRID_F32 (this build also reserves SMPC_GRID_F16) */
+  float origin[3];
+  float voxel;
+} smpc_grid;
+
+/*
+ * Arguments of one plan step.
+ *   q0, qd0   : current joint state (host, by value).
+ *   T_goal    : target end-effector pose, row-major 4x4 SE(3) (host, by value);
+ *               last row must be [0 0 0 1] and the rotation orthonormal to 1e-4.
+ *   esdf      : distance grid (device).
+ *   noise     : device float [K][H][7] disturbances eps (Algorithm 1, sampling
+ *               step), or NULL to request on-device sampling from seed/sigma
+ *               (returns SMPC_E_UNSUPPORTED in this build).
+ *   K, H      : samples and horizon; K >= 1, 1 <= H <= SMPC_MAX_H.
+ *   dt        : control period (s), finite and > 0.
+ *   lambda    : temperature of eq. 29, finite and > 0.
+ *   U_in      : device float [H][7], nominal sequence Ubar.
+ *   U_out     : device float [H][7], receives U*; may alias U_in.
+ *   costs_out : device float [K] receiving S^(m), or NULL.
+ *   weights_out: device float [K] receiving w^(m), or NULL.
+ *   stats_out : device float [4] receiving {S_min, Z, ESS, status}, or NULL;
+ *               status is 0, or SMPC_E_NUMERIC when every cost is non-finite (then
+ *               U_out = U_in and the weights are 0).  Z = sum_m exp(-(S-S_min)/lambda),
+ *               ESS = 1 / sum_m w^2.
+ * All work is enqueued on `stream` (a hipStream_t; NULL = default stream) and the
+ * call returns without waiting for it.
+ */
+typedef struct {
+  float q0[SMPC_NDOF];
+  float qd0[SMPC_NDOF];
+  float T_goal[16];
+  smpc_grid esdf;
+  const float* noise;
+  uint64_t seed;
+  float sigma[SMPC_NDOF];
+  int32_t K;
+  int32_t H;
+  float dt;
+  float lambda;
+  smpc_cost_weights weights;
+  const float* U_in;
+  float* U_out;
+  float* costs_out;
+  float* weights_out;
+  float* stats_out;
+} smpc_plan_args;
+
+/* Create a context on HIP device `hip_device`.  *out receives the handle. */
+smpc_status smpc_create(smpc_ctx** out, int32_t hip_device);
+
+/* Destroy a context and free its device memory (waits for the device). NULL is a no-op. */
+void smpc_destroy(smpc_ctx* ctx);
+
+/* Validate and copy a robot description to the device (synchronous). */
+smpc_status smpc_set_robot(smpc_ctx* ctx, const smpc_robot_desc* desc);
+
+/* Validate `args` and enqueue one plan step on `stream` (asynchronous). */
+smpc_status smpc_plan_step(smpc_ctx* ctx, const smpc_plan_args* args, void* stream);
+
+/* Static description of a status code. */
+const char* smpc_status_string(smpc_status status);
+
+/* Detail of the last failure on this context ("" if none).  Valid until the next call. */
+const char* smpc_last_error(const smpc_ctx* ctx);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t smpc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMPC_H */

@@ -1,0 +1,654 @@
+// gfx950 kernels of one SMPC plan step (ParaMaP, arXiv:2512.22575, Sec. IV, Algorithm 1).
+//
+// K1 rollout_cost_kernel: one block holds R whole rollouts, one thread per
+//    (rollout m, step k).  It stages the block's disturbances in LDS, integrates
+//    the controls (eq. 7), evaluates forward kinematics (eq. 6) and the running /
+//    terminal cost of its step (eqs. 16-25) in registers, sums each rollout's
+//    cost over k in double (eq. 28) and reduces the block's rollouts to a
+//    softmax partial (block minimum, sum of exponentials, exponential-weighted
+//    sum of disturbances) so that eqs. 29-30 need no second pass over eps.
+// K2 merge_kernel: merges the per-block partials into S_min, Z and
+//    U* = Ubar + sum w eps (eqs. 29-30), writes per-rollout weights and costs,
+//    and evaluates the rollout-independent state terms at k = 0 once.
+//
+// Thread k of a rollout charges the control terms of u_k and the state terms
+// of state k+1 (running terms for k+1 < H, terminal pose term for k+1 = H).
+// The state terms of state 0 are the same for every rollout; K2 computes them
+// once and adds them to the reported costs (weights are shift-invariant).
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "smpc_internal.h"
+
+namespace smpc {
+namespace {
+
+constexpr int kWave = 64;
+
+// Rotation columns (x, y, z axes) and translation of a link frame.
+struct Frame {
+  float xx, xy, xz;
+  float yx, yy, yz;
+  float zx, zy, zz;
+  float tx, ty, tz;
+};
+
+__device__ __forceinline__ Frame identity_frame() {
+  Frame T;
+  T.xx = 1.f; T.xy = 0.f; T.xz = 0.f;
+  T.yx = 0.f; T.yy = 1.f; T.yz = 0.f;
+  T.zx = 0.f; T.zy = 0.f; T.zz = 1.f;
+  T.tx = 0.f; T.ty = 0.f; T.tz = 0.f;
+  return T;
+}
+
+// T <- T RotX(alpha) TransX(a) RotZ(theta) TransZ(d), given cos/sin of alpha and theta.
+__device__ __forceinline__ void mdh_step(Frame& T, float ca, float sa, float a, float d,
+                                         float ct, float st) {
+  // TransX(a): RotX leaves the x axis unchanged, so the offset is along T's x axis.
+  T.tx = fmaf(a, T.xx, T.tx);
+  T.ty = fmaf(a, T.xy, T.ty);
+  T.tz = fmaf(a, T.xz, T.tz);
+  // RotX(alpha): y' = ca y + sa z, z' = ca z - sa y.
+  const float y0 = fmaf(ca, T.yx, sa * T.zx);
+  const float y1 = fmaf(ca, T.yy, sa * T.zy);
+  const float y2 = fmaf(ca, T.yz, sa * T.zz);
+  const float z0 = fmaf(ca, T.zx, -sa * T.yx);
+  const float z1 = fmaf(ca, T.zy, -sa * T.yy);
+  const float z2 = fmaf(ca, T.zz, -sa * T.yz);
+  // RotZ(theta): x'' = ct x + st y', y'' = ct y' - st x.
+  const float x0 = fmaf(ct, T.xx, st * y0);
+  const float x1 = fmaf(ct, T.xy, st * y1);
+  const float x2 = fmaf(ct, T.xz, st * y2);
+  const float w0 = fmaf(ct, y0, -st * T.xx);
+  const float w1 = fmaf(ct, y1, -st * T.xy);
+  const float w2 = fmaf(ct, y2, -st * T.xz);
+  T.xx = x0; T.xy = x1; T.xz = x2;
+  T.yx = w0; T.yy = w1; T.yz = w2;
+  T.zx = z0; T.zy = z1; T.zz = z2;
+  // TransZ(d) along the new z axis.
+  T.tx = fmaf(d, z0, T.tx);
+  T.ty = fmaf(d, z1, T.ty);
+  T.tz = fmaf(d, z2, T.tz);
+}
+
+__device__ __forceinline__ void transform_point(const Frame& T, float cx, float cy, float cz,
+                                                float& px, float& py, float& pz) {
+  px = fmaf(cx, T.xx, fmaf(cy, T.yx, fmaf(cz, T.zx, T.tx)));
+  py = fmaf(cx, T.xy, fmaf(cy, T.yy, fmaf(cz, T.zy, T.ty)));
+  pz = fmaf(cx, T.xz, fmaf(cy, T.yz, fmaf(cz, T.zz, T.tz)));
+}
+
+// g(theta) = (x^2 - sin^2 x) / (2 sin^4 x), x = theta / 2, for theta in [0, pi].
+// With it |v|^2 = |t|^2 + g(theta) t^T (I - R) t for the translational part v of
+// log(T) (eqs. 12-14): V(theta) acts as the identity along the rotation axis and
+// scales the orthogonal plane by sin(x)/x, and t^T (I - R) t = 2 sin^2(x) |t_perp|^2.
+__device__ __forceinline__ float log_norm_gain(float theta) {
+  const float x = 0.5f * theta;
+  const float x2 = x * x;
+  if (x < 1e-3f) return fmaf(x2, 4.f / 45.f, 1.f / 6.f);
+  const float s = sinf(x);
+  float xms;  // x - sin x, by its Taylor series where the subtraction would cancel
+  if (x < 0.75f) {
+    xms = x * x2 * (1.f / 6.f + x2 * (-1.f / 120.f + x2 * (1.f / 5040.f +
+          x2 * (-1.f / 362880.f + x2 * (1.f / 39916800.f)))));
+  } else {
+    xms = x - s;
+  }
+  const float s2 = s * s;
+  return xms * (x + s) / (2.f * s2 * s2);
+}
+
+// 1/2 xi^T Q xi for Delta T = T_g^{-1} T (eqs. 11-16, 25) with Q = diag(wt I3, wr I3).
+// |omega|^2 = theta^2 with theta = atan2(|vee(R - R^T)|/2, (tr R - 1)/2).
+__device__ __forceinline__ float pose_cost(const Frame& T, const StepParams& p, float wt,
+                                           float wr) {
+  const float* G = p.RgT;
+  // R_Delta = R_g^T R; R's column c holds (T.cx, T.cy, T.cz).
+  const float d00 = fmaf(G[0], T.xx, fmaf(G[1], T.xy, G[2] * T.xz));
+  const float d01 = fmaf(G[0], T.yx, fmaf(G[1], T.yy, G[2] * T.yz));
+  const float d02 = fmaf(G[0], T.zx, fmaf(G[1], T.zy, G[2] * T.zz));
+  const float d10 = fmaf(G[3], T.xx, fmaf(G[4], T.xy, G[5] * T.xz));
+  const float d11 = fmaf(G[3], T.yx, fmaf(G[4], T.yy, G[5] * T.yz));
+  const float d12 = fmaf(G[3], T.zx, fmaf(G[4], T.zy, G[5] * T.zz));
+  const float d20 = fmaf(G[6], T.xx, fmaf(G[7], T.xy, G[8] * T.xz));
+  const float d21 = fmaf(G[6], T.yx, fmaf(G[7], T.yy, G[8] * T.yz));
+  const float d22 = fmaf(G[6], T.zx, fmaf(G[7], T.zy, G[8] * T.zz));
+  // t_Delta = R_g^T (t - t_g) = R_g^T t - R_g^T t_g.
+  const float t0 = fmaf(G[0], T.tx, fmaf(G[1], T.ty, fmaf(G[2], T.tz, -p.tgr[0])));
+  const float t1 = fmaf(G[3], T.tx, fmaf(G[4], T.ty, fmaf(G[5], T.tz, -p.tgr[1])));
+  const float t2 = fmaf(G[6], T.tx, fmaf(G[7], T.ty, fmaf(G[8], T.tz, -p.tgr[2])));
+  const float c = 0.5f * (d00 + d11 + d22 - 1.f);
+  const float sx = 0.5f * (d21 - d12);
+  const float sy = 0.5f * (d02 - d20);
+  const float sz = 0.5f * (d10 - d01);
+  const float sn = sqrtf(fmaf(sx, sx, fmaf(sy, sy, sz * sz)));
+  const float theta = atan2f(sn, c);
+  const float n = fmaf(t0, t0, fmaf(t1, t1, t2 * t2));
+  const float r0 = fmaf(d00, t0, fmaf(d01, t1, d02 * t2));
+  const float r1 = fmaf(d10, t0, fmaf(d11, t1, d12 * t2));
+  const float r2 = fmaf(d20, t0, fmaf(d21, t1, d22 * t2));
+  const float tRt = fmaf(t0, r0, fmaf(t1, r1, t2 * r2));
+  const float v2 = fmaf(log_norm_gain(theta), fmaxf(n - tRt, 0.f), n);
+  return 0.5f * fmaf(wt, v2, wr * theta * theta);
+}
+
+// delta(x) of eq. 21 for a tightened interval [lo, hi].
+__device__ __forceinline__ float limit_violation(float x, float lo, float hi) {
+  return fmaxf(x - hi, 0.f) + fminf(x - lo, 0.f);
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t grid_resource(const void* grid,
+                                                                uint32_t bytes) {
+  // Raw byte-addressed buffer (stride 0): loads past `bytes` return 0 instead of faulting.
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(grid), 0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ float load_f32(__amdgpu_buffer_rsrc_t rsrc, uint32_t off,
+                                          uint32_t soff) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)off, (int)soff, 0));
+}
+
+// Trilinear phi(p) between voxel centres, query clamped to the grid (edge extension).
+__device__ __forceinline__ float esdf_lookup(__amdgpu_buffer_rsrc_t rsrc, const StepParams& p,
+                                             float px, float py, float pz) {
+  const float fx_hi = (float)(p.nx - 1), fy_hi = (float)(p.ny - 1), fz_hi = (float)(p.nz - 1);
+  float ux = fmaf(px - p.gox, p.inv_voxel, -0.5f);
+  float uy = fmaf(py - p.goy, p.inv_voxel, -0.5f);
+  float uz = fmaf(pz - p.goz, p.inv_voxel, -0.5f);
+  ux = fminf(fmaxf(ux, 0.f), fx_hi);
+  uy = fminf(fmaxf(uy, 0.f), fy_hi);
+  uz = fminf(fmaxf(uz, 0.f), fz_hi);
+  const float bx = fminf(floorf(ux), fx_hi - 1.f);
+  const float by = fminf(floorf(uy), fy_hi - 1.f);
+  const float bz = fminf(floorf(uz), fz_hi - 1.f);
+  const float fx = ux - bx, fy = uy - by, fz = uz - bz;
+  const uint32_t ix = (uint32_t)bx, iy = (uint32_t)by, iz = (uint32_t)bz;
+  const uint32_t sy = (uint32_t)p.nx * 4u;
+  const uint32_t sz = (uint32_t)p.nx * (uint32_t)p.ny * 4u;
+  const uint32_t off = ((iz * (uint32_t)p.ny + iy) * (uint32_t)p.nx + ix) * 4u;
+  const float v000 = load_f32(rsrc, off, 0u), v100 = load_f32(rsrc, off + 4u, 0u);
+  const float v010 = load_f32(rsrc, off, sy), v110 = load_f32(rsrc, off + 4u, sy);
+  const float v001 = load_f32(rsrc, off, sz), v101 = load_f32(rsrc, off + 4u, sz);
+  const float v011 = load_f32(rsrc, off, sy + sz), v111 = load_f32(rsrc, off + 4u, sy + sz);
+  const float c00 = fmaf(fx, v100 - v000, v000);
+  const float c10 = fmaf(fx, v110 - v010, v010);
+  const float c01 = fmaf(fx, v101 - v001, v001);
+  const float c11 = fmaf(fx, v111 - v011, v011);
+  const float c0 = fmaf(fy, c10 - c00, c00);
+  const float c1 = fmaf(fy, c11 - c01, c01);
+  return fmaf(fz, c1 - c0, c0);
+}
+
+// Cost charged by thread (m, k): control terms of u_k and state terms of state k+1.
+//   dq, qd : q_{k+1} - q0 and qd_{k+1};  u : u_k;  sc0 : sin(q0) then cos(q0) (LDS).
+__device__ __forceinline__ float step_cost(const DevRobot* __restrict__ rob, const StepParams& p,
+                                           __amdgpu_buffer_rsrc_t rsrc, const float* sc0,
+                                           const float (&dq)[kNdof], const float (&qd)[kNdof],
+                                           const float (&u)[kNdof], bool terminal) {
+  // Smoothness (eq. 23) and acceleration limit (eq. 22) on u_k.
+  float c_u2 = 0.f, c_ulim = 0.f;
+#pragma unroll
+  for (int j = 0; j < kNdof; ++j) {
+    c_u2 = fmaf(u[j], u[j], c_u2);
+    const float v = limit_violation(u[j], p.qddlo[j], p.qddhi[j]);
+    c_ulim = fmaf(v, v, c_ulim);
+  }
+  float cost = fmaf(p.w_smooth, c_u2, p.w_qdd * c_ulim);
+
+  // Forward kinematics (eq. 6) with sin/cos of q0 + dq by angle addition, so the
+  // large common angle q0 enters exactly once and only the small dq is rounded.
+  float px[kSlots], py[kSlots], pz[kSlots];
+  Frame T = identity_frame();
+#pragma unroll
+  for (int i = 0; i < kNdof; ++i) {
+    float s1, c1;
+    sincosf(dq[i], &s1, &c1);
+    const float s0 = sc0[i], c0 = sc0[kNdof + i];
+    const float st = fmaf(s0, c1, c0 * s1);
+    const float ct = fmaf(c0, c1, -s0 * s1);
+    mdh_step(T, rob->ca[i], rob->sa[i], rob->a[i], rob->d[i], ct, st);
+#pragma unroll
+    for (int j = 0; j < kSpl; ++j) {
+      const int s = i * kSpl + j;
+      transform_point(T, rob->sc[s][0], rob->sc[s][1], rob->sc[s][2], px[s], py[s], pz[s]);
+    }
+  }
+
+  // Pose tracking (eq. 16) or terminal (eq. 25) cost.
+  cost += pose_cost(T, p, terminal ? p.w_term_t : p.w_pose_t,
+                    terminal ? p.w_term_r : p.w_pose_r);
+  if (terminal) return cost;
+
+  // Environment collision (eqs. 17, 19, 20).
+  const uint32_t active = rob->slot_active;
+  float c_env = 0.f;
+#pragma unroll
+  for (int s = 0; s < kSlots; ++s) {
+    if (active & (1u << s)) {
+      const float phi = esdf_lookup(rsrc, p, px[s], py[s], pz[s]);
+      const float h = fmaxf(p.env_thr[s] - phi, 0.f);
+      c_env = fmaf(h, h, c_env);
+    }
+  }
+  cost = fmaf(p.w_env, c_env, cost);
+
+  // Self collision (eqs. 18-20): squared-distance test first, sqrt only on overlap.
+  float c_self = 0.f;
+#pragma unroll
+  for (int s = 0; s < kSlots; ++s) {
+    const uint32_t mask = rob->pair_mask[s];
+    if (mask == 0u) continue;
+#pragma unroll
+    for (int t = s + 1; t < kSlots; ++t) {
+      if (mask & (1u << t)) {
+        const float dx = px[s] - px[t], dy = py[s] - py[t], dz = pz[s] - pz[t];
+        const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        if (d2 < rob->pair_rsum2[s][t]) {
+          const float h = rob->pair_rsum[s][t] - sqrtf(d2);
+          c_self = fmaf(h, h, c_self);
+        }
+      }
+    }
+  }
+  cost = fmaf(p.w_self, c_self, cost);
+
+  // Position / velocity limits (eq. 22) and null-space term (eq. 24) at state k+1.
+  float c_q = 0.f, c_qd = 0.f, c_ns = 0.f;
+#pragma unroll
+  for (int j = 0; j < kNdof; ++j) {
+    const float q = p.q0[j] + dq[j];
+    const float vq = limit_violation(q, p.qlo[j], p.qhi[j]);
+    const float vqd = limit_violation(qd[j], p.qdlo[j], p.qdhi[j]);
+    const float e = q - p.qref[j];
+    c_q = fmaf(vq, vq, c_q);
+    c_qd = fmaf(vqd, vqd, c_qd);
+    c_ns = fmaf(e, e, c_ns);
+  }
+  cost = fmaf(p.w_q, c_q, cost);
+  cost = fmaf(p.w_qd, c_qd, cost);
+  cost = fmaf(p.w_ns, c_ns, cost);
+  return cost;
+}
+
+// LDS layout of K1 (floats unless noted), for R rollouts of H steps.
+struct K1Lds {
+  float* eps;    // [R*H*7]
+  float* dq;     // [R*H*7]  q_{k+1} - q0
+  float* qd;     // [R*H*7]  qd_{k+1}
+  float* ubar;   // [H*7]
+  float* cost;   // [R*H]
+  float* sc0;    // [16]     sin(q0), cos(q0)
+  float* e;      // [R]      exp(-(S - m_b)/lambda)
+  double* S;     // [R]
+};
+
+__device__ __forceinline__ K1Lds k1_lds(unsigned char* base, int R, int H) {
+  K1Lds L;
+  const int rh7 = R * H * kNdof;
+  L.eps = reinterpret_cast<float*>(base);
+  L.dq = L.eps + rh7;
+  L.qd = L.dq + rh7;
+  L.ubar = L.qd + rh7;
+  L.cost = L.ubar + H * kNdof;
+  L.sc0 = L.cost + R * H;
+  L.e = L.sc0 + 16;
+  size_t off = (size_t)(reinterpret_cast<unsigned char*>(L.e + R) - base);
+  off = (off + 7) & ~size_t(7);
+  L.S = reinterpret_cast<double*>(base + off);
+  return L;
+}
+
+__global__ __launch_bounds__(kK1MaxThreads) void rollout_cost_kernel(
+    const DevRobot* __restrict__ rob, const StepParams p, const float* __restrict__ noise,
+    const float* __restrict__ U_in, const void* __restrict__ grid, Workspace ws) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const int H = p.H, R = p.R, RH = R * H;
+  const K1Lds L = k1_lds(lds_raw, R, H);
+  const int tid = threadIdx.x;
+  const int nthreads = blockDim.x;
+  const int b = blockIdx.x;
+  const int m0 = b * R;
+  const int nroll = min(R, p.K - m0);
+
+  // Stage this block's disturbances (contiguous [nroll][H][7]) and the nominal sequence.
+  const float* src = noise + (size_t)m0 * H * kNdof;
+  const int n_eps = nroll * H * kNdof;
+  for (int i = tid; i < RH * kNdof; i += nthreads) L.eps[i] = (i < n_eps) ? src[i] : 0.f;
+  for (int i = tid; i < H * kNdof; i += nthreads) L.ubar[i] = U_in[i];
+  if (tid < kNdof) {
+    float s, c;
+    sincosf(p.q0[tid], &s, &c);
+    L.sc0[tid] = s;
+    L.sc0[kNdof + tid] = c;
+  }
+  __syncthreads();
+
+  // Roll out eq. 7 (semi-implicit Euler) per (rollout, joint), relative to (q0, qd0).
+  // Strided: a block has R*H threads, which is fewer than R*7 when H < 7.
+  for (int w = tid; w < R * kNdof; w += nthreads) {
+    const int r = w / kNdof, j = w - r * kNdof;
+    if (r < nroll) {
+      const float dt = p.dt, qd0 = p.qd0[j];
+      float dqd = 0.f, dq = 0.f;
+      for (int k = 0; k < H; ++k) {
+        const int idx = (r * H + k) * kNdof + j;
+        const float u = L.ubar[k * kNdof + j] + L.eps[idx];  // eq. 27
+        dqd = fmaf(u, dt, dqd);
+        const float qd = qd0 + dqd;
+        dq = fmaf(qd, dt, dq);
+        L.dq[idx] = dq;
+        L.qd[idx] = qd;
+      }
+    }
+  }
+  __syncthreads();
+
+  // Per-(rollout, step) cost.
+  if (tid < RH) {
+    const int r = tid / H, k = tid - r * H;
+    float cost = 0.f;
+    if (r < nroll) {
+      const int base = (r * H + k) * kNdof;
+      float dq[kNdof], qd[kNdof], u[kNdof];
+#pragma unroll
+      for (int j = 0; j < kNdof; ++j) {
+        dq[j] = L.dq[base + j];
+        qd[j] = L.qd[base + j];
+        u[j] = L.ubar[k * kNdof + j] + L.eps[base + j];
+      }
+      const __amdgpu_buffer_rsrc_t rsrc = grid_resource(grid, p.grid_bytes);
+      cost = step_cost(rob, p, rsrc, L.sc0, dq, qd, u, k == H - 1);
+    }
+    L.cost[tid] = cost;
+  }
+  __syncthreads();
+
+  // S^(m) without the k = 0 state terms (eq. 28), summed over k in double.
+  if (tid < R) {
+    double s = 0.0;
+    if (tid < nroll) {
+      for (int k = 0; k < H; ++k) s += (double)L.cost[tid * H + k];
+      ws.S[m0 + tid] = s;
+    }
+    L.S[tid] = s;
+  }
+  __syncthreads();
+
+  // Softmax partial of this block (eqs. 29-30 regrouped per block).
+  if (tid == 0) {
+    double mn = __builtin_inf();
+    for (int r = 0; r < nroll; ++r)
+      if (isfinite(L.S[r])) mn = fmin(mn, L.S[r]);
+    float Z = 0.f, Z2 = 0.f;
+    for (int r = 0; r < R; ++r) {
+      float e = 0.f;
+      if (r < nroll && isfinite(L.S[r]) && isfinite(mn))
+        e = expf(-(float)(L.S[r] - mn) * p.inv_lambda);
+      L.e[r] = e;
+      Z += e;
+      Z2 = fmaf(e, e, Z2);
+    }
+    ws.part_m[b] = mn;
+    ws.part_Z[b] = Z;
+    ws.part_Z2[b] = Z2;
+  }
+  __syncthreads();
+  for (int o = tid; o < H * kNdof; o += nthreads) {
+    float acc = 0.f;
+    for (int r = 0; r < nroll; ++r) acc = fmaf(L.e[r], L.eps[r * H * kNdof + o], acc);
+    ws.part_N[(size_t)o * p.P + b] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K2: merge
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, kWave));
+  return v;
+}
+
+struct MergeStats {
+  double m;   // minimum over finite S (+inf if none)
+  float Z;    // sum exp(-(S - m)/lambda)
+  float Z2;   // sum exp(-2 (S - m)/lambda)
+};
+
+// Every wave merges the block partials itself, in a fixed order (deterministic).
+__device__ __forceinline__ MergeStats merge_stats(const Workspace& ws, int P, float inv_lambda,
+                                                  int lane) {
+  double mn = __builtin_inf();
+  for (int i = lane; i < P; i += kWave) mn = fmin(mn, ws.part_m[i]);
+  mn = wave_min(mn);
+  float Z = 0.f, Z2 = 0.f;
+  if (isfinite(mn)) {
+    for (int i = lane; i < P; i += kWave) {
+      const double mb = ws.part_m[i];
+      if (!isfinite(mb)) continue;
+      const float s = expf(-(float)(mb - mn) * inv_lambda);
+      Z = fmaf(ws.part_Z[i], s, Z);
+      Z2 = fmaf(ws.part_Z2[i], s * s, Z2);
+    }
+  }
+  return MergeStats{mn, wave_sum(Z), wave_sum(Z2)};
+}
+
+// State terms at k = 0 (pose, environment, self, q/qd limits, null space): the same
+// for every rollout, evaluated once by a whole block.  Returns the sum in thread 0.
+__device__ float state0_cost_block(const DevRobot* __restrict__ rob, const StepParams& p,
+                                   const void* grid, float* centres /*LDS [kSlots*4]*/,
+                                   float* red /*LDS [kK2Threads/64]*/) {
+  const int tid = threadIdx.x;
+  Frame T = identity_frame();
+#pragma unroll
+  for (int i = 0; i < kNdof; ++i) {
+    float s, c;
+    sincosf(p.q0[i], &s, &c);
+    mdh_step(T, rob->ca[i], rob->sa[i], rob->a[i], rob->d[i], c, s);
+    if (tid == 0) {
+#pragma unroll
+      for (int j = 0; j < kSpl; ++j) {
+        const int sl = i * kSpl + j;
+        float x, y, z;
+        transform_point(T, rob->sc[sl][0], rob->sc[sl][1], rob->sc[sl][2], x, y, z);
+        centres[sl * 4 + 0] = x;
+        centres[sl * 4 + 1] = y;
+        centres[sl * 4 + 2] = z;
+      }
+    }
+  }
+  __syncthreads();
+  float part = 0.f;
+  if (tid < kSlots && (rob->slot_active & (1u << tid))) {
+    const __amdgpu_buffer_rsrc_t rsrc = grid_resource(grid, p.grid_bytes);
+    const float phi = esdf_lookup(rsrc, p, centres[tid * 4], centres[tid * 4 + 1],
+                                  centres[tid * 4 + 2]);
+    const float h = fmaxf(p.env_thr[tid] - phi, 0.f);
+    part = p.w_env * h * h;
+  }
+  for (int i = tid; i < rob->n_pairs; i += blockDim.x) {
+    const int s = rob->pair_list[i][0], t = rob->pair_list[i][1];
+    const float dx = centres[s * 4] - centres[t * 4];
+    const float dy = centres[s * 4 + 1] - centres[t * 4 + 1];
+    const float dz = centres[s * 4 + 2] - centres[t * 4 + 2];
+    const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    if (d2 < rob->pair_rsum2[s][t]) {
+      const float h = rob->pair_rsum[s][t] - sqrtf(d2);
+      part = fmaf(p.w_self * h, h, part);
+    }
+  }
+  if (tid == 0) {
+    part += pose_cost(T, p, p.w_pose_t, p.w_pose_r);
+    float c_q = 0.f, c_qd = 0.f, c_ns = 0.f;
+    for (int j = 0; j < kNdof; ++j) {
+      const float vq = limit_violation(p.q0[j], p.qlo[j], p.qhi[j]);
+      const float vqd = limit_violation(p.qd0[j], p.qdlo[j], p.qdhi[j]);
+      const float e = p.q0[j] - p.qref[j];
+      c_q = fmaf(vq, vq, c_q);
+      c_qd = fmaf(vqd, vqd, c_qd);
+      c_ns = fmaf(e, e, c_ns);
+    }
+    part += p.w_q * c_q + p.w_qd * c_qd + p.w_ns * c_ns;
+  }
+  part = wave_sum(part);
+  if ((tid & (kWave - 1)) == 0) red[tid / kWave] = part;
+  __syncthreads();
+  float total = 0.f;
+  if (tid == 0)
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) total += red[w];
+  return total;
+}
+
+__global__ __launch_bounds__(kK2Threads) void merge_kernel(
+    const DevRobot* __restrict__ rob, const StepParams p, const float* U_in, float* U_out,
+    const void* __restrict__ grid, Workspace ws, float* __restrict__ costs_out,
+    float* __restrict__ weights_out, float* __restrict__ stats_out) {
+  __shared__ float centres[kSlots * 4];
+  __shared__ float red[kK2Threads / kWave];
+  __shared__ float c0_s;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int K = p.K, P = p.P, HO = p.H * kNdof;
+
+  if (blockIdx.x == 0) {
+    const float c0 = state0_cost_block(rob, p, grid, centres, red);
+    if (threadIdx.x == 0) c0_s = c0;
+    __syncthreads();
+    const float c0v = c0_s;
+    if (costs_out) {
+      for (int i = threadIdx.x; i < K; i += blockDim.x)
+        costs_out[i] = (float)(ws.S[i] + (double)c0v);
+    }
+    if (stats_out && threadIdx.x < kWave) {
+      const MergeStats st = merge_stats(ws, P, p.inv_lambda, lane);
+      if (lane == 0) {
+        const bool ok = isfinite(st.m);
+        stats_out[0] = ok ? (float)(st.m + (double)c0v) : __builtin_nanf("");
+        stats_out[1] = ok ? st.Z : 0.f;
+        stats_out[2] = ok ? st.Z * st.Z / st.Z2 : 0.f;
+        stats_out[3] = ok ? 0.f : (float)SMPC_E_NUMERIC;
+      }
+    }
+    return;
+  }
+
+  const int wave = (blockIdx.x - 1) * (kK2Threads / kWave) + (threadIdx.x / kWave);
+  const int n_weight_waves = weights_out ? (K + kWeightsPerWave - 1) / kWeightsPerWave : 0;
+  if (wave >= HO + n_weight_waves) return;
+  const MergeStats st = merge_stats(ws, P, p.inv_lambda, lane);
+  const bool ok = isfinite(st.m);
+
+  if (wave < HO) {
+    // U*[o] = Ubar[o] + sum_b N_b[o] exp(-(m_b - m)/lambda) / Z   (eq. 30)
+    const int o = wave;
+    float acc = 0.f;
+    if (ok) {
+      for (int i = lane; i < P; i += kWave) {
+        const double mb = ws.part_m[i];
+        if (!isfinite(mb)) continue;
+        const float s = expf(-(float)(mb - st.m) * p.inv_lambda);
+        acc = fmaf(ws.part_N[(size_t)o * P + i], s, acc);
+      }
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) U_out[o] = ok ? U_in[o] + acc / st.Z : U_in[o];
+    return;
+  }
+
+  // w^(m) (eq. 29) for a chunk of rollouts.
+  const int chunk = wave - HO;
+  const int lo = chunk * kWeightsPerWave;
+  const int hi = min(K, lo + kWeightsPerWave);
+  const float invZ = ok ? 1.f / st.Z : 0.f;
+  for (int i = lo + lane; i < hi; i += kWave) {
+    const double s = ws.S[i];
+    float w = 0.f;
+    if (ok && isfinite(s)) w = expf(-(float)(s - st.m) * p.inv_lambda) * invZ;
+    weights_out[i] = w;
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Host-side launch helpers
+// ---------------------------------------------------------------------------
+
+static size_t k1_lds_bytes(int R, int H) {
+  size_t floats = (size_t)R * H * kNdof * 3 + (size_t)H * kNdof + (size_t)R * H + 16 + R;
+  size_t bytes = floats * 4;
+  bytes = (bytes + 7) & ~size_t(7);
+  return bytes + (size_t)R * 8;
+}
+
+LaunchConfig plan_launch_config(int K, int H) {
+  // Rollouts per block: whole rollouts only, at most kK1MaxThreads threads; pick the
+  // fewest idle lanes in the 64-padded block, then the block size closest to 256.
+  int bestR = 1;
+  double best_waste = 2.0;
+  int best_dist = 1 << 30;
+  for (int R = 1; R * H <= kK1MaxThreads; ++R) {
+    const int threads = (R * H + kWave - 1) / kWave * kWave;
+    const double waste = (double)(threads - R * H) / threads;
+    const int dist = threads > 256 ? threads - 256 : 256 - threads;
+    if (waste < best_waste - 1e-12 || (waste < best_waste + 1e-12 && dist < best_dist)) {
+      best_waste = waste;
+      best_dist = dist;
+      bestR = R;
+    }
+  }
+  LaunchConfig lc;
+  lc.R = bestR;
+  lc.k1_threads = (bestR * H + kWave - 1) / kWave * kWave;
+  lc.P = (K + bestR - 1) / bestR;
+  lc.k1_lds = k1_lds_bytes(bestR, H);
+  const int waves_per_block = kK2Threads / kWave;
+  const int work_waves = H * kNdof + (K + kWeightsPerWave - 1) / kWeightsPerWave;
+  lc.k2_blocks = 1 + (work_waves + waves_per_block - 1) / waves_per_block;
+  return lc;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t workspace_bytes(int K, int H, int P) {
+  return align256((size_t)K * 8) + align256((size_t)P * 8) + 2 * align256((size_t)P * 4) +
+         align256((size_t)H * kNdof * P * 4);
+}
+
+Workspace carve_workspace(void* base, int K, int H, int P) {
+  unsigned char* b = static_cast<unsigned char*>(base);
+  Workspace ws;
+  ws.S = reinterpret_cast<double*>(b);
+  b += align256((size_t)K * 8);
+  ws.part_m = reinterpret_cast<double*>(b);
+  b += align256((size_t)P * 8);
+  ws.part_Z = reinterpret_cast<float*>(b);
+  b += align256((size_t)P * 4);
+  ws.part_Z2 = reinterpret_cast<float*>(b);
+  b += align256((size_t)P * 4);
+  ws.part_N = reinterpret_cast<float*>(b);
+  return ws;
+}
+
+int launch_plan_step(const DevRobot* robot, const StepParams& p, const LaunchConfig& lc,
+                     const Workspace& ws, const smpc_plan_args& args, void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(rollout_cost_kernel, dim3(lc.P), dim3(lc.k1_threads), lc.k1_lds, s, robot,
+                     p, args.noise, args.U_in, args.esdf.data, ws);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return (int)e;
+  hipLaunchKernelGGL(merge_kernel, dim3(lc.k2_blocks), dim3(kK2Threads), 0, s, robot, p,
+                     args.U_in, args.U_out, args.esdf.data, ws, args.costs_out, args.weights_out,
+                     args.stats_out);
+  return (int)hipGetLastError();
+}
+
+}  // namespace smpc

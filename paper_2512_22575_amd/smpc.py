@@ -1,0 +1,255 @@
+"""ctypes binding of libsmpc (include/smpc.h): argument marshalling only.
+
+The functions ``smpc_create``, ``smpc_set_robot``, ``smpc_plan_step``,
+``smpc_destroy``, ``smpc_status_string``, ``smpc_last_error`` and
+``smpc_version`` mirror the C entry points one to one.  :class:`Planner` is a
+convenience wrapper that takes torch tensors (device memory and streams come
+from PyTorch); every step of the plan step itself runs in the HIP library.
+
+The library is loaded from this package directory.  If it is missing, loading
+raises immediately: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from ctypes import (POINTER, c_char_p, c_double, c_float, c_int32, c_uint64, c_void_p)
+
+import numpy as np
+
+NDOF = 7
+MAX_H = 64
+SPHERES_PER_LINK = 4
+MAX_SPHERES = 28
+MAX_PAIRS = 378
+GRID_F32, GRID_F16 = 0, 1
+
+SMPC_OK = 0
+SMPC_E_INVALID_ARG = -1
+SMPC_E_OOM = -2
+SMPC_E_DEVICE = -3
+SMPC_E_NUMERIC = -4
+SMPC_E_UNSUPPORTED = -5
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsmpc.so")
+
+
+class smpc_robot_desc(ctypes.Structure):
+    _fields_ = [
+        ("n_dof", c_int32),
+        ("a", c_double * NDOF), ("d", c_double * NDOF), ("alpha", c_double * NDOF),
+        ("q_min", c_double * NDOF), ("q_max", c_double * NDOF),
+        ("qd_min", c_double * NDOF), ("qd_max", c_double * NDOF),
+        ("qdd_min", c_double * NDOF), ("qdd_max", c_double * NDOF),
+        ("q_ref", c_double * NDOF),
+        ("n_spheres", c_int32),
+        ("sphere_link", c_int32 * MAX_SPHERES),
+        ("sphere_center", (c_double * 3) * MAX_SPHERES),
+        ("sphere_radius", c_double * MAX_SPHERES),
+        ("n_pairs", c_int32),
+        ("pairs", (c_int32 * 2) * MAX_PAIRS),
+    ]
+
+
+class smpc_cost_weights(ctypes.Structure):
+    _fields_ = [(name, c_float) for name in (
+        "w_pose_t", "w_pose_r", "w_term_t", "w_term_r", "w_env", "d_act", "w_self",
+        "w_q", "w_qd", "w_qdd", "limit_margin_frac", "w_smooth", "w_ns")]
+
+
+class smpc_grid(ctypes.Structure):
+    _fields_ = [
+        ("data", c_void_p),
+        ("nx", c_int32), ("ny", c_int32), ("nz", c_int32),
+        ("dtype", c_int32),
+        ("origin", c_float * 3),
+        ("voxel", c_float),
+    ]
+
+
+class smpc_plan_args(ctypes.Structure):
+    _fields_ = [
+        ("q0", c_float * NDOF), ("qd0", c_float * NDOF),
+        ("T_goal", c_float * 16),
+        ("esdf", smpc_grid),
+        ("noise", c_void_p),
+        ("seed", c_uint64),
+        ("sigma", c_float * NDOF),
+        ("K", c_int32), ("H", c_int32),
+        ("dt", c_float), ("lambda_", c_float),
+        ("weights", smpc_cost_weights),
+        ("U_in", c_void_p), ("U_out", c_void_p),
+        ("costs_out", c_void_p), ("weights_out", c_void_p), ("stats_out", c_void_p),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libsmpc (once).  Raises OSError if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OSError(f"{path} is missing: build it with `python -m paper_2512_22575_amd.build`")
+    lib = ctypes.CDLL(path)
+    lib.smpc_create.argtypes = [POINTER(c_void_p), c_int32]
+    lib.smpc_create.restype = c_int32
+    lib.smpc_destroy.argtypes = [c_void_p]
+    lib.smpc_destroy.restype = None
+    lib.smpc_set_robot.argtypes = [c_void_p, POINTER(smpc_robot_desc)]
+    lib.smpc_set_robot.restype = c_int32
+    lib.smpc_plan_step.argtypes = [c_void_p, POINTER(smpc_plan_args), c_void_p]
+    lib.smpc_plan_step.restype = c_int32
+    lib.smpc_status_string.argtypes = [c_int32]
+    lib.smpc_status_string.restype = c_char_p
+    lib.smpc_last_error.argtypes = [c_void_p]
+    lib.smpc_last_error.restype = c_char_p
+    lib.smpc_version.argtypes = []
+    lib.smpc_version.restype = c_int32
+    _lib = lib
+    return lib
+
+
+# --- one-to-one wrappers ------------------------------------------------------
+
+def smpc_create(hip_device: int = 0) -> tuple[int, c_void_p]:
+    h = c_void_p()
+    st = load_library().smpc_create(ctypes.byref(h), int(hip_device))
+    return st, h
+
+
+def smpc_destroy(ctx: c_void_p) -> None:
+    load_library().smpc_destroy(ctx)
+
+
+def smpc_set_robot(ctx: c_void_p, desc: smpc_robot_desc) -> int:
+    return load_library().smpc_set_robot(ctx, ctypes.byref(desc))
+
+
+def smpc_plan_step(ctx: c_void_p, args: smpc_plan_args, stream: int | None) -> int:
+    return load_library().smpc_plan_step(ctx, ctypes.byref(args), c_void_p(stream or 0))
+
+
+def smpc_status_string(status: int) -> str:
+    return load_library().smpc_status_string(int(status)).decode()
+
+
+def smpc_last_error(ctx: c_void_p) -> str:
+    return load_library().smpc_last_error(ctx).decode()
+
+
+def smpc_version() -> int:
+    return int(load_library().smpc_version())
+
+
+# --- marshalling helpers --------------------------------------------------------
+
+def robot_desc(robot) -> smpc_robot_desc:
+    """Fill an smpc_robot_desc from an object with the fields of synth.robot.Robot."""
+    d = smpc_robot_desc()
+    d.n_dof = NDOF
+    for name in ("a", "d", "alpha", "q_min", "q_max", "qd_min", "qd_max", "qdd_min",
+                 "qdd_max", "q_ref"):
+        getattr(d, name)[:] = [float(x) for x in np.asarray(getattr(robot, name))]
+    n_s = int(len(robot.sphere_radius))
+    if n_s > MAX_SPHERES:
+        raise ValueError(f"{n_s} spheres exceed the ABI limit {MAX_SPHERES}")
+    d.n_spheres = n_s
+    for s in range(n_s):
+        d.sphere_link[s] = int(robot.sphere_link[s])
+        d.sphere_center[s][:] = [float(x) for x in robot.sphere_center[s]]
+        d.sphere_radius[s] = float(robot.sphere_radius[s])
+    pairs = np.asarray(robot.pairs, dtype=np.int64).reshape(-1, 2)
+    if pairs.shape[0] > MAX_PAIRS:
+        raise ValueError(f"{pairs.shape[0]} pairs exceed the ABI limit {MAX_PAIRS}")
+    d.n_pairs = int(pairs.shape[0])
+    for i, (a, b) in enumerate(pairs):
+        d.pairs[i][0] = int(a)
+        d.pairs[i][1] = int(b)
+    return d
+
+
+def cost_weights(w: dict) -> smpc_cost_weights:
+    cw = smpc_cost_weights()
+    for name, _ in smpc_cost_weights._fields_:
+        setattr(cw, name, float(w[name]))
+    return cw
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def plan_args(q0, qd0, T_goal, grid, origin, voxel, noise, U_in, U_out, K, H, dt, lam,
+              weights: dict, costs_out=None, weights_out=None, stats_out=None, seed: int = 0,
+              sigma=None, grid_dtype: int = GRID_F32) -> smpc_plan_args:
+    """Build smpc_plan_args; tensors are torch tensors on the device (or None)."""
+    a = smpc_plan_args()
+    a.q0[:] = [float(x) for x in np.asarray(q0, np.float32)]
+    a.qd0[:] = [float(x) for x in np.asarray(qd0, np.float32)]
+    a.T_goal[:] = [float(x) for x in np.asarray(T_goal, np.float32).reshape(16)]
+    nz, ny, nx = (int(s) for s in grid.shape)
+    a.esdf = smpc_grid(c_void_p(_ptr(grid)), nx, ny, nz, int(grid_dtype),
+                       (c_float * 3)(*[float(x) for x in np.asarray(origin, np.float32)]),
+                       float(voxel))
+    a.noise = _ptr(noise)
+    a.seed = int(seed)
+    a.sigma[:] = [0.5] * NDOF if sigma is None else [float(x) for x in sigma]
+    a.K, a.H = int(K), int(H)
+    a.dt, a.lambda_ = float(dt), float(lam)
+    a.weights = cost_weights(weights)
+    a.U_in, a.U_out = _ptr(U_in), _ptr(U_out)
+    a.costs_out, a.weights_out, a.stats_out = _ptr(costs_out), _ptr(weights_out), _ptr(stats_out)
+    return a
+
+
+class SMPCError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"{smpc_status_string(status)} ({status}): {detail}")
+        self.status = status
+
+
+class Planner:
+    """Context owning one robot; plan steps take torch tensors on ``cuda:device``."""
+
+    def __init__(self, robot, device: int = 0):
+        st, self._ctx = smpc_create(device)
+        if st != SMPC_OK:
+            raise SMPCError(st, "smpc_create")
+        self.device = device
+        st = smpc_set_robot(self._ctx, robot_desc(robot))
+        if st != SMPC_OK:
+            raise SMPCError(st, smpc_last_error(self._ctx))
+
+    def close(self) -> None:
+        if getattr(self, "_ctx", None):
+            smpc_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def plan_step(self, *, q0, qd0, T_goal, grid, origin, voxel, noise, U_in, U_out, dt, lam,
+                  weights, costs_out=None, weights_out=None, stats_out=None, stream=None,
+                  seed: int = 0, sigma=None, grid_dtype: int = GRID_F32, K=None, H=None) -> None:
+        """Enqueue one plan step on ``stream`` (default: torch's current stream)."""
+        import torch
+        if noise is not None:
+            K, H = int(noise.shape[0]), int(noise.shape[1])
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+        a = plan_args(q0, qd0, T_goal, grid, origin, voxel, noise, U_in, U_out, K, H, dt, lam,
+                      weights, costs_out, weights_out, stats_out, seed, sigma, grid_dtype)
+        st = smpc_plan_step(self._ctx, a, stream)
+        if st != SMPC_OK:
+            raise SMPCError(st, smpc_last_error(self._ctx))
+
+
+def is_finite_float(x) -> bool:
+    return math.isfinite(float(x))

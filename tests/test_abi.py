@@ -1,0 +1,219 @@
+"""C-ABI checks that need no GPU: exports, struct layout and argument validation.
+
+Every invalid request must be rejected on the host before any HIP call, so these
+run on a machine without a GPU.  No test here passes valid arguments with fake
+device pointers while a GPU is present.
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2512_22575_amd import smpc as S
+from synth import robot as R
+from synth import workload as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "smpc.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(smpc_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_function():
+    lib = S.load_library()
+    names = header_functions()
+    assert {"smpc_create", "smpc_destroy", "smpc_set_robot", "smpc_plan_step",
+            "smpc_status_string", "smpc_last_error", "smpc_version"} <= set(names)
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in smpc.h but not exported"
+    out = subprocess.run(["nm", "-D", "--defined-only", S.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    for name in names:
+        assert re.search(rf"\bT {name}$", out, re.M), f"{name} is not a defined text symbol"
+
+
+LAYOUT_PROBE = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "smpc.h"
+#define F(T, f) printf(#T " " #f " %zu\n", offsetof(T, f));
+int main(void) {
+  printf("smpc_robot_desc sizeof %zu\n", sizeof(smpc_robot_desc));
+  printf("smpc_plan_args sizeof %zu\n", sizeof(smpc_plan_args));
+  printf("smpc_grid sizeof %zu\n", sizeof(smpc_grid));
+  printf("smpc_cost_weights sizeof %zu\n", sizeof(smpc_cost_weights));
+  F(smpc_robot_desc, a) F(smpc_robot_desc, q_ref) F(smpc_robot_desc, n_spheres)
+  F(smpc_robot_desc, sphere_center) F(smpc_robot_desc, n_pairs) F(smpc_robot_desc, pairs)
+  F(smpc_plan_args, T_goal) F(smpc_plan_args, esdf) F(smpc_plan_args, noise)
+  F(smpc_plan_args, seed) F(smpc_plan_args, K) F(smpc_plan_args, weights)
+  F(smpc_plan_args, U_in) F(smpc_plan_args, stats_out)
+  F(smpc_grid, nx) F(smpc_grid, origin) F(smpc_grid, voxel)
+  return 0;
+}
+"""
+
+
+def test_ctypes_structs_match_c_layout(tmp_path):
+    src = tmp_path / "probe.c"
+    exe = tmp_path / "probe"
+    src.write_text(LAYOUT_PROBE)
+    subprocess.run(["gcc", "-std=c99", f"-I{os.path.dirname(HEADER)}", str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    rename = {"lambda": "lambda_"}
+    for line in out.splitlines():
+        struct, field, value = line.split()
+        cls = getattr(S, struct)
+        if field == "sizeof":
+            assert ctypes.sizeof(cls) == int(value), struct
+        else:
+            assert getattr(cls, rename.get(field, field)).offset == int(value), (struct, field)
+
+
+def test_status_strings_and_version():
+    assert S.smpc_status_string(S.SMPC_OK) == "ok"
+    for st in (S.SMPC_E_INVALID_ARG, S.SMPC_E_OOM, S.SMPC_E_DEVICE, S.SMPC_E_NUMERIC,
+               S.SMPC_E_UNSUPPORTED):
+        assert S.smpc_status_string(st) not in ("ok", "unknown status")
+    assert S.smpc_status_string(12345) == "unknown status"
+    assert S.smpc_version() >= 100
+
+
+# ---------------------------------------------------------------------------
+# Validation (host-only paths)
+# ---------------------------------------------------------------------------
+
+@pytest.fixture()
+def ctx():
+    st, h = S.smpc_create(0)
+    assert st == S.SMPC_OK and h.value
+    yield h
+    S.smpc_destroy(h)
+
+
+def test_create_rejects_bad_arguments():
+    lib = S.load_library()
+    assert lib.smpc_create(None, 0) == S.SMPC_E_INVALID_ARG
+    st, h = S.smpc_create(-1)
+    assert st == S.SMPC_E_INVALID_ARG and not h.value
+    S.smpc_destroy(None)   # no-op
+
+
+def test_set_robot_validation(ctx):
+    good = S.robot_desc(R.make_robot(0))
+    assert S.smpc_set_robot(ctx, good) == S.SMPC_OK
+
+    def check(mutate, expected, msg):
+        d = S.robot_desc(R.make_robot(0))
+        mutate(d)
+        assert S.smpc_set_robot(ctx, d) == expected
+        assert msg in S.smpc_last_error(ctx)
+
+    check(lambda d: setattr(d, "n_dof", 6), S.SMPC_E_UNSUPPORTED, "n_dof")
+    check(lambda d: d.a.__setitem__(2, float("nan")), S.SMPC_E_INVALID_ARG, "DH")
+    check(lambda d: d.q_min.__setitem__(3, 5.0), S.SMPC_E_INVALID_ARG, "q_min[3]")
+    check(lambda d: d.qdd_max.__setitem__(0, float("inf")), S.SMPC_E_INVALID_ARG, "qdd limit")
+    check(lambda d: setattr(d, "n_spheres", 29), S.SMPC_E_INVALID_ARG, "n_spheres")
+    check(lambda d: d.sphere_link.__setitem__(0, 8), S.SMPC_E_INVALID_ARG, "sphere_link")
+    check(lambda d: d.sphere_link.__setitem__(0, 2), S.SMPC_E_UNSUPPORTED, "more than")
+    check(lambda d: d.sphere_radius.__setitem__(5, -0.1), S.SMPC_E_INVALID_ARG, "radius")
+    check(lambda d: setattr(d, "n_pairs", 379), S.SMPC_E_INVALID_ARG, "n_pairs")
+    check(lambda d: d.pairs[0].__setitem__(1, d.pairs[0][0]), S.SMPC_E_INVALID_ARG, "pair 0")
+    check(lambda d: d.pairs[3].__setitem__(0, 28), S.SMPC_E_INVALID_ARG, "pair 3")
+    lib = S.load_library()
+    assert lib.smpc_set_robot(ctx, None) == S.SMPC_E_INVALID_ARG
+    assert lib.smpc_set_robot(None, ctypes.byref(good)) == S.SMPC_E_INVALID_ARG
+
+
+class _FakeTensor:
+    """Stands in for a device tensor in host-only validation tests (never dereferenced)."""
+
+    def __init__(self, shape, ptr=0x1000):
+        self.shape = shape
+        self._ptr = ptr
+
+    def data_ptr(self):
+        return self._ptr
+
+
+def _args(**over):
+    inp = W.tiny()
+    K, H = inp.K, inp.H
+    kw = dict(q0=inp.q0, qd0=inp.qd0, T_goal=inp.T_goal, grid=_FakeTensor(inp.grid.shape),
+              origin=inp.origin, voxel=inp.voxel, noise=_FakeTensor((K, H, 7)),
+              U_in=_FakeTensor((H, 7)), U_out=_FakeTensor((H, 7)), K=K, H=H, dt=inp.dt,
+              lam=inp.lam, weights=dict(inp.weights))
+    kw.update(over)
+    return S.plan_args(**kw)
+
+
+def _expect(ctx, args, status, msg):
+    st = S.smpc_plan_step(ctx, args, None)
+    assert st == status, (st, S.smpc_last_error(ctx))
+    assert msg in S.smpc_last_error(ctx)
+
+
+def test_plan_step_requires_robot(ctx):
+    _expect(ctx, _args(), S.SMPC_E_INVALID_ARG, "no robot")
+
+
+@pytest.mark.parametrize("over,status,msg", [
+    (dict(K=0), S.SMPC_E_INVALID_ARG, "K=0"),
+    (dict(H=0), S.SMPC_E_INVALID_ARG, "H=0"),
+    (dict(H=65), S.SMPC_E_INVALID_ARG, "H=65"),
+    (dict(K=40_000_000, H=64), S.SMPC_E_INVALID_ARG, "2^31"),
+    (dict(dt=0.0), S.SMPC_E_INVALID_ARG, "dt"),
+    (dict(dt=float("nan")), S.SMPC_E_INVALID_ARG, "dt"),
+    (dict(lam=0.0), S.SMPC_E_INVALID_ARG, "lambda"),
+    (dict(lam=-1.0), S.SMPC_E_INVALID_ARG, "lambda"),
+    (dict(lam=float("inf")), S.SMPC_E_INVALID_ARG, "lambda"),
+    (dict(q0=np.full(7, np.nan)), S.SMPC_E_INVALID_ARG, "joint state"),
+    (dict(qd0=np.array([0, 0, 0, np.inf, 0, 0, 0])), S.SMPC_E_INVALID_ARG, "joint state"),
+    (dict(T_goal=np.diag([1.0, 1.0, 1.0, 2.0])), S.SMPC_E_INVALID_ARG, "last row"),
+    (dict(T_goal=np.diag([1.0, 1.1, 1.0, 1.0])), S.SMPC_E_INVALID_ARG, "orthonormal"),
+    (dict(voxel=0.0), S.SMPC_E_INVALID_ARG, "voxel"),
+    (dict(origin=np.array([0, np.nan, 0])), S.SMPC_E_INVALID_ARG, "origin"),
+    (dict(grid=_FakeTensor((1, 4, 4))), S.SMPC_E_INVALID_ARG, ">= 2"),
+    (dict(grid=_FakeTensor((4, 4, 4), ptr=0)), S.SMPC_E_INVALID_ARG, "esdf.data"),
+    (dict(grid=_FakeTensor((1024, 1024, 1024))), S.SMPC_E_INVALID_ARG, "2^31 bytes"),
+    (dict(grid_dtype=7), S.SMPC_E_INVALID_ARG, "dtype"),
+    (dict(grid_dtype=S.GRID_F16), S.SMPC_E_UNSUPPORTED, "float32"),
+    (dict(U_in=None), S.SMPC_E_INVALID_ARG, "U_in"),
+    (dict(U_out=None), S.SMPC_E_INVALID_ARG, "U_out"),
+    (dict(noise=None), S.SMPC_E_UNSUPPORTED, "sampling"),
+])
+def test_plan_step_rejects_invalid_arguments(ctx, over, status, msg):
+    assert S.smpc_set_robot(ctx, S.robot_desc(R.make_robot(0))) == S.SMPC_OK
+    _expect(ctx, _args(**over), status, msg)
+
+
+@pytest.mark.parametrize("field,value", [
+    ("w_env", -1.0), ("w_self", float("nan")), ("d_act", float("inf")),
+    ("limit_margin_frac", 0.5), ("w_ns", -0.1)])
+def test_plan_step_rejects_bad_weights(ctx, field, value):
+    assert S.smpc_set_robot(ctx, S.robot_desc(R.make_robot(0))) == S.SMPC_OK
+    w = dict(W.DEFAULT_WEIGHTS)
+    w[field] = value
+    _expect(ctx, _args(weights=w), S.SMPC_E_INVALID_ARG, "")
+
+
+def test_valid_request_without_gpu_fails_loudly(ctx):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present; this checks the GPU-less failure path")
+    assert S.smpc_set_robot(ctx, S.robot_desc(R.make_robot(0))) == S.SMPC_OK
+    st = S.smpc_plan_step(ctx, _args(), None)
+    assert st == S.SMPC_E_DEVICE
+    assert S.smpc_last_error(ctx)
+
+
+def test_planner_raises_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(S, "_lib", None)
+    with pytest.raises(OSError, match="missing"):
+        S.load_library(str(tmp_path / "libsmpc.so"))

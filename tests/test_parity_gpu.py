@@ -1,0 +1,223 @@
+"""GPU parity: libsmpc (float32, gfx950) against the FP64 oracle on identical inputs.
+
+Every call goes through the C ABI (ctypes binding).  The bar: per-rollout costs
+within 1e-4 relative (+1e-6 absolute floor), updated controls within 1e-5
+rad/s^2, weights within the bound the cost bar implies (gpu_helpers).
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import smpc_oracle as O
+from synth import robot as R
+from synth import scene as SC
+from synth import workload as W
+from tests.gpu_helpers import (U_ATOL, assert_controls_close, assert_costs_close, run_gpu,
+                               weight_tolerance)
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle(inp, lam=None):
+    out = O.plan_step(inp.robot.rounded_f32(), inp.q0, inp.qd0, inp.T_goal, inp.grid, inp.origin,
+                      inp.voxel, inp.noise, inp.U_bar, inp.dt, inp.lam if lam is None else lam,
+                      inp.weights)
+    out["lam"] = inp.lam if lam is None else lam
+    return out
+
+
+def check_full(inp, lam=None, **kw):
+    ref = oracle(inp, lam)
+    got = run_gpu(inp, lam=lam, **kw)
+    assert_costs_close(got["S"], ref["S"])
+    assert_controls_close(got["U_star"], ref["U_star"])
+    tol = weight_tolerance(ref)
+    assert np.all(np.abs(got["w"] - ref["w"]) <= tol), float(np.max(np.abs(got["w"] - ref["w"])))
+    st = got["stats"]
+    assert st[3] == 0.0
+    assert st[0] == pytest.approx(ref["S_min"], rel=1e-4)
+    assert st[1] == pytest.approx(ref["Z"], rel=1e-3)
+    assert st[2] == pytest.approx(ref["ess"], rel=1e-3)
+    return got, ref
+
+
+def small_inputs(seed, K, H, dt=0.05, n=32, voxel=0.05, **kw):
+    return W.make_inputs(seed, K=K, H=H, dt=dt, n=n, voxel=voxel, n_boxes=6, n_spheres=4, **kw)
+
+
+def test_tiny_workload_parity():
+    check_full(W.tiny())
+
+
+def test_mid_workload_parity():
+    check_full(W.mid())
+
+
+def test_reactive_workload_full_size_parity():
+    """K=4096, H=40, 200^3 grid: the benchmark's launch configuration."""
+    check_full(W.ReactiveScenario(seed=3).inputs())
+
+
+@pytest.mark.parametrize("K,H", [(1, 1), (3, 5), (65, 7), (129, 37), (100, 64), (257, 40),
+                                 (31, 16), (2, 63)])
+def test_ragged_sizes_parity(K, H):
+    check_full(small_inputs(10 + K + H, K, H))
+
+
+def test_every_cost_term_active():
+    """Non-zero nominal sequence and start velocity, null-space weight on, low-margin limits."""
+    inp = small_inputs(21, 96, 24, dt=0.04)
+    rng = np.random.default_rng(0)
+    inp.U_bar = W.f32(rng.normal(scale=0.8, size=inp.U_bar.shape))
+    inp.qd0 = W.f32(rng.uniform(-1.5, 1.5, size=7))
+    inp.weights = {**inp.weights, "w_ns": W.f32s(0.3), "limit_margin_frac": W.f32s(0.2),
+                   "d_act": W.f32s(0.08)}
+    check_full(inp)
+
+
+def test_small_temperature_selects_argmin():
+    inp = small_inputs(22, 200, 20)
+    got, ref = check_full(inp, lam=1e-3)
+    order = np.argsort(ref["S"])
+    if ref["S"][order[1]] - ref["S"][order[0]] > 0.05:
+        np.testing.assert_allclose(got["U_star"], inp.U_bar + inp.noise[order[0]], atol=U_ATOL)
+        assert int(np.argmax(got["w"])) == int(order[0])
+
+
+def test_large_temperature_weights_nearly_uniform():
+    inp = small_inputs(23, 128, 12)
+    got, _ = check_full(inp, lam=1e6)
+    np.testing.assert_allclose(got["w"], 1.0 / 128, rtol=1e-3)
+
+
+@pytest.mark.parametrize("which", ["reached", "flipped"])
+def test_log_map_near_zero_and_pi(which):
+    inp = small_inputs(24, 64, 16)
+    inp.qd0 = W.f32(np.zeros(7))
+    T = O.forward_kinematics(inp.robot.rounded_f32(), inp.q0.astype(np.float64)[None])[0, 7]
+    if which == "flipped":
+        flip = np.eye(4)
+        flip[:3, :3] = np.diag([1.0, -1.0, -1.0])     # rotation by pi about the goal's x axis
+        T = T @ flip
+    inp.T_goal = W.f32(T)
+    check_full(inp)
+
+
+def test_fewer_spheres_and_pair_subset():
+    inp = small_inputs(25, 80, 20)
+    rob = R.make_robot(25, spheres_per_link=2)
+    keep = np.random.default_rng(1).uniform(size=rob.n_pairs) < 0.5
+    rob.pairs = rob.pairs[keep]
+    inp.robot = rob
+    check_full(inp)
+
+
+def test_no_spheres_no_pairs():
+    inp = small_inputs(26, 33, 9)
+    rob = R.make_robot(26, spheres_per_link=0)
+    inp.robot = rob
+    check_full(inp)
+
+
+def test_robot_partly_outside_grid_uses_clamped_edges():
+    inp = small_inputs(27, 64, 16, n=12, voxel=0.05)
+    inp.origin = W.f32([0.1, -0.3, 0.2])
+    check_full(inp)
+
+
+def test_nan_rollouts_get_zero_weight():
+    inp = small_inputs(28, 70, 10)
+    inp.noise[5, 3, 2] = np.nan
+    inp.noise[44, 0, 0] = np.inf
+    ref = oracle(inp)
+    got = run_gpu(inp)
+    assert np.isnan(got["S"][5]) or np.isinf(got["S"][5])
+    assert not np.isfinite(got["S"][44])
+    assert got["w"][5] == 0.0 and got["w"][44] == 0.0
+    assert_costs_close(got["S"], ref["S"])
+    assert_controls_close(got["U_star"], ref["U_star"])
+
+
+def test_all_costs_non_finite_reports_numeric_status():
+    inp = small_inputs(29, 20, 6)
+    inp.noise[:] = np.nan
+    rng = np.random.default_rng(2)
+    inp.U_bar = W.f32(rng.normal(size=inp.U_bar.shape))
+    got = run_gpu(inp)
+    np.testing.assert_array_equal(got["U_star"], inp.U_bar.astype(np.float64))
+    assert np.all(got["w"] == 0.0)
+    assert got["stats"][3] == -4.0 and np.isnan(got["stats"][0])
+
+
+def test_U_out_may_alias_U_in():
+    inp = small_inputs(30, 50, 11)
+    inp.U_bar = W.f32(np.random.default_rng(3).normal(size=inp.U_bar.shape))
+    ref = oracle(inp)
+    got = run_gpu(inp, U_alias=True)
+    assert_controls_close(got["U_star"], ref["U_star"])
+
+
+def test_optional_outputs_may_be_null():
+    inp = small_inputs(31, 40, 8)
+    ref = oracle(inp)
+    got = run_gpu(inp, want_costs=False, want_weights=False, want_stats=False)
+    assert_controls_close(got["U_star"], ref["U_star"])
+
+
+def test_results_are_bitwise_deterministic():
+    inp = W.mid()
+    a = run_gpu(inp)
+    b = run_gpu(inp)
+    for key in ("U_star", "S", "w", "stats"):
+        np.testing.assert_array_equal(a[key], b[key])
+
+
+def test_planner_reused_across_sizes():
+    from paper_2512_22575_amd import smpc as S
+    big = small_inputs(32, 700, 30)
+    small = small_inputs(32, 20, 5)
+    planner = S.Planner(big.robot)
+    try:
+        for inp in (small, big, small):
+            got = run_gpu(inp, planner=planner)
+            ref = oracle(inp)
+            assert_costs_close(got["S"], ref["S"])
+            assert_controls_close(got["U_star"], ref["U_star"])
+    finally:
+        planner.close()
+
+
+def test_sharded_merge_equals_unsharded():
+    """Split K rollouts into shards, merge (S_min, Z, U*) with the log-sum-exp rule."""
+    inp = small_inputs(33, 600, 20)
+    full = run_gpu(inp)
+    lam = inp.lam
+    parts = []
+    for lo, hi in ((0, 150), (150, 420), (420, 600)):
+        shard = dataclasses.replace(inp, noise=inp.noise[lo:hi].copy())
+        parts.append(run_gpu(shard))
+    m = min(p["stats"][0] for p in parts)
+    Z = sum(p["stats"][1] * np.exp(-(p["stats"][0] - m) / lam) for p in parts)
+    N = sum((p["U_star"] - inp.U_bar) * p["stats"][1] * np.exp(-(p["stats"][0] - m) / lam)
+            for p in parts)
+    np.testing.assert_allclose(inp.U_bar + N / Z, full["U_star"], atol=U_ATOL)
+    assert m == pytest.approx(full["stats"][0], rel=1e-6)
+    assert Z == pytest.approx(full["stats"][1], rel=1e-4)
+
+
+def test_zero_noise_keeps_nominal_sequence():
+    inp = small_inputs(34, 32, 10)
+    inp.noise[:] = 0.0
+    inp.U_bar = W.f32(np.random.default_rng(4).normal(size=inp.U_bar.shape))
+    got = run_gpu(inp)
+    np.testing.assert_allclose(got["U_star"], inp.U_bar, atol=1e-6)
+    np.testing.assert_allclose(got["w"], 1.0 / 32, rtol=1e-6)
+    assert np.ptp(got["S"]) == 0.0
+
+
+def test_scene_with_no_obstacles():
+    inp = small_inputs(35, 48, 12)
+    occ = np.zeros((32, 32, 32), bool)
+    inp.grid = SC.signed_distance_grid(occ, inp.voxel)
+    check_full(inp)
