@@ -358,9 +358,15 @@ def soft_weights(S, lam):
 
 
 def update(U_bar, eps, w):
-    """U* = Ubar + sum_m w^(m) eps^(m) (eq. 30)."""
-    return np.asarray(U_bar, np.float64) + np.tensordot(np.asarray(w, np.float64),
-                                                        np.asarray(eps, np.float64), axes=1)
+    """U* = Ubar + sum_m w^(m) eps^(m) (eq. 30), over the rollouts with w^(m) > 0.
+
+    Rollouts of weight 0 contribute nothing, also when their disturbance is not
+    finite (such rollouts have a non-finite cost and are excluded by eq. 29's reading).
+    """
+    w = np.asarray(w, np.float64)
+    eps = np.asarray(eps, np.float64)
+    used = w > 0
+    return np.asarray(U_bar, np.float64) + np.tensordot(w[used], eps[used], axes=1)
 
 
 def plan_step(robot, q0, qd0, T_goal, grid, origin, voxel, noise, U_bar, dt, lam, weights):

@@ -522,3 +522,11 @@ def test_lookup_of_non_finite_point_is_nan():
     p = np.array([[0.1, 0.1, 0.1], [np.nan, 0.1, 0.1], [0.1, np.inf, 0.1]])
     got = O.esdf_lookup(grid, np.zeros(3), 0.1, p)
     assert got[0] == 0.0 and np.isnan(got[1]) and np.isnan(got[2])
+
+
+def test_update_excludes_zero_weight_rollouts_even_with_non_finite_noise():
+    Ubar = np.zeros((2, 7))
+    eps = np.ones((3, 2, 7))
+    eps[1] = np.nan
+    w = np.array([0.25, 0.0, 0.75])
+    np.testing.assert_allclose(O.update(Ubar, eps, w), np.ones((2, 7)))
