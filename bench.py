@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark of the SMPC plan step on one MI355X.
+
+Workload (the reactive-replanning configuration): K = 4096 rollouts, H = 40
+steps, dt = 0.02 s, a 200^3 float32 signed distance grid at 0.01 m built from 20
+boxes and 20 spheres, the 7-DoF arm with 28 collision spheres and 240
+self-collision pairs, temperature 1.  All inputs are seeded synthetic data and
+are resident in device memory before timing starts.
+
+One step = one call of smpc_plan_step (both kernels: rollout costs and the
+softmax update).  Consecutive steps are warm-started (U* of one step is the
+nominal sequence of the next) and the target moves on its circle; the
+disturbances cycle through a pool of pre-sampled buffers.
+
+Printed: one JSON line with rollout-steps/s (K*H per second) from back-to-back
+steps, per-step latency percentiles (each step synchronised on its own), the
+rollout-cost kernel's duration against the FP32 VALU peak, and the FP64 oracle's
+rate on the host cores (one full plan step).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "rollout-steps/s (K·H/s) at K=4096,H=40; p50/p99 plan-step latency"
+# Algorithmic work of one rollout step (FP32 FLOP, FMA = 2): integration, FK,
+# sphere centres, trilinear distance lookups, self pairs, limits, pose log map.
+FLOP_PER_ROLLOUT_STEP = 4300.0
+# Logical distance-field gathers per rollout step: 28 spheres x 8 corners x 4 B.
+GATHER_BYTES_PER_ROLLOUT_STEP = 896.0
+PEAK_FP32_TFLOPS = 157.3
+
+
+def parse_args():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--latency-steps", type=int, default=300)
+    ap.add_argument("--profile-steps", type=int, default=200)
+    ap.add_argument("--pool", type=int, default=16, help="distinct noise buffers cycled")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--K", type=int, default=4096)
+    ap.add_argument("--H", type=int, default=40)
+    ap.add_argument("--n", type=int, default=200, help="grid side in voxels")
+    return ap.parse_args()
+
+
+def cpu_baseline(sc, grid, noise, K, H):
+    """Time the FP64 oracle on one full plan step of the same workload, one thread."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import smpc_oracle as O
+    inp = sc.inputs(grid=grid)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        O.plan_step(inp.robot.rounded_f32(), inp.q0, inp.qd0, inp.T_goal, grid, inp.origin,
+                    inp.voxel, noise, inp.U_bar, inp.dt, inp.lam, inp.weights)
+        dt = time.perf_counter() - t0
+    return {"value": K * H / dt, "unit": "rollout-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"one full plan step (K={K}, H={H}) of the same scene, float64 numpy, "
+                      f"{dt:.2f} s on one host thread"}
+
+
+def main():
+    args = parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the plan step is not sharded "
+              "across GPUs); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2512_22575_amd import smpc as S
+    from synth import workload as W
+
+    K, H = args.K, args.H
+    sc = W.ReactiveScenario(seed=3, K=K, H=H, n=args.n)
+    grid_np = sc.grid()
+    dev = torch.device("cuda:0")
+    grid = torch.from_numpy(grid_np).to(dev)
+    n_pool = max(1, args.pool)
+    noise_np = [sc.noise() for _ in range(n_pool)]
+    noise = [torch.from_numpy(x).to(dev) for x in noise_np]
+    U = [torch.zeros((H, 7), device=dev), torch.zeros((H, 7), device=dev)]
+    costs = torch.empty((K,), device=dev)
+    stats = torch.empty((4,), device=dev)
+    planner = S.Planner(sc.robot, device=0)
+    ctx = planner._ctx
+    stream = torch.cuda.current_stream(dev).cuda_stream
+
+    total = args.warmup + args.steps + args.latency_steps + args.profile_steps
+    plan = []
+    for i in range(total):
+        plan.append(S.plan_args(sc.q0, sc.qd0, sc.target(), grid, sc.origin, sc.VOXEL,
+                                noise[i % n_pool], U[i % 2], U[(i + 1) % 2], K, H, sc.DT, 1.0,
+                                sc.weights, costs_out=costs, stats_out=stats))
+        sc.t += sc.DT
+
+    def step(i):
+        st = S.smpc_plan_step(ctx, plan[i], stream)
+        if st != S.SMPC_OK:
+            raise S.SMPCError(st, S.smpc_last_error(ctx))
+
+    # Warm-up (untimed).
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+
+    # Throughput: K steps back to back on one stream.
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    base = args.warmup
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for i in range(base, base + args.steps):
+        step(i)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = ev0.elapsed_time(ev1) / args.steps
+    value = K * H / (ms_per_step * 1e-3)
+    s = stats.cpu().numpy()
+    if s[3] != 0.0:
+        raise RuntimeError(f"plan step reported status {s[3]}")
+
+    # Latency: each step alone (device time between events, host time to completion).
+    base += args.steps
+    lat_dev, lat_host = [], []
+    for i in range(base, base + args.latency_steps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        h0 = time.perf_counter()
+        a.record()
+        step(i)
+        b.record()
+        b.synchronize()
+        lat_host.append((time.perf_counter() - h0) * 1e3)
+        lat_dev.append(a.elapsed_time(b))
+    lat_dev = np.array(lat_dev)
+    lat_host = np.array(lat_host)
+
+    # Per-kernel durations from events recorded by the library on the launch stream.
+    base += args.latency_steps
+    planner.profile_enable(args.profile_steps)
+    for i in range(base, base + args.profile_steps):
+        step(i)
+    torch.cuda.synchronize()
+    k1_ms, k2_ms = planner.profile_read(args.profile_steps)
+    planner.profile_enable(0)
+    k1_avg = float(np.mean(k1_ms))
+    flop = FLOP_PER_ROLLOUT_STEP * K * H
+    achieved = flop / (k1_avg * 1e-3) / 1e12
+    gather_gbs = GATHER_BYTES_PER_ROLLOUT_STEP * K * H / (k1_avg * 1e-3) / 1e9
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "rollout-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"reactive replanning plan step: K={K} rollouts x H={H} steps, "
+                        f"dt=0.02 s, {args.n}^3 f32 ESDF at 0.01 m from 40 primitives, "
+                        f"7-DoF arm, 28 spheres, {sc.robot.n_pairs} self pairs",
+            "K": K, "H": H, "grid": [args.n] * 3, "voxel_m": 0.01, "lambda": 1.0,
+            "noise": "pre-sampled device buffers (float32)",
+        },
+        "latency_ms": {
+            "p50": round(float(np.percentile(lat_dev, 50)), 5),
+            "p99": round(float(np.percentile(lat_dev, 99)), 5),
+            "mean": round(float(np.mean(lat_dev)), 5),
+            "host_p50": round(float(np.percentile(lat_host, 50)), 5),
+            "host_p99": round(float(np.percentile(lat_host, 99)), 5),
+            "steps": int(args.latency_steps),
+        },
+        "host_ms_per_step": round(wall * 1e3 / args.steps, 5),
+        "kernels_ms": {"rollout_cost": round(k1_avg, 6),
+                       "merge": round(float(np.mean(k2_ms)), 6)},
+        "roofline": {
+            "bound": "alu",
+            "kernel": "rollout_cost_kernel",
+            "achieved": round(achieved, 3),
+            "peak": PEAK_FP32_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+            "traffic": None,
+            "flop_per_launch": flop,
+            "gather_GBps": round(gather_gbs, 1),
+        },
+        "paper_context": "5.322 ms per replanning iteration at M=512 on an RTX 3090 "
+                         "(H not stated); not the same workload",
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sc, grid_np, noise_np[0], K, H)
+    print(json.dumps(out), flush=True)
+    planner.close()
+
+
+if __name__ == "__main__":
+    main()

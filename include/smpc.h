@@ -179,6 +179,20 @@ const char* smpc_status_string(smpc_status status);
 /* Detail of the last failure on this context ("" if none).  Valid until the next call. */
 const char* smpc_last_error(const smpc_ctx* ctx);
 
+/*
+ * Per-kernel timing (profiling aid).  smpc_profile_enable(ctx, n) makes the next n
+ * plan steps record HIP events on their stream before the rollout-cost kernel,
+ * between the two kernels and after the merge kernel; n = 0 disables recording.
+ * smpc_profile_read waits for the recorded events and returns, per recorded
+ * step, the durations in milliseconds of the rollout-cost kernel (rollout_ms[i])
+ * and of the merge kernel (merge_ms[i]); *n_steps receives the count written
+ * (at most `capacity`).  Reading resets the record.  Events are created by
+ * smpc_profile_enable; both calls return SMPC_E_DEVICE on HIP failures.
+ */
+smpc_status smpc_profile_enable(smpc_ctx* ctx, int32_t n_steps);
+smpc_status smpc_profile_read(smpc_ctx* ctx, float* rollout_ms, float* merge_ms,
+                              int32_t capacity, int32_t* n_steps);
+
 /* Library version as major*10000 + minor*100 + patch. */
 int32_t smpc_version(void);
 

@@ -73,7 +73,10 @@ size_t workspace_bytes(int K, int H, int P);
 Workspace carve_workspace(void* base, int K, int H, int P);
 
 // Enqueue both kernels of one plan step.  Returns a hipError_t value (0 = success).
+// When `events` is non-null, events[0..2] (hipEvent_t) are recorded before the
+// rollout-cost kernel, between the kernels and after the merge kernel.
 int launch_plan_step(const DevRobot* robot, const StepParams& p, const LaunchConfig& lc,
-                     const Workspace& ws, const smpc_plan_args& args, void* stream);
+                     const Workspace& ws, const smpc_plan_args& args, void* stream,
+                     void* events);
 
 }  // namespace smpc

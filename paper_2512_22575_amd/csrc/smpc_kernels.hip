@@ -396,7 +396,10 @@ __global__ __launch_bounds__(kK1MaxThreads) void rollout_cost_kernel(
   __syncthreads();
   for (int o = tid; o < H * kNdof; o += nthreads) {
     float acc = 0.f;
-    for (int r = 0; r < nroll; ++r) acc = fmaf(L.e[r], L.eps[r * H * kNdof + o], acc);
+    for (int r = 0; r < nroll; ++r) {
+      const float e = L.e[r];
+      if (e > 0.f) acc = fmaf(e, L.eps[r * H * kNdof + o], acc);  // weight-0 rollouts excluded
+    }
     ws.part_N[(size_t)o * p.P + b] = acc;
   }
 }
@@ -639,16 +642,22 @@ Workspace carve_workspace(void* base, int K, int H, int P) {
 }
 
 int launch_plan_step(const DevRobot* robot, const StepParams& p, const LaunchConfig& lc,
-                     const Workspace& ws, const smpc_plan_args& args, void* stream) {
+                     const Workspace& ws, const smpc_plan_args& args, void* stream,
+                     void* events) {
   hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t* ev = static_cast<hipEvent_t*>(events);
+  hipError_t e;
+  if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return (int)e;
   hipLaunchKernelGGL(rollout_cost_kernel, dim3(lc.P), dim3(lc.k1_threads), lc.k1_lds, s, robot,
                      p, args.noise, args.U_in, args.esdf.data, ws);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return (int)e;
+  if ((e = hipGetLastError()) != hipSuccess) return (int)e;
+  if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return (int)e;
   hipLaunchKernelGGL(merge_kernel, dim3(lc.k2_blocks), dim3(kK2Threads), 0, s, robot, p,
                      args.U_in, args.U_out, args.esdf.data, ws, args.costs_out, args.weights_out,
                      args.stats_out);
-  return (int)hipGetLastError();
+  if ((e = hipGetLastError()) != hipSuccess) return (int)e;
+  if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return (int)e;
+  return 0;
 }
 
 }  // namespace smpc

@@ -12,6 +12,7 @@
 #include <new>
 #include <string>
 #include <utility>
+#include <vector>
 
 #include "smpc.h"
 #include "smpc_internal.h"
@@ -32,6 +33,9 @@ struct smpc_ctx {
   double slot_radius[kSlots];
   void* workspace = nullptr;
   size_t workspace_bytes = 0;
+  std::vector<hipEvent_t> prof_events;  // 3 per recorded step
+  int prof_capacity = 0;                // steps that may still be recorded
+  int prof_recorded = 0;
   std::string last_error;
 };
 
@@ -261,11 +265,19 @@ smpc_status smpc_create(smpc_ctx** out, int32_t hip_device) {
   return SMPC_OK;
 }
 
+static void destroy_events(smpc_ctx* ctx) {
+  for (hipEvent_t e : ctx->prof_events) (void)hipEventDestroy(e);
+  ctx->prof_events.clear();
+  ctx->prof_capacity = 0;
+  ctx->prof_recorded = 0;
+}
+
 void smpc_destroy(smpc_ctx* ctx) {
   if (!ctx) return;
-  if (ctx->dev_robot || ctx->workspace) {
+  if (ctx->dev_robot || ctx->workspace || !ctx->prof_events.empty()) {
     DeviceGuard g(ctx->device);
     (void)hipDeviceSynchronize();
+    destroy_events(ctx);
     if (ctx->dev_robot) (void)hipFree(ctx->dev_robot);
     if (ctx->workspace) (void)hipFree(ctx->workspace);
   }
@@ -368,10 +380,53 @@ smpc_status smpc_plan_step(smpc_ctx* ctx, const smpc_plan_args* a, void* stream)
     ctx->workspace_bytes = need;
   }
   const Workspace ws = carve_workspace(ctx->workspace, a->K, a->H, lc.P);
-  const int e = launch_plan_step(ctx->dev_robot, p, lc, ws, *a, stream);
+  hipEvent_t* ev = nullptr;
+  if (ctx->prof_recorded < ctx->prof_capacity) ev = &ctx->prof_events[3 * ctx->prof_recorded++];
+  const int e = launch_plan_step(ctx->dev_robot, p, lc, ws, *a, stream, ev);
   if (e != 0)
     return fail(ctx, SMPC_E_DEVICE, "kernel launch failed: %s",
                 hipGetErrorString(static_cast<hipError_t>(e)));
+  return SMPC_OK;
+}
+
+smpc_status smpc_profile_enable(smpc_ctx* ctx, int32_t n_steps) {
+  if (!ctx) return SMPC_E_INVALID_ARG;
+  if (n_steps < 0 || n_steps > (1 << 20))
+    return fail(ctx, SMPC_E_INVALID_ARG, "n_steps=%d outside [0, 2^20]", n_steps);
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, SMPC_E_DEVICE, "hipSetDevice(%d) failed", ctx->device);
+  (void)hipDeviceSynchronize();
+  destroy_events(ctx);
+  ctx->prof_events.resize((size_t)3 * n_steps);
+  for (size_t i = 0; i < ctx->prof_events.size(); ++i) {
+    if (hipEventCreate(&ctx->prof_events[i]) != hipSuccess) {
+      ctx->prof_events.resize(i);
+      destroy_events(ctx);
+      return fail(ctx, SMPC_E_DEVICE, "hipEventCreate failed");
+    }
+  }
+  ctx->prof_capacity = n_steps;
+  ctx->prof_recorded = 0;
+  return SMPC_OK;
+}
+
+smpc_status smpc_profile_read(smpc_ctx* ctx, float* rollout_ms, float* merge_ms,
+                              int32_t capacity, int32_t* n_steps) {
+  if (!ctx) return SMPC_E_INVALID_ARG;
+  if (!rollout_ms || !merge_ms || !n_steps || capacity < 0)
+    return fail(ctx, SMPC_E_INVALID_ARG, "null output or negative capacity");
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, SMPC_E_DEVICE, "hipSetDevice(%d) failed", ctx->device);
+  const int n = ctx->prof_recorded < capacity ? ctx->prof_recorded : capacity;
+  for (int i = 0; i < n; ++i) {
+    hipEvent_t* ev = &ctx->prof_events[3 * i];
+    if (hipEventSynchronize(ev[2]) != hipSuccess ||
+        hipEventElapsedTime(&rollout_ms[i], ev[0], ev[1]) != hipSuccess ||
+        hipEventElapsedTime(&merge_ms[i], ev[1], ev[2]) != hipSuccess)
+      return fail(ctx, SMPC_E_DEVICE, "reading profiling events failed");
+  }
+  *n_steps = n;
+  ctx->prof_recorded = 0;
   return SMPC_OK;
 }
 

@@ -109,6 +109,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.smpc_last_error.restype = c_char_p
     lib.smpc_version.argtypes = []
     lib.smpc_version.restype = c_int32
+    lib.smpc_profile_enable.argtypes = [c_void_p, c_int32]
+    lib.smpc_profile_enable.restype = c_int32
+    lib.smpc_profile_read.argtypes = [c_void_p, POINTER(c_float), POINTER(c_float), c_int32,
+                                      POINTER(c_int32)]
+    lib.smpc_profile_read.restype = c_int32
     _lib = lib
     return lib
 
@@ -143,6 +148,19 @@ def smpc_last_error(ctx: c_void_p) -> str:
 
 def smpc_version() -> int:
     return int(load_library().smpc_version())
+
+
+def smpc_profile_enable(ctx: c_void_p, n_steps: int) -> int:
+    return load_library().smpc_profile_enable(ctx, int(n_steps))
+
+
+def smpc_profile_read(ctx: c_void_p, capacity: int):
+    """Returns (status, rollout_ms ndarray, merge_ms ndarray)."""
+    r = (c_float * capacity)()
+    m = (c_float * capacity)()
+    n = c_int32(0)
+    st = load_library().smpc_profile_read(ctx, r, m, int(capacity), ctypes.byref(n))
+    return st, np.array(r[:n.value], np.float64), np.array(m[:n.value], np.float64)
 
 
 # --- marshalling helpers --------------------------------------------------------
@@ -223,6 +241,18 @@ class Planner:
         st = smpc_set_robot(self._ctx, robot_desc(robot))
         if st != SMPC_OK:
             raise SMPCError(st, smpc_last_error(self._ctx))
+
+    def profile_enable(self, n_steps: int) -> None:
+        st = smpc_profile_enable(self._ctx, n_steps)
+        if st != SMPC_OK:
+            raise SMPCError(st, smpc_last_error(self._ctx))
+
+    def profile_read(self, capacity: int):
+        """Per-step kernel durations (ms) of the recorded steps: (rollout_ms, merge_ms)."""
+        st, r, m = smpc_profile_read(self._ctx, capacity)
+        if st != SMPC_OK:
+            raise SMPCError(st, smpc_last_error(self._ctx))
+        return r, m
 
     def close(self) -> None:
         if getattr(self, "_ctx", None):
