@@ -51,7 +51,23 @@ def parse_args():
     ap.add_argument("--K", type=int, default=4096)
     ap.add_argument("--H", type=int, default=40)
     ap.add_argument("--n", type=int, default=200, help="grid side in voxels")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="only run a plain device-to-device copy of this many MiB (to scale "
+                         "HBM byte counters) and exit")
     return ap.parse_args()
+
+
+def calibrate_copy(mib: int) -> None:
+    """A plain copy kernel of known size, for scaling FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "device copy", "bytes_read": n * 4, "bytes_written": n * 4,
+                      "launches": 3}), flush=True)
 
 
 def cpu_baseline(sc, grid, noise, K, H):
@@ -72,6 +88,9 @@ def cpu_baseline(sc, grid, noise, K, H):
 
 def main():
     args = parse_args()
+    if args.calibrate_copy_mib:
+        calibrate_copy(args.calibrate_copy_mib)
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the plan step is not sharded "
               "across GPUs); run with --gpus 1", file=sys.stderr)

@@ -23,13 +23,20 @@ struct DevRobot {
   float a[kNdof], d[kNdof];
   float sc[kSlots][4];         // sphere slot centre (x, y, z) in its link frame, radius
   uint32_t slot_active;        // bit s set when slot s holds a sphere
-  uint32_t pair_mask[kSlots];  // bit t (t > s) set when slots (s, t) form a pair
-  float pair_rsum[kSlots][kSlots];   // r_s + r_t
-  float pair_rsum2[kSlots][kSlots];  // (r_s + r_t)^2, rounded from double
-  int32_t n_pairs;
-  int32_t pad_[3];
-  int16_t pair_list[kMaxPairs][2];   // the same pairs as a list of slot indices
+  // Self-collision pairs grouped by link pair (la <= lb, index la * kNdof + lb): bit
+  // i * kSpl + j of lp_mask marks the pair (slot la*kSpl+i, slot lb*kSpl+j).
+  uint32_t lp_mask[kNdof * kNdof];
+  float lp_bthr[kNdof * kNdof];              // (R_la + R_lb)^2 of the link bounding spheres
+  float lp_rr2[kNdof * kNdof][kSpl * kSpl];  // (r_i + r_j)^2 per pair (0 if not a pair)
+  float lp_rs[kNdof * kNdof][kSpl * kSpl];   // r_i + r_j
+  float lbound[kNdof];         // bounding radius of each link's spheres about its slot-0 sphere
+  int32_t n_pairs;             // distinct pairs after de-duplication
 };
+
+// Margin added to each link bounding radius (metres).  Float32 sphere positions
+// are accurate to ~1e-6 m, so a pair culled by the bounding test has a hinge of
+// exactly 0 in the per-pair test as well.
+constexpr double kBoundMargin = 1e-4;
 
 // Per-call constants, passed by value as a kernel argument.
 struct StepParams {
@@ -58,6 +65,7 @@ struct Workspace {
   float* part_Z;    // [P]   sum_m exp(-(S - part_m)/lambda)
   float* part_Z2;   // [P]   sum_m exp(-2 (S - part_m)/lambda)
   float* part_N;    // [H*7][P] sum_m exp(-(S - part_m)/lambda) eps^(m)
+  float* c0;        // [1]   state terms of state 0 (the same for every rollout)
 };
 
 struct LaunchConfig {

@@ -8,13 +8,13 @@
 //    softmax partial (block minimum, sum of exponentials, exponential-weighted
 //    sum of disturbances) so that eqs. 29-30 need no second pass over eps.
 // K2 merge_kernel: merges the per-block partials into S_min, Z and
-//    U* = Ubar + sum w eps (eqs. 29-30), writes per-rollout weights and costs,
-//    and evaluates the rollout-independent state terms at k = 0 once.
+//    U* = Ubar + sum w eps (eqs. 29-30) and writes per-rollout weights and costs.
 //
 // Thread k of a rollout charges the control terms of u_k and the state terms
 // of state k+1 (running terms for k+1 < H, terminal pose term for k+1 = H).
-// The state terms of state 0 are the same for every rollout; K2 computes them
-// once and adds them to the reported costs (weights are shift-invariant).
+// The state terms of state 0 are the same for every rollout; one thread of K1
+// computes them once and K2 adds them to the reported costs (the weights are
+// invariant to a common shift of the costs).
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -79,6 +79,34 @@ __device__ __forceinline__ void transform_point(const Frame& T, float cx, float 
   pz = fmaf(cx, T.xz, fmaf(cy, T.yz, fmaf(cz, T.zz, T.tz)));
 }
 
+// sin and cos of x: Cody-Waite reduction by pi/2 (three-part constant, fused
+// multiply-adds) to r in [-pi/4, pi/4], Taylor polynomials of sin (to r^9) and cos
+// (to r^10) there, and the quadrant's swap/sign.  Truncation error < 2e-9; the
+// result is within ~1.2 * 2^-24 of the true values for |x| < 60.
+__device__ __forceinline__ void sincos_cw(float x, float& s, float& c) {
+  const float n = rintf(x * 0.636619772f);
+  float r = fmaf(-n, 1.57079637050628662f, x);
+  r = fmaf(-n, -4.37113882867379e-08f, r);
+  r = fmaf(-n, -1.77635683940025e-15f, r);
+  const float r2 = r * r;
+  float ps = fmaf(r2, 1.f / 362880.f, -1.f / 5040.f);
+  ps = fmaf(ps, r2, 1.f / 120.f);
+  ps = fmaf(ps, r2, -1.f / 6.f);
+  const float sr = fmaf(ps * r2, r, r);
+  float pc = fmaf(r2, -1.f / 3628800.f, 1.f / 40320.f);
+  pc = fmaf(pc, r2, -1.f / 720.f);
+  pc = fmaf(pc, r2, 1.f / 24.f);
+  pc = fmaf(pc, r2, -0.5f);
+  const float cr = fmaf(pc, r2, 1.f);
+  const int q = (int)n;
+  const float s1 = (q & 1) ? cr : sr;
+  const float c1 = (q & 1) ? sr : cr;
+  s = (q & 2) ? -s1 : s1;
+  c = ((q + 1) & 2) ? -c1 : c1;
+}
+
+__device__ __forceinline__ float sqrt_hw(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // g(theta) = (x^2 - sin^2 x) / (2 sin^4 x), x = theta / 2, for theta in [0, pi].
 // With it |v|^2 = |t|^2 + g(theta) t^T (I - R) t for the translational part v of
 // log(T) (eqs. 12-14): V(theta) acts as the identity along the rotation axis and
@@ -87,7 +115,8 @@ __device__ __forceinline__ float log_norm_gain(float theta) {
   const float x = 0.5f * theta;
   const float x2 = x * x;
   if (x < 1e-3f) return fmaf(x2, 4.f / 45.f, 1.f / 6.f);
-  const float s = sinf(x);
+  float s, c_unused;
+  sincos_cw(x, s, c_unused);
   float xms;  // x - sin x, by its Taylor series where the subtraction would cancel
   if (x < 0.75f) {
     xms = x * x2 * (1.f / 6.f + x2 * (-1.f / 120.f + x2 * (1.f / 5040.f +
@@ -122,7 +151,7 @@ __device__ __forceinline__ float pose_cost(const Frame& T, const StepParams& p, 
   const float sx = 0.5f * (d21 - d12);
   const float sy = 0.5f * (d02 - d20);
   const float sz = 0.5f * (d10 - d01);
-  const float sn = sqrtf(fmaf(sx, sx, fmaf(sy, sy, sz * sz)));
+  const float sn = sqrt_hw(fmaf(sx, sx, fmaf(sy, sy, sz * sz)));
   const float theta = atan2f(sn, c);
   const float n = fmaf(t0, t0, fmaf(t1, t1, t2 * t2));
   const float r0 = fmaf(d00, t0, fmaf(d01, t1, d02 * t2));
@@ -180,30 +209,17 @@ __device__ __forceinline__ float esdf_lookup(__amdgpu_buffer_rsrc_t rsrc, const 
   return fmaf(fz, c1 - c0, c0);
 }
 
-// Cost charged by thread (m, k): control terms of u_k and state terms of state k+1.
-//   dq, qd : q_{k+1} - q0 and qd_{k+1};  u : u_k;  sc0 : sin(q0) then cos(q0) (LDS).
-__device__ __forceinline__ float step_cost(const DevRobot* __restrict__ rob, const StepParams& p,
-                                           __amdgpu_buffer_rsrc_t rsrc, const float* sc0,
-                                           const float (&dq)[kNdof], const float (&qd)[kNdof],
-                                           const float (&u)[kNdof], bool terminal) {
-  // Smoothness (eq. 23) and acceleration limit (eq. 22) on u_k.
-  float c_u2 = 0.f, c_ulim = 0.f;
-#pragma unroll
-  for (int j = 0; j < kNdof; ++j) {
-    c_u2 = fmaf(u[j], u[j], c_u2);
-    const float v = limit_violation(u[j], p.qddlo[j], p.qddhi[j]);
-    c_ulim = fmaf(v, v, c_ulim);
-  }
-  float cost = fmaf(p.w_smooth, c_u2, p.w_qdd * c_ulim);
-
-  // Forward kinematics (eq. 6) with sin/cos of q0 + dq by angle addition, so the
-  // large common angle q0 enters exactly once and only the small dq is rounded.
-  float px[kSlots], py[kSlots], pz[kSlots];
+// Forward kinematics (eq. 6) of q0 + dq with sin/cos of q0 + dq by angle addition,
+// so the large common angle q0 enters exactly once and only the small dq is
+// rounded; writes the sphere slot centres and returns the end-effector frame.
+__device__ __forceinline__ Frame fk_spheres(const DevRobot* __restrict__ rob, const float* sc0,
+                                            const float (&dq)[kNdof], float (&px)[kSlots],
+                                            float (&py)[kSlots], float (&pz)[kSlots]) {
   Frame T = identity_frame();
 #pragma unroll
   for (int i = 0; i < kNdof; ++i) {
     float s1, c1;
-    sincosf(dq[i], &s1, &c1);
+    sincos_cw(dq[i], s1, c1);
     const float s0 = sc0[i], c0 = sc0[kNdof + i];
     const float st = fmaf(s0, c1, c0 * s1);
     const float ct = fmaf(c0, c1, -s0 * s1);
@@ -214,11 +230,64 @@ __device__ __forceinline__ float step_cost(const DevRobot* __restrict__ rob, con
       transform_point(T, rob->sc[s][0], rob->sc[s][1], rob->sc[s][2], px[s], py[s], pz[s]);
     }
   }
+  return T;
+}
 
+// Position / velocity limits (eq. 22) and null-space term (eq. 24) of one state.
+__device__ __forceinline__ float state_limit_cost(const StepParams& p, const float (&dq)[kNdof],
+                                                  const float (&qd)[kNdof]) {
+  float c_q = 0.f, c_qd = 0.f, c_ns = 0.f;
+#pragma unroll
+  for (int j = 0; j < kNdof; ++j) {
+    const float q = p.q0[j] + dq[j];
+    const float vq = limit_violation(q, p.qlo[j], p.qhi[j]);
+    const float vqd = limit_violation(qd[j], p.qdlo[j], p.qdhi[j]);
+    const float e = q - p.qref[j];
+    c_q = fmaf(vq, vq, c_q);
+    c_qd = fmaf(vqd, vqd, c_qd);
+    c_ns = fmaf(e, e, c_ns);
+  }
+  return fmaf(p.w_q, c_q, fmaf(p.w_qd, c_qd, p.w_ns * c_ns));
+}
+
+// Cost charged by thread (m, k): control terms of u_k and state terms of state k+1.
+//   dq, qd : q_{k+1} - q0 and qd_{k+1};  u : u_k;  sc0 : sin(q0) then cos(q0) (LDS).
+// The one thread with `state0` set (rollout 0, k = H-1, a terminal thread with no
+// collision work of its own) also evaluates the state terms of state 0, which are
+// the same for every rollout, and returns them in *c0.
+__device__ __forceinline__ float step_cost(const DevRobot* __restrict__ rob, const StepParams& p,
+                                           __amdgpu_buffer_rsrc_t rsrc, const float* sc0,
+                                           const float (&dq)[kNdof], const float (&qd)[kNdof],
+                                           const float (&u)[kNdof], bool terminal, bool state0,
+                                           float* c0) {
+  // Smoothness (eq. 23) and acceleration limit (eq. 22) on u_k.
+  float c_u2 = 0.f, c_ulim = 0.f;
+#pragma unroll
+  for (int j = 0; j < kNdof; ++j) {
+    c_u2 = fmaf(u[j], u[j], c_u2);
+    const float v = limit_violation(u[j], p.qddlo[j], p.qddhi[j]);
+    c_ulim = fmaf(v, v, c_ulim);
+  }
+  float cost = fmaf(p.w_smooth, c_u2, p.w_qdd * c_ulim);
+  if (!terminal) cost += state_limit_cost(p, dq, qd);
+
+  float px[kSlots], py[kSlots], pz[kSlots];
+  const Frame T = fk_spheres(rob, sc0, dq, px, py, pz);
   // Pose tracking (eq. 16) or terminal (eq. 25) cost.
-  cost += pose_cost(T, p, terminal ? p.w_term_t : p.w_pose_t,
-                    terminal ? p.w_term_r : p.w_pose_r);
-  if (terminal) return cost;
+  cost += pose_cost(T, p, terminal ? p.w_term_t : p.w_pose_t, terminal ? p.w_term_r : p.w_pose_r);
+
+  float state0_cost = 0.f;
+  if (state0) {
+    float zero[kNdof], qd0[kNdof];
+#pragma unroll
+    for (int j = 0; j < kNdof; ++j) {
+      zero[j] = 0.f;
+      qd0[j] = p.qd0[j];
+    }
+    const Frame T0 = fk_spheres(rob, sc0, zero, px, py, pz);
+    state0_cost = pose_cost(T0, p, p.w_pose_t, p.w_pose_r) + state_limit_cost(p, zero, qd0);
+  }
+  if (terminal && !state0) return cost;
 
   // Environment collision (eqs. 17, 19, 20).
   const uint32_t active = rob->slot_active;
@@ -231,44 +300,54 @@ __device__ __forceinline__ float step_cost(const DevRobot* __restrict__ rob, con
       c_env = fmaf(h, h, c_env);
     }
   }
-  cost = fmaf(p.w_env, c_env, cost);
 
-  // Self collision (eqs. 18-20): squared-distance test first, sqrt only on overlap.
+  // Self collision (eqs. 18-20), grouped by link pair.  When no lane's link bounding
+  // spheres overlap, no pair of the two links can overlap and the group is skipped
+  // (its hinges are exactly 0); otherwise each pair takes a squared-distance test,
+  // with a square root only on overlap.
   float c_self = 0.f;
 #pragma unroll
-  for (int s = 0; s < kSlots; ++s) {
-    const uint32_t mask = rob->pair_mask[s];
-    if (mask == 0u) continue;
+  for (int la = 0; la < kNdof; ++la) {
 #pragma unroll
-    for (int t = s + 1; t < kSlots; ++t) {
-      if (mask & (1u << t)) {
-        const float dx = px[s] - px[t], dy = py[s] - py[t], dz = pz[s] - pz[t];
-        const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-        if (d2 < rob->pair_rsum2[s][t]) {
-          const float h = rob->pair_rsum[s][t] - sqrtf(d2);
-          c_self = fmaf(h, h, c_self);
+    for (int lb = la; lb < kNdof; ++lb) {
+      const int lp = la * kNdof + lb;
+      const uint32_t mask = rob->lp_mask[lp];
+      if (mask == 0u) continue;
+      bool near = true;
+      if (la != lb) {
+        // A link's bounding sphere is centred on the sphere in its first slot.
+        const int ca = la * kSpl, cb = lb * kSpl;
+        const float dx = px[ca] - px[cb], dy = py[ca] - py[cb], dz = pz[ca] - pz[cb];
+        near = fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rob->lp_bthr[lp];
+      }
+      if (near) {
+        float rr2[kSpl * kSpl];
+#pragma unroll
+        for (int b = 0; b < kSpl * kSpl; ++b) rr2[b] = rob->lp_rr2[lp][b];
+#pragma unroll
+        for (int i = 0; i < kSpl; ++i) {
+#pragma unroll
+          for (int j = 0; j < kSpl; ++j) {
+            const int bit = i * kSpl + j;
+            if (!(mask & (1u << bit))) continue;
+            const int sa = la * kSpl + i, sb = lb * kSpl + j;
+            const float dx = px[sa] - px[sb], dy = py[sa] - py[sb], dz = pz[sa] - pz[sb];
+            const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            if (d2 < rr2[bit]) {
+              const float h = rob->lp_rs[lp][bit] - sqrt_hw(d2);
+              c_self = fmaf(h, h, c_self);
+            }
+          }
         }
       }
     }
   }
-  cost = fmaf(p.w_self, c_self, cost);
-
-  // Position / velocity limits (eq. 22) and null-space term (eq. 24) at state k+1.
-  float c_q = 0.f, c_qd = 0.f, c_ns = 0.f;
-#pragma unroll
-  for (int j = 0; j < kNdof; ++j) {
-    const float q = p.q0[j] + dq[j];
-    const float vq = limit_violation(q, p.qlo[j], p.qhi[j]);
-    const float vqd = limit_violation(qd[j], p.qdlo[j], p.qdhi[j]);
-    const float e = q - p.qref[j];
-    c_q = fmaf(vq, vq, c_q);
-    c_qd = fmaf(vqd, vqd, c_qd);
-    c_ns = fmaf(e, e, c_ns);
+  const float coll = fmaf(p.w_env, c_env, p.w_self * c_self);
+  if (state0) {
+    *c0 = state0_cost + coll;
+    return cost;
   }
-  cost = fmaf(p.w_q, c_q, cost);
-  cost = fmaf(p.w_qd, c_qd, cost);
-  cost = fmaf(p.w_ns, c_ns, cost);
-  return cost;
+  return cost + coll;
 }
 
 // LDS layout of K1 (floats unless noted), for R rollouts of H steps.
@@ -299,7 +378,7 @@ __device__ __forceinline__ K1Lds k1_lds(unsigned char* base, int R, int H) {
   return L;
 }
 
-__global__ __launch_bounds__(kK1MaxThreads) void rollout_cost_kernel(
+__global__ __launch_bounds__(kK1MaxThreads) __attribute__((amdgpu_waves_per_eu(3))) void rollout_cost_kernel(
     const DevRobot* __restrict__ rob, const StepParams p, const float* __restrict__ noise,
     const float* __restrict__ U_in, const void* __restrict__ grid, Workspace ws) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -358,7 +437,10 @@ __global__ __launch_bounds__(kK1MaxThreads) void rollout_cost_kernel(
         u[j] = L.ubar[k * kNdof + j] + L.eps[base + j];
       }
       const __amdgpu_buffer_rsrc_t rsrc = grid_resource(grid, p.grid_bytes);
-      cost = step_cost(rob, p, rsrc, L.sc0, dq, qd, u, k == H - 1);
+      const bool state0 = (b == 0 && r == 0 && k == H - 1);
+      float c0 = 0.f;
+      cost = step_cost(rob, p, rsrc, L.sc0, dq, qd, u, k == H - 1, state0, &c0);
+      if (state0) ws.c0[0] = c0;
     }
     L.cost[tid] = cost;
   }
@@ -408,174 +490,143 @@ __global__ __launch_bounds__(kK1MaxThreads) void rollout_cost_kernel(
 // K2: merge
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
-}
 
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, kWave));
-  return v;
-}
 
 struct MergeStats {
   double m;   // minimum over finite S (+inf if none)
   float Z;    // sum exp(-(S - m)/lambda)
   float Z2;   // sum exp(-2 (S - m)/lambda)
+  float N;    // sum exp(-(S - m)/lambda) eps[o] for the requested output o (0 if none)
 };
 
-// Every wave merges the block partials itself, in a fixed order (deterministic).
-__device__ __forceinline__ MergeStats merge_stats(const Workspace& ws, int P, float inv_lambda,
-                                                  int lane) {
-  double mn = __builtin_inf();
-  for (int i = lane; i < P; i += kWave) mn = fmin(mn, ws.part_m[i]);
-  mn = wave_min(mn);
-  float Z = 0.f, Z2 = 0.f;
-  if (isfinite(mn)) {
-    for (int i = lane; i < P; i += kWave) {
-      const double mb = ws.part_m[i];
-      if (!isfinite(mb)) continue;
-      const float s = expf(-(float)(mb - mn) * inv_lambda);
-      Z = fmaf(ws.part_Z[i], s, Z);
-      Z2 = fmaf(ws.part_Z2[i], s * s, Z2);
-    }
-  }
-  return MergeStats{mn, wave_sum(Z), wave_sum(Z2)};
+// Rescale a partial (m, Z, Z2, N) to a new reference minimum m_new <= m.
+__device__ __forceinline__ void rescale(MergeStats& a, double m_new, float inv_lambda) {
+  const float f = isfinite(a.m) ? expf(-(float)(a.m - m_new) * inv_lambda) : 0.f;
+  a.Z *= f;
+  a.Z2 *= f * f;
+  a.N *= f;
+  a.m = m_new;
 }
 
-// State terms at k = 0 (pose, environment, self, q/qd limits, null space): the same
-// for every rollout, evaluated once by a whole block.  Returns the sum in thread 0.
-__device__ float state0_cost_block(const DevRobot* __restrict__ rob, const StepParams& p,
-                                   const void* grid, float* centres /*LDS [kSlots*4]*/,
-                                   float* red /*LDS [kK2Threads/64]*/) {
-  const int tid = threadIdx.x;
-  Frame T = identity_frame();
+// Merge the per-block partials (m_b, Z_b, Z2_b, N_b[o]) of K1 into the totals for
+// output o (o < 0: statistics only).  Each lane folds a strided subset in chunks whose
+// loads are all issued before use; lanes are then merged by a butterfly.  The order
+// is fixed, so the result is deterministic.
+constexpr int kMergeChunk = 8;
+
+__device__ __forceinline__ MergeStats merge_partials(const Workspace& ws, int P, int o,
+                                                     float inv_lambda, int lane) {
+  MergeStats acc{__builtin_inf(), 0.f, 0.f, 0.f};
+  for (int base = 0; base < P; base += kWave * kMergeChunk) {
+    double mb[kMergeChunk];
+    float zb[kMergeChunk], z2b[kMergeChunk], nb[kMergeChunk];
 #pragma unroll
-  for (int i = 0; i < kNdof; ++i) {
-    float s, c;
-    sincosf(p.q0[i], &s, &c);
-    mdh_step(T, rob->ca[i], rob->sa[i], rob->a[i], rob->d[i], c, s);
-    if (tid == 0) {
+    for (int c = 0; c < kMergeChunk; ++c) {
+      const int i = base + lane + kWave * c;
+      const bool v = i < P;
+      mb[c] = v ? ws.part_m[i] : __builtin_inf();
+      zb[c] = v ? ws.part_Z[i] : 0.f;
+      z2b[c] = v ? ws.part_Z2[i] : 0.f;
+      nb[c] = (v && o >= 0) ? ws.part_N[(size_t)o * P + i] : 0.f;
+    }
+    double cm = acc.m;
 #pragma unroll
-      for (int j = 0; j < kSpl; ++j) {
-        const int sl = i * kSpl + j;
-        float x, y, z;
-        transform_point(T, rob->sc[sl][0], rob->sc[sl][1], rob->sc[sl][2], x, y, z);
-        centres[sl * 4 + 0] = x;
-        centres[sl * 4 + 1] = y;
-        centres[sl * 4 + 2] = z;
-      }
+    for (int c = 0; c < kMergeChunk; ++c) cm = fmin(cm, mb[c]);
+    if (!isfinite(cm)) continue;
+    rescale(acc, cm, inv_lambda);
+#pragma unroll
+    for (int c = 0; c < kMergeChunk; ++c) {
+      if (!isfinite(mb[c])) continue;
+      const float sc = expf(-(float)(mb[c] - cm) * inv_lambda);
+      acc.Z = fmaf(zb[c], sc, acc.Z);
+      acc.Z2 = fmaf(z2b[c], sc * sc, acc.Z2);
+      acc.N = fmaf(nb[c], sc, acc.N);
     }
   }
-  __syncthreads();
-  float part = 0.f;
-  if (tid < kSlots && (rob->slot_active & (1u << tid))) {
-    const __amdgpu_buffer_rsrc_t rsrc = grid_resource(grid, p.grid_bytes);
-    const float phi = esdf_lookup(rsrc, p, centres[tid * 4], centres[tid * 4 + 1],
-                                  centres[tid * 4 + 2]);
-    const float h = fmaxf(p.env_thr[tid] - phi, 0.f);
-    part = p.w_env * h * h;
-  }
-  for (int i = tid; i < rob->n_pairs; i += blockDim.x) {
-    const int s = rob->pair_list[i][0], t = rob->pair_list[i][1];
-    const float dx = centres[s * 4] - centres[t * 4];
-    const float dy = centres[s * 4 + 1] - centres[t * 4 + 1];
-    const float dz = centres[s * 4 + 2] - centres[t * 4 + 2];
-    const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-    if (d2 < rob->pair_rsum2[s][t]) {
-      const float h = rob->pair_rsum[s][t] - sqrtf(d2);
-      part = fmaf(p.w_self * h, h, part);
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    MergeStats other;
+    other.m = __shfl_xor(acc.m, off, kWave);
+    other.Z = __shfl_xor(acc.Z, off, kWave);
+    other.Z2 = __shfl_xor(acc.Z2, off, kWave);
+    other.N = __shfl_xor(acc.N, off, kWave);
+    const double mn = fmin(acc.m, other.m);
+    if (isfinite(mn)) {
+      // Fixed operand order (lower lane first) so both lanes of a pair agree bitwise.
+      const bool lower = (lane & off) == 0;
+      MergeStats lo = lower ? acc : other, hi = lower ? other : acc;
+      rescale(lo, mn, inv_lambda);
+      rescale(hi, mn, inv_lambda);
+      acc.m = mn;
+      acc.Z = lo.Z + hi.Z;
+      acc.Z2 = lo.Z2 + hi.Z2;
+      acc.N = lo.N + hi.N;
     }
   }
-  if (tid == 0) {
-    part += pose_cost(T, p, p.w_pose_t, p.w_pose_r);
-    float c_q = 0.f, c_qd = 0.f, c_ns = 0.f;
-    for (int j = 0; j < kNdof; ++j) {
-      const float vq = limit_violation(p.q0[j], p.qlo[j], p.qhi[j]);
-      const float vqd = limit_violation(p.qd0[j], p.qdlo[j], p.qdhi[j]);
-      const float e = p.q0[j] - p.qref[j];
-      c_q = fmaf(vq, vq, c_q);
-      c_qd = fmaf(vqd, vqd, c_qd);
-      c_ns = fmaf(e, e, c_ns);
-    }
-    part += p.w_q * c_q + p.w_qd * c_qd + p.w_ns * c_ns;
-  }
-  part = wave_sum(part);
-  if ((tid & (kWave - 1)) == 0) red[tid / kWave] = part;
-  __syncthreads();
-  float total = 0.f;
-  if (tid == 0)
-    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) total += red[w];
-  return total;
+  return acc;
 }
 
+// Grid of K2: waves [0, 7H) merge one output each, waves [7H, 7H + C) write the
+// weights and costs of a chunk of kWeightsPerWave rollouts, the last wave writes the
+// statistics.  Every wave merges the block partials itself (one memory round).
 __global__ __launch_bounds__(kK2Threads) void merge_kernel(
-    const DevRobot* __restrict__ rob, const StepParams p, const float* U_in, float* U_out,
-    const void* __restrict__ grid, Workspace ws, float* __restrict__ costs_out,
-    float* __restrict__ weights_out, float* __restrict__ stats_out) {
-  __shared__ float centres[kSlots * 4];
-  __shared__ float red[kK2Threads / kWave];
-  __shared__ float c0_s;
+    const StepParams p, const float* U_in, float* U_out, Workspace ws,
+    float* __restrict__ costs_out, float* __restrict__ weights_out,
+    float* __restrict__ stats_out) {
   const int lane = threadIdx.x & (kWave - 1);
   const int K = p.K, P = p.P, HO = p.H * kNdof;
+  const int n_chunks = (K + kWeightsPerWave - 1) / kWeightsPerWave;
+  const int wave = blockIdx.x * (kK2Threads / kWave) + (threadIdx.x / kWave);
+  if (wave > HO + n_chunks) return;
+  const bool is_stats = wave == HO + n_chunks;
+  const bool is_chunk = wave >= HO && !is_stats;
+  if (is_stats && !stats_out) return;
+  if (is_chunk && !weights_out && !costs_out) return;
 
-  if (blockIdx.x == 0) {
-    const float c0 = state0_cost_block(rob, p, grid, centres, red);
-    if (threadIdx.x == 0) c0_s = c0;
-    __syncthreads();
-    const float c0v = c0_s;
-    if (costs_out) {
-      for (int i = threadIdx.x; i < K; i += blockDim.x)
-        costs_out[i] = (float)(ws.S[i] + (double)c0v);
+  // Prefetch the chunk's costs before the merge so both memory rounds overlap.
+  constexpr int kPerLane = kWeightsPerWave / kWave;
+  const int lo = (wave - HO) * kWeightsPerWave;
+  const int hi = min(K, lo + kWeightsPerWave);
+  double sv[kPerLane];
+  if (is_chunk) {
+#pragma unroll
+    for (int c = 0; c < kPerLane; ++c) {
+      const int i = lo + lane + kWave * c;
+      sv[c] = i < hi ? ws.S[i] : 0.0;
     }
-    if (stats_out && threadIdx.x < kWave) {
-      const MergeStats st = merge_stats(ws, P, p.inv_lambda, lane);
-      if (lane == 0) {
-        const bool ok = isfinite(st.m);
-        stats_out[0] = ok ? (float)(st.m + (double)c0v) : __builtin_nanf("");
-        stats_out[1] = ok ? st.Z : 0.f;
-        stats_out[2] = ok ? st.Z * st.Z / st.Z2 : 0.f;
-        stats_out[3] = ok ? 0.f : (float)SMPC_E_NUMERIC;
-      }
-    }
-    return;
   }
+  const float c0 = (is_chunk || is_stats) ? ws.c0[0] : 0.f;
 
-  const int wave = (blockIdx.x - 1) * (kK2Threads / kWave) + (threadIdx.x / kWave);
-  const int n_weight_waves = weights_out ? (K + kWeightsPerWave - 1) / kWeightsPerWave : 0;
-  if (wave >= HO + n_weight_waves) return;
-  const MergeStats st = merge_stats(ws, P, p.inv_lambda, lane);
+  const int o = wave < HO ? wave : -1;
+  const MergeStats st = merge_partials(ws, P, o, p.inv_lambda, lane);
   const bool ok = isfinite(st.m);
 
   if (wave < HO) {
     // U*[o] = Ubar[o] + sum_b N_b[o] exp(-(m_b - m)/lambda) / Z   (eq. 30)
-    const int o = wave;
-    float acc = 0.f;
-    if (ok) {
-      for (int i = lane; i < P; i += kWave) {
-        const double mb = ws.part_m[i];
-        if (!isfinite(mb)) continue;
-        const float s = expf(-(float)(mb - st.m) * p.inv_lambda);
-        acc = fmaf(ws.part_N[(size_t)o * P + i], s, acc);
-      }
-    }
-    acc = wave_sum(acc);
-    if (lane == 0) U_out[o] = ok ? U_in[o] + acc / st.Z : U_in[o];
+    if (lane == 0) U_out[o] = ok ? U_in[o] + st.N / st.Z : U_in[o];
     return;
   }
-
-  // w^(m) (eq. 29) for a chunk of rollouts.
-  const int chunk = wave - HO;
-  const int lo = chunk * kWeightsPerWave;
-  const int hi = min(K, lo + kWeightsPerWave);
+  if (is_stats) {
+    if (lane == 0) {
+      stats_out[0] = ok ? (float)(st.m + (double)c0) : __builtin_nanf("");
+      stats_out[1] = ok ? st.Z : 0.f;
+      stats_out[2] = ok ? st.Z * st.Z / st.Z2 : 0.f;
+      stats_out[3] = ok ? 0.f : (float)SMPC_E_NUMERIC;
+    }
+    return;
+  }
+  // w^(m) (eq. 29) and S^(m) = S'^(m) + c0 (eq. 28) for this chunk of rollouts.
   const float invZ = ok ? 1.f / st.Z : 0.f;
-  for (int i = lo + lane; i < hi; i += kWave) {
-    const double s = ws.S[i];
-    float w = 0.f;
-    if (ok && isfinite(s)) w = expf(-(float)(s - st.m) * p.inv_lambda) * invZ;
-    weights_out[i] = w;
+#pragma unroll
+  for (int c = 0; c < kPerLane; ++c) {
+    const int i = lo + lane + kWave * c;
+    if (i >= hi) continue;
+    if (weights_out) {
+      float w = 0.f;
+      if (ok && isfinite(sv[c])) w = expf(-(float)(sv[c] - st.m) * p.inv_lambda) * invZ;
+      weights_out[i] = w;
+    }
+    if (costs_out) costs_out[i] = (float)(sv[c] + (double)c0);
   }
 }
 
@@ -614,8 +665,8 @@ LaunchConfig plan_launch_config(int K, int H) {
   lc.P = (K + bestR - 1) / bestR;
   lc.k1_lds = k1_lds_bytes(bestR, H);
   const int waves_per_block = kK2Threads / kWave;
-  const int work_waves = H * kNdof + (K + kWeightsPerWave - 1) / kWeightsPerWave;
-  lc.k2_blocks = 1 + (work_waves + waves_per_block - 1) / waves_per_block;
+  const int work_waves = H * kNdof + (K + kWeightsPerWave - 1) / kWeightsPerWave + 1;
+  lc.k2_blocks = (work_waves + waves_per_block - 1) / waves_per_block;
   return lc;
 }
 
@@ -623,7 +674,7 @@ static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 size_t workspace_bytes(int K, int H, int P) {
   return align256((size_t)K * 8) + align256((size_t)P * 8) + 2 * align256((size_t)P * 4) +
-         align256((size_t)H * kNdof * P * 4);
+         align256((size_t)H * kNdof * P * 4) + 256;
 }
 
 Workspace carve_workspace(void* base, int K, int H, int P) {
@@ -638,6 +689,8 @@ Workspace carve_workspace(void* base, int K, int H, int P) {
   ws.part_Z2 = reinterpret_cast<float*>(b);
   b += align256((size_t)P * 4);
   ws.part_N = reinterpret_cast<float*>(b);
+  b += align256((size_t)H * kNdof * P * 4);
+  ws.c0 = reinterpret_cast<float*>(b);
   return ws;
 }
 
@@ -652,9 +705,8 @@ int launch_plan_step(const DevRobot* robot, const StepParams& p, const LaunchCon
                      p, args.noise, args.U_in, args.esdf.data, ws);
   if ((e = hipGetLastError()) != hipSuccess) return (int)e;
   if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return (int)e;
-  hipLaunchKernelGGL(merge_kernel, dim3(lc.k2_blocks), dim3(kK2Threads), 0, s, robot, p,
-                     args.U_in, args.U_out, args.esdf.data, ws, args.costs_out, args.weights_out,
-                     args.stats_out);
+  hipLaunchKernelGGL(merge_kernel, dim3(lc.k2_blocks), dim3(kK2Threads), 0, s, p, args.U_in,
+                     args.U_out, ws, args.costs_out, args.weights_out, args.stats_out);
   if ((e = hipGetLastError()) != hipSuccess) return (int)e;
   if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return (int)e;
   return 0;

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <algorithm>
 #include <utility>
 #include <vector>
 
@@ -306,34 +307,68 @@ smpc_status smpc_set_robot(smpc_ctx* ctx, const smpc_robot_desc* d) {
     ctx->raw_d_qddhi[j] = (double)(float)d->qdd_max[j];
     ctx->qref[j] = (float)d->q_ref[j];
   }
-  // Sphere s goes to the next free slot of its link: slot = (link - 1) * kSpl + j.
+  // Spheres of link l fill slots (l - 1) * kSpl + j.  Within a link the sphere that
+  // gives the smallest bounding radius (max over the link's spheres of
+  // |c_i - c_0| + r_i) goes to slot 0: the kernel centres the link's bounding
+  // sphere there.
   int slot_of[SMPC_MAX_SPHERES];
-  int used[kNdof + 1] = {0};
   for (int s = 0; s < kSlots; ++s) ctx->slot_radius[s] = 0.0;
-  for (int s = 0; s < d->n_spheres; ++s) {
-    const int l = d->sphere_link[s];
-    const int slot = (l - 1) * kSpl + used[l]++;
-    slot_of[s] = slot;
-    const float radius = (float)d->sphere_radius[s];
-    r.sc[slot][0] = (float)d->sphere_center[s][0];
-    r.sc[slot][1] = (float)d->sphere_center[s][1];
-    r.sc[slot][2] = (float)d->sphere_center[s][2];
-    r.sc[slot][3] = radius;
-    r.slot_active |= 1u << slot;
-    ctx->slot_radius[slot] = (double)radius;
+  double bound_r[kNdof] = {0};
+  for (int l = 1; l <= kNdof; ++l) {
+    int members[kSpl], n = 0;
+    for (int s = 0; s < d->n_spheres; ++s)
+      if (d->sphere_link[s] == l) members[n++] = s;
+    if (n == 0) continue;
+    int best = 0;
+    double best_R = 1e300;
+    for (int c = 0; c < n; ++c) {
+      double R = 0.0;
+      for (int i = 0; i < n; ++i) {
+        double d2 = 0.0;
+        for (int k = 0; k < 3; ++k) {
+          const double diff = (double)(float)d->sphere_center[members[i]][k] -
+                              (double)(float)d->sphere_center[members[c]][k];
+          d2 += diff * diff;
+        }
+        R = std::max(R, std::sqrt(d2) + (double)(float)d->sphere_radius[members[i]]);
+      }
+      if (R < best_R) {
+        best_R = R;
+        best = c;
+      }
+    }
+    std::swap(members[0], members[best]);
+    bound_r[l - 1] = best_R + kBoundMargin;
+    r.lbound[l - 1] = (float)bound_r[l - 1];
+    for (int j = 0; j < n; ++j) {
+      const int s = members[j];
+      const int slot = (l - 1) * kSpl + j;
+      slot_of[s] = slot;
+      const float radius = (float)d->sphere_radius[s];
+      r.sc[slot][0] = (float)d->sphere_center[s][0];
+      r.sc[slot][1] = (float)d->sphere_center[s][1];
+      r.sc[slot][2] = (float)d->sphere_center[s][2];
+      r.sc[slot][3] = radius;
+      r.slot_active |= 1u << slot;
+      ctx->slot_radius[slot] = (double)radius;
+    }
   }
   int n_unique = 0;
+  uint32_t seen[kSlots] = {0};
   for (int i = 0; i < d->n_pairs; ++i) {
     int a = slot_of[d->pairs[i][0]], b = slot_of[d->pairs[i][1]];
     if (a > b) std::swap(a, b);
-    if (r.pair_mask[a] & (1u << b)) continue;  // duplicate pair: counted once
-    r.pair_mask[a] |= 1u << b;
+    if (seen[a] & (1u << b)) continue;  // duplicate pair: counted once
+    seen[a] |= 1u << b;
     const double rs = ctx->slot_radius[a] + ctx->slot_radius[b];
-    r.pair_rsum[a][b] = (float)rs;
-    r.pair_rsum2[a][b] = (float)(rs * rs);
-    r.pair_list[n_unique][0] = (int16_t)a;
-    r.pair_list[n_unique][1] = (int16_t)b;
     ++n_unique;
+    const int la = a / kSpl, lb = b / kSpl, lp = la * kNdof + lb;
+    const int bit = (a % kSpl) * kSpl + (b % kSpl);
+    r.lp_mask[lp] |= 1u << bit;
+    r.lp_rr2[lp][bit] = (float)(rs * rs);
+    r.lp_rs[lp][bit] = (float)rs;
+    const double bt = bound_r[la] + bound_r[lb];
+    r.lp_bthr[lp] = (float)(bt * bt);
   }
   r.n_pairs = n_unique;
   ctx->host_robot = r;
