@@ -4,4 +4,4 @@ Only ``tests/``, the smoke check in ``__graft_entry__`` and the CPU-baseline leg
 of ``bench.py`` may import this package.  It shares no code with the HIP library
 and is never on the product path.
 """
-from . import edt, smpc_oracle  # noqa: F401
+from . import edt, rng, smpc_oracle  # noqa: F401

@@ -3,6 +3,8 @@
 
 #include <stdint.h>
 
+#include <hip/hip_runtime.h>
+
 #include "smpc.h"
 
 namespace smpc {
@@ -31,6 +33,9 @@ struct DevRobot {
   float lp_rs[kNdof * kNdof][kSpl * kSpl];   // r_i + r_j
   float lbound[kNdof];         // bounding radius of each link's spheres about its slot-0 sphere
   int32_t n_pairs;             // distinct pairs after de-duplication
+  int32_t pad_[3];
+  // The same pairs as records (slot a, slot b as int bits, (r_a + r_b)^2, r_a + r_b).
+  float4 pair_rec[kMaxPairs];
 };
 
 // Margin added to each link bounding radius (metres).  Float32 sphere positions
@@ -64,8 +69,7 @@ struct Workspace {
   double* part_m;   // [P]   per-block minimum of S (+inf when the block has none finite)
   float* part_Z;    // [P]   sum_m exp(-(S - part_m)/lambda)
   float* part_Z2;   // [P]   sum_m exp(-2 (S - part_m)/lambda)
-  float* part_N;    // [H*7][P] sum_m exp(-(S - part_m)/lambda) eps^(m)
-  float* c0;        // [1]   state terms of state 0 (the same for every rollout)
+  float* part_N;    // [P][HO4] sum_m exp(-(S - part_m)/lambda) eps^(m), HO4 = 7H padded to 4
 };
 
 struct LaunchConfig {

@@ -12,9 +12,9 @@
 //
 // Thread k of a rollout charges the control terms of u_k and the state terms
 // of state k+1 (running terms for k+1 < H, terminal pose term for k+1 = H).
-// The state terms of state 0 are the same for every rollout; one thread of K1
-// computes them once and K2 adds them to the reported costs (the weights are
-// invariant to a common shift of the costs).
+// The state terms of state 0 are the same for every rollout; K2 computes them
+// once and adds them to the reported costs (the weights are invariant to a common
+// shift of the costs).
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -252,14 +252,10 @@ __device__ __forceinline__ float state_limit_cost(const StepParams& p, const flo
 
 // Cost charged by thread (m, k): control terms of u_k and state terms of state k+1.
 //   dq, qd : q_{k+1} - q0 and qd_{k+1};  u : u_k;  sc0 : sin(q0) then cos(q0) (LDS).
-// The one thread with `state0` set (rollout 0, k = H-1, a terminal thread with no
-// collision work of its own) also evaluates the state terms of state 0, which are
-// the same for every rollout, and returns them in *c0.
 __device__ __forceinline__ float step_cost(const DevRobot* __restrict__ rob, const StepParams& p,
                                            __amdgpu_buffer_rsrc_t rsrc, const float* sc0,
                                            const float (&dq)[kNdof], const float (&qd)[kNdof],
-                                           const float (&u)[kNdof], bool terminal, bool state0,
-                                           float* c0) {
+                                           const float (&u)[kNdof], bool terminal) {
   // Smoothness (eq. 23) and acceleration limit (eq. 22) on u_k.
   float c_u2 = 0.f, c_ulim = 0.f;
 #pragma unroll
@@ -276,18 +272,7 @@ __device__ __forceinline__ float step_cost(const DevRobot* __restrict__ rob, con
   // Pose tracking (eq. 16) or terminal (eq. 25) cost.
   cost += pose_cost(T, p, terminal ? p.w_term_t : p.w_pose_t, terminal ? p.w_term_r : p.w_pose_r);
 
-  float state0_cost = 0.f;
-  if (state0) {
-    float zero[kNdof], qd0[kNdof];
-#pragma unroll
-    for (int j = 0; j < kNdof; ++j) {
-      zero[j] = 0.f;
-      qd0[j] = p.qd0[j];
-    }
-    const Frame T0 = fk_spheres(rob, sc0, zero, px, py, pz);
-    state0_cost = pose_cost(T0, p, p.w_pose_t, p.w_pose_r) + state_limit_cost(p, zero, qd0);
-  }
-  if (terminal && !state0) return cost;
+  if (terminal) return cost;
 
   // Environment collision (eqs. 17, 19, 20).
   const uint32_t active = rob->slot_active;
@@ -342,12 +327,7 @@ __device__ __forceinline__ float step_cost(const DevRobot* __restrict__ rob, con
       }
     }
   }
-  const float coll = fmaf(p.w_env, c_env, p.w_self * c_self);
-  if (state0) {
-    *c0 = state0_cost + coll;
-    return cost;
-  }
-  return cost + coll;
+  return cost + fmaf(p.w_env, c_env, p.w_self * c_self);
 }
 
 // LDS layout of K1 (floats unless noted), for R rollouts of H steps.
@@ -404,20 +384,35 @@ __global__ __launch_bounds__(kK1MaxThreads) __attribute__((amdgpu_waves_per_eu(3
   __syncthreads();
 
   // Roll out eq. 7 (semi-implicit Euler) per (rollout, joint), relative to (q0, qd0).
-  // Strided: a block has R*H threads, which is fewer than R*7 when H < 7.
+  // Strided: a block has R*H threads, which is fewer than R*7 when H < 7.  The
+  // controls of 8 steps are read before the dependent updates so that the LDS
+  // latency is paid once per 8 steps.
   for (int w = tid; w < R * kNdof; w += nthreads) {
     const int r = w / kNdof, j = w - r * kNdof;
     if (r < nroll) {
       const float dt = p.dt, qd0 = p.qd0[j];
       float dqd = 0.f, dq = 0.f;
-      for (int k = 0; k < H; ++k) {
-        const int idx = (r * H + k) * kNdof + j;
-        const float u = L.ubar[k * kNdof + j] + L.eps[idx];  // eq. 27
-        dqd = fmaf(u, dt, dqd);
-        const float qd = qd0 + dqd;
-        dq = fmaf(qd, dt, dq);
-        L.dq[idx] = dq;
-        L.qd[idx] = qd;
+      const float* eps_r = L.eps + r * H * kNdof + j;
+      float* dq_r = L.dq + r * H * kNdof + j;
+      float* qd_r = L.qd + r * H * kNdof + j;
+      for (int k0 = 0; k0 < H; k0 += 8) {
+        float u[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const int k = k0 + c;
+          u[c] = k < H ? L.ubar[k * kNdof + j] + eps_r[k * kNdof] : 0.f;  // eq. 27
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const int k = k0 + c;
+          if (k < H) {
+            dqd = fmaf(u[c], dt, dqd);
+            const float qd = qd0 + dqd;
+            dq = fmaf(qd, dt, dq);
+            dq_r[k * kNdof] = dq;
+            qd_r[k * kNdof] = qd;
+          }
+        }
       }
     }
   }
@@ -437,10 +432,7 @@ __global__ __launch_bounds__(kK1MaxThreads) __attribute__((amdgpu_waves_per_eu(3
         u[j] = L.ubar[k * kNdof + j] + L.eps[base + j];
       }
       const __amdgpu_buffer_rsrc_t rsrc = grid_resource(grid, p.grid_bytes);
-      const bool state0 = (b == 0 && r == 0 && k == H - 1);
-      float c0 = 0.f;
-      cost = step_cost(rob, p, rsrc, L.sc0, dq, qd, u, k == H - 1, state0, &c0);
-      if (state0) ws.c0[0] = c0;
+      cost = step_cost(rob, p, rsrc, L.sc0, dq, qd, u, k == H - 1);
     }
     L.cost[tid] = cost;
   }
@@ -450,7 +442,14 @@ __global__ __launch_bounds__(kK1MaxThreads) __attribute__((amdgpu_waves_per_eu(3
   if (tid < R) {
     double s = 0.0;
     if (tid < nroll) {
-      for (int k = 0; k < H; ++k) s += (double)L.cost[tid * H + k];
+      const float* c_r = L.cost + tid * H;
+      for (int k0 = 0; k0 < H; k0 += 8) {
+        float c8[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) c8[c] = (k0 + c < H) ? c_r[k0 + c] : 0.f;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) s += (double)c8[c];
+      }
       ws.S[m0 + tid] = s;
     }
     L.S[tid] = s;
@@ -476,13 +475,17 @@ __global__ __launch_bounds__(kK1MaxThreads) __attribute__((amdgpu_waves_per_eu(3
     ws.part_Z2[b] = Z2;
   }
   __syncthreads();
-  for (int o = tid; o < H * kNdof; o += nthreads) {
+  // N_b[o] = sum_r e_r eps_r[o], one contiguous row per block (padded to 4 floats).
+  const int HO = H * kNdof, HO4 = (HO + 3) & ~3;
+  for (int o = tid; o < HO4; o += nthreads) {
     float acc = 0.f;
-    for (int r = 0; r < nroll; ++r) {
-      const float e = L.e[r];
-      if (e > 0.f) acc = fmaf(e, L.eps[r * H * kNdof + o], acc);  // weight-0 rollouts excluded
+    if (o < HO) {
+      for (int r = 0; r < nroll; ++r) {
+        const float e = L.e[r];
+        if (e > 0.f) acc = fmaf(e, L.eps[r * HO + o], acc);  // weight-0 rollouts excluded
+      }
     }
-    ws.part_N[(size_t)o * p.P + b] = acc;
+    ws.part_N[(size_t)b * HO4 + o] = acc;
   }
 }
 
@@ -496,30 +499,34 @@ struct MergeStats {
   double m;   // minimum over finite S (+inf if none)
   float Z;    // sum exp(-(S - m)/lambda)
   float Z2;   // sum exp(-2 (S - m)/lambda)
-  float N;    // sum exp(-(S - m)/lambda) eps[o] for the requested output o (0 if none)
+  float4 N;   // sum exp(-(S - m)/lambda) eps[o .. o+3] for the requested outputs (0 if none)
 };
 
-// Rescale a partial (m, Z, Z2, N) to a new reference minimum m_new <= m.
+// Rescale a partial to a new reference minimum m_new <= a.m.
 __device__ __forceinline__ void rescale(MergeStats& a, double m_new, float inv_lambda) {
   const float f = isfinite(a.m) ? expf(-(float)(a.m - m_new) * inv_lambda) : 0.f;
   a.Z *= f;
   a.Z2 *= f * f;
-  a.N *= f;
+  a.N.x *= f;
+  a.N.y *= f;
+  a.N.z *= f;
+  a.N.w *= f;
   a.m = m_new;
 }
 
-// Merge the per-block partials (m_b, Z_b, Z2_b, N_b[o]) of K1 into the totals for
-// output o (o < 0: statistics only).  Each lane folds a strided subset in chunks whose
-// loads are all issued before use; lanes are then merged by a butterfly.  The order
-// is fixed, so the result is deterministic.
+// Merge the per-block partials (m_b, Z_b, Z2_b, N_b[o..o+3]) of K1 (o4 < 0: statistics
+// only).  Each lane folds a strided subset in chunks whose loads are all issued
+// before use; lanes are then merged by a butterfly with a fixed operand order, so
+// the result is deterministic and identical in every lane.
 constexpr int kMergeChunk = 8;
 
-__device__ __forceinline__ MergeStats merge_partials(const Workspace& ws, int P, int o,
+__device__ __forceinline__ MergeStats merge_partials(const Workspace& ws, int P, int HO4, int o4,
                                                      float inv_lambda, int lane) {
-  MergeStats acc{__builtin_inf(), 0.f, 0.f, 0.f};
+  MergeStats acc{__builtin_inf(), 0.f, 0.f, make_float4(0.f, 0.f, 0.f, 0.f)};
   for (int base = 0; base < P; base += kWave * kMergeChunk) {
     double mb[kMergeChunk];
-    float zb[kMergeChunk], z2b[kMergeChunk], nb[kMergeChunk];
+    float zb[kMergeChunk], z2b[kMergeChunk];
+    float4 nb[kMergeChunk];
 #pragma unroll
     for (int c = 0; c < kMergeChunk; ++c) {
       const int i = base + lane + kWave * c;
@@ -527,7 +534,8 @@ __device__ __forceinline__ MergeStats merge_partials(const Workspace& ws, int P,
       mb[c] = v ? ws.part_m[i] : __builtin_inf();
       zb[c] = v ? ws.part_Z[i] : 0.f;
       z2b[c] = v ? ws.part_Z2[i] : 0.f;
-      nb[c] = (v && o >= 0) ? ws.part_N[(size_t)o * P + i] : 0.f;
+      nb[c] = (v && o4 >= 0) ? *reinterpret_cast<const float4*>(ws.part_N + (size_t)i * HO4 + o4)
+                             : make_float4(0.f, 0.f, 0.f, 0.f);
     }
     double cm = acc.m;
 #pragma unroll
@@ -540,7 +548,10 @@ __device__ __forceinline__ MergeStats merge_partials(const Workspace& ws, int P,
       const float sc = expf(-(float)(mb[c] - cm) * inv_lambda);
       acc.Z = fmaf(zb[c], sc, acc.Z);
       acc.Z2 = fmaf(z2b[c], sc * sc, acc.Z2);
-      acc.N = fmaf(nb[c], sc, acc.N);
+      acc.N.x = fmaf(nb[c].x, sc, acc.N.x);
+      acc.N.y = fmaf(nb[c].y, sc, acc.N.y);
+      acc.N.z = fmaf(nb[c].z, sc, acc.N.z);
+      acc.N.w = fmaf(nb[c].w, sc, acc.N.w);
     }
   }
 #pragma unroll
@@ -549,10 +560,12 @@ __device__ __forceinline__ MergeStats merge_partials(const Workspace& ws, int P,
     other.m = __shfl_xor(acc.m, off, kWave);
     other.Z = __shfl_xor(acc.Z, off, kWave);
     other.Z2 = __shfl_xor(acc.Z2, off, kWave);
-    other.N = __shfl_xor(acc.N, off, kWave);
+    other.N.x = __shfl_xor(acc.N.x, off, kWave);
+    other.N.y = __shfl_xor(acc.N.y, off, kWave);
+    other.N.z = __shfl_xor(acc.N.z, off, kWave);
+    other.N.w = __shfl_xor(acc.N.w, off, kWave);
     const double mn = fmin(acc.m, other.m);
     if (isfinite(mn)) {
-      // Fixed operand order (lower lane first) so both lanes of a pair agree bitwise.
       const bool lower = (lane & off) == 0;
       MergeStats lo = lower ? acc : other, hi = lower ? other : acc;
       rescale(lo, mn, inv_lambda);
@@ -560,32 +573,130 @@ __device__ __forceinline__ MergeStats merge_partials(const Workspace& ws, int P,
       acc.m = mn;
       acc.Z = lo.Z + hi.Z;
       acc.Z2 = lo.Z2 + hi.Z2;
-      acc.N = lo.N + hi.N;
+      acc.N.x = lo.N.x + hi.N.x;
+      acc.N.y = lo.N.y + hi.N.y;
+      acc.N.z = lo.N.z + hi.N.z;
+      acc.N.w = lo.N.w + hi.N.w;
     }
   }
   return acc;
 }
 
-// Grid of K2: waves [0, 7H) merge one output each, waves [7H, 7H + C) write the
-// weights and costs of a chunk of kWeightsPerWave rollouts, the last wave writes the
-// statistics.  Every wave merges the block partials itself (one memory round).
-__global__ __launch_bounds__(kK2Threads) void merge_kernel(
-    const StepParams p, const float* U_in, float* U_out, Workspace ws,
-    float* __restrict__ costs_out, float* __restrict__ weights_out,
-    float* __restrict__ stats_out) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int K = p.K, P = p.P, HO = p.H * kNdof;
-  const int n_chunks = (K + kWeightsPerWave - 1) / kWeightsPerWave;
-  const int wave = blockIdx.x * (kK2Threads / kWave) + (threadIdx.x / kWave);
-  if (wave > HO + n_chunks) return;
-  const bool is_stats = wave == HO + n_chunks;
-  const bool is_chunk = wave >= HO && !is_stats;
-  if (is_stats && !stats_out) return;
-  if (is_chunk && !weights_out && !costs_out) return;
+// State terms of state 0 (pose, environment, self, q/qd limits, null space) are the
+// same for every rollout (reading of eq. 28 at k = 0); K2's block 0 evaluates them
+// once: one thread runs the forward kinematics, then the lookups and the pairs are
+// spread over the block.  Everything that does not depend on them (pair records,
+// the costs to be shifted, the statistics merge) is fetched first.
+//
+// Grid of K2: block 0 as above (costs and statistics); then one wave per four
+// outputs o in [0, 7H) merges the block partials into U*[o]; then one wave per
+// chunk of kWeightsPerWave rollouts writes the weights.
+constexpr int kCostsPerThread = 32;   // K <= kK2Threads * kCostsPerThread per pass
 
-  // Prefetch the chunk's costs before the merge so both memory rounds overlap.
+__global__ __launch_bounds__(kK2Threads) void merge_kernel(
+    const DevRobot* __restrict__ rob, const StepParams p, const float* U_in, float* U_out,
+    const void* __restrict__ grid, Workspace ws, float* __restrict__ costs_out,
+    float* __restrict__ weights_out, float* __restrict__ stats_out) {
+  __shared__ float centres[kSlots * 4];
+  __shared__ float sc0[2 * kNdof];
+  __shared__ float red[kK2Threads / kWave];
+  __shared__ float pose0;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int tid = threadIdx.x;
+  const int K = p.K, P = p.P, HO = p.H * kNdof, HO4 = (HO + 3) & ~3;
+  const int n_merge = HO4 / 4;  // merge waves, 4 outputs each
+
+  if (blockIdx.x == 0) {
+    // --- independent fetches first
+    const bool has_pair = tid < rob->n_pairs;
+    float4 pr = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (has_pair) pr = rob->pair_rec[tid];
+    MergeStats st{};
+    if (stats_out && tid < kWave) st = merge_partials(ws, P, HO4, -1, p.inv_lambda, lane);
+    // --- forward kinematics of q0 (one thread) and the terms of q0 alone
+    if (tid < kNdof) {
+      float s_, c_;
+      sincosf(p.q0[tid], &s_, &c_);
+      sc0[tid] = s_;
+      sc0[kNdof + tid] = c_;
+    }
+    __syncthreads();
+    if (tid == kWave) {
+      float zero[kNdof], qd0[kNdof], px[kSlots], py[kSlots], pz[kSlots];
+#pragma unroll
+      for (int j = 0; j < kNdof; ++j) {
+        zero[j] = 0.f;
+        qd0[j] = p.qd0[j];
+      }
+      const Frame T0 = fk_spheres(rob, sc0, zero, px, py, pz);
+#pragma unroll
+      for (int sl = 0; sl < kSlots; ++sl) {
+        centres[sl * 4 + 0] = px[sl];
+        centres[sl * 4 + 1] = py[sl];
+        centres[sl * 4 + 2] = pz[sl];
+      }
+      pose0 = pose_cost(T0, p, p.w_pose_t, p.w_pose_r) + state_limit_cost(p, zero, qd0);
+    }
+    __syncthreads();
+    float part = 0.f;
+    if (tid < kSlots && (rob->slot_active & (1u << tid))) {
+      const __amdgpu_buffer_rsrc_t rsrc = grid_resource(grid, p.grid_bytes);
+      const float phi = esdf_lookup(rsrc, p, centres[tid * 4], centres[tid * 4 + 1],
+                                    centres[tid * 4 + 2]);
+      const float h = fmaxf(p.env_thr[tid] - phi, 0.f);
+      part = p.w_env * h * h;
+    }
+    if (has_pair) {
+      const int a = __float_as_int(pr.x), c = __float_as_int(pr.y);
+      const float dx = centres[a * 4] - centres[c * 4];
+      const float dy = centres[a * 4 + 1] - centres[c * 4 + 1];
+      const float dz = centres[a * 4 + 2] - centres[c * 4 + 2];
+      const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+      if (d2 < pr.z) {
+        const float h = pr.w - sqrt_hw(d2);
+        part = fmaf(p.w_self * h, h, part);
+      }
+    }
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) part += __shfl_xor(part, off, kWave);
+    if (lane == 0) red[tid / kWave] = part;
+    __syncthreads();
+    float c0 = pose0;
+    for (int w = 0; w < kK2Threads / kWave; ++w) c0 += red[w];
+    // --- costs S = S' + c0 (eq. 28) and statistics
+    if (costs_out) {
+      for (int base = 0; base < K; base += kK2Threads * kCostsPerThread) {
+        double sv[kCostsPerThread];
+#pragma unroll
+        for (int c = 0; c < kCostsPerThread; ++c) {
+          const int i = base + tid + kK2Threads * c;
+          sv[c] = i < K ? ws.S[i] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < kCostsPerThread; ++c) {
+          const int i = base + tid + kK2Threads * c;
+          if (i < K) costs_out[i] = (float)(sv[c] + (double)c0);
+        }
+      }
+    }
+    if (stats_out && tid == 0) {
+      const bool ok = isfinite(st.m);
+      stats_out[0] = ok ? (float)(st.m + (double)c0) : __builtin_nanf("");
+      stats_out[1] = ok ? st.Z : 0.f;
+      stats_out[2] = ok ? st.Z * st.Z / st.Z2 : 0.f;
+      stats_out[3] = ok ? 0.f : (float)SMPC_E_NUMERIC;
+    }
+    return;
+  }
+
+  const int wave = (blockIdx.x - 1) * (kK2Threads / kWave) + (threadIdx.x / kWave);
+  const int n_chunks = weights_out ? (K + kWeightsPerWave - 1) / kWeightsPerWave : 0;
+  if (wave >= n_merge + n_chunks) return;
+  const bool is_chunk = wave >= n_merge;
+
+  // Prefetch the chunk's costs so that both memory rounds overlap.
   constexpr int kPerLane = kWeightsPerWave / kWave;
-  const int lo = (wave - HO) * kWeightsPerWave;
+  const int lo = (wave - n_merge) * kWeightsPerWave;
   const int hi = min(K, lo + kWeightsPerWave);
   double sv[kPerLane];
   if (is_chunk) {
@@ -595,38 +706,28 @@ __global__ __launch_bounds__(kK2Threads) void merge_kernel(
       sv[c] = i < hi ? ws.S[i] : 0.0;
     }
   }
-  const float c0 = (is_chunk || is_stats) ? ws.c0[0] : 0.f;
-
-  const int o = wave < HO ? wave : -1;
-  const MergeStats st = merge_partials(ws, P, o, p.inv_lambda, lane);
+  const int o4 = is_chunk ? -1 : 4 * wave;
+  const MergeStats st = merge_partials(ws, P, HO4, o4, p.inv_lambda, lane);
   const bool ok = isfinite(st.m);
 
-  if (wave < HO) {
+  if (!is_chunk) {
     // U*[o] = Ubar[o] + sum_b N_b[o] exp(-(m_b - m)/lambda) / Z   (eq. 30)
-    if (lane == 0) U_out[o] = ok ? U_in[o] + st.N / st.Z : U_in[o];
-    return;
-  }
-  if (is_stats) {
-    if (lane == 0) {
-      stats_out[0] = ok ? (float)(st.m + (double)c0) : __builtin_nanf("");
-      stats_out[1] = ok ? st.Z : 0.f;
-      stats_out[2] = ok ? st.Z * st.Z / st.Z2 : 0.f;
-      stats_out[3] = ok ? 0.f : (float)SMPC_E_NUMERIC;
+    if (lane < 4) {
+      const int o = o4 + lane;
+      const float n = lane == 0 ? st.N.x : lane == 1 ? st.N.y : lane == 2 ? st.N.z : st.N.w;
+      if (o < HO) U_out[o] = ok ? U_in[o] + n / st.Z : U_in[o];
     }
     return;
   }
-  // w^(m) (eq. 29) and S^(m) = S'^(m) + c0 (eq. 28) for this chunk of rollouts.
+  // w^(m) (eq. 29) for this chunk of rollouts.
   const float invZ = ok ? 1.f / st.Z : 0.f;
 #pragma unroll
   for (int c = 0; c < kPerLane; ++c) {
     const int i = lo + lane + kWave * c;
     if (i >= hi) continue;
-    if (weights_out) {
-      float w = 0.f;
-      if (ok && isfinite(sv[c])) w = expf(-(float)(sv[c] - st.m) * p.inv_lambda) * invZ;
-      weights_out[i] = w;
-    }
-    if (costs_out) costs_out[i] = (float)(sv[c] + (double)c0);
+    float w = 0.f;
+    if (ok && isfinite(sv[c])) w = expf(-(float)(sv[c] - st.m) * p.inv_lambda) * invZ;
+    weights_out[i] = w;
   }
 }
 
@@ -665,16 +766,19 @@ LaunchConfig plan_launch_config(int K, int H) {
   lc.P = (K + bestR - 1) / bestR;
   lc.k1_lds = k1_lds_bytes(bestR, H);
   const int waves_per_block = kK2Threads / kWave;
-  const int work_waves = H * kNdof + (K + kWeightsPerWave - 1) / kWeightsPerWave + 1;
-  lc.k2_blocks = (work_waves + waves_per_block - 1) / waves_per_block;
+  const int HO4 = (H * kNdof + 3) & ~3;
+  const int work_waves = HO4 / 4 + (K + kWeightsPerWave - 1) / kWeightsPerWave;
+  lc.k2_blocks = 1 + (work_waves + waves_per_block - 1) / waves_per_block;
   return lc;
 }
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+static size_t padded_outputs(int H) { return ((size_t)H * kNdof + 3) & ~size_t(3); }
+
 size_t workspace_bytes(int K, int H, int P) {
   return align256((size_t)K * 8) + align256((size_t)P * 8) + 2 * align256((size_t)P * 4) +
-         align256((size_t)H * kNdof * P * 4) + 256;
+         align256(padded_outputs(H) * P * 4);
 }
 
 Workspace carve_workspace(void* base, int K, int H, int P) {
@@ -689,8 +793,6 @@ Workspace carve_workspace(void* base, int K, int H, int P) {
   ws.part_Z2 = reinterpret_cast<float*>(b);
   b += align256((size_t)P * 4);
   ws.part_N = reinterpret_cast<float*>(b);
-  b += align256((size_t)H * kNdof * P * 4);
-  ws.c0 = reinterpret_cast<float*>(b);
   return ws;
 }
 
@@ -705,8 +807,9 @@ int launch_plan_step(const DevRobot* robot, const StepParams& p, const LaunchCon
                      p, args.noise, args.U_in, args.esdf.data, ws);
   if ((e = hipGetLastError()) != hipSuccess) return (int)e;
   if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return (int)e;
-  hipLaunchKernelGGL(merge_kernel, dim3(lc.k2_blocks), dim3(kK2Threads), 0, s, p, args.U_in,
-                     args.U_out, ws, args.costs_out, args.weights_out, args.stats_out);
+  hipLaunchKernelGGL(merge_kernel, dim3(lc.k2_blocks), dim3(kK2Threads), 0, s, robot, p,
+                     args.U_in, args.U_out, args.esdf.data, ws, args.costs_out, args.weights_out,
+                     args.stats_out);
   if ((e = hipGetLastError()) != hipSuccess) return (int)e;
   if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return (int)e;
   return 0;

@@ -3,7 +3,7 @@
 // Every entry point checks its arguments completely before it makes any HIP call,
 // so invalid requests fail without touching the device (and can be tested on a
 // machine without a GPU).
-#include <hip/hip_runtime_api.h>
+#include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstdarg>
@@ -361,6 +361,13 @@ smpc_status smpc_set_robot(smpc_ctx* ctx, const smpc_robot_desc* d) {
     if (seen[a] & (1u << b)) continue;  // duplicate pair: counted once
     seen[a] |= 1u << b;
     const double rs = ctx->slot_radius[a] + ctx->slot_radius[b];
+    float4 rec;
+    int32_t ia = a, ib = b;
+    std::memcpy(&rec.x, &ia, 4);
+    std::memcpy(&rec.y, &ib, 4);
+    rec.z = (float)(rs * rs);
+    rec.w = (float)rs;
+    r.pair_rec[n_unique] = rec;
     ++n_unique;
     const int la = a / kSpl, lb = b / kSpl, lp = la * kNdof + lb;
     const int bit = (a % kSpl) * kSpl + (b % kSpl);
