@@ -113,7 +113,7 @@ typedef struct {
 typedef struct {
   const void* data;
   int32_t nx, ny, nz;
-  int32_t dtype; /* SMPC_GRID_F32 (this build also reserves SMPC_GRID_F16) */
+  int32_t dtype; /* SMPC_GRID_F32, or SMPC_GRID_F16 (IEEE binary16, widened to float32) */
   float origin[3];
   float voxel;
 } smpc_grid;
@@ -125,8 +125,10 @@ typedef struct {
  *               last row must be [0 0 0 1] and the rotation orthonormal to 1e-4.
  *   esdf      : distance grid (device).
  *   noise     : device float [K][H][7] disturbances eps (Algorithm 1, sampling
- *               step), or NULL to request on-device sampling from seed/sigma
- *               (returns SMPC_E_UNSUPPORTED in this build).
+ *               step), or NULL to sample them on the device from `seed` and
+ *               `sigma` (see smpc_sample_noise for the generator).
+ *   seed, sigma: sampling mode only: 64-bit Philox key and per-joint standard
+ *               deviations (finite, >= 0).
  *   K, H      : samples and horizon; K >= 1, 1 <= H <= SMPC_MAX_H.
  *   dt        : control period (s), finite and > 0.
  *   lambda    : temperature of eq. 29, finite and > 0.
@@ -178,6 +180,30 @@ const char* smpc_status_string(smpc_status status);
 
 /* Detail of the last failure on this context ("" if none).  Valid until the next call. */
 const char* smpc_last_error(const smpc_ctx* ctx);
+
+/*
+ * The disturbances that smpc_plan_step samples when noise == NULL (Algorithm 1's
+ * sampling step with D = N(0, diag(sigma^2))): for rollout m and step k the
+ * Philox4x32-10 generator (Salmon et al., SC'11) with key = seed (low word first)
+ * is evaluated at counters n = 2 (m H + k) and n + 1, each as (n mod 2^32,
+ * n >> 32, 0, 0); every 32-bit word w gives u = ((w >> 9) + 1/2) 2^-23; Box-Muller
+ * turns (u0, u1) into (sqrt(-2 ln u0) cos 2 pi u1, sqrt(-2 ln u0) sin 2 pi u1); the
+ * first counter's words give joints 0..3, the second's joints 4..6.
+ *   eps_out   : device float [K][H][7] receiving sigma_j z_j, or NULL;
+ *   words_out : device uint32 [K][H][8] receiving the raw words, or NULL.
+ * At least one output must be non-NULL; 1 <= H <= SMPC_MAX_H; K*H*8 < 2^31.
+ * Runs on the device current to the calling thread, asynchronously on `stream`.
+ */
+smpc_status smpc_sample_noise(uint64_t seed, int32_t K, int32_t H, const float* sigma,
+                              float* eps_out, uint32_t* words_out, void* stream);
+
+/*
+ * Convert a float32 grid (device, n elements) into binary16 (device, n elements,
+ * stored as uint16 bit patterns): each value is clamped to [-clamp, clamp] and
+ * rounded to the nearest float16 (ties to even).  clamp finite and > 0.
+ * Runs on the device current to the calling thread, asynchronously on `stream`.
+ */
+smpc_status smpc_grid_to_f16(const float* src, void* dst, int64_t n, float clamp, void* stream);
 
 /*
  * Per-kernel timing (profiling aid).  smpc_profile_enable(ctx, n) makes the next n

@@ -55,12 +55,19 @@ struct StepParams {
   float env_thr[kSlots];       // d_act + r_s; hinge is max(0, env_thr - phi)
   float w_pose_t, w_pose_r, w_term_t, w_term_r;
   float w_env, w_self, w_q, w_qd, w_qdd, w_smooth, w_ns;
-  float gox, goy, goz, inv_voxel;    // grid origin and 1/voxel
+  float inv_voxel;             // 1 / voxel
+  float gcx, gcy, gcz;         // -origin / voxel - 1/2 per axis (continuous-index offset)
   int32_t nx, ny, nz;
   uint32_t grid_bytes;
   int32_t K, H, R, P;          // samples, horizon, rollouts per K1 block, K1 blocks
   float dt;
   float inv_lambda;
+  uint32_t seed_lo, seed_hi;   // sampling mode: Philox key
+  float sigma[kNdof];          // sampling mode: per-joint standard deviation
+};
+
+struct SigmaArg {
+  float v[kNdof];
 };
 
 // Device workspace carved from one allocation.
@@ -90,5 +97,13 @@ Workspace carve_workspace(void* base, int K, int H, int P);
 int launch_plan_step(const DevRobot* robot, const StepParams& p, const LaunchConfig& lc,
                      const Workspace& ws, const smpc_plan_args& args, void* stream,
                      void* events);
+
+// Disturbances of the sampling mode written to memory (eps [K][H][7], words [K][H][8];
+// either may be null).  Returns a hipError_t value.
+int launch_sample_noise(uint64_t seed, int K, int H, const float* sigma, float* eps,
+                        uint32_t* words, void* stream);
+
+// float32 -> float16 grid conversion with clamping.  Returns a hipError_t value.
+int launch_grid_to_f16(const float* src, void* dst, long long n, float clamp, void* stream);
 
 }  // namespace smpc

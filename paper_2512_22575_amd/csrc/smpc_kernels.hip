@@ -79,30 +79,102 @@ __device__ __forceinline__ void transform_point(const Frame& T, float cx, float 
   pz = fmaf(cx, T.xz, fmaf(cy, T.yz, fmaf(cz, T.zz, T.tz)));
 }
 
+// sin and cos of r for |r| <= pi/4 by Taylor polynomials (sin to r^9, cos to r^10);
+// truncation error < 2e-9.
+__device__ __forceinline__ void sincos_poly(float r, float& sr, float& cr) {
+  const float r2 = r * r;
+  float ps = fmaf(r2, 1.f / 362880.f, -1.f / 5040.f);
+  ps = fmaf(ps, r2, 1.f / 120.f);
+  ps = fmaf(ps, r2, -1.f / 6.f);
+  sr = fmaf(ps * r2, r, r);
+  float pc = fmaf(r2, -1.f / 3628800.f, 1.f / 40320.f);
+  pc = fmaf(pc, r2, -1.f / 720.f);
+  pc = fmaf(pc, r2, 1.f / 24.f);
+  pc = fmaf(pc, r2, -0.5f);
+  cr = fmaf(pc, r2, 1.f);
+}
+
+// Rotate (sin r, cos r) by q quarter turns: sin/cos of r + q pi/2.
+__device__ __forceinline__ void quadrant(int q, float sr, float cr, float& s, float& c) {
+  const float s1 = (q & 1) ? cr : sr;
+  const float c1 = (q & 1) ? sr : cr;
+  s = (q & 2) ? -s1 : s1;
+  c = ((q + 1) & 2) ? -c1 : c1;
+}
+
 // sin and cos of x: Cody-Waite reduction by pi/2 (three-part constant, fused
-// multiply-adds) to r in [-pi/4, pi/4], Taylor polynomials of sin (to r^9) and cos
-// (to r^10) there, and the quadrant's swap/sign.  Truncation error < 2e-9; the
+// multiply-adds) to r in [-pi/4, pi/4], then sincos_poly and the quadrant.  The
 // result is within ~1.2 * 2^-24 of the true values for |x| < 60.
 __device__ __forceinline__ void sincos_cw(float x, float& s, float& c) {
   const float n = rintf(x * 0.636619772f);
   float r = fmaf(-n, 1.57079637050628662f, x);
   r = fmaf(-n, -4.37113882867379e-08f, r);
   r = fmaf(-n, -1.77635683940025e-15f, r);
-  const float r2 = r * r;
-  float ps = fmaf(r2, 1.f / 362880.f, -1.f / 5040.f);
-  ps = fmaf(ps, r2, 1.f / 120.f);
-  ps = fmaf(ps, r2, -1.f / 6.f);
-  const float sr = fmaf(ps * r2, r, r);
-  float pc = fmaf(r2, -1.f / 3628800.f, 1.f / 40320.f);
-  pc = fmaf(pc, r2, -1.f / 720.f);
-  pc = fmaf(pc, r2, 1.f / 24.f);
-  pc = fmaf(pc, r2, -0.5f);
-  const float cr = fmaf(pc, r2, 1.f);
-  const int q = (int)n;
-  const float s1 = (q & 1) ? cr : sr;
-  const float c1 = (q & 1) ? sr : cr;
-  s = (q & 2) ? -s1 : s1;
-  c = ((q + 1) & 2) ? -c1 : c1;
+  float sr, cr;
+  sincos_poly(r, sr, cr);
+  quadrant((int)n, sr, cr, s, c);
+}
+
+// sin and cos of 2 pi t: the quarter-turn count q = rint(4t) is removed exactly in
+// turns (t - q/4 is exact for t with at most 24 significant bits), then the
+// remaining angle, at most pi/4, goes through sincos_poly.
+__device__ __forceinline__ void sincos_turns(float t, float& s, float& c) {
+  const float q = rintf(4.f * t);
+  const float a = fmaf(-0.25f, q, t) * 6.28318530717958648f;
+  float sr, cr;
+  sincos_poly(a, sr, cr);
+  quadrant((int)q, sr, cr, s, c);
+}
+
+// ---------------------------------------------------------------------------
+// Counter-based sampling of the disturbances (Algorithm 1, sampling step) when
+// the caller passes no noise buffer: Philox4x32-10 (Salmon et al., SC'11), key =
+// the 64-bit seed, counter n = 2 (m H + k) + b as (n_lo, n_hi, 0, 0); 23-bit
+// uniforms u = ((w >> 9) + 1/2) 2^-23; Box-Muller pairs; counter b = 0 gives
+// joints 0..3, b = 1 joints 4..6.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
+    c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+  }
+  return c;
+}
+
+__device__ __forceinline__ float uniform23(uint32_t w) {
+  return ((float)(w >> 9) + 0.5f) * 1.1920928955078125e-07f;  // 2^-23
+}
+
+__device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& za, float& zb) {
+  const float r = sqrtf(-2.f * logf(uniform23(wa)));
+  float s, c;
+  sincos_turns(uniform23(wb), s, c);
+  za = r * c;
+  zb = r * s;
+}
+
+// Normals of item (m, k) with n0 = 2 (m H + k): z[0..6] are used, z[7] is spare;
+// w receives the 8 raw words.
+__device__ __forceinline__ void step_normals(uint64_t n0, uint32_t k0, uint32_t k1,
+                                             float (&z)[8], uint32_t (&w)[8]) {
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    const uint64_t n = n0 + (uint64_t)b;
+    const uint4 v = philox4x32_10(make_uint4((uint32_t)n, (uint32_t)(n >> 32), 0u, 0u), k0, k1);
+    w[4 * b + 0] = v.x;
+    w[4 * b + 1] = v.y;
+    w[4 * b + 2] = v.z;
+    w[4 * b + 3] = v.w;
+    box_muller(v.x, v.y, z[4 * b + 0], z[4 * b + 1]);
+    box_muller(v.z, v.w, z[4 * b + 2], z[4 * b + 3]);
+  }
 }
 
 __device__ __forceinline__ float sqrt_hw(float x) { return __builtin_amdgcn_sqrtf(x); }
@@ -173,33 +245,44 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t grid_resource(const void* grid
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(grid), 0, (int)bytes, 0x00020000);
 }
 
-__device__ __forceinline__ float load_f32(__amdgpu_buffer_rsrc_t rsrc, uint32_t off,
-                                          uint32_t soff) {
-  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)off, (int)soff, 0));
+// One grid element at byte offset off + soff: float32, or float16 widened to float32.
+template <int kElemBytes>
+__device__ __forceinline__ float load_grid(__amdgpu_buffer_rsrc_t rsrc, uint32_t off,
+                                           uint32_t soff) {
+  if constexpr (kElemBytes == 4) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)off, (int)soff, 0));
+  } else {
+    const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(rsrc, (int)off, (int)soff, 0);
+    return (float)__builtin_bit_cast(_Float16, h);
+  }
 }
 
 // Trilinear phi(p) between voxel centres, query clamped to the grid (edge extension).
+// u = p / voxel + (-origin / voxel - 1/2) per axis (p.gcx.. hold the second term).
+template <int kElemBytes>
 __device__ __forceinline__ float esdf_lookup(__amdgpu_buffer_rsrc_t rsrc, const StepParams& p,
                                              float px, float py, float pz) {
   const float fx_hi = (float)(p.nx - 1), fy_hi = (float)(p.ny - 1), fz_hi = (float)(p.nz - 1);
-  float ux = fmaf(px - p.gox, p.inv_voxel, -0.5f);
-  float uy = fmaf(py - p.goy, p.inv_voxel, -0.5f);
-  float uz = fmaf(pz - p.goz, p.inv_voxel, -0.5f);
-  ux = fminf(fmaxf(ux, 0.f), fx_hi);
-  uy = fminf(fmaxf(uy, 0.f), fy_hi);
-  uz = fminf(fmaxf(uz, 0.f), fz_hi);
+  const float ux = __builtin_amdgcn_fmed3f(fmaf(px, p.inv_voxel, p.gcx), 0.f, fx_hi);
+  const float uy = __builtin_amdgcn_fmed3f(fmaf(py, p.inv_voxel, p.gcy), 0.f, fy_hi);
+  const float uz = __builtin_amdgcn_fmed3f(fmaf(pz, p.inv_voxel, p.gcz), 0.f, fz_hi);
   const float bx = fminf(floorf(ux), fx_hi - 1.f);
   const float by = fminf(floorf(uy), fy_hi - 1.f);
   const float bz = fminf(floorf(uz), fz_hi - 1.f);
   const float fx = ux - bx, fy = uy - by, fz = uz - bz;
   const uint32_t ix = (uint32_t)bx, iy = (uint32_t)by, iz = (uint32_t)bz;
-  const uint32_t sy = (uint32_t)p.nx * 4u;
-  const uint32_t sz = (uint32_t)p.nx * (uint32_t)p.ny * 4u;
-  const uint32_t off = ((iz * (uint32_t)p.ny + iy) * (uint32_t)p.nx + ix) * 4u;
-  const float v000 = load_f32(rsrc, off, 0u), v100 = load_f32(rsrc, off + 4u, 0u);
-  const float v010 = load_f32(rsrc, off, sy), v110 = load_f32(rsrc, off + 4u, sy);
-  const float v001 = load_f32(rsrc, off, sz), v101 = load_f32(rsrc, off + 4u, sz);
-  const float v011 = load_f32(rsrc, off, sy + sz), v111 = load_f32(rsrc, off + 4u, sy + sz);
+  constexpr uint32_t e = kElemBytes;
+  const uint32_t sy = (uint32_t)p.nx * e;
+  const uint32_t sz = (uint32_t)p.nx * (uint32_t)p.ny * e;
+  const uint32_t off = ((iz * (uint32_t)p.ny + iy) * (uint32_t)p.nx + ix) * e;
+  const float v000 = load_grid<kElemBytes>(rsrc, off, 0u);
+  const float v100 = load_grid<kElemBytes>(rsrc, off + e, 0u);
+  const float v010 = load_grid<kElemBytes>(rsrc, off, sy);
+  const float v110 = load_grid<kElemBytes>(rsrc, off + e, sy);
+  const float v001 = load_grid<kElemBytes>(rsrc, off, sz);
+  const float v101 = load_grid<kElemBytes>(rsrc, off + e, sz);
+  const float v011 = load_grid<kElemBytes>(rsrc, off, sy + sz);
+  const float v111 = load_grid<kElemBytes>(rsrc, off + e, sy + sz);
   const float c00 = fmaf(fx, v100 - v000, v000);
   const float c10 = fmaf(fx, v110 - v010, v010);
   const float c01 = fmaf(fx, v101 - v001, v001);
@@ -252,6 +335,7 @@ __device__ __forceinline__ float state_limit_cost(const StepParams& p, const flo
 
 // Cost charged by thread (m, k): control terms of u_k and state terms of state k+1.
 //   dq, qd : q_{k+1} - q0 and qd_{k+1};  u : u_k;  sc0 : sin(q0) then cos(q0) (LDS).
+template <int kElemBytes>
 __device__ __forceinline__ float step_cost(const DevRobot* __restrict__ rob, const StepParams& p,
                                            __amdgpu_buffer_rsrc_t rsrc, const float* sc0,
                                            const float (&dq)[kNdof], const float (&qd)[kNdof],
@@ -280,7 +364,7 @@ __device__ __forceinline__ float step_cost(const DevRobot* __restrict__ rob, con
 #pragma unroll
   for (int s = 0; s < kSlots; ++s) {
     if (active & (1u << s)) {
-      const float phi = esdf_lookup(rsrc, p, px[s], py[s], pz[s]);
+      const float phi = esdf_lookup<kElemBytes>(rsrc, p, px[s], py[s], pz[s]);
       const float h = fmaxf(p.env_thr[s] - phi, 0.f);
       c_env = fmaf(h, h, c_env);
     }
@@ -358,6 +442,7 @@ __device__ __forceinline__ K1Lds k1_lds(unsigned char* base, int R, int H) {
   return L;
 }
 
+template <int kElemBytes, bool kSample>
 __global__ __launch_bounds__(kK1MaxThreads) __attribute__((amdgpu_waves_per_eu(3))) void rollout_cost_kernel(
     const DevRobot* __restrict__ rob, const StepParams p, const float* __restrict__ noise,
     const float* __restrict__ U_in, const void* __restrict__ grid, Workspace ws) {
@@ -370,10 +455,25 @@ __global__ __launch_bounds__(kK1MaxThreads) __attribute__((amdgpu_waves_per_eu(3
   const int m0 = b * R;
   const int nroll = min(R, p.K - m0);
 
-  // Stage this block's disturbances (contiguous [nroll][H][7]) and the nominal sequence.
-  const float* src = noise + (size_t)m0 * H * kNdof;
-  const int n_eps = nroll * H * kNdof;
-  for (int i = tid; i < RH * kNdof; i += nthreads) L.eps[i] = (i < n_eps) ? src[i] : 0.f;
+  // Stage this block's disturbances (contiguous [nroll][H][7]) and the nominal sequence:
+  // read them, or sample them here (one (rollout, step) item per thread).
+  if constexpr (kSample) {
+    for (int t = tid; t < RH; t += nthreads) {
+      const int r = t / H, k = t - r * H;
+      float z[8];
+      uint32_t w[8];
+      if (r < nroll) {
+        step_normals(2ull * ((uint64_t)(m0 + r) * (uint64_t)H + (uint64_t)k), p.seed_lo,
+                     p.seed_hi, z, w);
+      }
+#pragma unroll
+      for (int j = 0; j < kNdof; ++j) L.eps[t * kNdof + j] = r < nroll ? p.sigma[j] * z[j] : 0.f;
+    }
+  } else {
+    const float* src = noise + (size_t)m0 * H * kNdof;
+    const int n_eps = nroll * H * kNdof;
+    for (int i = tid; i < RH * kNdof; i += nthreads) L.eps[i] = (i < n_eps) ? src[i] : 0.f;
+  }
   for (int i = tid; i < H * kNdof; i += nthreads) L.ubar[i] = U_in[i];
   if (tid < kNdof) {
     float s, c;
@@ -432,7 +532,7 @@ __global__ __launch_bounds__(kK1MaxThreads) __attribute__((amdgpu_waves_per_eu(3
         u[j] = L.ubar[k * kNdof + j] + L.eps[base + j];
       }
       const __amdgpu_buffer_rsrc_t rsrc = grid_resource(grid, p.grid_bytes);
-      cost = step_cost(rob, p, rsrc, L.sc0, dq, qd, u, k == H - 1);
+      cost = step_cost<kElemBytes>(rob, p, rsrc, L.sc0, dq, qd, u, k == H - 1);
     }
     L.cost[tid] = cost;
   }
@@ -593,6 +693,7 @@ __device__ __forceinline__ MergeStats merge_partials(const Workspace& ws, int P,
 // chunk of kWeightsPerWave rollouts writes the weights.
 constexpr int kCostsPerThread = 32;   // K <= kK2Threads * kCostsPerThread per pass
 
+template <int kElemBytes>
 __global__ __launch_bounds__(kK2Threads) void merge_kernel(
     const DevRobot* __restrict__ rob, const StepParams p, const float* U_in, float* U_out,
     const void* __restrict__ grid, Workspace ws, float* __restrict__ costs_out,
@@ -641,7 +742,7 @@ __global__ __launch_bounds__(kK2Threads) void merge_kernel(
     float part = 0.f;
     if (tid < kSlots && (rob->slot_active & (1u << tid))) {
       const __amdgpu_buffer_rsrc_t rsrc = grid_resource(grid, p.grid_bytes);
-      const float phi = esdf_lookup(rsrc, p, centres[tid * 4], centres[tid * 4 + 1],
+      const float phi = esdf_lookup<kElemBytes>(rsrc, p, centres[tid * 4], centres[tid * 4 + 1],
                                     centres[tid * 4 + 2]);
       const float h = fmaxf(p.env_thr[tid] - phi, 0.f);
       part = p.w_env * h * h;
@@ -731,10 +832,42 @@ __global__ __launch_bounds__(kK2Threads) void merge_kernel(
   }
 }
 
+// The disturbances of the sampling mode, for inspection: eps [K][H][7] and the raw
+// Philox words [K][H][8] (either output may be null).  One thread per item.
+__global__ __launch_bounds__(256) void sample_noise_kernel(uint32_t k0, uint32_t k1, int K, int H,
+                                                           SigmaArg sigma, float* eps,
+                                                           uint32_t* words) {
+  const long long item = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (item >= (long long)K * H) return;
+  float z[8];
+  uint32_t w[8];
+  step_normals(2ull * (uint64_t)item, k0, k1, z, w);
+  if (eps) {
+#pragma unroll
+    for (int j = 0; j < kNdof; ++j) eps[item * kNdof + j] = sigma.v[j] * z[j];
+  }
+  if (words) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) words[item * 8 + j] = w[j];
+  }
+}
+
+// float32 -> float16 grid: clamp to [-clamp, clamp], round to nearest even.
+__global__ __launch_bounds__(256) void grid_to_f16_kernel(const float* __restrict__ src,
+                                                          unsigned short* __restrict__ dst,
+                                                          long long n, float clamp) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const float v = __builtin_amdgcn_fmed3f(src[i], -clamp, clamp);
+    dst[i] = __builtin_bit_cast(unsigned short, (_Float16)v);
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // Host-side launch helpers
+
 // ---------------------------------------------------------------------------
 
 static size_t k1_lds_bytes(int R, int H) {
@@ -803,16 +936,42 @@ int launch_plan_step(const DevRobot* robot, const StepParams& p, const LaunchCon
   hipEvent_t* ev = static_cast<hipEvent_t*>(events);
   hipError_t e;
   if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return (int)e;
-  hipLaunchKernelGGL(rollout_cost_kernel, dim3(lc.P), dim3(lc.k1_threads), lc.k1_lds, s, robot,
-                     p, args.noise, args.U_in, args.esdf.data, ws);
+  const bool f16 = args.esdf.dtype == SMPC_GRID_F16;
+  const bool sample = args.noise == nullptr;
+  auto k1 = f16 ? (sample ? rollout_cost_kernel<2, true> : rollout_cost_kernel<2, false>)
+                : (sample ? rollout_cost_kernel<4, true> : rollout_cost_kernel<4, false>);
+  hipLaunchKernelGGL(k1, dim3(lc.P), dim3(lc.k1_threads), lc.k1_lds, s, robot, p, args.noise,
+                     args.U_in, args.esdf.data, ws);
   if ((e = hipGetLastError()) != hipSuccess) return (int)e;
   if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return (int)e;
-  hipLaunchKernelGGL(merge_kernel, dim3(lc.k2_blocks), dim3(kK2Threads), 0, s, robot, p,
+  auto k2 = f16 ? merge_kernel<2> : merge_kernel<4>;
+  hipLaunchKernelGGL(k2, dim3(lc.k2_blocks), dim3(kK2Threads), 0, s, robot, p,
                      args.U_in, args.U_out, args.esdf.data, ws, args.costs_out, args.weights_out,
                      args.stats_out);
   if ((e = hipGetLastError()) != hipSuccess) return (int)e;
   if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return (int)e;
   return 0;
+}
+
+int launch_sample_noise(uint64_t seed, int K, int H, const float* sigma, float* eps,
+                        uint32_t* words, void* stream) {
+  SigmaArg sg;
+  for (int j = 0; j < kNdof; ++j) sg.v[j] = sigma[j];
+  const long long items = (long long)K * H;
+  const int blocks = (int)((items + 255) / 256);
+  hipLaunchKernelGGL(sample_noise_kernel, dim3(blocks), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), (uint32_t)seed, (uint32_t)(seed >> 32), K,
+                     H, sg, eps, words);
+  return (int)hipGetLastError();
+}
+
+int launch_grid_to_f16(const float* src, void* dst, long long n, float clamp, void* stream) {
+  const long long want = (n + 255) / 256;
+  const int blocks = (int)(want < 65536 ? (want > 0 ? want : 1) : 65536);
+  hipLaunchKernelGGL(grid_to_f16_kernel, dim3(blocks), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), src, static_cast<unsigned short*>(dst), n,
+                     clamp);
+  return (int)hipGetLastError();
 }
 
 }  // namespace smpc

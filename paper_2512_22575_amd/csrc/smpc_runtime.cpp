@@ -160,16 +160,17 @@ smpc_status validate_args(smpc_ctx* ctx, const smpc_plan_args* a) {
     return fail(ctx, SMPC_E_INVALID_ARG, "grid dimensions must be >= 2");
   if (g.dtype != SMPC_GRID_F32 && g.dtype != SMPC_GRID_F16)
     return fail(ctx, SMPC_E_INVALID_ARG, "unknown grid dtype %d", g.dtype);
-  if (g.dtype != SMPC_GRID_F32)
-    return fail(ctx, SMPC_E_UNSUPPORTED, "this build reads float32 grids only");
   const long long elems = (long long)g.nx * g.ny * g.nz;
-  if (elems * 4 >= (1LL << 31))
+  if (elems * (g.dtype == SMPC_GRID_F16 ? 2 : 4) >= (1LL << 31))
     return fail(ctx, SMPC_E_INVALID_ARG, "grid exceeds 2^31 bytes");
   if (!finite_all(g.origin, 3) || !std::isfinite(g.voxel) || !(g.voxel > 0.f))
     return fail(ctx, SMPC_E_INVALID_ARG, "grid origin/voxel must be finite, voxel > 0");
   if (!a->U_in || !a->U_out) return fail(ctx, SMPC_E_INVALID_ARG, "U_in/U_out is NULL");
-  if (!a->noise)
-    return fail(ctx, SMPC_E_UNSUPPORTED, "on-device sampling (noise = NULL) is not built");
+  if (!a->noise) {
+    for (int j = 0; j < kNdof; ++j)
+      if (!std::isfinite(a->sigma[j]) || a->sigma[j] < 0.f)
+        return fail(ctx, SMPC_E_INVALID_ARG, "sampling: sigma must be finite and >= 0");
+  }
   return SMPC_OK;
 }
 
@@ -216,14 +217,19 @@ StepParams make_params(const smpc_ctx* ctx, const smpc_plan_args* a, const Launc
   p.w_qdd = w.w_qdd;
   p.w_smooth = w.w_smooth;
   p.w_ns = w.w_ns;
-  p.gox = a->esdf.origin[0];
-  p.goy = a->esdf.origin[1];
-  p.goz = a->esdf.origin[2];
-  p.inv_voxel = (float)(1.0 / (double)a->esdf.voxel);
+  const double inv_voxel = 1.0 / (double)a->esdf.voxel;
+  p.inv_voxel = (float)inv_voxel;
+  p.gcx = (float)(-(double)a->esdf.origin[0] * inv_voxel - 0.5);
+  p.gcy = (float)(-(double)a->esdf.origin[1] * inv_voxel - 0.5);
+  p.gcz = (float)(-(double)a->esdf.origin[2] * inv_voxel - 0.5);
   p.nx = a->esdf.nx;
   p.ny = a->esdf.ny;
   p.nz = a->esdf.nz;
-  p.grid_bytes = (uint32_t)((long long)a->esdf.nx * a->esdf.ny * a->esdf.nz * 4);
+  const int elem = a->esdf.dtype == SMPC_GRID_F16 ? 2 : 4;
+  p.grid_bytes = (uint32_t)((long long)a->esdf.nx * a->esdf.ny * a->esdf.nz * elem);
+  p.seed_lo = (uint32_t)a->seed;
+  p.seed_hi = (uint32_t)(a->seed >> 32);
+  for (int j = 0; j < kNdof; ++j) p.sigma[j] = a->sigma[j];
   p.K = a->K;
   p.H = a->H;
   p.R = lc.R;
@@ -429,6 +435,26 @@ smpc_status smpc_plan_step(smpc_ctx* ctx, const smpc_plan_args* a, void* stream)
     return fail(ctx, SMPC_E_DEVICE, "kernel launch failed: %s",
                 hipGetErrorString(static_cast<hipError_t>(e)));
   return SMPC_OK;
+}
+
+smpc_status smpc_sample_noise(uint64_t seed, int32_t K, int32_t H, const float* sigma,
+                              float* eps_out, uint32_t* words_out, void* stream) {
+  if (K < 1 || H < 1 || H > kMaxH || !sigma || (!eps_out && !words_out))
+    return SMPC_E_INVALID_ARG;
+  if ((long long)K * H * 8 > (1LL << 31) - 1) return SMPC_E_INVALID_ARG;
+  for (int j = 0; j < kNdof; ++j)
+    if (!std::isfinite(sigma[j]) || sigma[j] < 0.f) return SMPC_E_INVALID_ARG;
+  return launch_sample_noise(seed, K, H, sigma, eps_out, words_out, stream) == 0
+             ? SMPC_OK
+             : SMPC_E_DEVICE;
+}
+
+smpc_status smpc_grid_to_f16(const float* src, void* dst, int64_t n, float clamp, void* stream) {
+  if (!src || !dst || n < 0 || !std::isfinite(clamp) || !(clamp > 0.f))
+    return SMPC_E_INVALID_ARG;
+  if (n == 0) return SMPC_OK;
+  return launch_grid_to_f16(src, dst, (long long)n, clamp, stream) == 0 ? SMPC_OK
+                                                                        : SMPC_E_DEVICE;
 }
 
 smpc_status smpc_profile_enable(smpc_ctx* ctx, int32_t n_steps) {

@@ -109,6 +109,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.smpc_last_error.restype = c_char_p
     lib.smpc_version.argtypes = []
     lib.smpc_version.restype = c_int32
+    lib.smpc_sample_noise.argtypes = [c_uint64, c_int32, c_int32, POINTER(c_float), c_void_p,
+                                      c_void_p, c_void_p]
+    lib.smpc_sample_noise.restype = c_int32
+    lib.smpc_grid_to_f16.argtypes = [c_void_p, c_void_p, ctypes.c_int64, c_float, c_void_p]
+    lib.smpc_grid_to_f16.restype = c_int32
     lib.smpc_profile_enable.argtypes = [c_void_p, c_int32]
     lib.smpc_profile_enable.restype = c_int32
     lib.smpc_profile_read.argtypes = [c_void_p, POINTER(c_float), POINTER(c_float), c_int32,
@@ -148,6 +153,19 @@ def smpc_last_error(ctx: c_void_p) -> str:
 
 def smpc_version() -> int:
     return int(load_library().smpc_version())
+
+
+def smpc_sample_noise(seed: int, K: int, H: int, sigma, eps_out: int, words_out: int,
+                      stream: int | None) -> int:
+    """eps_out / words_out are device addresses (0 for none)."""
+    sg = (c_float * NDOF)(*[float(x) for x in np.broadcast_to(np.asarray(sigma, np.float32), (NDOF,))])
+    return load_library().smpc_sample_noise(int(seed), int(K), int(H), sg, c_void_p(eps_out or 0),
+                                            c_void_p(words_out or 0), c_void_p(stream or 0))
+
+
+def smpc_grid_to_f16(src: int, dst: int, n: int, clamp: float, stream: int | None) -> int:
+    return load_library().smpc_grid_to_f16(c_void_p(src or 0), c_void_p(dst or 0), int(n),
+                                           float(clamp), c_void_p(stream or 0))
 
 
 def smpc_profile_enable(ctx: c_void_p, n_steps: int) -> int:
@@ -272,6 +290,8 @@ class Planner:
         import torch
         if noise is not None:
             K, H = int(noise.shape[0]), int(noise.shape[1])
+        elif K is None or H is None:
+            raise ValueError("K and H are required when the plan step samples its own noise")
         if stream is None:
             stream = torch.cuda.current_stream(self.device).cuda_stream
         a = plan_args(q0, qd0, T_goal, grid, origin, voxel, noise, U_in, U_out, K, H, dt, lam,

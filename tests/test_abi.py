@@ -183,10 +183,12 @@ def test_plan_step_requires_robot(ctx):
     (dict(grid=_FakeTensor((4, 4, 4), ptr=0)), S.SMPC_E_INVALID_ARG, "esdf.data"),
     (dict(grid=_FakeTensor((1024, 1024, 1024))), S.SMPC_E_INVALID_ARG, "2^31 bytes"),
     (dict(grid_dtype=7), S.SMPC_E_INVALID_ARG, "dtype"),
-    (dict(grid_dtype=S.GRID_F16), S.SMPC_E_UNSUPPORTED, "float32"),
+    (dict(grid_dtype=S.GRID_F16, grid=_FakeTensor((1024, 1024, 1024))), S.SMPC_E_INVALID_ARG,
+     "2^31 bytes"),
     (dict(U_in=None), S.SMPC_E_INVALID_ARG, "U_in"),
     (dict(U_out=None), S.SMPC_E_INVALID_ARG, "U_out"),
-    (dict(noise=None), S.SMPC_E_UNSUPPORTED, "sampling"),
+    (dict(noise=None, sigma=[0.5, 0.5, -0.1, 0.5, 0.5, 0.5, 0.5]), S.SMPC_E_INVALID_ARG, "sigma"),
+    (dict(noise=None, sigma=[0.5, 0.5, 0.5, np.nan, 0.5, 0.5, 0.5]), S.SMPC_E_INVALID_ARG, "sigma"),
 ])
 def test_plan_step_rejects_invalid_arguments(ctx, over, status, msg):
     assert S.smpc_set_robot(ctx, S.robot_desc(R.make_robot(0))) == S.SMPC_OK
@@ -217,3 +219,20 @@ def test_planner_raises_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(S, "_lib", None)
     with pytest.raises(OSError, match="missing"):
         S.load_library(str(tmp_path / "libsmpc.so"))
+
+
+def test_sample_noise_and_grid_conversion_validate_on_host():
+    ok_sigma = [0.5] * 7
+    assert S.smpc_sample_noise(1, 0, 4, ok_sigma, 0x1000, 0, None) == S.SMPC_E_INVALID_ARG
+    assert S.smpc_sample_noise(1, 4, 0, ok_sigma, 0x1000, 0, None) == S.SMPC_E_INVALID_ARG
+    assert S.smpc_sample_noise(1, 4, 65, ok_sigma, 0x1000, 0, None) == S.SMPC_E_INVALID_ARG
+    assert S.smpc_sample_noise(1, 4, 4, ok_sigma, 0, 0, None) == S.SMPC_E_INVALID_ARG
+    assert S.smpc_sample_noise(1, 4, 4, [0.5] * 6 + [-1.0], 0x1000, 0, None) == \
+        S.SMPC_E_INVALID_ARG
+    assert S.smpc_sample_noise(1, 5_000_000, 64, ok_sigma, 0x1000, 0, None) == \
+        S.SMPC_E_INVALID_ARG
+    assert S.smpc_grid_to_f16(0, 0x1000, 8, 2.0, None) == S.SMPC_E_INVALID_ARG
+    assert S.smpc_grid_to_f16(0x1000, 0, 8, 2.0, None) == S.SMPC_E_INVALID_ARG
+    assert S.smpc_grid_to_f16(0x1000, 0x2000, -1, 2.0, None) == S.SMPC_E_INVALID_ARG
+    assert S.smpc_grid_to_f16(0x1000, 0x2000, 8, 0.0, None) == S.SMPC_E_INVALID_ARG
+    assert S.smpc_grid_to_f16(0x1000, 0x2000, 0, 2.0, None) == S.SMPC_OK   # nothing to do

@@ -1,0 +1,180 @@
+"""GPU tests of the precision/sampling variant: on-device Philox sampling and FP16 grids.
+
+* raw Philox4x32-10 words from the library equal the oracle's bit for bit;
+* sampled disturbances agree with the oracle's float64 Box-Muller on the same
+  words within a float32 bound;
+* a plan step that samples on the device equals (bitwise) a plan step given the
+  library's own samples, and matches the FP64 oracle at the usual bar;
+* float32 -> float16 grid conversion is bit-exact against numpy's rounding;
+* plan steps on a float16 grid match the oracle run on the decoded grid; their
+  difference from the float32-grid result is reported.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import rng as ORNG
+from oracle import smpc_oracle as O
+from synth import workload as W
+from tests.gpu_helpers import (COST_ATOL, COST_RTOL, assert_controls_close, assert_costs_close,
+                               run_gpu)
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def oracle(inp, grid=None, noise=None):
+    return O.plan_step(inp.robot.rounded_f32(), inp.q0, inp.qd0, inp.T_goal,
+                       inp.grid if grid is None else grid, inp.origin, inp.voxel,
+                       inp.noise if noise is None else noise, inp.U_bar, inp.dt, inp.lam,
+                       inp.weights)
+
+
+def gpu_sample(seed, K, H, sigma):
+    torch = _torch()
+    from paper_2512_22575_amd import smpc as S
+    eps = torch.full((K, H, 7), float("nan"), device="cuda:0")
+    words = torch.zeros((K, H, 8), dtype=torch.int32, device="cuda:0")
+    st = S.smpc_sample_noise(seed, K, H, sigma, eps.data_ptr(), words.data_ptr(),
+                             torch.cuda.current_stream().cuda_stream)
+    assert st == S.SMPC_OK
+    torch.cuda.synchronize()
+    return eps.cpu().numpy().astype(np.float64), words.cpu().numpy().view(np.uint32)
+
+
+@pytest.mark.parametrize("seed,K,H", [(0, 3, 5), (2**40 + 5, 37, 13), (2**64 - 1, 9, 64)])
+def test_sampled_words_bit_exact(seed, K, H):
+    _, words = gpu_sample(seed, K, H, [0.5] * 7)
+    item = np.arange(K * H, dtype=np.uint64)
+    for b in (0, 1):
+        n = np.uint64(2) * item + np.uint64(b)
+        ref = ORNG.philox4x32_10_np(n & np.uint64(0xFFFFFFFF), n >> np.uint64(32), 0 * n, 0 * n,
+                                    seed & 0xFFFFFFFF, seed >> 32)
+        for j in range(4):
+            np.testing.assert_array_equal(words.reshape(-1, 8)[:, 4 * b + j],
+                                          ref[j].astype(np.uint32))
+
+
+def test_sampled_noise_matches_oracle_transform():
+    sigma = np.array([0.5, 0.25, 1.0, 0.5, 0.5, 2.0, 0.5], np.float32)
+    K, H, seed = 200, 40, 77
+    eps, _ = gpu_sample(seed, K, H, sigma)
+    ref = ORNG.sample_noise(seed, K, H, sigma.astype(np.float64))
+    z = np.abs(ref / sigma.astype(np.float64))
+    # float32 log, sqrt and sin/cos: a few ulp of each factor.
+    bound = sigma * (6e-7 * (1.0 + z))
+    assert np.all(np.abs(eps - ref) <= bound), float(np.max(np.abs(eps - ref) / bound))
+
+
+def _sampled_inputs(seed_noise, K=192, H=24):
+    inp = W.make_inputs(41, K=K, H=H, dt=0.03, n=40, voxel=0.04, n_boxes=8, n_spheres=6)
+    sigma = np.full(7, 0.5, np.float32)
+    return inp, sigma
+
+
+def test_sampling_mode_plan_step_matches_oracle_and_buffer_mode():
+    torch = _torch()
+    from paper_2512_22575_amd import smpc as S
+    inp, sigma = _sampled_inputs(0)
+    seed = 4
+    dev = torch.device("cuda:0")
+    grid = torch.from_numpy(inp.grid).to(dev)
+    U_in = torch.from_numpy(inp.U_bar).to(dev)
+    outs = {}
+    planner = S.Planner(inp.robot)
+    eps_gpu, _ = gpu_sample(seed, inp.K, inp.H, sigma)
+    noise_buf = torch.from_numpy(eps_gpu.astype(np.float32)).to(dev)
+    for mode in ("sample", "buffer"):
+        U_out = torch.empty_like(U_in)
+        costs = torch.empty((inp.K,), device=dev)
+        w = torch.empty((inp.K,), device=dev)
+        planner.plan_step(q0=inp.q0, qd0=inp.qd0, T_goal=inp.T_goal, grid=grid,
+                          origin=inp.origin, voxel=inp.voxel,
+                          noise=None if mode == "sample" else noise_buf, K=inp.K, H=inp.H,
+                          U_in=U_in, U_out=U_out, dt=inp.dt, lam=inp.lam, weights=inp.weights,
+                          costs_out=costs, weights_out=w, seed=seed, sigma=sigma)
+        torch.cuda.synchronize()
+        outs[mode] = [t.cpu().numpy() for t in (U_out, costs, w)]
+    planner.close()
+    for a, b in zip(outs["sample"], outs["buffer"]):
+        np.testing.assert_array_equal(a, b)
+    ref = oracle(inp, noise=ORNG.sample_noise(seed, inp.K, inp.H, sigma.astype(np.float64)))
+    assert_costs_close(outs["sample"][1].astype(np.float64), ref["S"])
+    assert_controls_close(outs["sample"][0].astype(np.float64), ref["U_star"])
+
+
+def test_grid_to_f16_bit_exact():
+    torch = _torch()
+    from paper_2512_22575_amd import smpc as S
+    rng = np.random.default_rng(5)
+    src = np.concatenate([rng.normal(scale=1.5, size=10000),
+                          [2.5, -3.0, 2.0, -2.0, 0.0, -0.0, 1e-8, 65504.0,
+                           1.0 + 2.0 ** -11, 1.0 + 3 * 2.0 ** -11]]).astype(np.float32)
+    d_src = torch.from_numpy(src).cuda()
+    d_dst = torch.zeros(src.size, dtype=torch.int16, device="cuda:0")
+    st = S.smpc_grid_to_f16(d_src.data_ptr(), d_dst.data_ptr(), src.size, 2.0,
+                            torch.cuda.current_stream().cuda_stream)
+    assert st == S.SMPC_OK
+    torch.cuda.synchronize()
+    got = d_dst.cpu().numpy().view(np.uint16)
+    ref = np.clip(src, -2.0, 2.0).astype(np.float16).view(np.uint16)
+    np.testing.assert_array_equal(got, ref)
+
+
+def f16_grid(grid):
+    return np.clip(grid, -2.0, 2.0).astype(np.float16)
+
+
+def run_f16(inp, grid16, **kw):
+    """run_gpu with the grid stored as float16 bit patterns."""
+    torch = _torch()
+    from paper_2512_22575_amd import smpc as S
+    dev = torch.device("cuda:0")
+    g = torch.from_numpy(grid16.view(np.int16).copy()).to(dev)
+    noise = torch.from_numpy(inp.noise).to(dev) if inp.noise is not None else None
+    U_in = torch.from_numpy(inp.U_bar).to(dev)
+    U_out = torch.empty_like(U_in)
+    costs = torch.empty((inp.K,), device=dev)
+    planner = S.Planner(inp.robot)
+    planner.plan_step(q0=inp.q0, qd0=inp.qd0, T_goal=inp.T_goal, grid=g, origin=inp.origin,
+                      voxel=inp.voxel, noise=noise, U_in=U_in, U_out=U_out, dt=inp.dt,
+                      lam=inp.lam, weights=inp.weights, costs_out=costs,
+                      grid_dtype=S.GRID_F16, **kw)
+    torch.cuda.synchronize()
+    planner.close()
+    return dict(U_star=U_out.cpu().numpy().astype(np.float64),
+                S=costs.cpu().numpy().astype(np.float64))
+
+
+def test_f16_grid_matches_oracle_on_decoded_grid():
+    inp = W.mid()
+    g16 = f16_grid(inp.grid)
+    got = run_f16(inp, g16)
+    ref = oracle(inp, grid=g16.astype(np.float64))
+    assert_costs_close(got["S"], ref["S"])
+    assert_controls_close(got["U_star"], ref["U_star"])
+
+
+def test_precision_variant_workload_reports_error_against_fp32_grid(capsys):
+    """Mid workload, float16 grid clamped to +-2 m, on-device sampling (seed 4, sigma 0.5)."""
+    inp = W.mid()
+    sigma = np.full(7, 0.5, np.float32)
+    g16 = f16_grid(inp.grid)
+    inp_s = dataclasses.replace(inp, noise=None)
+    got = run_f16(inp_s, g16, seed=4, sigma=sigma, K=inp.K, H=inp.H)
+    eps = ORNG.sample_noise(4, inp.K, inp.H, sigma.astype(np.float64))
+    ref16 = oracle(inp, grid=g16.astype(np.float64), noise=eps)
+    ref32 = oracle(inp, noise=eps)
+    assert_costs_close(got["S"], ref16["S"])
+    assert_controls_close(got["U_star"], ref16["U_star"])
+    rel32 = np.max(np.abs(got["S"] - ref32["S"]) / np.abs(ref32["S"]))
+    du32 = np.max(np.abs(got["U_star"] - ref32["U_star"]))
+    with capsys.disabled():
+        print(f"\n[f16 grid] max rel cost err vs fp32-grid oracle {rel32:.3g}, "
+              f"max |dU*| {du32:.3g}; vs decoded-grid oracle within "
+              f"{COST_RTOL:g} rel + {COST_ATOL:g}")
