@@ -219,6 +219,86 @@ smpc_status smpc_profile_enable(smpc_ctx* ctx, int32_t n_steps);
 smpc_status smpc_profile_read(smpc_ctx* ctx, float* rollout_ms, float* merge_ms,
                               int32_t capacity, int32_t* n_steps);
 
+/* ------------------------------------------------------------------------------
+ * Serving: many independent controllers, each with a resident distance grid and a
+ * resident warm-started nominal sequence, served by continuous batching.
+ *
+ * A request is one plan step of one controller from the joint state and target it
+ * carries; the disturbances are sampled on the device from the request's seed (see
+ * smpc_sample_noise).  The server keeps a FIFO queue; smpc_server_pump() retires
+ * finished batches and forms new ones from the queue in arrival order -- at most one
+ * request per controller per batch, and only while the batch's workspace fits in
+ * half of the HBM budget (a request that can never fit is refused at submit) -- and
+ * launches each batch as one rollout-cost launch and one merge launch covering all
+ * of its requests.  Up to two batches are in flight, so requests that arrive while
+ * one batch runs are admitted into the next, which is queued behind it on the device.
+ * After a step, the controller's nominal sequence becomes [u*_1 .. u*_{H-1}, 0]
+ * (receding horizon) and u*_0 is returned in the completion.  A request's result is
+ * bitwise the same whether it runs alone or in a batch.
+ * The server is not thread-safe; all its work runs on the stream given to pump.
+ * ------------------------------------------------------------------------------ */
+typedef struct smpc_server smpc_server;
+
+/* A controller: its grid (device memory owned by the caller, valid while the
+ * controller exists) and the constants of its plan steps.  The grid dtype must be
+ * the same for every controller of a server. */
+typedef struct {
+  smpc_grid esdf;
+  int32_t K, H;
+  float dt;
+  float lambda;
+  smpc_cost_weights weights;
+  float sigma[SMPC_NDOF];
+} smpc_controller_desc;
+
+typedef struct {
+  int64_t tag;        /* caller's identifier, returned in the completion */
+  int32_t controller; /* id from smpc_server_add_controller */
+  int32_t reserved;   /* must be 0 */
+  float q0[SMPC_NDOF];
+  float qd0[SMPC_NDOF];
+  float T_goal[16];
+  uint64_t seed;      /* sampling seed of this step */
+} smpc_request;
+
+typedef struct {
+  int64_t tag;
+  int32_t controller;
+  int32_t status;     /* SMPC_OK, or SMPC_E_NUMERIC when no rollout cost was finite */
+  float u0[SMPC_NDOF];/* u*_0, the control to execute */
+  float S_min, Z, ess;
+} smpc_completion;
+
+/* Device workspace bytes one plan step of K rollouts and horizon H uses (0 if the
+ * sizes are invalid); a server needs twice the largest of its controllers' values. */
+uint64_t smpc_plan_workspace_bytes(int32_t K, int32_t H);
+
+/* Create a server on `ctx` (which must hold the robot).  hbm_budget_bytes bounds the
+ * device memory of requests in flight; max_batch bounds requests per batch (>= 1). */
+smpc_status smpc_server_create(smpc_server** out, smpc_ctx* ctx, uint64_t hbm_budget_bytes,
+                               int32_t max_batch);
+/* Destroy a server (waits for its work).  NULL is a no-op. */
+void smpc_server_destroy(smpc_server* server);
+/* Register a controller; its nominal sequence starts at 0.  *id_out receives its id. */
+smpc_status smpc_server_add_controller(smpc_server* server, const smpc_controller_desc* desc,
+                                       int32_t* id_out);
+/* Set a controller's nominal sequence back to 0 (synchronous; no request of it may be
+ * queued or in flight). */
+smpc_status smpc_server_reset_controller(smpc_server* server, int32_t id);
+/* Queue a request (validated on the host; nothing is launched). */
+smpc_status smpc_server_submit(smpc_server* server, const smpc_request* request);
+/* Retire finished batches and launch new ones on `stream`; never waits for the device.
+ * *n_launched (optional) receives the number of requests launched by this call. */
+smpc_status smpc_server_pump(smpc_server* server, void* stream, int32_t* n_launched);
+/* Move up to `capacity` completions, oldest first, into `out`; *n_out receives the count. */
+smpc_status smpc_server_poll(smpc_server* server, smpc_completion* out, int32_t capacity,
+                             int32_t* n_out);
+/* Requests queued (not yet launched) and in flight (launched, not yet retired). */
+int32_t smpc_server_queued(const smpc_server* server);
+int32_t smpc_server_in_flight(const smpc_server* server);
+/* Detail of the last failure of a server call ("" if none). */
+const char* smpc_server_last_error(const smpc_server* server);
+
 /* Library version as major*10000 + minor*100 + patch. */
 int32_t smpc_version(void);
 

@@ -14,7 +14,7 @@ constexpr int kSpl = SMPC_SPHERES_PER_LINK;   // sphere slots per link
 constexpr int kSlots = kNdof * kSpl;          // slot s = (link - 1) * kSpl + j
 constexpr int kMaxPairs = SMPC_MAX_PAIRS;
 constexpr int kMaxH = SMPC_MAX_H;
-constexpr int kK1MaxThreads = 512;            // rollout-cost block size limit
+constexpr int kK1Threads = 320;               // rollout-cost block size (5 waves)
 constexpr int kK2Threads = 256;               // reduce/update block size
 constexpr int kWeightsPerWave = 1024;         // weights_out elements per wave in K2
 
@@ -79,6 +79,25 @@ struct Workspace {
   float* part_N;    // [P][HO4] sum_m exp(-(S - part_m)/lambda) eps^(m), HO4 = 7H padded to 4
 };
 
+// One plan step as the kernels see it (by value for a single step, in a device
+// array for a batch).
+struct Request {
+  StepParams p;
+  const void* grid;            // device distance grid
+  const float* noise;          // device [K][H][7], or null: sample on the device
+  const float* U_in;           // device [H][7]
+  float* U_out;                // device [H][7]
+  float* costs_out;            // device [K] or null
+  float* weights_out;          // device [K] or null
+  float* stats_out;            // device [4] or null
+  float* u0_out;               // device [7] or null (shift_out only)
+  Workspace ws;
+  int32_t k1_begin;            // first rollout-cost block of this request in a batch
+  int32_t k2_begin;            // first merge block of this request in a batch
+  int32_t shift_out;           // 1: U_out = [u*_1 .. u*_{H-1}, 0] and u0_out = u*_0
+  int32_t pad_;
+};
+
 struct LaunchConfig {
   int R;            // rollouts per K1 block
   int k1_threads;   // K1 block size (multiple of 64)
@@ -94,9 +113,14 @@ Workspace carve_workspace(void* base, int K, int H, int P);
 // Enqueue both kernels of one plan step.  Returns a hipError_t value (0 = success).
 // When `events` is non-null, events[0..2] (hipEvent_t) are recorded before the
 // rollout-cost kernel, between the kernels and after the merge kernel.
-int launch_plan_step(const DevRobot* robot, const StepParams& p, const LaunchConfig& lc,
-                     const Workspace& ws, const smpc_plan_args& args, void* stream,
-                     void* events);
+int launch_plan_step(const DevRobot* robot, const Request& q, const LaunchConfig& lc, bool f16,
+                     void* stream, void* events);
+
+// Enqueue both kernels for a batch of requests (device array `reqs`, block maps
+// k1_map [k1_blocks] and k2_map [k2_blocks] giving each block's request index).
+int launch_batch(const DevRobot* robot, const Request* reqs, const int32_t* k1_map,
+                 int k1_blocks, const int32_t* k2_map, int k2_blocks, size_t k1_lds, bool f16,
+                 void* stream);
 
 // Disturbances of the sampling mode written to memory (eps [K][H][7], words [K][H][8];
 // either may be null).  Returns a hipError_t value.

@@ -442,22 +442,25 @@ __device__ __forceinline__ K1Lds k1_lds(unsigned char* base, int R, int H) {
   return L;
 }
 
-template <int kElemBytes, bool kSample>
-__global__ __launch_bounds__(kK1MaxThreads) __attribute__((amdgpu_waves_per_eu(3))) void rollout_cost_kernel(
-    const DevRobot* __restrict__ rob, const StepParams p, const float* __restrict__ noise,
-    const float* __restrict__ U_in, const void* __restrict__ grid, Workspace ws) {
+// Rollout-cost work of block b (counted within its request) of request q.
+template <int kElemBytes>
+__device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ rob,
+                                                   const Request& q, int b) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
+  const StepParams& p = q.p;
+  const Workspace& ws = q.ws;
+  const float* __restrict__ noise = q.noise;
+  const float* __restrict__ U_in = q.U_in;
   const int H = p.H, R = p.R, RH = R * H;
   const K1Lds L = k1_lds(lds_raw, R, H);
   const int tid = threadIdx.x;
   const int nthreads = blockDim.x;
-  const int b = blockIdx.x;
   const int m0 = b * R;
   const int nroll = min(R, p.K - m0);
 
   // Stage this block's disturbances (contiguous [nroll][H][7]) and the nominal sequence:
   // read them, or sample them here (one (rollout, step) item per thread).
-  if constexpr (kSample) {
+  if (noise == nullptr) {
     for (int t = tid; t < RH; t += nthreads) {
       const int r = t / H, k = t - r * H;
       float z[8];
@@ -531,7 +534,7 @@ __global__ __launch_bounds__(kK1MaxThreads) __attribute__((amdgpu_waves_per_eu(3
         qd[j] = L.qd[base + j];
         u[j] = L.ubar[k * kNdof + j] + L.eps[base + j];
       }
-      const __amdgpu_buffer_rsrc_t rsrc = grid_resource(grid, p.grid_bytes);
+      const __amdgpu_buffer_rsrc_t rsrc = grid_resource(q.grid, p.grid_bytes);
       cost = step_cost<kElemBytes>(rob, p, rsrc, L.sc0, dq, qd, u, k == H - 1);
     }
     L.cost[tid] = cost;
@@ -587,6 +590,22 @@ __global__ __launch_bounds__(kK1MaxThreads) __attribute__((amdgpu_waves_per_eu(3
     }
     ws.part_N[(size_t)b * HO4 + o] = acc;
   }
+}
+
+// One plan step: the request travels by value in the kernel arguments.
+template <int kElemBytes>
+__global__ __launch_bounds__(kK1Threads) __attribute__((amdgpu_waves_per_eu(3))) void
+rollout_cost_kernel(const DevRobot* __restrict__ rob, const Request q) {
+  rollout_cost_block<kElemBytes>(rob, q, blockIdx.x);
+}
+
+// A batch of plan steps: block_req maps each block to its request.
+template <int kElemBytes>
+__global__ __launch_bounds__(kK1Threads) __attribute__((amdgpu_waves_per_eu(3))) void
+rollout_cost_batch_kernel(const DevRobot* __restrict__ rob, const Request* __restrict__ reqs,
+                          const int32_t* __restrict__ block_req) {
+  const Request& q = reqs[block_req[blockIdx.x]];
+  rollout_cost_block<kElemBytes>(rob, q, (int)blockIdx.x - q.k1_begin);
 }
 
 // ---------------------------------------------------------------------------
@@ -694,10 +713,16 @@ __device__ __forceinline__ MergeStats merge_partials(const Workspace& ws, int P,
 constexpr int kCostsPerThread = 32;   // K <= kK2Threads * kCostsPerThread per pass
 
 template <int kElemBytes>
-__global__ __launch_bounds__(kK2Threads) void merge_kernel(
-    const DevRobot* __restrict__ rob, const StepParams p, const float* U_in, float* U_out,
-    const void* __restrict__ grid, Workspace ws, float* __restrict__ costs_out,
-    float* __restrict__ weights_out, float* __restrict__ stats_out) {
+__device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, const Request& q,
+                                            int kb) {
+  const StepParams& p = q.p;
+  const Workspace& ws = q.ws;
+  const void* grid = q.grid;
+  const float* U_in = q.U_in;
+  float* U_out = q.U_out;
+  float* __restrict__ costs_out = q.costs_out;
+  float* __restrict__ weights_out = q.weights_out;
+  float* __restrict__ stats_out = q.stats_out;
   __shared__ float centres[kSlots * 4];
   __shared__ float sc0[2 * kNdof];
   __shared__ float red[kK2Threads / kWave];
@@ -707,7 +732,7 @@ __global__ __launch_bounds__(kK2Threads) void merge_kernel(
   const int K = p.K, P = p.P, HO = p.H * kNdof, HO4 = (HO + 3) & ~3;
   const int n_merge = HO4 / 4;  // merge waves, 4 outputs each
 
-  if (blockIdx.x == 0) {
+  if (kb == 0) {
     // --- independent fetches first
     const bool has_pair = tid < rob->n_pairs;
     float4 pr = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -790,7 +815,7 @@ __global__ __launch_bounds__(kK2Threads) void merge_kernel(
     return;
   }
 
-  const int wave = (blockIdx.x - 1) * (kK2Threads / kWave) + (threadIdx.x / kWave);
+  const int wave = (kb - 1) * (kK2Threads / kWave) + (threadIdx.x / kWave);
   const int n_chunks = weights_out ? (K + kWeightsPerWave - 1) / kWeightsPerWave : 0;
   if (wave >= n_merge + n_chunks) return;
   const bool is_chunk = wave >= n_merge;
@@ -816,7 +841,20 @@ __global__ __launch_bounds__(kK2Threads) void merge_kernel(
     if (lane < 4) {
       const int o = o4 + lane;
       const float n = lane == 0 ? st.N.x : lane == 1 ? st.N.y : lane == 2 ? st.N.z : st.N.w;
-      if (o < HO) U_out[o] = ok ? U_in[o] + n / st.Z : U_in[o];
+      if (o < HO) {
+        const float u = ok ? U_in[o] + n / st.Z : U_in[o];
+        if (!q.shift_out) {
+          U_out[o] = u;
+        } else {
+          // Receding-horizon warm start: U_out = [u*_1 .. u*_{H-1}, 0], u0_out = u*_0.
+          if (o < kNdof) {
+            if (q.u0_out) q.u0_out[o] = u;
+          } else {
+            U_out[o - kNdof] = u;
+          }
+          if (o >= HO - kNdof) U_out[o] = 0.f;
+        }
+      }
     }
     return;
   }
@@ -830,6 +868,20 @@ __global__ __launch_bounds__(kK2Threads) void merge_kernel(
     if (ok && isfinite(sv[c])) w = expf(-(float)(sv[c] - st.m) * p.inv_lambda) * invZ;
     weights_out[i] = w;
   }
+}
+
+template <int kElemBytes>
+__global__ __launch_bounds__(kK2Threads) void merge_kernel(const DevRobot* __restrict__ rob,
+                                                           const Request q) {
+  merge_block<kElemBytes>(rob, q, blockIdx.x);
+}
+
+template <int kElemBytes>
+__global__ __launch_bounds__(kK2Threads) void merge_batch_kernel(
+    const DevRobot* __restrict__ rob, const Request* __restrict__ reqs,
+    const int32_t* __restrict__ block_req) {
+  const Request& q = reqs[block_req[blockIdx.x]];
+  merge_block<kElemBytes>(rob, q, (int)blockIdx.x - q.k2_begin);
 }
 
 // The disturbances of the sampling mode, for inspection: eps [K][H][7] and the raw
@@ -878,26 +930,17 @@ static size_t k1_lds_bytes(int R, int H) {
 }
 
 LaunchConfig plan_launch_config(int K, int H) {
-  // Rollouts per block: whole rollouts only, at most kK1MaxThreads threads; pick the
-  // fewest idle lanes in the 64-padded block, then the block size closest to 256.
-  int bestR = 1;
-  double best_waste = 2.0;
-  int best_dist = 1 << 30;
-  for (int R = 1; R * H <= kK1MaxThreads; ++R) {
-    const int threads = (R * H + kWave - 1) / kWave * kWave;
-    const double waste = (double)(threads - R * H) / threads;
-    const int dist = threads > 256 ? threads - 256 : 256 - threads;
-    if (waste < best_waste - 1e-12 || (waste < best_waste + 1e-12 && dist < best_dist)) {
-      best_waste = waste;
-      best_dist = dist;
-      bestR = R;
-    }
-  }
+  // Every block has kK1Threads threads and holds R = kK1Threads / H whole rollouts
+  // (at most 64), whatever else shares the launch: a request's arithmetic is the
+  // same alone and in a batch.  320 = 5 waves fits H = 16, 32, 40 and 64 exactly.
+  int R = kK1Threads / H;
+  if (R > 64) R = 64;
+  if (R < 1) R = 1;
   LaunchConfig lc;
-  lc.R = bestR;
-  lc.k1_threads = (bestR * H + kWave - 1) / kWave * kWave;
-  lc.P = (K + bestR - 1) / bestR;
-  lc.k1_lds = k1_lds_bytes(bestR, H);
+  lc.R = R;
+  lc.k1_threads = kK1Threads;
+  lc.P = (K + R - 1) / R;
+  lc.k1_lds = k1_lds_bytes(R, H);
   const int waves_per_block = kK2Threads / kWave;
   const int HO4 = (H * kNdof + 3) & ~3;
   const int work_waves = HO4 / 4 + (K + kWeightsPerWave - 1) / kWeightsPerWave;
@@ -929,28 +972,34 @@ Workspace carve_workspace(void* base, int K, int H, int P) {
   return ws;
 }
 
-int launch_plan_step(const DevRobot* robot, const StepParams& p, const LaunchConfig& lc,
-                     const Workspace& ws, const smpc_plan_args& args, void* stream,
-                     void* events) {
+int launch_plan_step(const DevRobot* robot, const Request& q, const LaunchConfig& lc,
+                     bool f16, void* stream, void* events) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipEvent_t* ev = static_cast<hipEvent_t*>(events);
   hipError_t e;
   if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return (int)e;
-  const bool f16 = args.esdf.dtype == SMPC_GRID_F16;
-  const bool sample = args.noise == nullptr;
-  auto k1 = f16 ? (sample ? rollout_cost_kernel<2, true> : rollout_cost_kernel<2, false>)
-                : (sample ? rollout_cost_kernel<4, true> : rollout_cost_kernel<4, false>);
-  hipLaunchKernelGGL(k1, dim3(lc.P), dim3(lc.k1_threads), lc.k1_lds, s, robot, p, args.noise,
-                     args.U_in, args.esdf.data, ws);
+  auto k1 = f16 ? rollout_cost_kernel<2> : rollout_cost_kernel<4>;
+  hipLaunchKernelGGL(k1, dim3(lc.P), dim3(lc.k1_threads), lc.k1_lds, s, robot, q);
   if ((e = hipGetLastError()) != hipSuccess) return (int)e;
   if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return (int)e;
   auto k2 = f16 ? merge_kernel<2> : merge_kernel<4>;
-  hipLaunchKernelGGL(k2, dim3(lc.k2_blocks), dim3(kK2Threads), 0, s, robot, p,
-                     args.U_in, args.U_out, args.esdf.data, ws, args.costs_out, args.weights_out,
-                     args.stats_out);
+  hipLaunchKernelGGL(k2, dim3(lc.k2_blocks), dim3(kK2Threads), 0, s, robot, q);
   if ((e = hipGetLastError()) != hipSuccess) return (int)e;
   if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return (int)e;
   return 0;
+}
+
+int launch_batch(const DevRobot* robot, const Request* reqs, const int32_t* k1_map,
+                 int k1_blocks, const int32_t* k2_map, int k2_blocks, size_t k1_lds, bool f16,
+                 void* stream) {
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  auto k1 = f16 ? rollout_cost_batch_kernel<2> : rollout_cost_batch_kernel<4>;
+  hipLaunchKernelGGL(k1, dim3(k1_blocks), dim3(kK1Threads), k1_lds, s, robot, reqs, k1_map);
+  if ((e = hipGetLastError()) != hipSuccess) return (int)e;
+  auto k2 = f16 ? merge_batch_kernel<2> : merge_batch_kernel<4>;
+  hipLaunchKernelGGL(k2, dim3(k2_blocks), dim3(kK2Threads), 0, s, robot, reqs, k2_map);
+  return (int)hipGetLastError();
 }
 
 int launch_sample_noise(uint64_t seed, int K, int H, const float* sigma, float* eps,

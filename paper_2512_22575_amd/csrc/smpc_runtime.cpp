@@ -12,6 +12,7 @@
 #include <new>
 #include <string>
 #include <algorithm>
+#include <deque>
 #include <utility>
 #include <vector>
 
@@ -239,6 +240,25 @@ StepParams make_params(const smpc_ctx* ctx, const smpc_plan_args* a, const Launc
   return p;
 }
 
+// Allocates the device robot buffer if needed and uploads a changed robot.  The
+// caller has made the context's device current.
+smpc_status ensure_device_robot(smpc_ctx* ctx) {
+  if (!ctx->dev_robot &&
+      hipMalloc(reinterpret_cast<void**>(&ctx->dev_robot), sizeof(DevRobot)) != hipSuccess) {
+    ctx->dev_robot = nullptr;
+    return fail(ctx, SMPC_E_OOM, "robot buffer allocation failed");
+  }
+  if (ctx->robot_dirty) {
+    // Synchronous, so it is ordered before every later launch and the host copy may
+    // change afterwards.
+    if (hipMemcpy(ctx->dev_robot, &ctx->host_robot, sizeof(DevRobot),
+                  hipMemcpyHostToDevice) != hipSuccess)
+      return fail(ctx, SMPC_E_DEVICE, "robot upload failed");
+    ctx->robot_dirty = false;
+  }
+  return SMPC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -402,19 +422,8 @@ smpc_status smpc_plan_step(smpc_ctx* ctx, const smpc_plan_args* a, void* stream)
 
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(ctx, SMPC_E_DEVICE, "hipSetDevice(%d) failed", ctx->device);
-  if (!ctx->dev_robot &&
-      hipMalloc(reinterpret_cast<void**>(&ctx->dev_robot), sizeof(DevRobot)) != hipSuccess) {
-    ctx->dev_robot = nullptr;
-    return fail(ctx, SMPC_E_OOM, "robot buffer allocation failed");
-  }
-  if (ctx->robot_dirty) {
-    // Ordered before this step's kernels on `stream`; synchronous so the host copy
-    // may change afterwards.
-    if (hipMemcpy(ctx->dev_robot, &ctx->host_robot, sizeof(DevRobot),
-                  hipMemcpyHostToDevice) != hipSuccess)
-      return fail(ctx, SMPC_E_DEVICE, "robot upload failed");
-    ctx->robot_dirty = false;
-  }
+  const smpc_status rs = ensure_device_robot(ctx);
+  if (rs != SMPC_OK) return rs;
   const size_t need = workspace_bytes(a->K, a->H, lc.P);
   if (need > ctx->workspace_bytes) {
     // Grow-only arena.  hipFree waits for outstanding work that may use the old one.
@@ -430,7 +439,18 @@ smpc_status smpc_plan_step(smpc_ctx* ctx, const smpc_plan_args* a, void* stream)
   const Workspace ws = carve_workspace(ctx->workspace, a->K, a->H, lc.P);
   hipEvent_t* ev = nullptr;
   if (ctx->prof_recorded < ctx->prof_capacity) ev = &ctx->prof_events[3 * ctx->prof_recorded++];
-  const int e = launch_plan_step(ctx->dev_robot, p, lc, ws, *a, stream, ev);
+  Request q;
+  std::memset(&q, 0, sizeof q);
+  q.p = p;
+  q.grid = a->esdf.data;
+  q.noise = a->noise;
+  q.U_in = a->U_in;
+  q.U_out = a->U_out;
+  q.costs_out = a->costs_out;
+  q.weights_out = a->weights_out;
+  q.stats_out = a->stats_out;
+  q.ws = ws;
+  const int e = launch_plan_step(ctx->dev_robot, q, lc, a->esdf.dtype == SMPC_GRID_F16, stream, ev);
   if (e != 0)
     return fail(ctx, SMPC_E_DEVICE, "kernel launch failed: %s",
                 hipGetErrorString(static_cast<hipError_t>(e)));
@@ -496,6 +516,393 @@ smpc_status smpc_profile_read(smpc_ctx* ctx, float* rollout_ms, float* merge_ms,
   *n_steps = n;
   ctx->prof_recorded = 0;
   return SMPC_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Serving
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr int kResultStride = 12;  // floats per request: u0[7], stats[4], pad
+
+struct Controller {
+  smpc_controller_desc desc;
+  LaunchConfig lc;
+  size_t ws_bytes = 0;
+  float* ubar[2] = {nullptr, nullptr};  // device [H][7] ping-pong
+  int cur = 0;                          // buffer holding the current nominal sequence
+  int queued = 0;                       // requests queued or in flight
+};
+
+struct BatchSlot {
+  int n = 0;                            // requests in the batch (0: slot free)
+  std::vector<int64_t> tags;
+  std::vector<int32_t> ctls;
+  hipEvent_t done = nullptr;
+  void* ws = nullptr;                   // half of the budget
+  size_t req_cap = 0, map_cap = 0;
+  Request* h_reqs = nullptr;            // pinned
+  Request* d_reqs = nullptr;
+  int32_t* h_maps = nullptr;            // pinned [k1 blocks + k2 blocks]
+  int32_t* d_maps = nullptr;
+  float* h_res = nullptr;               // pinned [req_cap * kResultStride]
+  float* d_res = nullptr;
+};
+
+}  // namespace
+
+struct smpc_server {
+  smpc_ctx* ctx = nullptr;
+  size_t budget = 0;
+  int max_batch = 1;
+  int elem_dtype = -1;
+  std::vector<Controller> ctl;
+  std::deque<smpc_request> queue;
+  std::deque<smpc_completion> done;
+  BatchSlot slot[2];
+  int oldest = 0;                       // slot of the oldest batch in flight
+  int n_in_flight = 0;                  // batches in flight
+  std::string last_error;
+};
+
+namespace {
+
+smpc_status sfail(smpc_server* s, smpc_status st, const std::string& msg) {
+  s->last_error = msg;
+  return st;
+}
+
+void free_slot(BatchSlot& b) {
+  if (b.done) (void)hipEventDestroy(b.done);
+  if (b.ws) (void)hipFree(b.ws);
+  if (b.d_reqs) (void)hipFree(b.d_reqs);
+  if (b.d_maps) (void)hipFree(b.d_maps);
+  if (b.d_res) (void)hipFree(b.d_res);
+  if (b.h_reqs) (void)hipHostFree(b.h_reqs);
+  if (b.h_maps) (void)hipHostFree(b.h_maps);
+  if (b.h_res) (void)hipHostFree(b.h_res);
+  b = BatchSlot();
+}
+
+// Grow a slot's descriptor, map and result buffers (only while the slot is free).
+bool reserve_slot(BatchSlot& b, size_t reqs, size_t maps) {
+  if (reqs > b.req_cap) {
+    if (b.h_reqs) (void)hipHostFree(b.h_reqs);
+    if (b.d_reqs) (void)hipFree(b.d_reqs);
+    if (b.h_res) (void)hipHostFree(b.h_res);
+    if (b.d_res) (void)hipFree(b.d_res);
+    b.h_reqs = nullptr;
+    b.d_reqs = nullptr;
+    b.h_res = nullptr;
+    b.d_res = nullptr;
+    b.req_cap = 0;
+    if (hipHostMalloc(reinterpret_cast<void**>(&b.h_reqs), reqs * sizeof(Request)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&b.d_reqs), reqs * sizeof(Request)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&b.h_res), reqs * kResultStride * 4) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&b.d_res), reqs * kResultStride * 4) != hipSuccess)
+      return false;
+    b.req_cap = reqs;
+  }
+  if (maps > b.map_cap) {
+    if (b.h_maps) (void)hipHostFree(b.h_maps);
+    if (b.d_maps) (void)hipFree(b.d_maps);
+    b.h_maps = nullptr;
+    b.d_maps = nullptr;
+    b.map_cap = 0;
+    if (hipHostMalloc(reinterpret_cast<void**>(&b.h_maps), maps * 4) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&b.d_maps), maps * 4) != hipSuccess)
+      return false;
+    b.map_cap = maps;
+  }
+  return true;
+}
+
+// The plan-step arguments of request r for controller c (sampling mode).
+smpc_plan_args request_args(const Controller& c, const smpc_request& r) {
+  smpc_plan_args a;
+  std::memset(&a, 0, sizeof a);
+  std::memcpy(a.q0, r.q0, sizeof a.q0);
+  std::memcpy(a.qd0, r.qd0, sizeof a.qd0);
+  std::memcpy(a.T_goal, r.T_goal, sizeof a.T_goal);
+  a.esdf = c.desc.esdf;
+  a.noise = nullptr;
+  a.seed = r.seed;
+  std::memcpy(a.sigma, c.desc.sigma, sizeof a.sigma);
+  a.K = c.desc.K;
+  a.H = c.desc.H;
+  a.dt = c.desc.dt;
+  a.lambda = c.desc.lambda;
+  a.weights = c.desc.weights;
+  a.U_in = c.ubar[c.cur];
+  a.U_out = c.ubar[1 - c.cur];
+  return a;
+}
+
+// Retire finished batches, oldest first.
+smpc_status retire(smpc_server* s) {
+  while (s->n_in_flight > 0) {
+    BatchSlot& b = s->slot[s->oldest];
+    const hipError_t q = hipEventQuery(b.done);
+    if (q == hipErrorNotReady) break;
+    if (q != hipSuccess) return sfail(s, SMPC_E_DEVICE, "batch event query failed");
+    for (int i = 0; i < b.n; ++i) {
+      const float* r = b.h_res + (size_t)i * kResultStride;
+      smpc_completion c;
+      c.tag = b.tags[i];
+      c.controller = b.ctls[i];
+      c.status = r[kNdof + 3] == 0.f ? SMPC_OK : SMPC_E_NUMERIC;
+      std::memcpy(c.u0, r, sizeof c.u0);
+      c.S_min = r[kNdof + 0];
+      c.Z = r[kNdof + 1];
+      c.ess = r[kNdof + 2];
+      s->done.push_back(c);
+      --s->ctl[b.ctls[i]].queued;
+    }
+    b.n = 0;
+    s->oldest ^= 1;
+    --s->n_in_flight;
+  }
+  return SMPC_OK;
+}
+
+// Form and launch one batch in the free slot; returns the number of requests launched.
+smpc_status launch_next(smpc_server* s, void* stream, int* launched) {
+  *launched = 0;
+  const int si = (s->oldest + s->n_in_flight) & 1;
+  BatchSlot& b = s->slot[si];
+  const size_t half = s->budget / 2;
+  std::vector<int> take;
+  std::vector<size_t> ws_off;
+  std::vector<char> used(s->ctl.size(), 0);
+  size_t ws_total = 0, k1_total = 0, k2_total = 0;
+  for (size_t i = 0; i < s->queue.size() && (int)take.size() < s->max_batch; ++i) {
+    const smpc_request& r = s->queue[i];
+    const Controller& c = s->ctl[r.controller];
+    if (used[r.controller]) continue;           // one request per controller per batch
+    const size_t need = (c.ws_bytes + 255) & ~size_t(255);
+    if (ws_total + need > half) continue;        // waits for memory
+    used[r.controller] = 1;
+    take.push_back((int)i);
+    ws_off.push_back(ws_total);
+    ws_total += need;
+    k1_total += (size_t)c.lc.P;
+    k2_total += (size_t)c.lc.k2_blocks;
+  }
+  if (take.empty()) return SMPC_OK;
+  if (!reserve_slot(b, (size_t)s->max_batch, k1_total + k2_total))
+    return sfail(s, SMPC_E_OOM, "batch buffer allocation failed");
+
+  size_t lds = 0;
+  int k1 = 0, k2 = 0;
+  b.tags.assign(take.size(), 0);
+  b.ctls.assign(take.size(), 0);
+  for (size_t t = 0; t < take.size(); ++t) {
+    const smpc_request& r = s->queue[take[t]];
+    Controller& c = s->ctl[r.controller];
+    const smpc_plan_args a = request_args(c, r);
+    Request& q = b.h_reqs[t];
+    std::memset(&q, 0, sizeof q);
+    q.p = make_params(s->ctx, &a, c.lc);
+    q.grid = a.esdf.data;
+    q.noise = nullptr;
+    q.U_in = a.U_in;
+    q.U_out = a.U_out;
+    q.u0_out = b.d_res + t * kResultStride;
+    q.stats_out = b.d_res + t * kResultStride + kNdof;
+    q.ws = carve_workspace(static_cast<unsigned char*>(b.ws) + ws_off[t], c.desc.K, c.desc.H,
+                           c.lc.P);
+    q.k1_begin = k1;
+    q.k2_begin = k2;
+    q.shift_out = 1;
+    for (int j = 0; j < c.lc.P; ++j) b.h_maps[k1 + j] = (int32_t)t;
+    for (int j = 0; j < c.lc.k2_blocks; ++j) b.h_maps[k1_total + k2 + j] = (int32_t)t;
+    k1 += c.lc.P;
+    k2 += c.lc.k2_blocks;
+    lds = std::max(lds, c.lc.k1_lds);
+    c.cur ^= 1;  // the next request of this controller reads this step's result
+    b.tags[t] = r.tag;
+    b.ctls[t] = r.controller;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (hipMemcpyAsync(b.d_reqs, b.h_reqs, take.size() * sizeof(Request), hipMemcpyHostToDevice,
+                     st) != hipSuccess ||
+      hipMemcpyAsync(b.d_maps, b.h_maps, (k1_total + k2_total) * 4, hipMemcpyHostToDevice, st) !=
+          hipSuccess)
+    return sfail(s, SMPC_E_DEVICE, "descriptor upload failed");
+  const int e = launch_batch(s->ctx->dev_robot, b.d_reqs, b.d_maps, (int)k1_total,
+                             b.d_maps + k1_total, (int)k2_total, lds,
+                             s->elem_dtype == SMPC_GRID_F16, stream);
+  if (e != 0) return sfail(s, SMPC_E_DEVICE, std::string("batch launch failed: ") +
+                                                 hipGetErrorString(static_cast<hipError_t>(e)));
+  if (hipMemcpyAsync(b.h_res, b.d_res, take.size() * kResultStride * 4, hipMemcpyDeviceToHost,
+                     st) != hipSuccess ||
+      hipEventRecord(b.done, st) != hipSuccess)
+    return sfail(s, SMPC_E_DEVICE, "result download failed");
+  b.n = (int)take.size();
+  for (int t = (int)take.size() - 1; t >= 0; --t) s->queue.erase(s->queue.begin() + take[t]);
+  ++s->n_in_flight;
+  *launched = (int)take.size();
+  return SMPC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t smpc_plan_workspace_bytes(int32_t K, int32_t H) {
+  if (K < 1 || H < 1 || H > kMaxH) return 0;
+  const LaunchConfig lc = plan_launch_config(K, H);
+  return (uint64_t)((workspace_bytes(K, H, lc.P) + 255) & ~size_t(255));
+}
+
+smpc_status smpc_server_create(smpc_server** out, smpc_ctx* ctx, uint64_t hbm_budget_bytes,
+                               int32_t max_batch) {
+  if (!out) return SMPC_E_INVALID_ARG;
+  *out = nullptr;
+  if (!ctx || max_batch < 1 || hbm_budget_bytes < 4096) return SMPC_E_INVALID_ARG;
+  if (!ctx->robot_set) return fail(ctx, SMPC_E_INVALID_ARG, "server: no robot set");
+  smpc_server* s = new (std::nothrow) smpc_server();
+  if (!s) return SMPC_E_OOM;
+  s->ctx = ctx;
+  s->budget = (size_t)hbm_budget_bytes & ~size_t(511);
+  s->max_batch = max_batch;
+  DeviceGuard g(ctx->device);
+  if (!g.ok || ensure_device_robot(ctx) != SMPC_OK) {
+    delete s;
+    return SMPC_E_DEVICE;
+  }
+  for (BatchSlot& b : s->slot) {
+    if (hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess ||
+        hipMalloc(&b.ws, s->budget / 2) != hipSuccess) {
+      for (BatchSlot& c : s->slot) free_slot(c);
+      delete s;
+      return SMPC_E_OOM;
+    }
+  }
+  *out = s;
+  return SMPC_OK;
+}
+
+void smpc_server_destroy(smpc_server* s) {
+  if (!s) return;
+  DeviceGuard g(s->ctx->device);
+  (void)hipDeviceSynchronize();
+  for (BatchSlot& b : s->slot) free_slot(b);
+  for (Controller& c : s->ctl)
+    for (float* u : c.ubar)
+      if (u) (void)hipFree(u);
+  delete s;
+}
+
+smpc_status smpc_server_add_controller(smpc_server* s, const smpc_controller_desc* d,
+                                       int32_t* id_out) {
+  if (!s) return SMPC_E_INVALID_ARG;
+  s->last_error.clear();
+  if (!d || !id_out) return sfail(s, SMPC_E_INVALID_ARG, "null argument");
+  if (s->elem_dtype >= 0 && d->esdf.dtype != s->elem_dtype)
+    return sfail(s, SMPC_E_UNSUPPORTED, "all controllers of a server share one grid dtype");
+  Controller c;
+  c.desc = *d;
+  // Validate like a plan step of this controller (with placeholder buffers).
+  smpc_request probe;
+  std::memset(&probe, 0, sizeof probe);
+  for (int j = 0; j < kNdof; ++j) probe.q0[j] = 0.f;
+  probe.T_goal[0] = probe.T_goal[5] = probe.T_goal[10] = probe.T_goal[15] = 1.f;
+  float dummy;
+  c.ubar[0] = c.ubar[1] = &dummy;
+  const smpc_plan_args a = request_args(c, probe);
+  if (validate_args(s->ctx, &a) != SMPC_OK)
+    return sfail(s, SMPC_E_INVALID_ARG, std::string("controller: ") + s->ctx->last_error);
+  c.lc = plan_launch_config(d->K, d->H);
+  c.ws_bytes = workspace_bytes(d->K, d->H, c.lc.P);
+  if (((c.ws_bytes + 255) & ~size_t(255)) > s->budget / 2)
+    return sfail(s, SMPC_E_OOM, "controller workspace exceeds half the HBM budget");
+  DeviceGuard g(s->ctx->device);
+  const size_t ub = (size_t)d->H * kNdof * sizeof(float);
+  c.ubar[0] = c.ubar[1] = nullptr;
+  for (float*& u : c.ubar) {
+    if (hipMalloc(reinterpret_cast<void**>(&u), ub) != hipSuccess ||
+        hipMemset(u, 0, ub) != hipSuccess)
+      return sfail(s, SMPC_E_OOM, "controller buffers");
+  }
+  s->elem_dtype = d->esdf.dtype;
+  s->ctl.push_back(c);
+  *id_out = (int32_t)s->ctl.size() - 1;
+  return SMPC_OK;
+}
+
+smpc_status smpc_server_reset_controller(smpc_server* s, int32_t id) {
+  if (!s) return SMPC_E_INVALID_ARG;
+  if (id < 0 || id >= (int32_t)s->ctl.size()) return sfail(s, SMPC_E_INVALID_ARG, "bad id");
+  Controller& c = s->ctl[id];
+  if (c.queued) return sfail(s, SMPC_E_INVALID_ARG, "controller has requests outstanding");
+  DeviceGuard g(s->ctx->device);
+  const size_t ub = (size_t)c.desc.H * kNdof * sizeof(float);
+  if (hipMemset(c.ubar[c.cur], 0, ub) != hipSuccess)
+    return sfail(s, SMPC_E_DEVICE, "reset failed");
+  return SMPC_OK;
+}
+
+smpc_status smpc_server_submit(smpc_server* s, const smpc_request* r) {
+  if (!s) return SMPC_E_INVALID_ARG;
+  s->last_error.clear();
+  if (!r) return sfail(s, SMPC_E_INVALID_ARG, "null request");
+  if (r->controller < 0 || r->controller >= (int32_t)s->ctl.size() || r->reserved != 0)
+    return sfail(s, SMPC_E_INVALID_ARG, "bad controller id");
+  Controller& c = s->ctl[r->controller];
+  const smpc_plan_args a = request_args(c, *r);
+  if (validate_args(s->ctx, &a) != SMPC_OK)
+    return sfail(s, SMPC_E_INVALID_ARG, std::string("request: ") + s->ctx->last_error);
+  s->queue.push_back(*r);
+  ++c.queued;
+  return SMPC_OK;
+}
+
+smpc_status smpc_server_pump(smpc_server* s, void* stream, int32_t* n_launched) {
+  if (!s) return SMPC_E_INVALID_ARG;
+  if (n_launched) *n_launched = 0;
+  DeviceGuard g(s->ctx->device);
+  if (!g.ok) return sfail(s, SMPC_E_DEVICE, "hipSetDevice failed");
+  smpc_status st = retire(s);
+  if (st != SMPC_OK) return st;
+  int total = 0;
+  while (s->n_in_flight < 2 && !s->queue.empty()) {
+    int n = 0;
+    st = launch_next(s, stream, &n);
+    if (st != SMPC_OK) return st;
+    if (n == 0) break;
+    total += n;
+  }
+  if (n_launched) *n_launched = total;
+  return SMPC_OK;
+}
+
+smpc_status smpc_server_poll(smpc_server* s, smpc_completion* out, int32_t capacity,
+                             int32_t* n_out) {
+  if (!s || !n_out || capacity < 0 || (capacity > 0 && !out)) return SMPC_E_INVALID_ARG;
+  int n = 0;
+  while (n < capacity && !s->done.empty()) {
+    out[n++] = s->done.front();
+    s->done.pop_front();
+  }
+  *n_out = n;
+  return SMPC_OK;
+}
+
+int32_t smpc_server_queued(const smpc_server* s) { return s ? (int32_t)s->queue.size() : 0; }
+
+int32_t smpc_server_in_flight(const smpc_server* s) {
+  if (!s) return 0;
+  int n = 0;
+  for (int i = 0; i < s->n_in_flight; ++i) n += s->slot[(s->oldest + i) & 1].n;
+  return n;
+}
+
+const char* smpc_server_last_error(const smpc_server* s) {
+  return s ? s->last_error.c_str() : "null server";
 }
 
 }  // extern "C"

@@ -84,6 +84,35 @@ class smpc_plan_args(ctypes.Structure):
     ]
 
 
+class smpc_controller_desc(ctypes.Structure):
+    _fields_ = [
+        ("esdf", smpc_grid),
+        ("K", c_int32), ("H", c_int32),
+        ("dt", c_float), ("lambda_", c_float),
+        ("weights", smpc_cost_weights),
+        ("sigma", c_float * NDOF),
+    ]
+
+
+class smpc_request(ctypes.Structure):
+    _fields_ = [
+        ("tag", ctypes.c_int64),
+        ("controller", c_int32), ("reserved", c_int32),
+        ("q0", c_float * NDOF), ("qd0", c_float * NDOF),
+        ("T_goal", c_float * 16),
+        ("seed", c_uint64),
+    ]
+
+
+class smpc_completion(ctypes.Structure):
+    _fields_ = [
+        ("tag", ctypes.c_int64),
+        ("controller", c_int32), ("status", c_int32),
+        ("u0", c_float * NDOF),
+        ("S_min", c_float), ("Z", c_float), ("ess", c_float),
+    ]
+
+
 _lib = None
 
 
@@ -114,6 +143,29 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.smpc_sample_noise.restype = c_int32
     lib.smpc_grid_to_f16.argtypes = [c_void_p, c_void_p, ctypes.c_int64, c_float, c_void_p]
     lib.smpc_grid_to_f16.restype = c_int32
+    lib.smpc_plan_workspace_bytes.argtypes = [c_int32, c_int32]
+    lib.smpc_plan_workspace_bytes.restype = c_uint64
+    lib.smpc_server_create.argtypes = [POINTER(c_void_p), c_void_p, c_uint64, c_int32]
+    lib.smpc_server_create.restype = c_int32
+    lib.smpc_server_destroy.argtypes = [c_void_p]
+    lib.smpc_server_destroy.restype = None
+    lib.smpc_server_add_controller.argtypes = [c_void_p, POINTER(smpc_controller_desc),
+                                               POINTER(c_int32)]
+    lib.smpc_server_add_controller.restype = c_int32
+    lib.smpc_server_reset_controller.argtypes = [c_void_p, c_int32]
+    lib.smpc_server_reset_controller.restype = c_int32
+    lib.smpc_server_submit.argtypes = [c_void_p, POINTER(smpc_request)]
+    lib.smpc_server_submit.restype = c_int32
+    lib.smpc_server_pump.argtypes = [c_void_p, c_void_p, POINTER(c_int32)]
+    lib.smpc_server_pump.restype = c_int32
+    lib.smpc_server_poll.argtypes = [c_void_p, POINTER(smpc_completion), c_int32, POINTER(c_int32)]
+    lib.smpc_server_poll.restype = c_int32
+    lib.smpc_server_queued.argtypes = [c_void_p]
+    lib.smpc_server_queued.restype = c_int32
+    lib.smpc_server_in_flight.argtypes = [c_void_p]
+    lib.smpc_server_in_flight.restype = c_int32
+    lib.smpc_server_last_error.argtypes = [c_void_p]
+    lib.smpc_server_last_error.restype = c_char_p
     lib.smpc_profile_enable.argtypes = [c_void_p, c_int32]
     lib.smpc_profile_enable.restype = c_int32
     lib.smpc_profile_read.argtypes = [c_void_p, POINTER(c_float), POINTER(c_float), c_int32,
@@ -303,3 +355,141 @@ class Planner:
 
 def is_finite_float(x) -> bool:
     return math.isfinite(float(x))
+
+
+# --- serving ---------------------------------------------------------------------
+
+def smpc_plan_workspace_bytes(K: int, H: int) -> int:
+    return int(load_library().smpc_plan_workspace_bytes(int(K), int(H)))
+
+
+def smpc_server_create(ctx: c_void_p, hbm_budget_bytes: int, max_batch: int):
+    h = c_void_p()
+    st = load_library().smpc_server_create(ctypes.byref(h), ctx, int(hbm_budget_bytes),
+                                           int(max_batch))
+    return st, h
+
+
+def smpc_server_destroy(server: c_void_p) -> None:
+    load_library().smpc_server_destroy(server)
+
+
+def smpc_server_add_controller(server: c_void_p, desc: smpc_controller_desc):
+    cid = c_int32(-1)
+    st = load_library().smpc_server_add_controller(server, ctypes.byref(desc), ctypes.byref(cid))
+    return st, cid.value
+
+
+def smpc_server_reset_controller(server: c_void_p, cid: int) -> int:
+    return load_library().smpc_server_reset_controller(server, int(cid))
+
+
+def smpc_server_submit(server: c_void_p, req: smpc_request) -> int:
+    return load_library().smpc_server_submit(server, ctypes.byref(req))
+
+
+def smpc_server_pump(server: c_void_p, stream: int | None):
+    n = c_int32(0)
+    st = load_library().smpc_server_pump(server, c_void_p(stream or 0), ctypes.byref(n))
+    return st, n.value
+
+
+def smpc_server_poll(server: c_void_p, capacity: int = 256):
+    buf = (smpc_completion * capacity)()
+    n = c_int32(0)
+    st = load_library().smpc_server_poll(server, buf, int(capacity), ctypes.byref(n))
+    return st, [buf[i] for i in range(n.value)]
+
+
+def smpc_server_queued(server: c_void_p) -> int:
+    return int(load_library().smpc_server_queued(server))
+
+
+def smpc_server_in_flight(server: c_void_p) -> int:
+    return int(load_library().smpc_server_in_flight(server))
+
+
+def smpc_server_last_error(server: c_void_p) -> str:
+    return load_library().smpc_server_last_error(server).decode()
+
+
+def controller_desc(grid, origin, voxel, K, H, dt, lam, weights, sigma,
+                    grid_dtype: int = GRID_F32) -> smpc_controller_desc:
+    d = smpc_controller_desc()
+    nz, ny, nx = (int(x) for x in grid.shape)
+    d.esdf = smpc_grid(c_void_p(_ptr(grid)), nx, ny, nz, int(grid_dtype),
+                       (c_float * 3)(*[float(x) for x in np.asarray(origin, np.float32)]),
+                       float(voxel))
+    d.K, d.H = int(K), int(H)
+    d.dt, d.lambda_ = float(dt), float(lam)
+    d.weights = cost_weights(weights)
+    d.sigma[:] = [float(x) for x in np.broadcast_to(np.asarray(sigma, np.float32), (NDOF,))]
+    return d
+
+
+def request(tag: int, controller: int, q0, qd0, T_goal, seed: int) -> smpc_request:
+    r = smpc_request()
+    r.tag = int(tag)
+    r.controller = int(controller)
+    r.reserved = 0
+    r.q0[:] = [float(x) for x in np.asarray(q0, np.float32)]
+    r.qd0[:] = [float(x) for x in np.asarray(qd0, np.float32)]
+    r.T_goal[:] = [float(x) for x in np.asarray(T_goal, np.float32).reshape(16)]
+    r.seed = int(seed)
+    return r
+
+
+class Server:
+    """Continuous-batching server on a Planner's context (see include/smpc.h)."""
+
+    def __init__(self, planner: "Planner", hbm_budget_bytes: int = 256 << 20, max_batch: int = 64):
+        st, self._h = smpc_server_create(planner._ctx, hbm_budget_bytes, max_batch)
+        if st != SMPC_OK:
+            raise SMPCError(st, smpc_last_error(planner._ctx))
+        self._keep = []   # device tensors the controllers reference
+
+    def add_controller(self, grid, origin, voxel, K, H, dt, lam, weights, sigma,
+                       grid_dtype: int = GRID_F32) -> int:
+        self._keep.append(grid)
+        st, cid = smpc_server_add_controller(
+            self._h, controller_desc(grid, origin, voxel, K, H, dt, lam, weights, sigma, grid_dtype))
+        if st != SMPC_OK:
+            raise SMPCError(st, smpc_server_last_error(self._h))
+        return cid
+
+    def submit(self, tag, controller, q0, qd0, T_goal, seed) -> None:
+        st = smpc_server_submit(self._h, request(tag, controller, q0, qd0, T_goal, seed))
+        if st != SMPC_OK:
+            raise SMPCError(st, smpc_server_last_error(self._h))
+
+    def pump(self, stream=None) -> int:
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        st, n = smpc_server_pump(self._h, stream)
+        if st != SMPC_OK:
+            raise SMPCError(st, smpc_server_last_error(self._h))
+        return n
+
+    def poll(self, capacity: int = 256):
+        st, out = smpc_server_poll(self._h, capacity)
+        if st != SMPC_OK:
+            raise SMPCError(st, "poll")
+        return out
+
+    def queued(self) -> int:
+        return smpc_server_queued(self._h)
+
+    def in_flight(self) -> int:
+        return smpc_server_in_flight(self._h)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            smpc_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -54,6 +54,12 @@ int main(void) {
   F(smpc_plan_args, seed) F(smpc_plan_args, K) F(smpc_plan_args, weights)
   F(smpc_plan_args, U_in) F(smpc_plan_args, stats_out)
   F(smpc_grid, nx) F(smpc_grid, origin) F(smpc_grid, voxel)
+  printf("smpc_controller_desc sizeof %zu\n", sizeof(smpc_controller_desc));
+  printf("smpc_request sizeof %zu\n", sizeof(smpc_request));
+  printf("smpc_completion sizeof %zu\n", sizeof(smpc_completion));
+  F(smpc_controller_desc, K) F(smpc_controller_desc, weights) F(smpc_controller_desc, sigma)
+  F(smpc_request, controller) F(smpc_request, q0) F(smpc_request, T_goal) F(smpc_request, seed)
+  F(smpc_completion, status) F(smpc_completion, u0) F(smpc_completion, ess)
   return 0;
 }
 """
@@ -236,3 +242,34 @@ def test_sample_noise_and_grid_conversion_validate_on_host():
     assert S.smpc_grid_to_f16(0x1000, 0x2000, -1, 2.0, None) == S.SMPC_E_INVALID_ARG
     assert S.smpc_grid_to_f16(0x1000, 0x2000, 8, 0.0, None) == S.SMPC_E_INVALID_ARG
     assert S.smpc_grid_to_f16(0x1000, 0x2000, 0, 2.0, None) == S.SMPC_OK   # nothing to do
+
+
+def test_server_create_validates_before_device_work(ctx):
+    lib = S.load_library()
+    assert lib.smpc_server_create(None, ctx, 1 << 20, 4) == S.SMPC_E_INVALID_ARG
+    st, h = S.smpc_server_create(ctx, 1 << 20, 0)
+    assert st == S.SMPC_E_INVALID_ARG and not h.value
+    st, h = S.smpc_server_create(None, 1 << 20, 4)
+    assert st == S.SMPC_E_INVALID_ARG
+    st, h = S.smpc_server_create(ctx, 1 << 20, 4)      # no robot set yet
+    assert st == S.SMPC_E_INVALID_ARG and "no robot" in S.smpc_last_error(ctx)
+    S.smpc_server_destroy(None)
+    assert S.smpc_server_queued(None) == 0 and S.smpc_server_in_flight(None) == 0
+
+
+def test_server_create_without_gpu_fails_loudly(ctx):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present; this checks the GPU-less failure path")
+    assert S.smpc_set_robot(ctx, S.robot_desc(R.make_robot(0))) == S.SMPC_OK
+    st, h = S.smpc_server_create(ctx, 1 << 20, 4)
+    assert st == S.SMPC_E_DEVICE and not h.value
+
+
+def test_plan_workspace_bytes():
+    assert S.smpc_plan_workspace_bytes(0, 10) == 0
+    assert S.smpc_plan_workspace_bytes(10, 65) == 0
+    a = S.smpc_plan_workspace_bytes(4096, 40)
+    # costs (double) + per-block partials for 512 blocks of 8 rollouts
+    assert a >= 4096 * 8 + 512 * (8 + 4 + 4 + 280 * 4)
+    assert S.smpc_plan_workspace_bytes(8192, 40) > a
