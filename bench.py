@@ -51,6 +51,13 @@ def parse_args():
     ap.add_argument("--K", type=int, default=4096)
     ap.add_argument("--H", type=int, default=40)
     ap.add_argument("--n", type=int, default=200, help="grid side in voxels")
+    ap.add_argument("--serving", action="store_true",
+                    help="run the multi-controller serving benchmark instead")
+    ap.add_argument("--controllers", type=int, default=64)
+    ap.add_argument("--requests", type=int, default=512)
+    ap.add_argument("--rate", type=float, default=2000.0, help="mean arrivals per second")
+    ap.add_argument("--budget-mib", type=int, default=512, help="server HBM budget")
+    ap.add_argument("--max-batch", type=int, default=64)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (to scale "
                          "HBM byte counters) and exit")
@@ -68,6 +75,101 @@ def calibrate_copy(mib: int) -> None:
     torch.cuda.synchronize()
     print(json.dumps({"calibration": "device copy", "bytes_read": n * 4, "bytes_written": n * 4,
                       "launches": 3}), flush=True)
+
+
+def serving_bench(args) -> None:
+    """Poisson request stream over many controllers through the batching server."""
+    import torch
+
+    from paper_2512_22575_amd import smpc as S
+    from synth import serving as SV
+
+    t_gen = time.perf_counter()
+    rob, ctl = SV.make_controllers(5, args.controllers)
+    trace = SV.make_trace(5, ctl, args.requests, args.rate)
+    t_gen = time.perf_counter() - t_gen
+    dev = torch.device("cuda:0")
+    grids = [torch.from_numpy(c.grid).to(dev) for c in ctl]
+    planner = S.Planner(rob, device=0)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    total_rs = sum(ctl[r.controller].K * ctl[r.controller].H for r in trace)
+    n = len(trace)
+
+    def new_server():
+        srv = S.Server(planner, hbm_budget_bytes=args.budget_mib << 20, max_batch=args.max_batch)
+        ids = [srv.add_controller(g, c.origin, c.voxel, c.K, c.H, c.dt, c.lam, c.weights,
+                                  c.sigma) for g, c in zip(grids, ctl)]
+        return srv, ids
+
+    def run(srv, ids, realtime):
+        done_t, batches = {}, 0
+        i = 0
+        t0 = time.perf_counter()
+        while len(done_t) < n:
+            now = time.perf_counter() - t0
+            while i < n and (not realtime or trace[i].t_arrival <= now):
+                r = trace[i]
+                srv.submit(i, ids[r.controller], r.q0, r.qd0, r.T_goal, r.seed)
+                i += 1
+            if srv.pump(stream):
+                batches += 1
+            for c in srv.poll():
+                if c.status != S.SMPC_OK:
+                    raise RuntimeError(f"request {c.tag}: status {c.status}")
+                done_t[c.tag] = time.perf_counter() - t0
+        span = max(done_t.values())
+        lat = np.array([done_t[k] - (trace[k].t_arrival if realtime else 0.0) for k in range(n)])
+        return span, lat * 1e3, batches
+
+    # Warm-up pass (first launches, allocations), then the timed passes.
+    srv, ids = new_server()
+    run(srv, ids, realtime=False)
+    srv.close()
+    srv, ids = new_server()
+    rt_span, rt_lat, rt_batches = run(srv, ids, realtime=True)
+    srv.close()
+    srv, ids = new_server()
+    sat_span, _, sat_batches = run(srv, ids, realtime=False)
+    srv.close()
+
+    # Sequential plain plan steps (one call per request, each waited for).
+    U = [torch.zeros((c.H, 7), device=dev) for c in ctl]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in trace:
+        c = ctl[r.controller]
+        planner.plan_step(q0=r.q0, qd0=r.qd0, T_goal=r.T_goal, grid=grids[r.controller],
+                          origin=c.origin, voxel=c.voxel, noise=None, K=c.K, H=c.H,
+                          U_in=U[r.controller], U_out=U[r.controller], dt=c.dt, lam=c.lam,
+                          weights=c.weights, seed=r.seed, sigma=c.sigma, stream=stream)
+        torch.cuda.synchronize()
+    seq_span = time.perf_counter() - t0
+    out = {
+        "metric": "serving: plan-request latency (arrival to completion) and aggregate "
+                  "rollout-steps/s",
+        "value": round(float(np.percentile(rt_lat, 99)), 4),
+        "unit": "ms (p99 latency)",
+        "higher_is_better": False,
+        "n_gpus": 1,
+        "data": "synthetic",
+        "dtype": "f32",
+        "config": {"workload": f"{args.controllers} controllers (K in 256..4096, H in 16/32/64, "
+                               f"grids 64^3..160^3), {n} requests, Poisson {args.rate:g}/s",
+                   "budget_mib": args.budget_mib, "max_batch": args.max_batch,
+                   "total_rollout_steps": int(total_rs)},
+        "realtime": {"p50_ms": round(float(np.percentile(rt_lat, 50)), 4),
+                     "p99_ms": round(float(np.percentile(rt_lat, 99)), 4),
+                     "max_ms": round(float(rt_lat.max()), 4),
+                     "batches": rt_batches, "span_s": round(rt_span, 4),
+                     "replanning_budget_ms": 20.0},
+        "saturated": {"rollout_steps_per_s": round(total_rs / sat_span, 1),
+                      "span_ms": round(sat_span * 1e3, 3), "batches": sat_batches},
+        "sequential_plain": {"rollout_steps_per_s": round(total_rs / seq_span, 1),
+                             "span_ms": round(seq_span * 1e3, 3)},
+        "setup_s": round(t_gen, 1),
+    }
+    print(json.dumps(out), flush=True)
+    planner.close()
 
 
 def cpu_baseline(sc, grid, noise, K, H):
@@ -90,6 +192,9 @@ def main():
     args = parse_args()
     if args.calibrate_copy_mib:
         calibrate_copy(args.calibrate_copy_mib)
+        return
+    if args.serving:
+        serving_bench(args)
         return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the plan step is not sharded "
