@@ -139,7 +139,8 @@ def run_f16(inp, grid16, **kw):
     noise = torch.from_numpy(inp.noise).to(dev) if inp.noise is not None else None
     U_in = torch.from_numpy(inp.U_bar).to(dev)
     U_out = torch.empty_like(U_in)
-    costs = torch.empty((inp.K,), device=dev)
+    K = kw["K"] if inp.noise is None else inp.K
+    costs = torch.empty((K,), device=dev)
     planner = S.Planner(inp.robot)
     planner.plan_step(q0=inp.q0, qd0=inp.qd0, T_goal=inp.T_goal, grid=g, origin=inp.origin,
                       voxel=inp.voxel, noise=noise, U_in=U_in, U_out=U_out, dt=inp.dt,
