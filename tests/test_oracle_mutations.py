@@ -6,6 +6,7 @@ term, a swapped factor, a wrong sign or an off-by-one index is too weak.
 import numpy as np
 import pytest
 
+from oracle import edt as E
 from oracle import smpc_oracle as O
 from tests import test_oracle_pins as P
 from synth import robot as R
@@ -80,6 +81,42 @@ def _self_no_radius_sum(robot, centres, w_self):
     return total
 
 
+def _fh_1d_no_root_square(f):
+    n = f.shape[0]
+    out = np.full(n, E.INF, dtype=np.int64)
+    roots = [q for q in range(n) if f[q] < E.INF]
+    if not roots:
+        return out
+    v, z = [], []
+    for q in roots:
+        while True:
+            if not v:
+                v.append(q), z.append(-np.inf)
+                break
+            p = v[-1]
+            s = (float(f[q]) - float(f[p])) / (2.0 * (q - p))      # mistake: q^2 - p^2 dropped
+            if s <= z[-1]:
+                v.pop(), z.pop()
+                continue
+            v.append(q), z.append(s)
+            break
+    piece = 0
+    for p in range(n):
+        while piece + 1 < len(v) and z[piece + 1] < p:
+            piece += 1
+        out[p] = (p - v[piece]) ** 2 + int(f[v[piece]])
+    return out
+
+
+def _signed_distance_no_inside(occ, voxel, transform=None):
+    occ = np.asarray(occ, bool)
+    d_out = E.edt_separable_fh(occ)
+    big = E.no_source_value(occ.shape)
+    d_out = np.where(d_out >= E.INF, big, d_out)
+    phi = voxel * np.sqrt(d_out.astype(np.float64))                 # mistake: no inside depth
+    return phi.astype(np.float32), d_out, np.zeros_like(d_out)
+
+
 def _margin_not_applied(x, lo, hi, margin_frac):
     lo = np.asarray(lo, np.float64)
     hi = np.asarray(hi, np.float64)
@@ -130,6 +167,8 @@ MUTANTS = {
     "terminal_cost_dropped": ("rollout_costs", _rollout_costs_no_terminal),
     "self_hinge_missing_radius": ("self_collision_cost", _self_no_radius_sum),
     "limit_margin_dropped": ("limit_violation", _margin_not_applied),
+    "fh_intersection_without_squares": ("fh_1d", _fh_1d_no_root_square, E),
+    "signed_distance_without_inside": ("signed_distance", _signed_distance_no_inside, E),
 }
 
 
@@ -139,6 +178,6 @@ def test_unmutated_oracle_passes_every_pin():
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_each_planted_mistake_is_caught(name, monkeypatch):
-    attr, fn = MUTANTS[name]
-    monkeypatch.setattr(O, attr, fn)
+    attr, fn, *mod = MUTANTS[name]
+    monkeypatch.setattr(mod[0] if mod else O, attr, fn)
     assert _run_all_pins() > 0, f"no pin catches the planted mistake {name!r}"

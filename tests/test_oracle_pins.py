@@ -208,6 +208,64 @@ def test_edt_brute_force_equals_separable_fh_equals_scipy(seed):
     np.testing.assert_array_equal(brute, SC.squared_index_edt(occ))
 
 
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_edt_minplus_equals_brute_force_on_ragged_grids(seed):
+    rng = np.random.default_rng(100 + seed)
+    for shape in [(5, 9, 4), (1, 1, 7), (6, 1, 1), (3, 8, 1)]:
+        occ = rng.uniform(size=shape) < 0.12
+        np.testing.assert_array_equal(E.edt_separable_minplus(occ), E.edt_brute_force(occ))
+
+
+def test_edt_single_source_is_squared_index_distance():
+    occ = np.zeros((7, 9, 8), bool)
+    c = np.array([2, 5, 3])
+    occ[tuple(c)] = True
+    idx = np.stack(np.meshgrid(*[np.arange(n) for n in occ.shape], indexing="ij"), -1)
+    want = np.sum((idx - c) ** 2, axis=-1)
+    for fn in (E.edt_separable_fh, E.edt_separable_minplus):
+        np.testing.assert_array_equal(fn(occ), want)
+
+
+def test_signed_distance_half_space_closed_form():
+    """Every voxel with x < 4 occupied: D_out = (x - 3)^2 outside, D_in = (4 - x)^2 inside."""
+    occ = np.zeros((3, 5, 10), bool)
+    occ[..., :4] = True
+    voxel = 0.25
+    phi, d_out, d_in = E.signed_distance(occ, voxel)
+    x = np.arange(10)
+    np.testing.assert_array_equal(d_out[1, 2], np.where(x < 4, 0, (x - 3) ** 2))
+    np.testing.assert_array_equal(d_in[1, 2], np.where(x < 4, (4 - x) ** 2, 0))
+    np.testing.assert_array_equal(phi[0, 0], np.where(x < 4, -(4 - x), x - 3) * voxel)
+
+
+def test_signed_distance_empty_and_full_grids():
+    shape = (4, 6, 5)
+    big = 16 + 36 + 25
+    phi, d_out, d_in = E.signed_distance(np.zeros(shape, bool), 0.5)
+    assert (d_out == big).all() and (d_in == 0).all()
+    assert (phi == np.float32(0.5 * np.sqrt(big))).all()
+    phi, d_out, d_in = E.signed_distance(np.ones(shape, bool), 0.5)
+    assert (d_out == 0).all() and (d_in == big).all()
+    assert (phi == np.float32(-0.5 * np.sqrt(big))).all()
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_signed_distance_equals_library_edt_grid(seed):
+    """Both transforms agree bit for bit with the grid built from scipy's exact EDT."""
+    rng = np.random.default_rng(seed)
+    n = (20, 17, 23)
+    voxel = float(np.float32(0.03))
+    origin = np.zeros(3)
+    prims = [SC.Primitive("box", rng.uniform(0.1, 0.5, 3), rng.uniform(0.05, 0.2, 3), np.zeros(3)),
+             SC.Primitive("sphere", rng.uniform(0.1, 0.5, 3), np.array([0.08, 0, 0]), np.zeros(3))]
+    occ = SC.occupancy(prims, n, origin, voxel)
+    assert 0 < occ.sum() < occ.size
+    want = SC.signed_distance_grid(occ, voxel)
+    for tr in (E.edt_separable_fh, E.edt_separable_minplus):
+        phi, _, _ = E.signed_distance(occ, voxel, transform=tr)
+        np.testing.assert_array_equal(phi, want)
+
+
 def test_fh_1d_against_definition():
     rng = np.random.default_rng(9)
     for _ in range(50):
