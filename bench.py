@@ -38,6 +38,30 @@ FLOP_PER_ROLLOUT_STEP = 4300.0
 GATHER_BYTES_PER_ROLLOUT_STEP = 896.0
 PEAK_FP32_TFLOPS = 157.3
 
+# HBM traffic of one rollout-cost launch on the default workload, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE (KiB per dispatch, averaged over dispatches), each
+# scaled by what the counter reads for a plain 256 MiB device copy (FETCH_SIZE
+# reads half the bytes copied: x2; WRITE_SIZE reads them all: x1).  Valid only for
+# the kernel sources it was taken on: bench.py reports null traffic when their
+# hash differs.
+ROLLOUT_TRAFFIC = None
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("smpc_kernels.hip", "smpc_internal.h"):
+        with open(os.path.join(ROOT, "paper_2512_22575_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def rollout_traffic_bytes():
+    t = ROLLOUT_TRAFFIC
+    if t is None or t["sources_sha256"] != kernel_sources_sha256():
+        return None
+    return round(1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]))
+
 
 def parse_args():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
@@ -58,6 +82,9 @@ def parse_args():
     ap.add_argument("--rate", type=float, default=2000.0, help="mean arrivals per second")
     ap.add_argument("--budget-mib", type=int, default=512, help="server HBM budget")
     ap.add_argument("--max-batch", type=int, default=64)
+    ap.add_argument("--edt", action="store_true",
+                    help="time the distance-field construction (200^3 occupancy -> signed "
+                         "field) and the construction + plan step pipeline instead")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain device-to-device copy of this many MiB (to scale "
                          "HBM byte counters) and exit")
@@ -172,6 +199,116 @@ def serving_bench(args) -> None:
     planner.close()
 
 
+# Compulsory traffic of the distance-field construction per voxel: the occupancy
+# byte read and the float32 field written.
+EDT_BYTES_PER_VOXEL = 5.0
+PEAK_HBM_GBPS = 8000.0
+
+
+def edt_bench(args) -> None:
+    """Distance field from occupancy on the device, alone and followed by a plan step.
+
+    The reactive scene is advanced by one control period per pool entry, so
+    consecutive constructions see moving obstacles; occupancy grids are resident in
+    device memory (their host-to-device copy is timed separately, from pinned memory).
+    """
+    import torch
+
+    from paper_2512_22575_amd import smpc as S
+    from synth import workload as W
+
+    K, H, n = args.K, args.H, args.n
+    sc = W.ReactiveScenario(seed=3, K=K, H=H, n=n)
+    dev = torch.device("cuda:0")
+    pool = max(1, min(args.pool, 8))
+    occs_np = []
+    for _ in range(pool):
+        occs_np.append(sc.occupancy().astype(np.uint8))
+        sc.advance()
+    occs = [torch.from_numpy(o).to(dev) for o in occs_np]
+    nvox = n ** 3
+    need = S.smpc_edt_workspace_bytes(n, n, n)
+    work = torch.empty(need // 4, dtype=torch.int32, device=dev)
+    phi = torch.empty((n, n, n), device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+
+    def edt(i):
+        st = S.smpc_edt(occs[i % pool].data_ptr(), n, n, n, sc.VOXEL, phi.data_ptr(),
+                        work.data_ptr(), need, stream)
+        if st != S.SMPC_OK:
+            raise S.SMPCError(st, S.smpc_status_string(st))
+
+    for i in range(args.warmup):
+        edt(i)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for i in range(args.steps):
+        edt(i)
+    ev1.record()
+    torch.cuda.synchronize()
+    edt_ms = ev0.elapsed_time(ev1) / args.steps
+
+    # Host-to-device copy of one occupancy grid from pinned memory.
+    pinned = torch.from_numpy(occs_np[0]).pin_memory()
+    staging = torch.empty_like(occs[0])
+    ev0.record()
+    for _ in range(20):
+        staging.copy_(pinned, non_blocking=True)
+    ev1.record()
+    torch.cuda.synchronize()
+    h2d_ms = ev0.elapsed_time(ev1) / 20
+
+    # Construction followed by a warm-started plan step on the fresh field.
+    noise = [torch.from_numpy(sc.noise()).to(dev) for _ in range(4)]
+    U = [torch.zeros((H, 7), device=dev), torch.zeros((H, 7), device=dev)]
+    planner = S.Planner(sc.robot, device=0)
+    plans = [S.plan_args(sc.q0, sc.qd0, sc.target(), phi, sc.origin, sc.VOXEL, noise[i % 4],
+                         U[i % 2], U[(i + 1) % 2], K, H, sc.DT, 1.0, sc.weights)
+             for i in range(args.steps)]
+
+    def pipeline(i):
+        edt(i)
+        st = S.smpc_plan_step(planner._ctx, plans[i], stream)
+        if st != S.SMPC_OK:
+            raise S.SMPCError(st, S.smpc_last_error(planner._ctx))
+
+    for i in range(min(args.warmup, args.steps)):
+        pipeline(i)
+    torch.cuda.synchronize()
+    ev0.record()
+    for i in range(args.steps):
+        pipeline(i)
+    ev1.record()
+    torch.cuda.synchronize()
+    pipe_ms = ev0.elapsed_time(ev1) / args.steps
+    planner.close()
+
+    achieved = EDT_BYTES_PER_VOXEL * nvox / (edt_ms * 1e-3) / 1e9
+    print(json.dumps({
+        "metric": "voxels/s of signed distance field construction (occupancy -> field)",
+        "value": round(nvox / (edt_ms * 1e-3), 1),
+        "unit": "voxels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(edt_ms, 6),
+        "higher_is_better": True,
+        "dtype": "u32 squared distances, f64 -> f32 field",
+        "data": "synthetic",
+        "config": {"workload": f"reactive scene occupancy {n}^3 at 0.01 m, 20 boxes and 20 "
+                               f"spheres drifting at 0.2 m/s, {pool} consecutive periods",
+                   "grid": [n] * 3},
+        "roofline": {"bound": "hbm", "kernel": "smpc_edt (3 kernels)",
+                     "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None,
+                     "bytes_per_voxel": EDT_BYTES_PER_VOXEL},
+        "occupancy_h2d_ms": round(h2d_ms, 5),
+        "pipeline_ms_per_step": round(pipe_ms, 5),
+        "pipeline": f"smpc_edt then smpc_plan_step (K={K}, H={H}) on the new field",
+    }), flush=True)
+
+
 def cpu_baseline(sc, grid, noise, K, H):
     """Time the FP64 oracle on one full plan step of the same workload, one thread."""
     from threadpoolctl import threadpool_limits
@@ -195,6 +332,9 @@ def main():
         return
     if args.serving:
         serving_bench(args)
+        return
+    if args.edt:
+        edt_bench(args)
         return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the plan step is not sharded "
@@ -323,7 +463,7 @@ def main():
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-            "traffic": None,
+            "traffic": rollout_traffic_bytes(),
             "flop_per_launch": flop,
             "gather_GBps": round(gather_gbs, 1),
         },

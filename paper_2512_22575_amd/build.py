@@ -18,7 +18,7 @@ LIB_NAME = "libsmpc.so"
 LIB_PATH = os.path.join(PKG_DIR, LIB_NAME)
 ARCH = "gfx950"
 
-SOURCES = ["smpc_kernels.hip", "smpc_runtime.cpp"]
+SOURCES = ["smpc_kernels.hip", "smpc_edt.hip", "smpc_runtime.cpp"]
 
 # Packed FP32 instructions are disabled for device code on purpose (the compiler
 # would otherwise form v_pk_* ops from ordinary float code).

@@ -130,4 +130,9 @@ int launch_sample_noise(uint64_t seed, int K, int H, const float* sigma, float* 
 // float32 -> float16 grid conversion with clamping.  Returns a hipError_t value.
 int launch_grid_to_f16(const float* src, void* dst, long long n, float clamp, void* stream);
 
+constexpr int kEdtMaxSide = SMPC_EDT_MAX_SIDE;
+// Signed distance field from occupancy (smpc_edt.hip); sizes already validated.
+int launch_edt(const uint8_t* occ, int nx, int ny, int nz, float voxel, float* phi,
+               uint32_t* work, hipStream_t stream);
+
 }  // namespace smpc

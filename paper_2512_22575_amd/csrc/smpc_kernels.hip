@@ -257,11 +257,18 @@ __device__ __forceinline__ float load_grid(__amdgpu_buffer_rsrc_t rsrc, uint32_t
   }
 }
 
-// Trilinear phi(p) between voxel centres, query clamped to the grid (edge extension).
-// u = p / voxel + (-origin / voxel - 1/2) per axis (p.gcx.. hold the second term).
+// Trilinear phi(p) between voxel centres, query clamped to the grid (edge extension),
+// in two halves so that several lookups can have their loads in flight together:
+// esdf_fetch computes the base corner and fractions and issues the 8 loads,
+// esdf_blend interpolates.  u = p / voxel + (-origin / voxel - 1/2) per axis.
+struct GridSample {
+  float v[8];          // corners 000, 100, 010, 110, 001, 101, 011, 111
+  float fx, fy, fz;
+};
+
 template <int kElemBytes>
-__device__ __forceinline__ float esdf_lookup(__amdgpu_buffer_rsrc_t rsrc, const StepParams& p,
-                                             float px, float py, float pz) {
+__device__ __forceinline__ void esdf_fetch(__amdgpu_buffer_rsrc_t rsrc, const StepParams& p,
+                                           float px, float py, float pz, GridSample& g) {
   const float fx_hi = (float)(p.nx - 1), fy_hi = (float)(p.ny - 1), fz_hi = (float)(p.nz - 1);
   const float ux = __builtin_amdgcn_fmed3f(fmaf(px, p.inv_voxel, p.gcx), 0.f, fx_hi);
   const float uy = __builtin_amdgcn_fmed3f(fmaf(py, p.inv_voxel, p.gcy), 0.f, fy_hi);
@@ -269,27 +276,40 @@ __device__ __forceinline__ float esdf_lookup(__amdgpu_buffer_rsrc_t rsrc, const 
   const float bx = fminf(floorf(ux), fx_hi - 1.f);
   const float by = fminf(floorf(uy), fy_hi - 1.f);
   const float bz = fminf(floorf(uz), fz_hi - 1.f);
-  const float fx = ux - bx, fy = uy - by, fz = uz - bz;
+  g.fx = ux - bx;
+  g.fy = uy - by;
+  g.fz = uz - bz;
   const uint32_t ix = (uint32_t)bx, iy = (uint32_t)by, iz = (uint32_t)bz;
   constexpr uint32_t e = kElemBytes;
   const uint32_t sy = (uint32_t)p.nx * e;
   const uint32_t sz = (uint32_t)p.nx * (uint32_t)p.ny * e;
   const uint32_t off = ((iz * (uint32_t)p.ny + iy) * (uint32_t)p.nx + ix) * e;
-  const float v000 = load_grid<kElemBytes>(rsrc, off, 0u);
-  const float v100 = load_grid<kElemBytes>(rsrc, off + e, 0u);
-  const float v010 = load_grid<kElemBytes>(rsrc, off, sy);
-  const float v110 = load_grid<kElemBytes>(rsrc, off + e, sy);
-  const float v001 = load_grid<kElemBytes>(rsrc, off, sz);
-  const float v101 = load_grid<kElemBytes>(rsrc, off + e, sz);
-  const float v011 = load_grid<kElemBytes>(rsrc, off, sy + sz);
-  const float v111 = load_grid<kElemBytes>(rsrc, off + e, sy + sz);
-  const float c00 = fmaf(fx, v100 - v000, v000);
-  const float c10 = fmaf(fx, v110 - v010, v010);
-  const float c01 = fmaf(fx, v101 - v001, v001);
-  const float c11 = fmaf(fx, v111 - v011, v011);
-  const float c0 = fmaf(fy, c10 - c00, c00);
-  const float c1 = fmaf(fy, c11 - c01, c01);
-  return fmaf(fz, c1 - c0, c0);
+  g.v[0] = load_grid<kElemBytes>(rsrc, off, 0u);
+  g.v[1] = load_grid<kElemBytes>(rsrc, off + e, 0u);
+  g.v[2] = load_grid<kElemBytes>(rsrc, off, sy);
+  g.v[3] = load_grid<kElemBytes>(rsrc, off + e, sy);
+  g.v[4] = load_grid<kElemBytes>(rsrc, off, sz);
+  g.v[5] = load_grid<kElemBytes>(rsrc, off + e, sz);
+  g.v[6] = load_grid<kElemBytes>(rsrc, off, sy + sz);
+  g.v[7] = load_grid<kElemBytes>(rsrc, off + e, sy + sz);
+}
+
+__device__ __forceinline__ float esdf_blend(const GridSample& g) {
+  const float c00 = fmaf(g.fx, g.v[1] - g.v[0], g.v[0]);
+  const float c10 = fmaf(g.fx, g.v[3] - g.v[2], g.v[2]);
+  const float c01 = fmaf(g.fx, g.v[5] - g.v[4], g.v[4]);
+  const float c11 = fmaf(g.fx, g.v[7] - g.v[6], g.v[6]);
+  const float c0 = fmaf(g.fy, c10 - c00, c00);
+  const float c1 = fmaf(g.fy, c11 - c01, c01);
+  return fmaf(g.fz, c1 - c0, c0);
+}
+
+template <int kElemBytes>
+__device__ __forceinline__ float esdf_lookup(__amdgpu_buffer_rsrc_t rsrc, const StepParams& p,
+                                             float px, float py, float pz) {
+  GridSample g;
+  esdf_fetch<kElemBytes>(rsrc, p, px, py, pz, g);
+  return esdf_blend(g);
 }
 
 // Forward kinematics (eq. 6) of q0 + dq with sin/cos of q0 + dq by angle addition,
@@ -733,7 +753,16 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
   const int n_merge = HO4 / 4;  // merge waves, 4 outputs each
 
   if (kb == 0) {
-    // --- independent fetches first
+    // --- independent fetches first: pair records, the first pass of costs, the
+    // statistics merge
+    double sv0[kCostsPerThread];
+    if (costs_out) {
+#pragma unroll
+      for (int c = 0; c < kCostsPerThread; ++c) {
+        const int i = tid + kK2Threads * c;
+        sv0[c] = i < K ? ws.S[i] : 0.0;
+      }
+    }
     const bool has_pair = tid < rob->n_pairs;
     float4 pr = make_float4(0.f, 0.f, 0.f, 0.f);
     if (has_pair) pr = rob->pair_rec[tid];
@@ -796,7 +825,7 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
 #pragma unroll
         for (int c = 0; c < kCostsPerThread; ++c) {
           const int i = base + tid + kK2Threads * c;
-          sv[c] = i < K ? ws.S[i] : 0.0;
+          sv[c] = base == 0 ? sv0[c] : (i < K ? ws.S[i] : 0.0);
         }
 #pragma unroll
         for (int c = 0; c < kCostsPerThread; ++c) {

@@ -205,7 +205,9 @@ StepParams make_params(const smpc_ctx* ctx, const smpc_plan_args* a, const Launc
   tighten(ctx->raw_d_qdlo, ctx->raw_d_qdhi, frac, p.qdlo, p.qdhi);
   tighten(ctx->raw_d_qddlo, ctx->raw_d_qddhi, frac, p.qddlo, p.qddhi);
   for (int s = 0; s < kSlots; ++s)
-    p.env_thr[s] = (float)((double)a->weights.d_act + ctx->slot_radius[s]);
+    p.env_thr[s] = (ctx->host_robot.slot_active & (1u << s))
+                       ? (float)((double)a->weights.d_act + ctx->slot_radius[s])
+                       : -1e30f;  // empty slot: hinge is always 0
   const smpc_cost_weights& w = a->weights;
   p.w_pose_t = w.w_pose_t;
   p.w_pose_r = w.w_pose_r;
@@ -475,6 +477,34 @@ smpc_status smpc_grid_to_f16(const float* src, void* dst, int64_t n, float clamp
   if (n == 0) return SMPC_OK;
   return launch_grid_to_f16(src, dst, (long long)n, clamp, stream) == 0 ? SMPC_OK
                                                                         : SMPC_E_DEVICE;
+}
+
+size_t smpc_edt_workspace_bytes(int32_t nx, int32_t ny, int32_t nz) {
+  if (nx < 1 || ny < 1 || nz < 1 || nx > kEdtMaxSide || ny > kEdtMaxSide || nz > kEdtMaxSide)
+    return 0;
+  return (size_t)2 * nx * ny * nz * sizeof(uint32_t);
+}
+
+smpc_status smpc_edt(const uint8_t* occ, int32_t nx, int32_t ny, int32_t nz, float voxel,
+                     float* phi_out, uint32_t* work, size_t work_bytes, void* stream) {
+  const size_t need = smpc_edt_workspace_bytes(nx, ny, nz);
+  if (!occ || !work || need == 0 || work_bytes < need || !std::isfinite(voxel) || !(voxel > 0.f))
+    return SMPC_E_INVALID_ARG;
+  const size_t nvox = (size_t)nx * ny * nz;
+  const auto lo = [](const void* p) { return (uintptr_t)p; };
+  const bool overlap_occ = lo(occ) < lo(work) + need && lo(work) < lo(occ) + nvox;
+  const bool overlap_phi =
+      phi_out && lo(phi_out) < lo(work) + need && lo(work) < lo(phi_out) + nvox * sizeof(float);
+  if (overlap_occ || overlap_phi) return SMPC_E_INVALID_ARG;
+  int dev = 0, max_lds = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+          hipSuccess)
+    return SMPC_E_DEVICE;
+  if ((long long)64 * sizeof(uint32_t) * std::max(ny, nz) > max_lds) return SMPC_E_UNSUPPORTED;
+  return launch_edt(occ, nx, ny, nz, voxel, phi_out, work, (hipStream_t)stream) == 0
+             ? SMPC_OK
+             : SMPC_E_DEVICE;
 }
 
 smpc_status smpc_profile_enable(smpc_ctx* ctx, int32_t n_steps) {

@@ -123,6 +123,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         return _lib
     if not os.path.exists(path):
         raise OSError(f"{path} is missing: build it with `python -m paper_2512_22575_amd.build`")
+    # PyTorch wheels bundle their own HIP runtime.  Loading torch first makes this
+    # library bind to that same runtime (same soname); the other order leaves two
+    # runtimes in the process and device calls fail.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     lib.smpc_create.argtypes = [POINTER(c_void_p), c_int32]
     lib.smpc_create.restype = c_int32
@@ -144,6 +151,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.smpc_grid_to_f16.argtypes = [c_void_p, c_void_p, ctypes.c_int64, c_float, c_void_p]
     lib.smpc_grid_to_f16.restype = c_int32
     lib.smpc_plan_workspace_bytes.argtypes = [c_int32, c_int32]
+    lib.smpc_edt_workspace_bytes.argtypes = [c_int32, c_int32, c_int32]
+    lib.smpc_edt_workspace_bytes.restype = c_uint64
+    lib.smpc_edt.argtypes = [c_void_p, c_int32, c_int32, c_int32, c_float, c_void_p, c_void_p,
+                             c_uint64, c_void_p]
+    lib.smpc_edt.restype = c_int32
     lib.smpc_plan_workspace_bytes.restype = c_uint64
     lib.smpc_server_create.argtypes = [POINTER(c_void_p), c_void_p, c_uint64, c_int32]
     lib.smpc_server_create.restype = c_int32
@@ -361,6 +373,18 @@ def is_finite_float(x) -> bool:
 
 def smpc_plan_workspace_bytes(K: int, H: int) -> int:
     return int(load_library().smpc_plan_workspace_bytes(int(K), int(H)))
+
+
+def smpc_edt_workspace_bytes(nx: int, ny: int, nz: int) -> int:
+    return int(load_library().smpc_edt_workspace_bytes(int(nx), int(ny), int(nz)))
+
+
+def smpc_edt(occ: int, nx: int, ny: int, nz: int, voxel: float, phi_out: int | None, work: int,
+             work_bytes: int, stream: int | None) -> int:
+    """Signed distance field of a device occupancy grid (pointers as integers)."""
+    return load_library().smpc_edt(c_void_p(occ or 0), int(nx), int(ny), int(nz), float(voxel),
+                                   c_void_p(phi_out or 0), c_void_p(work or 0), int(work_bytes),
+                                   c_void_p(stream or 0))
 
 
 def smpc_server_create(ctx: c_void_p, hbm_budget_bytes: int, max_batch: int):

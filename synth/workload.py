@@ -179,9 +179,11 @@ class ReactiveScenario:
         self.t = 0.0
         self.weights = {k: f32s(v) for k, v in DEFAULT_WEIGHTS.items()}
 
+    def occupancy(self) -> np.ndarray:
+        return scene_mod.occupancy(self.prims, (self.N,) * 3, self.origin, self.VOXEL)
+
     def grid(self) -> np.ndarray:
-        occ = scene_mod.occupancy(self.prims, (self.N,) * 3, self.origin, self.VOXEL)
-        return scene_mod.signed_distance_grid(occ, self.VOXEL)
+        return scene_mod.signed_distance_grid(self.occupancy(), self.VOXEL)
 
     def target(self) -> np.ndarray:
         p = self.centre + 0.3 * np.array([math.cos(0.5 * self.t), math.sin(0.5 * self.t), 0.0])

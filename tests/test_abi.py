@@ -266,6 +266,23 @@ def test_server_create_without_gpu_fails_loudly(ctx):
     assert st == S.SMPC_E_DEVICE and not h.value
 
 
+def test_edt_validates_on_host():
+    need = S.smpc_edt_workspace_bytes(10, 20, 30)
+    assert need == 2 * 4 * 10 * 20 * 30
+    assert S.smpc_edt_workspace_bytes(0, 5, 5) == 0
+    assert S.smpc_edt_workspace_bytes(5, 513, 5) == 0
+    assert S.smpc_edt_workspace_bytes(512, 512, 512) == 2 * 4 * 512 ** 3
+    occ, phi, work = 0x10000000, 0x20000000, 0x40000000
+    ok = dict(occ=occ, nx=10, ny=20, nz=30, voxel=0.05, phi_out=phi, work=work, work_bytes=need,
+              stream=None)
+    bad = [dict(occ=0), dict(work=0), dict(nx=0), dict(nz=513), dict(voxel=0.0),
+           dict(voxel=float("nan")), dict(work_bytes=need - 1),
+           dict(work=occ + 100),                     # overlaps the occupancy grid
+           dict(phi_out=work + need - 4)]           # overlaps the workspace
+    for over in bad:
+        assert S.smpc_edt(**{**ok, **over}) == S.SMPC_E_INVALID_ARG, over
+
+
 def test_plan_workspace_bytes():
     assert S.smpc_plan_workspace_bytes(0, 10) == 0
     assert S.smpc_plan_workspace_bytes(10, 65) == 0

@@ -1,0 +1,105 @@
+"""GPU parity of the distance-field construction (smpc_edt) against the oracle.
+
+Squared index distances are integers and must match bit for bit; phi is one
+float64 formula rounded once to float32 on both sides (correctly rounded square
+roots), so it must match bit for bit too.  Cases: ragged grids spanning several
+64-voxel chunks and 64-lane line groups with partial tails, a single source,
+empty and full grids, sides of 1, the longest side along each axis, the
+workloads' scene grids, and the 200^3 reactive-scene grid.
+"""
+import numpy as np
+import pytest
+
+from oracle import edt as E
+from synth import scene as SC
+from synth import workload as W
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_edt(occ: np.ndarray, voxel: float, with_phi: bool = True):
+    import torch
+
+    from paper_2512_22575_amd import smpc as S
+    nz, ny, nx = occ.shape
+    need = S.smpc_edt_workspace_bytes(nx, ny, nz)
+    assert need == 8 * occ.size
+    dev = torch.device("cuda:0")
+    d_occ = torch.from_numpy(np.ascontiguousarray(occ, dtype=np.uint8)).to(dev)
+    work = torch.full((2,) + occ.shape, -1, dtype=torch.int32, device=dev)
+    phi = torch.full(occ.shape, float("nan"), device=dev) if with_phi else None
+    st = S.smpc_edt(d_occ.data_ptr(), nx, ny, nz, voxel, phi.data_ptr() if with_phi else None,
+                    work.data_ptr(), need, torch.cuda.current_stream().cuda_stream)
+    assert st == S.SMPC_OK, S.smpc_status_string(st)
+    torch.cuda.synchronize()
+    w = work.cpu().numpy().view(np.uint32).astype(np.int64)
+    return (phi.cpu().numpy() if with_phi else None), w[0], w[1]
+
+
+def check(occ, voxel, transform=E.edt_separable_fh):
+    """The library takes the voxel edge as float32; the oracle gets that same value."""
+    voxel = float(np.float32(voxel))
+    phi, d_out, d_in = gpu_edt(occ, voxel)
+    ref_phi, ref_out, ref_in = E.signed_distance(occ, voxel, transform=transform)
+    np.testing.assert_array_equal(d_out, ref_out)
+    np.testing.assert_array_equal(d_in, ref_in)
+    np.testing.assert_array_equal(phi.view(np.uint32), ref_phi.view(np.uint32))
+
+
+@pytest.mark.parametrize("shape,density,seed", [
+    ((23, 50, 37), 0.02, 0), ((9, 70, 130), 0.01, 1), ((17, 3, 200), 0.05, 2),
+    ((64, 64, 64), 0.002, 3), ((1, 1, 1), 0.5, 4), ((1, 129, 1), 0.03, 5), ((31, 1, 65), 0.1, 6)])
+def test_random_ragged_grids(shape, density, seed):
+    rng = np.random.default_rng(seed)
+    occ = rng.uniform(size=shape) < density
+    check(occ, float(np.float32(0.02)))
+
+
+def test_single_source_empty_and_full():
+    occ = np.zeros((12, 19, 70), bool)
+    check(occ, 0.05)                      # no occupied voxel anywhere
+    check(~occ, 0.05)                     # no free voxel anywhere
+    occ[5, 17, 66] = True
+    check(occ, 0.05)
+    check(~occ, 0.05)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_longest_side_along_each_axis(axis):
+    shape = [3, 2, 4]
+    shape[axis] = 512
+    rng = np.random.default_rng(axis)
+    occ = rng.uniform(size=shape) < 0.004
+    check(occ, 0.01, transform=E.edt_separable_minplus)
+
+
+def test_work_only_without_phi():
+    rng = np.random.default_rng(11)
+    occ = rng.uniform(size=(10, 20, 30)) < 0.03
+    phi, d_out, d_in = gpu_edt(occ, 0.1, with_phi=False)
+    _, ref_out, ref_in = E.signed_distance(occ, 0.1)
+    np.testing.assert_array_equal(d_out, ref_out)
+    np.testing.assert_array_equal(d_in, ref_in)
+
+
+@pytest.mark.parametrize("which", ["tiny", "mid"])
+def test_workload_scene_grids(which):
+    """Scene occupancy of the small and mid workloads: the device field equals the
+    oracle's and the grid the workload generator produced for the planner."""
+    rng = np.random.default_rng({"tiny": 0, "mid": 1}[which])
+    n, voxel = {"tiny": (32, 0.05), "mid": (64, 0.03)}[which]
+    voxel = W.f32s(voxel)
+    origin = SC.grid_origin(n, voxel)
+    prims = SC.random_primitives(rng, origin + 0.05 * n * voxel, origin + 0.95 * n * voxel, 6, 4)
+    occ = SC.occupancy(prims, (n, n, n), origin, voxel)
+    assert 0 < occ.sum() < occ.size
+    check(occ, voxel)
+    phi, _, _ = gpu_edt(occ, voxel)
+    np.testing.assert_array_equal(phi, SC.signed_distance_grid(occ, voxel))
+
+
+def test_reactive_scene_full_size():
+    """The 200^3, 0.01 m grid of the reactive scene, against the oracle's min-plus passes."""
+    sc = W.ReactiveScenario()
+    occ = sc.occupancy()
+    check(occ, sc.VOXEL, transform=E.edt_separable_minplus)
