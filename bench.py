@@ -228,12 +228,12 @@ def edt_bench(args) -> None:
     occs = [torch.from_numpy(o).to(dev) for o in occs_np]
     nvox = n ** 3
     need = S.smpc_edt_workspace_bytes(n, n, n)
-    work = torch.empty(need // 4, dtype=torch.int32, device=dev)
+    work = torch.empty((need + 3) // 4, dtype=torch.int32, device=dev)
     phi = torch.empty((n, n, n), device=dev)
     stream = torch.cuda.current_stream(dev).cuda_stream
 
     def edt(i):
-        st = S.smpc_edt(occs[i % pool].data_ptr(), n, n, n, sc.VOXEL, phi.data_ptr(),
+        st = S.smpc_edt(occs[i % pool].data_ptr(), n, n, n, sc.VOXEL, phi.data_ptr(), None,
                         work.data_ptr(), need, stream)
         if st != S.SMPC_OK:
             raise S.SMPCError(st, S.smpc_status_string(st))

@@ -211,34 +211,38 @@ smpc_status smpc_grid_to_f16(const float* src, void* dst, int64_t n, float clamp
 #define SMPC_EDT_MAX_SIDE 512
 
 /*
- * Device workspace smpc_edt needs for an nx x ny x nz grid: two uint32 words per
- * voxel.  Returns 0 when a side lies outside [1, SMPC_EDT_MAX_SIDE].
+ * Device workspace smpc_edt needs for an nx x ny x nz grid: six bytes per voxel.
+ * Returns 0 when a side lies outside [1, SMPC_EDT_MAX_SIDE].
  */
 size_t smpc_edt_workspace_bytes(int32_t nx, int32_t ny, int32_t nz);
 
 /*
  * Signed distance field of an occupancy grid, the map the planner reads
  * (Sec. III-B: occupied voxels are zero-distance sources of an exact separable
- * squared Euclidean distance transform, 1-D Felzenszwalb-Huttenlocher passes).
+ * squared Euclidean distance transform built from 1-D Felzenszwalb-Huttenlocher
+ * passes).
  *   occ       : device uint8 [nz][ny][nx] (x fastest); nonzero = occupied.
  *   voxel     : voxel edge in metres, finite and > 0.
- *   phi_out   : device float [nz][ny][nx], or NULL (then only `work` is filled):
+ *   phi_out   : device float [nz][ny][nx], or NULL:
  *               phi = voxel * (sqrt(D_out) - sqrt(D_in)), evaluated in float64 and
  *               rounded to float32 -- positive in free space, negative inside
  *               obstacles, in the layout smpc_grid expects.
- *   work      : device, at least smpc_edt_workspace_bytes(nx, ny, nz) bytes, must
- *               not overlap occ or phi_out.  On completion it holds uint32
- *               [2][nz][ny][nx]: [0] = D_out, the squared index distance from each
- *               voxel centre to the nearest occupied one, [1] = D_in, to the nearest
- *               free one (each 0 on its own sources; nx^2 + ny^2 + nz^2 everywhere
- *               when the grid holds no such voxel).
- * Each side must lie in [1, SMPC_EDT_MAX_SIDE]; SMPC_E_UNSUPPORTED when the device
- * cannot give one wave 256 bytes of LDS per voxel of the longer of ny and nz.
+ *   d2_out    : device uint32 [2][nz][ny][nx], or NULL: [0] = D_out, the squared
+ *               index distance from each voxel centre to the nearest occupied one,
+ *               [1] = D_in, to the nearest free one (each 0 on its own sources;
+ *               nx^2 + ny^2 + nz^2 everywhere when the grid holds no such voxel).
+ *   work      : device scratch of at least smpc_edt_workspace_bytes(nx, ny, nz)
+ *               bytes, 4-byte aligned.
+ * At least one of phi_out and d2_out is non-NULL; no two of occ, phi_out, d2_out
+ * and work overlap.  Each side must lie in [1, SMPC_EDT_MAX_SIDE];
+ * SMPC_E_UNSUPPORTED when the device cannot give one block the LDS the longer of
+ * ny and nz needs (about 264 bytes per voxel of that side).
  * Runs on the device current to the calling thread, asynchronously on `stream`;
  * the caller owns every buffer.
  */
 smpc_status smpc_edt(const uint8_t* occ, int32_t nx, int32_t ny, int32_t nz, float voxel,
-                     float* phi_out, uint32_t* work, size_t work_bytes, void* stream);
+                     float* phi_out, uint32_t* d2_out, void* work, size_t work_bytes,
+                     void* stream);
 
 /*
  * Per-kernel timing (profiling aid).  smpc_profile_enable(ctx, n) makes the next n

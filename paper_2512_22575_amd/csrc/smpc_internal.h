@@ -132,7 +132,9 @@ int launch_grid_to_f16(const float* src, void* dst, long long n, float clamp, vo
 
 constexpr int kEdtMaxSide = SMPC_EDT_MAX_SIDE;
 // Signed distance field from occupancy (smpc_edt.hip); sizes already validated.
+size_t edt_workspace_bytes(long long nvox);
+size_t edt_lds_bytes(int n_line);  // LDS of one block for lines of n_line voxels
 int launch_edt(const uint8_t* occ, int nx, int ny, int nz, float voxel, float* phi,
-               uint32_t* work, hipStream_t stream);
+               uint32_t* d2, void* work, hipStream_t stream);
 
 }  // namespace smpc

@@ -482,27 +482,34 @@ smpc_status smpc_grid_to_f16(const float* src, void* dst, int64_t n, float clamp
 size_t smpc_edt_workspace_bytes(int32_t nx, int32_t ny, int32_t nz) {
   if (nx < 1 || ny < 1 || nz < 1 || nx > kEdtMaxSide || ny > kEdtMaxSide || nz > kEdtMaxSide)
     return 0;
-  return (size_t)2 * nx * ny * nz * sizeof(uint32_t);
+  return edt_workspace_bytes((long long)nx * ny * nz);
 }
 
 smpc_status smpc_edt(const uint8_t* occ, int32_t nx, int32_t ny, int32_t nz, float voxel,
-                     float* phi_out, uint32_t* work, size_t work_bytes, void* stream) {
+                     float* phi_out, uint32_t* d2_out, void* work, size_t work_bytes,
+                     void* stream) {
   const size_t need = smpc_edt_workspace_bytes(nx, ny, nz);
-  if (!occ || !work || need == 0 || work_bytes < need || !std::isfinite(voxel) || !(voxel > 0.f))
+  if (!occ || !work || (!phi_out && !d2_out) || need == 0 || work_bytes < need ||
+      ((uintptr_t)work & 3u) || !std::isfinite(voxel) || !(voxel > 0.f))
     return SMPC_E_INVALID_ARG;
   const size_t nvox = (size_t)nx * ny * nz;
-  const auto lo = [](const void* p) { return (uintptr_t)p; };
-  const bool overlap_occ = lo(occ) < lo(work) + need && lo(work) < lo(occ) + nvox;
-  const bool overlap_phi =
-      phi_out && lo(phi_out) < lo(work) + need && lo(work) < lo(phi_out) + nvox * sizeof(float);
-  if (overlap_occ || overlap_phi) return SMPC_E_INVALID_ARG;
+  struct Span {
+    uintptr_t lo, hi;
+  };
+  const Span spans[4] = {{(uintptr_t)occ, (uintptr_t)occ + nvox},
+                         {(uintptr_t)work, (uintptr_t)work + need},
+                         {(uintptr_t)phi_out, phi_out ? (uintptr_t)phi_out + 4 * nvox : 0},
+                         {(uintptr_t)d2_out, d2_out ? (uintptr_t)d2_out + 8 * nvox : 0}};
+  for (int a = 0; a < 4; ++a)
+    for (int b = a + 1; b < 4; ++b)
+      if (spans[a].lo < spans[b].hi && spans[b].lo < spans[a].hi) return SMPC_E_INVALID_ARG;
   int dev = 0, max_lds = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
           hipSuccess)
     return SMPC_E_DEVICE;
-  if ((long long)64 * sizeof(uint32_t) * std::max(ny, nz) > max_lds) return SMPC_E_UNSUPPORTED;
-  return launch_edt(occ, nx, ny, nz, voxel, phi_out, work, (hipStream_t)stream) == 0
+  if (edt_lds_bytes(std::max(ny, nz)) > (size_t)max_lds) return SMPC_E_UNSUPPORTED;
+  return launch_edt(occ, nx, ny, nz, voxel, phi_out, d2_out, work, (hipStream_t)stream) == 0
              ? SMPC_OK
              : SMPC_E_DEVICE;
 }

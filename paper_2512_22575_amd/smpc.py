@@ -154,7 +154,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.smpc_edt_workspace_bytes.argtypes = [c_int32, c_int32, c_int32]
     lib.smpc_edt_workspace_bytes.restype = c_uint64
     lib.smpc_edt.argtypes = [c_void_p, c_int32, c_int32, c_int32, c_float, c_void_p, c_void_p,
-                             c_uint64, c_void_p]
+                             c_void_p, c_uint64, c_void_p]
     lib.smpc_edt.restype = c_int32
     lib.smpc_plan_workspace_bytes.restype = c_uint64
     lib.smpc_server_create.argtypes = [POINTER(c_void_p), c_void_p, c_uint64, c_int32]
@@ -379,12 +379,12 @@ def smpc_edt_workspace_bytes(nx: int, ny: int, nz: int) -> int:
     return int(load_library().smpc_edt_workspace_bytes(int(nx), int(ny), int(nz)))
 
 
-def smpc_edt(occ: int, nx: int, ny: int, nz: int, voxel: float, phi_out: int | None, work: int,
-             work_bytes: int, stream: int | None) -> int:
+def smpc_edt(occ: int, nx: int, ny: int, nz: int, voxel: float, phi_out: int | None,
+             d2_out: int | None, work: int, work_bytes: int, stream: int | None) -> int:
     """Signed distance field of a device occupancy grid (pointers as integers)."""
     return load_library().smpc_edt(c_void_p(occ or 0), int(nx), int(ny), int(nz), float(voxel),
-                                   c_void_p(phi_out or 0), c_void_p(work or 0), int(work_bytes),
-                                   c_void_p(stream or 0))
+                                   c_void_p(phi_out or 0), c_void_p(d2_out or 0),
+                                   c_void_p(work or 0), int(work_bytes), c_void_p(stream or 0))
 
 
 def smpc_server_create(ctx: c_void_p, hbm_budget_bytes: int, max_batch: int):

@@ -268,17 +268,20 @@ def test_server_create_without_gpu_fails_loudly(ctx):
 
 def test_edt_validates_on_host():
     need = S.smpc_edt_workspace_bytes(10, 20, 30)
-    assert need == 2 * 4 * 10 * 20 * 30
+    assert need == 6 * 10 * 20 * 30
     assert S.smpc_edt_workspace_bytes(0, 5, 5) == 0
     assert S.smpc_edt_workspace_bytes(5, 513, 5) == 0
-    assert S.smpc_edt_workspace_bytes(512, 512, 512) == 2 * 4 * 512 ** 3
-    occ, phi, work = 0x10000000, 0x20000000, 0x40000000
-    ok = dict(occ=occ, nx=10, ny=20, nz=30, voxel=0.05, phi_out=phi, work=work, work_bytes=need,
-              stream=None)
-    bad = [dict(occ=0), dict(work=0), dict(nx=0), dict(nz=513), dict(voxel=0.0),
-           dict(voxel=float("nan")), dict(work_bytes=need - 1),
-           dict(work=occ + 100),                     # overlaps the occupancy grid
-           dict(phi_out=work + need - 4)]           # overlaps the workspace
+    assert S.smpc_edt_workspace_bytes(512, 512, 512) == 6 * 512 ** 3
+    nvox = 6000
+    occ, phi, d2, work = 0x10000000, 0x20000000, 0x30000000, 0x40000000
+    ok = dict(occ=occ, nx=10, ny=20, nz=30, voxel=0.05, phi_out=phi, d2_out=d2, work=work,
+              work_bytes=need, stream=None)
+    bad = [dict(occ=0), dict(work=0), dict(phi_out=0, d2_out=0), dict(nx=0), dict(nz=513),
+           dict(voxel=0.0), dict(voxel=float("nan")), dict(work_bytes=need - 1),
+           dict(work=work + 2),                       # not 4-byte aligned
+           dict(work=occ + 100),                      # overlaps the occupancy grid
+           dict(phi_out=work + need - 4),             # overlaps the workspace
+           dict(d2_out=phi + 4 * nvox - 8)]           # overlaps the field
     for over in bad:
         assert S.smpc_edt(**{**ok, **over}) == S.SMPC_E_INVALID_ARG, over
 

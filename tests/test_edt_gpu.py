@@ -17,23 +17,28 @@ from synth import workload as W
 pytestmark = pytest.mark.gpu
 
 
-def gpu_edt(occ: np.ndarray, voxel: float, with_phi: bool = True):
+def gpu_edt(occ: np.ndarray, voxel: float, with_phi: bool = True, with_d2: bool = True):
     import torch
 
     from paper_2512_22575_amd import smpc as S
     nz, ny, nx = occ.shape
     need = S.smpc_edt_workspace_bytes(nx, ny, nz)
-    assert need == 8 * occ.size
+    assert need == 6 * occ.size
     dev = torch.device("cuda:0")
     d_occ = torch.from_numpy(np.ascontiguousarray(occ, dtype=np.uint8)).to(dev)
-    work = torch.full((2,) + occ.shape, -1, dtype=torch.int32, device=dev)
+    work = torch.full((need // 2 + 1,), -1, dtype=torch.int16, device=dev)
+    d2 = torch.full((2,) + occ.shape, -1, dtype=torch.int32, device=dev) if with_d2 else None
     phi = torch.full(occ.shape, float("nan"), device=dev) if with_phi else None
     st = S.smpc_edt(d_occ.data_ptr(), nx, ny, nz, voxel, phi.data_ptr() if with_phi else None,
-                    work.data_ptr(), need, torch.cuda.current_stream().cuda_stream)
+                    d2.data_ptr() if with_d2 else None, work.data_ptr(), need,
+                    torch.cuda.current_stream().cuda_stream)
     assert st == S.SMPC_OK, S.smpc_status_string(st)
     torch.cuda.synchronize()
-    w = work.cpu().numpy().view(np.uint32).astype(np.int64)
-    return (phi.cpu().numpy() if with_phi else None), w[0], w[1]
+    out_phi = phi.cpu().numpy() if with_phi else None
+    if not with_d2:
+        return out_phi, None, None
+    w = d2.cpu().numpy().view(np.uint32).astype(np.int64)
+    return out_phi, w[0], w[1]
 
 
 def check(occ, voxel, transform=E.edt_separable_fh):
@@ -73,13 +78,33 @@ def test_longest_side_along_each_axis(axis):
     check(occ, 0.01, transform=E.edt_separable_minplus)
 
 
-def test_work_only_without_phi():
+def test_distances_only_and_field_only():
     rng = np.random.default_rng(11)
     occ = rng.uniform(size=(10, 20, 30)) < 0.03
-    phi, d_out, d_in = gpu_edt(occ, 0.1, with_phi=False)
-    _, ref_out, ref_in = E.signed_distance(occ, 0.1)
+    voxel = float(np.float32(0.1))
+    ref_phi, ref_out, ref_in = E.signed_distance(occ, voxel)
+    phi, d_out, d_in = gpu_edt(occ, voxel, with_phi=False)
+    assert phi is None
     np.testing.assert_array_equal(d_out, ref_out)
     np.testing.assert_array_equal(d_in, ref_in)
+    phi, _, _ = gpu_edt(occ, voxel, with_d2=False)
+    np.testing.assert_array_equal(phi.view(np.uint32), ref_phi.view(np.uint32))
+
+
+def test_long_sparse_lines_and_dense_stripes():
+    """Lines with a single far source, alternating stripes (every point on the
+    envelope) and sources only at the ends stress the band merges."""
+    occ = np.zeros((9, 300, 7), bool)
+    occ[4, 0, 3] = True
+    occ[2, 299, 0] = True
+    check(occ, 0.02, transform=E.edt_separable_minplus)
+    occ = np.zeros((40, 6, 5), bool)
+    occ[::2] = True
+    check(occ, 0.02)
+    occ = np.zeros((100, 3, 3), bool)
+    occ[0] = True
+    occ[-1, 1, 1] = True
+    check(occ, 0.02, transform=E.edt_separable_minplus)
 
 
 @pytest.mark.parametrize("which", ["tiny", "mid"])
