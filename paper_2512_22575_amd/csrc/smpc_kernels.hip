@@ -744,6 +744,7 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
   float* __restrict__ weights_out = q.weights_out;
   float* __restrict__ stats_out = q.stats_out;
   __shared__ float centres[kSlots * 4];
+  __shared__ Frame frames[kNdof];
   __shared__ float sc0[2 * kNdof];
   __shared__ float red[kK2Threads / kWave];
   __shared__ float pose0;
@@ -753,16 +754,7 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
   const int n_merge = HO4 / 4;  // merge waves, 4 outputs each
 
   if (kb == 0) {
-    // --- independent fetches first: pair records, the first pass of costs, the
-    // statistics merge
-    double sv0[kCostsPerThread];
-    if (costs_out) {
-#pragma unroll
-      for (int c = 0; c < kCostsPerThread; ++c) {
-        const int i = tid + kK2Threads * c;
-        sv0[c] = i < K ? ws.S[i] : 0.0;
-      }
-    }
+    // --- independent fetches first: pair records, the statistics merge
     const bool has_pair = tid < rob->n_pairs;
     float4 pr = make_float4(0.f, 0.f, 0.f, 0.f);
     if (has_pair) pr = rob->pair_rec[tid];
@@ -777,20 +769,30 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
     }
     __syncthreads();
     if (tid == kWave) {
-      float zero[kNdof], qd0[kNdof], px[kSlots], py[kSlots], pz[kSlots];
+      // The joint frames of q0 (one thread: the chain is sequential); the sphere
+      // centres are then transformed by one thread each.
+      float zero[kNdof], qd0[kNdof];
 #pragma unroll
       for (int j = 0; j < kNdof; ++j) {
         zero[j] = 0.f;
         qd0[j] = p.qd0[j];
       }
-      const Frame T0 = fk_spheres(rob, sc0, zero, px, py, pz);
+      Frame T = identity_frame();
 #pragma unroll
-      for (int sl = 0; sl < kSlots; ++sl) {
-        centres[sl * 4 + 0] = px[sl];
-        centres[sl * 4 + 1] = py[sl];
-        centres[sl * 4 + 2] = pz[sl];
+      for (int i = 0; i < kNdof; ++i) {
+        mdh_step(T, rob->ca[i], rob->sa[i], rob->a[i], rob->d[i], sc0[kNdof + i], sc0[i]);
+        frames[i] = T;
       }
-      pose0 = pose_cost(T0, p, p.w_pose_t, p.w_pose_r) + state_limit_cost(p, zero, qd0);
+      pose0 = pose_cost(T, p, p.w_pose_t, p.w_pose_r) + state_limit_cost(p, zero, qd0);
+    }
+    __syncthreads();
+    if (tid < kSlots) {
+      float px, py, pz;
+      transform_point(frames[tid / kSpl], rob->sc[tid][0], rob->sc[tid][1], rob->sc[tid][2], px,
+                      py, pz);
+      centres[tid * 4 + 0] = px;
+      centres[tid * 4 + 1] = py;
+      centres[tid * 4 + 2] = pz;
     }
     __syncthreads();
     float part = 0.f;
@@ -825,7 +827,7 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
 #pragma unroll
         for (int c = 0; c < kCostsPerThread; ++c) {
           const int i = base + tid + kK2Threads * c;
-          sv[c] = base == 0 ? sv0[c] : (i < K ? ws.S[i] : 0.0);
+          sv[c] = i < K ? ws.S[i] : 0.0;
         }
 #pragma unroll
         for (int c = 0; c < kCostsPerThread; ++c) {
