@@ -443,7 +443,6 @@ struct K1Lds {
   float* cost;   // [R*H]
   float* sc0;    // [16]     sin(q0), cos(q0)
   float* e;      // [R]      exp(-(S - m_b)/lambda)
-  double* S;     // [R]
 };
 
 __device__ __forceinline__ K1Lds k1_lds(unsigned char* base, int R, int H) {
@@ -456,9 +455,6 @@ __device__ __forceinline__ K1Lds k1_lds(unsigned char* base, int R, int H) {
   L.cost = L.ubar + H * kNdof;
   L.sc0 = L.cost + R * H;
   L.e = L.sc0 + 16;
-  size_t off = (size_t)(reinterpret_cast<unsigned char*>(L.e + R) - base);
-  off = (off + 7) & ~size_t(7);
-  L.S = reinterpret_cast<double*>(base + off);
   return L;
 }
 
@@ -561,8 +557,10 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
   }
   __syncthreads();
 
-  // S^(m) without the k = 0 state terms (eq. 28), summed over k in double.
-  if (tid < R) {
+  // S^(m) without the k = 0 state terms (eq. 28), summed over k in double, and the
+  // block's softmax partial (eqs. 29-30 regrouped per block), by wave 0: lane r
+  // holds rollout r (R <= 64); minimum and sums go through a fixed butterfly.
+  if (tid < kWave) {
     double s = 0.0;
     if (tid < nroll) {
       const float* c_r = L.cost + tid * H;
@@ -575,27 +573,23 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
       }
       ws.S[m0 + tid] = s;
     }
-    L.S[tid] = s;
-  }
-  __syncthreads();
-
-  // Softmax partial of this block (eqs. 29-30 regrouped per block).
-  if (tid == 0) {
-    double mn = __builtin_inf();
-    for (int r = 0; r < nroll; ++r)
-      if (isfinite(L.S[r])) mn = fmin(mn, L.S[r]);
-    float Z = 0.f, Z2 = 0.f;
-    for (int r = 0; r < R; ++r) {
-      float e = 0.f;
-      if (r < nroll && isfinite(L.S[r]) && isfinite(mn))
-        e = expf(-(float)(L.S[r] - mn) * p.inv_lambda);
-      L.e[r] = e;
-      Z += e;
-      Z2 = fmaf(e, e, Z2);
+    const bool fin = tid < nroll && isfinite(s);
+    double mn = fin ? s : __builtin_inf();
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) mn = fmin(mn, __shfl_xor(mn, off, kWave));
+    const float e = (fin && isfinite(mn)) ? expf(-(float)(s - mn) * p.inv_lambda) : 0.f;
+    float Z = e, Z2 = e * e;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+      Z += __shfl_xor(Z, off, kWave);
+      Z2 += __shfl_xor(Z2, off, kWave);
     }
-    ws.part_m[b] = mn;
-    ws.part_Z[b] = Z;
-    ws.part_Z2[b] = Z2;
+    if (tid < R) L.e[tid] = e;
+    if (tid == 0) {
+      ws.part_m[b] = mn;
+      ws.part_Z[b] = Z;
+      ws.part_Z2[b] = Z2;
+    }
   }
   __syncthreads();
   // N_b[o] = sum_r e_r eps_r[o], one contiguous row per block (padded to 4 floats).
@@ -633,104 +627,72 @@ rollout_cost_batch_kernel(const DevRobot* __restrict__ rob, const Request* __res
 // ---------------------------------------------------------------------------
 
 
-
-struct MergeStats {
-  double m;   // minimum over finite S (+inf if none)
-  float Z;    // sum exp(-(S - m)/lambda)
-  float Z2;   // sum exp(-2 (S - m)/lambda)
-  float4 N;   // sum exp(-(S - m)/lambda) eps[o .. o+3] for the requested outputs (0 if none)
+// Global statistics of the block partials, by every thread of the block:
+// m = min_b m_b over finite m_b, then with c_b = exp(-(m_b - m)/lambda),
+// Z = sum_b Z_b c_b and Z2 = sum_b Z2_b c_b^2 (eqs. 29-30 regrouped).  Each thread
+// folds a fixed subset of partials in order, then waves and the block combine in a
+// fixed order, so the result is deterministic.  m = +inf when no cost is finite.
+struct GlobalStats {
+  double m;
+  float Z, Z2;
 };
 
-// Rescale a partial to a new reference minimum m_new <= a.m.
-__device__ __forceinline__ void rescale(MergeStats& a, double m_new, float inv_lambda) {
-  const float f = isfinite(a.m) ? expf(-(float)(a.m - m_new) * inv_lambda) : 0.f;
-  a.Z *= f;
-  a.Z2 *= f * f;
-  a.N.x *= f;
-  a.N.y *= f;
-  a.N.z *= f;
-  a.N.w *= f;
-  a.m = m_new;
-}
-
-// Merge the per-block partials (m_b, Z_b, Z2_b, N_b[o..o+3]) of K1 (o4 < 0: statistics
-// only).  Each lane folds a strided subset in chunks whose loads are all issued
-// before use; lanes are then merged by a butterfly with a fixed operand order, so
-// the result is deterministic and identical in every lane.
-constexpr int kMergeChunk = 8;
-
-__device__ __forceinline__ MergeStats merge_partials(const Workspace& ws, int P, int HO4, int o4,
-                                                     float inv_lambda, int lane) {
-  MergeStats acc{__builtin_inf(), 0.f, 0.f, make_float4(0.f, 0.f, 0.f, 0.f)};
-  for (int base = 0; base < P; base += kWave * kMergeChunk) {
-    double mb[kMergeChunk];
-    float zb[kMergeChunk], z2b[kMergeChunk];
-    float4 nb[kMergeChunk];
+__device__ __forceinline__ GlobalStats block_stats(const Workspace& ws, int P, float inv_lambda) {
+  __shared__ double red_m[kK2Threads / kWave];
+  __shared__ float red_z[kK2Threads / kWave], red_z2[kK2Threads / kWave];
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+  double mn = __builtin_inf();
+  for (int b = tid; b < P; b += kK2Threads) mn = fmin(mn, ws.part_m[b]);
 #pragma unroll
-    for (int c = 0; c < kMergeChunk; ++c) {
-      const int i = base + lane + kWave * c;
-      const bool v = i < P;
-      mb[c] = v ? ws.part_m[i] : __builtin_inf();
-      zb[c] = v ? ws.part_Z[i] : 0.f;
-      z2b[c] = v ? ws.part_Z2[i] : 0.f;
-      nb[c] = (v && o4 >= 0) ? *reinterpret_cast<const float4*>(ws.part_N + (size_t)i * HO4 + o4)
-                             : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-    double cm = acc.m;
+  for (int off = kWave / 2; off > 0; off >>= 1) mn = fmin(mn, __shfl_xor(mn, off, kWave));
+  if (lane == 0) red_m[w] = mn;
+  __syncthreads();
+  mn = red_m[0];
 #pragma unroll
-    for (int c = 0; c < kMergeChunk; ++c) cm = fmin(cm, mb[c]);
-    if (!isfinite(cm)) continue;
-    rescale(acc, cm, inv_lambda);
-#pragma unroll
-    for (int c = 0; c < kMergeChunk; ++c) {
-      if (!isfinite(mb[c])) continue;
-      const float sc = expf(-(float)(mb[c] - cm) * inv_lambda);
-      acc.Z = fmaf(zb[c], sc, acc.Z);
-      acc.Z2 = fmaf(z2b[c], sc * sc, acc.Z2);
-      acc.N.x = fmaf(nb[c].x, sc, acc.N.x);
-      acc.N.y = fmaf(nb[c].y, sc, acc.N.y);
-      acc.N.z = fmaf(nb[c].z, sc, acc.N.z);
-      acc.N.w = fmaf(nb[c].w, sc, acc.N.w);
+  for (int i = 1; i < kK2Threads / kWave; ++i) mn = fmin(mn, red_m[i]);
+  float Z = 0.f, Z2 = 0.f;
+  if (isfinite(mn)) {
+    for (int b = tid; b < P; b += kK2Threads) {
+      const double mb = ws.part_m[b];
+      if (!isfinite(mb)) continue;
+      const float c = expf(-(float)(mb - mn) * inv_lambda);
+      Z = fmaf(ws.part_Z[b], c, Z);
+      Z2 = fmaf(ws.part_Z2[b], c * c, Z2);
     }
   }
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) {
-    MergeStats other;
-    other.m = __shfl_xor(acc.m, off, kWave);
-    other.Z = __shfl_xor(acc.Z, off, kWave);
-    other.Z2 = __shfl_xor(acc.Z2, off, kWave);
-    other.N.x = __shfl_xor(acc.N.x, off, kWave);
-    other.N.y = __shfl_xor(acc.N.y, off, kWave);
-    other.N.z = __shfl_xor(acc.N.z, off, kWave);
-    other.N.w = __shfl_xor(acc.N.w, off, kWave);
-    const double mn = fmin(acc.m, other.m);
-    if (isfinite(mn)) {
-      const bool lower = (lane & off) == 0;
-      MergeStats lo = lower ? acc : other, hi = lower ? other : acc;
-      rescale(lo, mn, inv_lambda);
-      rescale(hi, mn, inv_lambda);
-      acc.m = mn;
-      acc.Z = lo.Z + hi.Z;
-      acc.Z2 = lo.Z2 + hi.Z2;
-      acc.N.x = lo.N.x + hi.N.x;
-      acc.N.y = lo.N.y + hi.N.y;
-      acc.N.z = lo.N.z + hi.N.z;
-      acc.N.w = lo.N.w + hi.N.w;
-    }
+    Z += __shfl_xor(Z, off, kWave);
+    Z2 += __shfl_xor(Z2, off, kWave);
   }
-  return acc;
+  if (lane == 0) {
+    red_z[w] = Z;
+    red_z2[w] = Z2;
+  }
+  __syncthreads();
+  Z = red_z[0];
+  Z2 = red_z2[0];
+#pragma unroll
+  for (int i = 1; i < kK2Threads / kWave; ++i) {
+    Z += red_z[i];
+    Z2 += red_z2[i];
+  }
+  return {mn, Z, Z2};
 }
 
 // State terms of state 0 (pose, environment, self, q/qd limits, null space) are the
 // same for every rollout (reading of eq. 28 at k = 0); K2's block 0 evaluates them
-// once: one thread runs the forward kinematics, then the lookups and the pairs are
-// spread over the block.  Everything that does not depend on them (pair records,
-// the costs to be shifted, the statistics merge) is fetched first.
+// once: one thread runs the forward kinematics, then the sphere centres, lookups
+// and pairs are spread over the block.
 //
-// Grid of K2: block 0 as above (costs and statistics); then one wave per four
-// outputs o in [0, 7H) merges the block partials into U*[o]; then one wave per
-// chunk of kWeightsPerWave rollouts writes the weights.
+// Grid of K2: block 0 as above (costs and statistics); then one block per
+// kOutPerBlock outputs o in [0, 7H) merges the block partials into U*[o]: thread t
+// folds partial rows b = t / kOutPerBlock (mod kRowGroups) of output t % kOutPerBlock,
+// so one load instruction of a wave reads 4 rows x 64 contiguous bytes; then one
+// block per kWeightsPerBlock rollouts writes the weights.
 constexpr int kCostsPerThread = 32;   // K <= kK2Threads * kCostsPerThread per pass
+constexpr int kRowGroups = kK2Threads / kOutPerBlock;
+constexpr int kWeightsPerThread = kWeightsPerBlock / kK2Threads;
 
 template <int kElemBytes>
 __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, const Request& q,
@@ -746,21 +708,18 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
   __shared__ float centres[kSlots * 4];
   __shared__ Frame frames[kNdof];
   __shared__ float sc0[2 * kNdof];
-  __shared__ float red[kK2Threads / kWave];
+  __shared__ float red[kK2Threads];
   __shared__ float pose0;
   const int lane = threadIdx.x & (kWave - 1);
   const int tid = threadIdx.x;
   const int K = p.K, P = p.P, HO = p.H * kNdof, HO4 = (HO + 3) & ~3;
-  const int n_merge = HO4 / 4;  // merge waves, 4 outputs each
+  const int n_out_blocks = (HO + kOutPerBlock - 1) / kOutPerBlock;
 
   if (kb == 0) {
-    // --- independent fetches first: pair records, the statistics merge
+    // --- independent fetches first: pair records
     const bool has_pair = tid < rob->n_pairs;
     float4 pr = make_float4(0.f, 0.f, 0.f, 0.f);
     if (has_pair) pr = rob->pair_rec[tid];
-    MergeStats st{};
-    if (stats_out && tid < kWave) st = merge_partials(ws, P, HO4, -1, p.inv_lambda, lane);
-    // --- forward kinematics of q0 (one thread) and the terms of q0 alone
     if (tid < kNdof) {
       float s_, c_;
       sincosf(p.q0[tid], &s_, &c_);
@@ -785,6 +744,8 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
       }
       pose0 = pose_cost(T, p, p.w_pose_t, p.w_pose_r) + state_limit_cost(p, zero, qd0);
     }
+    GlobalStats st{__builtin_inf(), 0.f, 0.f};
+    if (stats_out) st = block_stats(ws, P, p.inv_lambda);  // holds barriers
     __syncthreads();
     if (tid < kSlots) {
       float px, py, pz;
@@ -799,7 +760,7 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
     if (tid < kSlots && (rob->slot_active & (1u << tid))) {
       const __amdgpu_buffer_rsrc_t rsrc = grid_resource(grid, p.grid_bytes);
       const float phi = esdf_lookup<kElemBytes>(rsrc, p, centres[tid * 4], centres[tid * 4 + 1],
-                                    centres[tid * 4 + 2]);
+                                                centres[tid * 4 + 2]);
       const float h = fmaxf(p.env_thr[tid] - phi, 0.f);
       part = p.w_env * h * h;
     }
@@ -846,55 +807,68 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
     return;
   }
 
-  const int wave = (kb - 1) * (kK2Threads / kWave) + (threadIdx.x / kWave);
-  const int n_chunks = weights_out ? (K + kWeightsPerWave - 1) / kWeightsPerWave : 0;
-  if (wave >= n_merge + n_chunks) return;
-  const bool is_chunk = wave >= n_merge;
-
-  // Prefetch the chunk's costs so that both memory rounds overlap.
-  constexpr int kPerLane = kWeightsPerWave / kWave;
-  const int lo = (wave - n_merge) * kWeightsPerWave;
-  const int hi = min(K, lo + kWeightsPerWave);
-  double sv[kPerLane];
-  if (is_chunk) {
-#pragma unroll
-    for (int c = 0; c < kPerLane; ++c) {
-      const int i = lo + lane + kWave * c;
-      sv[c] = i < hi ? ws.S[i] : 0.0;
-    }
-  }
-  const int o4 = is_chunk ? -1 : 4 * wave;
-  const MergeStats st = merge_partials(ws, P, HO4, o4, p.inv_lambda, lane);
+  const int ob = kb - 1;  // output block, or weight block after them
+  if (ob >= n_out_blocks && !weights_out) return;
+  const GlobalStats st = block_stats(ws, P, p.inv_lambda);
   const bool ok = isfinite(st.m);
 
-  if (!is_chunk) {
-    // U*[o] = Ubar[o] + sum_b N_b[o] exp(-(m_b - m)/lambda) / Z   (eq. 30)
-    if (lane < 4) {
-      const int o = o4 + lane;
-      const float n = lane == 0 ? st.N.x : lane == 1 ? st.N.y : lane == 2 ? st.N.z : st.N.w;
-      if (o < HO) {
-        const float u = ok ? U_in[o] + n / st.Z : U_in[o];
-        if (!q.shift_out) {
-          U_out[o] = u;
-        } else {
-          // Receding-horizon warm start: U_out = [u*_1 .. u*_{H-1}, 0], u0_out = u*_0.
-          if (o < kNdof) {
-            if (q.u0_out) q.u0_out[o] = u;
-          } else {
-            U_out[o - kNdof] = u;
-          }
-          if (o >= HO - kNdof) U_out[o] = 0.f;
+  if (ob < n_out_blocks) {
+    // U*[o] = Ubar[o] + sum_b N_b[o] c_b / Z   (eq. 30)
+    const int oi = tid % kOutPerBlock, g = tid / kOutPerBlock;
+    const int o = ob * kOutPerBlock + oi;
+    float acc = 0.f;
+    if (ok && o < HO) {
+      constexpr int kBatch = 8;
+      for (int b0 = g; b0 < P; b0 += kRowGroups * kBatch) {
+        float nv[kBatch];
+        double mv[kBatch];
+#pragma unroll
+        for (int c = 0; c < kBatch; ++c) {
+          const int b = min(b0 + kRowGroups * c, P - 1);
+          nv[c] = ws.part_N[(size_t)b * HO4 + o];
+          mv[c] = ws.part_m[b];
         }
+#pragma unroll
+        for (int c = 0; c < kBatch; ++c) {
+          if (b0 + kRowGroups * c < P && isfinite(mv[c]))
+            acc = fmaf(nv[c], expf(-(float)(mv[c] - st.m) * p.inv_lambda), acc);
+        }
+      }
+    }
+    red[tid] = acc;
+    __syncthreads();
+    if (g == 0 && o < HO) {
+      float n = 0.f;
+#pragma unroll
+      for (int r = 0; r < kRowGroups; ++r) n += red[r * kOutPerBlock + oi];
+      const float u = ok ? U_in[o] + n / st.Z : U_in[o];
+      if (!q.shift_out) {
+        U_out[o] = u;
+      } else {
+        // Receding-horizon warm start: U_out = [u*_1 .. u*_{H-1}, 0], u0_out = u*_0.
+        if (o < kNdof) {
+          if (q.u0_out) q.u0_out[o] = u;
+        } else {
+          U_out[o - kNdof] = u;
+        }
+        if (o >= HO - kNdof) U_out[o] = 0.f;
       }
     }
     return;
   }
-  // w^(m) (eq. 29) for this chunk of rollouts.
+  // w^(m) (eq. 29) for this block's rollouts.
+  const int lo = (ob - n_out_blocks) * kWeightsPerBlock;
   const float invZ = ok ? 1.f / st.Z : 0.f;
+  double sv[kWeightsPerThread];
 #pragma unroll
-  for (int c = 0; c < kPerLane; ++c) {
-    const int i = lo + lane + kWave * c;
-    if (i >= hi) continue;
+  for (int c = 0; c < kWeightsPerThread; ++c) {
+    const int i = min(lo + tid + kK2Threads * c, K - 1);
+    sv[c] = ws.S[i];
+  }
+#pragma unroll
+  for (int c = 0; c < kWeightsPerThread; ++c) {
+    const int i = lo + tid + kK2Threads * c;
+    if (i >= K) continue;
     float w = 0.f;
     if (ok && isfinite(sv[c])) w = expf(-(float)(sv[c] - st.m) * p.inv_lambda) * invZ;
     weights_out[i] = w;
@@ -954,10 +928,8 @@ __global__ __launch_bounds__(256) void grid_to_f16_kernel(const float* __restric
 // ---------------------------------------------------------------------------
 
 static size_t k1_lds_bytes(int R, int H) {
-  size_t floats = (size_t)R * H * kNdof * 3 + (size_t)H * kNdof + (size_t)R * H + 16 + R;
-  size_t bytes = floats * 4;
-  bytes = (bytes + 7) & ~size_t(7);
-  return bytes + (size_t)R * 8;
+  const size_t floats = (size_t)R * H * kNdof * 3 + (size_t)H * kNdof + (size_t)R * H + 16 + R;
+  return floats * 4;
 }
 
 LaunchConfig plan_launch_config(int K, int H) {
@@ -972,10 +944,8 @@ LaunchConfig plan_launch_config(int K, int H) {
   lc.k1_threads = kK1Threads;
   lc.P = (K + R - 1) / R;
   lc.k1_lds = k1_lds_bytes(R, H);
-  const int waves_per_block = kK2Threads / kWave;
-  const int HO4 = (H * kNdof + 3) & ~3;
-  const int work_waves = HO4 / 4 + (K + kWeightsPerWave - 1) / kWeightsPerWave;
-  lc.k2_blocks = 1 + (work_waves + waves_per_block - 1) / waves_per_block;
+  lc.k2_blocks = 1 + (H * kNdof + kOutPerBlock - 1) / kOutPerBlock +
+                 (K + kWeightsPerBlock - 1) / kWeightsPerBlock;
   return lc;
 }
 
