@@ -16,7 +16,7 @@ constexpr int kMaxPairs = SMPC_MAX_PAIRS;
 constexpr int kMaxH = SMPC_MAX_H;
 constexpr int kK1Threads = 320;               // rollout-cost block size (5 waves)
 constexpr int kK2Threads = 256;               // reduce/update block size
-constexpr int kOutPerBlock = 16;              // U* outputs merged per K2 block
+constexpr int kOutPerBlock = 8;               // U* outputs merged per K2 block
 constexpr int kWeightsPerBlock = 1024;        // weights_out elements per K2 block
 
 // Robot constants in device memory.  Every field is read at a wave-uniform

@@ -627,55 +627,58 @@ rollout_cost_batch_kernel(const DevRobot* __restrict__ rob, const Request* __res
 // ---------------------------------------------------------------------------
 
 
-// Global statistics of the block partials, by every thread of the block:
+// Global statistics of the block partials, computed by one whole wave:
 // m = min_b m_b over finite m_b, then with c_b = exp(-(m_b - m)/lambda),
-// Z = sum_b Z_b c_b and Z2 = sum_b Z2_b c_b^2 (eqs. 29-30 regrouped).  Each thread
-// folds a fixed subset of partials in order, then waves and the block combine in a
-// fixed order, so the result is deterministic.  m = +inf when no cost is finite.
+// Z = sum_b Z_b c_b and Z2 = sum_b Z2_b c_b^2 (eqs. 29-30 regrouped).  Lane l folds
+// rows b = l + 64 c in order and the lanes combine through a fixed butterfly, so
+// every wave that calls this (in any block) gets bitwise the same result, with no
+// barrier.  The first kStatRows rows per lane are loaded in one round and kept;
+// larger P reloads the rest.  m = +inf when no cost is finite.
 struct GlobalStats {
   double m;
   float Z, Z2;
 };
+constexpr int kStatRows = 8;
 
-__device__ __forceinline__ GlobalStats block_stats(const Workspace& ws, int P, float inv_lambda) {
-  __shared__ double red_m[kK2Threads / kWave];
-  __shared__ float red_z[kK2Threads / kWave], red_z2[kK2Threads / kWave];
-  const int tid = threadIdx.x, lane = tid & (kWave - 1), w = tid / kWave;
+__device__ __forceinline__ GlobalStats wave_stats(const Workspace& ws, int P, float inv_lambda,
+                                                  int lane) {
+  double m0[kStatRows];
+  float z0[kStatRows], z20[kStatRows];
+#pragma unroll
+  for (int c = 0; c < kStatRows; ++c) {
+    const int b = min(lane + kWave * c, P - 1);
+    m0[c] = ws.part_m[b];
+    z0[c] = ws.part_Z[b];
+    z20[c] = ws.part_Z2[b];
+  }
   double mn = __builtin_inf();
-  for (int b = tid; b < P; b += kK2Threads) mn = fmin(mn, ws.part_m[b]);
+#pragma unroll
+  for (int c = 0; c < kStatRows; ++c)
+    if (lane + kWave * c < P) mn = fmin(mn, m0[c]);
+  for (int b = lane + kWave * kStatRows; b < P; b += kWave) mn = fmin(mn, ws.part_m[b]);
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) mn = fmin(mn, __shfl_xor(mn, off, kWave));
-  if (lane == 0) red_m[w] = mn;
-  __syncthreads();
-  mn = red_m[0];
-#pragma unroll
-  for (int i = 1; i < kK2Threads / kWave; ++i) mn = fmin(mn, red_m[i]);
   float Z = 0.f, Z2 = 0.f;
   if (isfinite(mn)) {
-    for (int b = tid; b < P; b += kK2Threads) {
+#pragma unroll
+    for (int c = 0; c < kStatRows; ++c) {
+      if (lane + kWave * c >= P || !isfinite(m0[c])) continue;
+      const float e = expf(-(float)(m0[c] - mn) * inv_lambda);
+      Z = fmaf(z0[c], e, Z);
+      Z2 = fmaf(z20[c], e * e, Z2);
+    }
+    for (int b = lane + kWave * kStatRows; b < P; b += kWave) {
       const double mb = ws.part_m[b];
       if (!isfinite(mb)) continue;
-      const float c = expf(-(float)(mb - mn) * inv_lambda);
-      Z = fmaf(ws.part_Z[b], c, Z);
-      Z2 = fmaf(ws.part_Z2[b], c * c, Z2);
+      const float e = expf(-(float)(mb - mn) * inv_lambda);
+      Z = fmaf(ws.part_Z[b], e, Z);
+      Z2 = fmaf(ws.part_Z2[b], e * e, Z2);
     }
   }
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) {
     Z += __shfl_xor(Z, off, kWave);
     Z2 += __shfl_xor(Z2, off, kWave);
-  }
-  if (lane == 0) {
-    red_z[w] = Z;
-    red_z2[w] = Z2;
-  }
-  __syncthreads();
-  Z = red_z[0];
-  Z2 = red_z2[0];
-#pragma unroll
-  for (int i = 1; i < kK2Threads / kWave; ++i) {
-    Z += red_z[i];
-    Z2 += red_z2[i];
   }
   return {mn, Z, Z2};
 }
@@ -688,10 +691,11 @@ __device__ __forceinline__ GlobalStats block_stats(const Workspace& ws, int P, f
 // Grid of K2: block 0 as above (costs and statistics); then one block per
 // kOutPerBlock outputs o in [0, 7H) merges the block partials into U*[o]: thread t
 // folds partial rows b = t / kOutPerBlock (mod kRowGroups) of output t % kOutPerBlock,
-// so one load instruction of a wave reads 4 rows x 64 contiguous bytes; then one
+// so one load instruction of a wave reads 8 rows x 32 contiguous bytes; then one
 // block per kWeightsPerBlock rollouts writes the weights.
 constexpr int kCostsPerThread = 32;   // K <= kK2Threads * kCostsPerThread per pass
 constexpr int kRowGroups = kK2Threads / kOutPerBlock;
+constexpr int kRowsAhead = 16;  // partial rows per thread loaded before the statistics
 constexpr int kWeightsPerThread = kWeightsPerBlock / kK2Threads;
 
 template <int kElemBytes>
@@ -745,7 +749,7 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
       pose0 = pose_cost(T, p, p.w_pose_t, p.w_pose_r) + state_limit_cost(p, zero, qd0);
     }
     GlobalStats st{__builtin_inf(), 0.f, 0.f};
-    if (stats_out) st = block_stats(ws, P, p.inv_lambda);  // holds barriers
+    if (stats_out && tid < kWave) st = wave_stats(ws, P, p.inv_lambda, lane);
     __syncthreads();
     if (tid < kSlots) {
       float px, py, pz;
@@ -809,29 +813,53 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
 
   const int ob = kb - 1;  // output block, or weight block after them
   if (ob >= n_out_blocks && !weights_out) return;
-  const GlobalStats st = block_stats(ws, P, p.inv_lambda);
+  // The loads of this block's partial rows (or costs) are issued before the
+  // statistics, which they do not depend on, so both memory rounds overlap.
+  const int oi = tid % kOutPerBlock, g = tid / kOutPerBlock;
+  const int o = ob * kOutPerBlock + oi;
+  const int o_rd = min(o, HO4 - 1);
+  const bool is_out = ob < n_out_blocks;
+  float nv[kRowsAhead];
+  double mv[kRowsAhead];
+  const int lo = (ob - n_out_blocks) * kWeightsPerBlock;
+  double sv[kWeightsPerThread];
+  if (is_out) {
+#pragma unroll
+    for (int c = 0; c < kRowsAhead; ++c) {
+      const int b = min(g + kRowGroups * c, P - 1);
+      nv[c] = ws.part_N[(size_t)b * HO4 + o_rd];
+      mv[c] = ws.part_m[b];
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < kWeightsPerThread; ++c) sv[c] = ws.S[min(lo + tid + kK2Threads * c, K - 1)];
+  }
+  const GlobalStats st = wave_stats(ws, P, p.inv_lambda, lane);
   const bool ok = isfinite(st.m);
 
-  if (ob < n_out_blocks) {
+  if (is_out) {
     // U*[o] = Ubar[o] + sum_b N_b[o] c_b / Z   (eq. 30)
-    const int oi = tid % kOutPerBlock, g = tid / kOutPerBlock;
-    const int o = ob * kOutPerBlock + oi;
     float acc = 0.f;
     if (ok && o < HO) {
+#pragma unroll
+      for (int c = 0; c < kRowsAhead; ++c) {
+        if (g + kRowGroups * c < P && isfinite(mv[c]))
+          acc = fmaf(nv[c], expf(-(float)(mv[c] - st.m) * p.inv_lambda), acc);
+      }
       constexpr int kBatch = 8;
-      for (int b0 = g; b0 < P; b0 += kRowGroups * kBatch) {
-        float nv[kBatch];
-        double mv[kBatch];
+      for (int b0 = g + kRowGroups * kRowsAhead; b0 < P; b0 += kRowGroups * kBatch) {
+        float nb[kBatch];
+        double mb[kBatch];
 #pragma unroll
         for (int c = 0; c < kBatch; ++c) {
           const int b = min(b0 + kRowGroups * c, P - 1);
-          nv[c] = ws.part_N[(size_t)b * HO4 + o];
-          mv[c] = ws.part_m[b];
+          nb[c] = ws.part_N[(size_t)b * HO4 + o];
+          mb[c] = ws.part_m[b];
         }
 #pragma unroll
         for (int c = 0; c < kBatch; ++c) {
-          if (b0 + kRowGroups * c < P && isfinite(mv[c]))
-            acc = fmaf(nv[c], expf(-(float)(mv[c] - st.m) * p.inv_lambda), acc);
+          if (b0 + kRowGroups * c < P && isfinite(mb[c]))
+            acc = fmaf(nb[c], expf(-(float)(mb[c] - st.m) * p.inv_lambda), acc);
         }
       }
     }
@@ -857,14 +885,7 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
     return;
   }
   // w^(m) (eq. 29) for this block's rollouts.
-  const int lo = (ob - n_out_blocks) * kWeightsPerBlock;
   const float invZ = ok ? 1.f / st.Z : 0.f;
-  double sv[kWeightsPerThread];
-#pragma unroll
-  for (int c = 0; c < kWeightsPerThread; ++c) {
-    const int i = min(lo + tid + kK2Threads * c, K - 1);
-    sv[c] = ws.S[i];
-  }
 #pragma unroll
   for (int c = 0; c < kWeightsPerThread; ++c) {
     const int i = lo + tid + kK2Threads * c;
