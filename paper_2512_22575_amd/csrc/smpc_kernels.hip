@@ -640,21 +640,29 @@ struct GlobalStats {
 };
 constexpr int kStatRows = 8;
 
-__device__ __forceinline__ GlobalStats wave_stats(const Workspace& ws, int P, float inv_lambda,
-                                                  int lane) {
-  double m0[kStatRows];
-  float z0[kStatRows], z20[kStatRows];
+// Rows of the first round, loaded by stats_load and folded by stats_finish (so a
+// caller can issue the loads early and overlap their latency with other work).
+struct StatRows {
+  double m[kStatRows];
+  float z[kStatRows], z2[kStatRows];
+};
+
+__device__ __forceinline__ void stats_load(const Workspace& ws, int P, int lane, StatRows& r) {
 #pragma unroll
   for (int c = 0; c < kStatRows; ++c) {
     const int b = min(lane + kWave * c, P - 1);
-    m0[c] = ws.part_m[b];
-    z0[c] = ws.part_Z[b];
-    z20[c] = ws.part_Z2[b];
+    r.m[c] = ws.part_m[b];
+    r.z[c] = ws.part_Z[b];
+    r.z2[c] = ws.part_Z2[b];
   }
+}
+
+__device__ __forceinline__ GlobalStats stats_finish(const Workspace& ws, int P, float inv_lambda,
+                                                    int lane, const StatRows& r) {
   double mn = __builtin_inf();
 #pragma unroll
   for (int c = 0; c < kStatRows; ++c)
-    if (lane + kWave * c < P) mn = fmin(mn, m0[c]);
+    if (lane + kWave * c < P) mn = fmin(mn, r.m[c]);
   for (int b = lane + kWave * kStatRows; b < P; b += kWave) mn = fmin(mn, ws.part_m[b]);
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) mn = fmin(mn, __shfl_xor(mn, off, kWave));
@@ -662,10 +670,10 @@ __device__ __forceinline__ GlobalStats wave_stats(const Workspace& ws, int P, fl
   if (isfinite(mn)) {
 #pragma unroll
     for (int c = 0; c < kStatRows; ++c) {
-      if (lane + kWave * c >= P || !isfinite(m0[c])) continue;
-      const float e = expf(-(float)(m0[c] - mn) * inv_lambda);
-      Z = fmaf(z0[c], e, Z);
-      Z2 = fmaf(z20[c], e * e, Z2);
+      if (lane + kWave * c >= P || !isfinite(r.m[c])) continue;
+      const float e = expf(-(float)(r.m[c] - mn) * inv_lambda);
+      Z = fmaf(r.z[c], e, Z);
+      Z2 = fmaf(r.z2[c], e * e, Z2);
     }
     for (int b = lane + kWave * kStatRows; b < P; b += kWave) {
       const double mb = ws.part_m[b];
@@ -683,6 +691,13 @@ __device__ __forceinline__ GlobalStats wave_stats(const Workspace& ws, int P, fl
   return {mn, Z, Z2};
 }
 
+__device__ __forceinline__ GlobalStats wave_stats(const Workspace& ws, int P, float inv_lambda,
+                                                  int lane) {
+  StatRows r;
+  stats_load(ws, P, lane, r);
+  return stats_finish(ws, P, inv_lambda, lane, r);
+}
+
 // State terms of state 0 (pose, environment, self, q/qd limits, null space) are the
 // same for every rollout (reading of eq. 28 at k = 0); K2's block 0 evaluates them
 // once: one thread runs the forward kinematics, then the sphere centres, lookups
@@ -693,7 +708,8 @@ __device__ __forceinline__ GlobalStats wave_stats(const Workspace& ws, int P, fl
 // folds partial rows b = t / kOutPerBlock (mod kRowGroups) of output t % kOutPerBlock,
 // so one load instruction of a wave reads 8 rows x 32 contiguous bytes; then one
 // block per kWeightsPerBlock rollouts writes the weights.
-constexpr int kCostsPerThread = 32;   // K <= kK2Threads * kCostsPerThread per pass
+constexpr int kCostsPerThread = 32;   // costs per thread per later pass
+constexpr int kCostsAhead = 16;       // costs per thread loaded before c0 (K <= 4096)
 constexpr int kRowGroups = kK2Threads / kOutPerBlock;
 constexpr int kRowsAhead = 16;  // partial rows per thread loaded before the statistics
 constexpr int kWeightsPerThread = kWeightsPerBlock / kK2Threads;
@@ -720,10 +736,18 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
   const int n_out_blocks = (HO + kOutPerBlock - 1) / kOutPerBlock;
 
   if (kb == 0) {
-    // --- independent fetches first: pair records
+    // --- independent fetches first: pair records, the statistics rows (wave 0)
+    // and the first pass of costs to shift
     const bool has_pair = tid < rob->n_pairs;
     float4 pr = make_float4(0.f, 0.f, 0.f, 0.f);
     if (has_pair) pr = rob->pair_rec[tid];
+    StatRows rows;
+    if (stats_out && tid < kWave) stats_load(ws, P, lane, rows);
+    double sv0[kCostsAhead];
+    if (costs_out) {
+#pragma unroll
+      for (int c = 0; c < kCostsAhead; ++c) sv0[c] = ws.S[min(tid + kK2Threads * c, K - 1)];
+    }
     if (tid < kNdof) {
       float s_, c_;
       sincosf(p.q0[tid], &s_, &c_);
@@ -748,8 +772,6 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
       }
       pose0 = pose_cost(T, p, p.w_pose_t, p.w_pose_r) + state_limit_cost(p, zero, qd0);
     }
-    GlobalStats st{__builtin_inf(), 0.f, 0.f};
-    if (stats_out && tid < kWave) st = wave_stats(ws, P, p.inv_lambda, lane);
     __syncthreads();
     if (tid < kSlots) {
       float px, py, pz;
@@ -787,7 +809,12 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
     for (int w = 0; w < kK2Threads / kWave; ++w) c0 += red[w];
     // --- costs S = S' + c0 (eq. 28) and statistics
     if (costs_out) {
-      for (int base = 0; base < K; base += kK2Threads * kCostsPerThread) {
+#pragma unroll
+      for (int c = 0; c < kCostsAhead; ++c) {
+        const int i = tid + kK2Threads * c;
+        if (i < K) costs_out[i] = (float)(sv0[c] + (double)c0);
+      }
+      for (int base = kK2Threads * kCostsAhead; base < K; base += kK2Threads * kCostsPerThread) {
         double sv[kCostsPerThread];
 #pragma unroll
         for (int c = 0; c < kCostsPerThread; ++c) {
@@ -801,6 +828,8 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
         }
       }
     }
+    GlobalStats st{__builtin_inf(), 0.f, 0.f};
+    if (stats_out && tid < kWave) st = stats_finish(ws, P, p.inv_lambda, lane, rows);
     if (stats_out && tid == 0) {
       const bool ok = isfinite(st.m);
       stats_out[0] = ok ? (float)(st.m + (double)c0) : __builtin_nanf("");
