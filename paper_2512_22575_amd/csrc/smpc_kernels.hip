@@ -443,7 +443,12 @@ struct K1Lds {
   float* cost;   // [R*H]
   float* sc0;    // [16]     sin(q0), cos(q0)
   float* e;      // [R]      exp(-(S - m_b)/lambda)
+  float* seg;    // [R*7*nseg*2] velocity / displacement increments of 8-step segments
 };
+
+constexpr int kSeg = 8;  // integration segment length
+
+__host__ __device__ constexpr int k1_segments(int H) { return (H + kSeg - 1) / kSeg; }
 
 __device__ __forceinline__ K1Lds k1_lds(unsigned char* base, int R, int H) {
   K1Lds L;
@@ -455,6 +460,7 @@ __device__ __forceinline__ K1Lds k1_lds(unsigned char* base, int R, int H) {
   L.cost = L.ubar + H * kNdof;
   L.sc0 = L.cost + R * H;
   L.e = L.sc0 + 16;
+  L.seg = L.e + R;
   return L;
 }
 
@@ -489,9 +495,21 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
       for (int j = 0; j < kNdof; ++j) L.eps[t * kNdof + j] = r < nroll ? p.sigma[j] * z[j] : 0.f;
     }
   } else {
+    // All loads of a thread are issued before any is stored (indices clamped into
+    // range, so no load sits behind a branch).
     const float* src = noise + (size_t)m0 * H * kNdof;
     const int n_eps = nroll * H * kNdof;
-    for (int i = tid; i < RH * kNdof; i += nthreads) L.eps[i] = (i < n_eps) ? src[i] : 0.f;
+    constexpr int kLoads = 8;
+    for (int i0 = tid; i0 < RH * kNdof; i0 += nthreads * kLoads) {
+      float v[kLoads];
+#pragma unroll
+      for (int c = 0; c < kLoads; ++c) v[c] = src[min(i0 + c * nthreads, n_eps - 1)];
+#pragma unroll
+      for (int c = 0; c < kLoads; ++c) {
+        const int i = i0 + c * nthreads;
+        if (i < RH * kNdof) L.eps[i] = i < n_eps ? v[c] : 0.f;
+      }
+    }
   }
   for (int i = tid; i < H * kNdof; i += nthreads) L.ubar[i] = U_in[i];
   if (tid < kNdof) {
@@ -502,35 +520,69 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
   }
   __syncthreads();
 
-  // Roll out eq. 7 (semi-implicit Euler) per (rollout, joint), relative to (q0, qd0).
-  // Strided: a block has R*H threads, which is fewer than R*7 when H < 7.  The
-  // controls of 8 steps are read before the dependent updates so that the LDS
-  // latency is paid once per 8 steps.
-  for (int w = tid; w < R * kNdof; w += nthreads) {
-    const int r = w / kNdof, j = w - r * kNdof;
+  // Roll out eq. 7 (semi-implicit Euler) per (rollout, joint), relative to (q0, qd0),
+  // in segments of kSeg steps so that the dependent chain stays short: every
+  // (rollout, joint, segment) item first integrates its segment from a zero start
+  // (velocity increment dv, displacement dx), then starts from the state the earlier
+  // segments reach (a segment of n steps entered with velocity offset v moves
+  // dx + n dt v) and replays its steps.
+  const int nseg = k1_segments(H);
+  const int n_items = R * kNdof * nseg;
+  for (int w = tid; w < n_items; w += nthreads) {
+    const int sg = w % nseg, rj = w / nseg, r = rj / kNdof, j = rj - r * kNdof;
     if (r < nroll) {
       const float dt = p.dt, qd0 = p.qd0[j];
-      float dqd = 0.f, dq = 0.f;
+      const int k0 = sg * kSeg;
       const float* eps_r = L.eps + r * H * kNdof + j;
+      float u[kSeg];
+#pragma unroll
+      for (int c = 0; c < kSeg; ++c) {
+        const int k = min(k0 + c, H - 1);
+        u[c] = L.ubar[k * kNdof + j] + eps_r[k * kNdof];  // eq. 27
+      }
+      float dv = 0.f, dx = 0.f;
+#pragma unroll
+      for (int c = 0; c < kSeg; ++c) {
+        if (k0 + c < H) {
+          dv = fmaf(u[c], dt, dv);
+          dx = fmaf(qd0 + dv, dt, dx);
+        }
+      }
+      L.seg[2 * w] = dv;
+      L.seg[2 * w + 1] = dx;
+    }
+  }
+  __syncthreads();
+  for (int w = tid; w < n_items; w += nthreads) {
+    const int sg = w % nseg, rj = w / nseg, r = rj / kNdof, j = rj - r * kNdof;
+    if (r < nroll) {
+      const float dt = p.dt, qd0 = p.qd0[j];
+      const int k0 = sg * kSeg;
+      const float* eps_r = L.eps + r * H * kNdof + j;
+      float u[kSeg];
+#pragma unroll
+      for (int c = 0; c < kSeg; ++c) {
+        const int k = min(k0 + c, H - 1);
+        u[c] = L.ubar[k * kNdof + j] + eps_r[k * kNdof];
+      }
+      float dqd = 0.f, dq = 0.f;
+      const float full = (float)kSeg * dt;
+      for (int s2 = 0; s2 < sg; ++s2) {  // earlier segments are full
+        const float dv = L.seg[2 * (rj * nseg + s2)], dx = L.seg[2 * (rj * nseg + s2) + 1];
+        dq = fmaf(full, dqd, dq + dx);
+        dqd += dv;
+      }
       float* dq_r = L.dq + r * H * kNdof + j;
       float* qd_r = L.qd + r * H * kNdof + j;
-      for (int k0 = 0; k0 < H; k0 += 8) {
-        float u[8];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          const int k = k0 + c;
-          u[c] = k < H ? L.ubar[k * kNdof + j] + eps_r[k * kNdof] : 0.f;  // eq. 27
-        }
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          const int k = k0 + c;
-          if (k < H) {
-            dqd = fmaf(u[c], dt, dqd);
-            const float qd = qd0 + dqd;
-            dq = fmaf(qd, dt, dq);
-            dq_r[k * kNdof] = dq;
-            qd_r[k * kNdof] = qd;
-          }
+      for (int c = 0; c < kSeg; ++c) {
+        const int k = k0 + c;
+        if (k < H) {
+          dqd = fmaf(u[c], dt, dqd);
+          const float qd = qd0 + dqd;
+          dq = fmaf(qd, dt, dq);
+          dq_r[k * kNdof] = dq;
+          qd_r[k * kNdof] = qd;
         }
       }
     }
@@ -564,13 +616,12 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
     double s = 0.0;
     if (tid < nroll) {
       const float* c_r = L.cost + tid * H;
-      for (int k0 = 0; k0 < H; k0 += 8) {
-        float c8[8];
+      float cv[kMaxH];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) c8[c] = (k0 + c < H) ? c_r[k0 + c] : 0.f;
+      for (int k = 0; k < kMaxH; ++k) cv[k] = c_r[min(k, H - 1)];
 #pragma unroll
-        for (int c = 0; c < 8; ++c) s += (double)c8[c];
-      }
+      for (int k = 0; k < kMaxH; ++k)
+        if (k < H) s += (double)cv[k];
       ws.S[m0 + tid] = s;
     }
     const bool fin = tid < nroll && isfinite(s);
@@ -597,9 +648,17 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
   for (int o = tid; o < HO4; o += nthreads) {
     float acc = 0.f;
     if (o < HO) {
-      for (int r = 0; r < nroll; ++r) {
-        const float e = L.e[r];
-        if (e > 0.f) acc = fmaf(e, L.eps[r * HO + o], acc);  // weight-0 rollouts excluded
+      for (int r0 = 0; r0 < nroll; r0 += 8) {
+        float ev[8], xv[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const int r = min(r0 + c, nroll - 1);
+          ev[c] = L.e[r];
+          xv[c] = L.eps[r * HO + o];
+        }
+#pragma unroll
+        for (int c = 0; c < 8; ++c)  // weight-0 rollouts excluded
+          if (r0 + c < nroll && ev[c] > 0.f) acc = fmaf(ev[c], xv[c], acc);
       }
     }
     ws.part_N[(size_t)b * HO4 + o] = acc;
@@ -978,7 +1037,8 @@ __global__ __launch_bounds__(256) void grid_to_f16_kernel(const float* __restric
 // ---------------------------------------------------------------------------
 
 static size_t k1_lds_bytes(int R, int H) {
-  const size_t floats = (size_t)R * H * kNdof * 3 + (size_t)H * kNdof + (size_t)R * H + 16 + R;
+  const size_t floats = (size_t)R * H * kNdof * 3 + (size_t)H * kNdof + (size_t)R * H + 16 + R +
+                        (size_t)R * kNdof * k1_segments(H) * 2;
   return floats * 4;
 }
 
