@@ -30,6 +30,7 @@ struct DevRobot {
   // i * kSpl + j of lp_mask marks the pair (slot la*kSpl+i, slot lb*kSpl+j).
   uint32_t lp_mask[kNdof * kNdof];
   float lp_bthr[kNdof * kNdof];              // (R_la + R_lb)^2 of the link bounding spheres
+  float lp_sthr[kNdof * kNdof][kSpl];        // (r_i + R_lb)^2: sphere i of la vs lb's bound
   float lp_rr2[kNdof * kNdof][kSpl * kSpl];  // (r_i + r_j)^2 per pair (0 if not a pair)
   float lp_rs[kNdof * kNdof][kSpl * kSpl];   // r_i + r_j
   float lbound[kNdof];         // bounding radius of each link's spheres about its slot-0 sphere

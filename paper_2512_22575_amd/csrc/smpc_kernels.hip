@@ -392,8 +392,9 @@ __device__ __forceinline__ float step_cost(const DevRobot* __restrict__ rob, con
 
   // Self collision (eqs. 18-20), grouped by link pair.  When no lane's link bounding
   // spheres overlap, no pair of the two links can overlap and the group is skipped
-  // (its hinges are exactly 0); otherwise each pair takes a squared-distance test,
-  // with a square root only on overlap.
+  // (its hinges are exactly 0); otherwise each sphere of the first link is tested
+  // against the second link's bounding sphere the same way, and each remaining pair
+  // takes a squared-distance test, with a square root only on overlap.
   float c_self = 0.f;
 #pragma unroll
   for (int la = 0; la < kNdof; ++la) {
@@ -415,6 +416,14 @@ __device__ __forceinline__ float step_cost(const DevRobot* __restrict__ rob, con
         for (int b = 0; b < kSpl * kSpl; ++b) rr2[b] = rob->lp_rr2[lp][b];
 #pragma unroll
         for (int i = 0; i < kSpl; ++i) {
+          if (!(mask & (0xFu << (i * kSpl)))) continue;
+          // Sphere i of la against lb's bounding sphere: when clear, so is each of
+          // its pairs with lb (exactly, by the same margin as the link test).
+          if (la != lb) {
+            const int sa = la * kSpl + i, cb = lb * kSpl;
+            const float dx = px[sa] - px[cb], dy = py[sa] - py[cb], dz = pz[sa] - pz[cb];
+            if (!(fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rob->lp_sthr[lp][i])) continue;
+          }
 #pragma unroll
           for (int j = 0; j < kSpl; ++j) {
             const int bit = i * kSpl + j;

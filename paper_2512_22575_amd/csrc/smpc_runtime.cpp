@@ -404,6 +404,8 @@ smpc_status smpc_set_robot(smpc_ctx* ctx, const smpc_robot_desc* d) {
     r.lp_rs[lp][bit] = (float)rs;
     const double bt = bound_r[la] + bound_r[lb];
     r.lp_bthr[lp] = (float)(bt * bt);
+    const double st = ctx->slot_radius[a] + bound_r[lb];
+    r.lp_sthr[lp][a % kSpl] = (float)(st * st);
   }
   r.n_pairs = n_unique;
   ctx->host_robot = r;
