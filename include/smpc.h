@@ -116,7 +116,16 @@ typedef struct {
   int32_t dtype; /* SMPC_GRID_F32, or SMPC_GRID_F16 (IEEE binary16, widened to float32) */
   float origin[3];
   float voxel;
+  /* Optional (NULL: none): device float lower bounds of phi per coarse cell, built by
+   * smpc_grid_coarse_min from the same grid contents.  A rollout sphere whose cell
+   * bound clears its collision threshold skips the trilinear lookup: its hinge is
+   * exactly 0 either way, so costs and U* are bitwise the same with or without it.
+   * Bounds that do not belong to the grid's current contents give wrong costs. */
+  const float* coarse;
 } smpc_grid;
+
+/* Edge of a coarse bound cell, in voxels. */
+#define SMPC_COARSE_CELL 8
 
 /*
  * Arguments of one plan step.
@@ -204,6 +213,25 @@ smpc_status smpc_sample_noise(uint64_t seed, int32_t K, int32_t H, const float* 
  * Runs on the device current to the calling thread, asynchronously on `stream`.
  */
 smpc_status smpc_grid_to_f16(const float* src, void* dst, int64_t n, float clamp, void* stream);
+
+/*
+ * Number of coarse cells of a grid: cx(n) = ceil((n - 1) / SMPC_COARSE_CELL) per
+ * axis, cx(nx) * cx(ny) * cx(nz) in all; 0 when a side is < 2.
+ */
+int64_t smpc_grid_coarse_cells(int32_t nx, int32_t ny, int32_t nz);
+
+/*
+ * Lower bounds of trilinear phi for smpc_grid.coarse.  Cell (cx, cy, cz), stored at
+ * (cz * ncy + cy) * ncx + cx, covers the lookups whose lower corner index i0 (R5:
+ * min(floor(u), n - 2) per axis) lies in [8 c, 8 c + 7]; its bound is the minimum
+ * of phi over voxels [8 c, min(8 c + 8, n - 1)] per axis, minus 1e-5 m + 2^-18 times
+ * the largest |phi| there, which covers float32 rounding in the interpolation.
+ *   grid      : host struct describing the device grid (data, sizes, dtype; its
+ *               `coarse` field is ignored).
+ *   coarse_out: device float [smpc_grid_coarse_cells(nx, ny, nz)].
+ * Runs on the device current to the calling thread, asynchronously on `stream`.
+ */
+smpc_status smpc_grid_coarse_min(const smpc_grid* grid, float* coarse_out, void* stream);
 
 /* ---- Distance field construction (Sec. III-B) ------------------------------- */
 

@@ -61,6 +61,8 @@ struct StepParams {
   float gcx, gcy, gcz;         // -origin / voxel - 1/2 per axis (continuous-index offset)
   int32_t nx, ny, nz;
   uint32_t grid_bytes;
+  int32_t ncx, ncy, ncz;       // coarse bound cells per axis
+  uint32_t coarse_bytes;       // 0: no coarse bounds
   int32_t K, H, R, P;          // samples, horizon, rollouts per K1 block, K1 blocks
   float dt;
   float inv_lambda;
@@ -86,6 +88,7 @@ struct Workspace {
 struct Request {
   StepParams p;
   const void* grid;            // device distance grid
+  const float* coarse;         // device coarse lower bounds of the grid, or null
   const float* noise;          // device [K][H][7], or null: sample on the device
   const float* U_in;           // device [H][7]
   float* U_out;                // device [H][7]
@@ -131,6 +134,12 @@ int launch_sample_noise(uint64_t seed, int K, int H, const float* sigma, float* 
 
 // float32 -> float16 grid conversion with clamping.  Returns a hipError_t value.
 int launch_grid_to_f16(const float* src, void* dst, long long n, float clamp, void* stream);
+constexpr int kCoarseCell = SMPC_COARSE_CELL;
+constexpr int kCoarseShift = 3;  // log2(kCoarseCell)
+static_assert((1 << kCoarseShift) == kCoarseCell, "coarse cell edge");
+inline int coarse_cells_1d(int n) { return (n - 2) / kCoarseCell + 1; }
+int launch_grid_coarse_min(const void* grid, bool f16, int nx, int ny, int nz, float* out,
+                           void* stream);
 
 constexpr int kEdtMaxSide = SMPC_EDT_MAX_SIDE;
 // Signed distance field from occupancy (smpc_edt.hip); sizes already validated.

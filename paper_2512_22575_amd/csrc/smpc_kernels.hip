@@ -258,17 +258,16 @@ __device__ __forceinline__ float load_grid(__amdgpu_buffer_rsrc_t rsrc, uint32_t
 }
 
 // Trilinear phi(p) between voxel centres, query clamped to the grid (edge extension),
-// in two halves so that several lookups can have their loads in flight together:
-// esdf_fetch computes the base corner and fractions and issues the 8 loads,
-// esdf_blend interpolates.  u = p / voxel + (-origin / voxel - 1/2) per axis.
-struct GridSample {
-  float v[8];          // corners 000, 100, 010, 110, 001, 101, 011, 111
+// in two halves: esdf_locate finds the lower corner and the fractions
+// (u = p / voxel + (-origin / voxel - 1/2) per axis, clamped to [0, n - 1]; corner
+// min(floor(u), n - 2)), esdf_blend_at loads the 8 corners and interpolates.
+struct GridLoc {
+  uint32_t ix, iy, iz;
   float fx, fy, fz;
 };
 
-template <int kElemBytes>
-__device__ __forceinline__ void esdf_fetch(__amdgpu_buffer_rsrc_t rsrc, const StepParams& p,
-                                           float px, float py, float pz, GridSample& g) {
+__device__ __forceinline__ GridLoc esdf_locate(const StepParams& p, float px, float py,
+                                               float pz) {
   const float fx_hi = (float)(p.nx - 1), fy_hi = (float)(p.ny - 1), fz_hi = (float)(p.nz - 1);
   const float ux = __builtin_amdgcn_fmed3f(fmaf(px, p.inv_voxel, p.gcx), 0.f, fx_hi);
   const float uy = __builtin_amdgcn_fmed3f(fmaf(py, p.inv_voxel, p.gcy), 0.f, fy_hi);
@@ -276,29 +275,35 @@ __device__ __forceinline__ void esdf_fetch(__amdgpu_buffer_rsrc_t rsrc, const St
   const float bx = fminf(floorf(ux), fx_hi - 1.f);
   const float by = fminf(floorf(uy), fy_hi - 1.f);
   const float bz = fminf(floorf(uz), fz_hi - 1.f);
+  GridLoc g;
   g.fx = ux - bx;
   g.fy = uy - by;
   g.fz = uz - bz;
-  const uint32_t ix = (uint32_t)bx, iy = (uint32_t)by, iz = (uint32_t)bz;
+  g.ix = (uint32_t)bx;
+  g.iy = (uint32_t)by;
+  g.iz = (uint32_t)bz;
+  return g;
+}
+
+template <int kElemBytes>
+__device__ __forceinline__ float esdf_blend_at(__amdgpu_buffer_rsrc_t rsrc, const StepParams& p,
+                                               const GridLoc& g) {
   constexpr uint32_t e = kElemBytes;
   const uint32_t sy = (uint32_t)p.nx * e;
   const uint32_t sz = (uint32_t)p.nx * (uint32_t)p.ny * e;
-  const uint32_t off = ((iz * (uint32_t)p.ny + iy) * (uint32_t)p.nx + ix) * e;
-  g.v[0] = load_grid<kElemBytes>(rsrc, off, 0u);
-  g.v[1] = load_grid<kElemBytes>(rsrc, off + e, 0u);
-  g.v[2] = load_grid<kElemBytes>(rsrc, off, sy);
-  g.v[3] = load_grid<kElemBytes>(rsrc, off + e, sy);
-  g.v[4] = load_grid<kElemBytes>(rsrc, off, sz);
-  g.v[5] = load_grid<kElemBytes>(rsrc, off + e, sz);
-  g.v[6] = load_grid<kElemBytes>(rsrc, off, sy + sz);
-  g.v[7] = load_grid<kElemBytes>(rsrc, off + e, sy + sz);
-}
-
-__device__ __forceinline__ float esdf_blend(const GridSample& g) {
-  const float c00 = fmaf(g.fx, g.v[1] - g.v[0], g.v[0]);
-  const float c10 = fmaf(g.fx, g.v[3] - g.v[2], g.v[2]);
-  const float c01 = fmaf(g.fx, g.v[5] - g.v[4], g.v[4]);
-  const float c11 = fmaf(g.fx, g.v[7] - g.v[6], g.v[6]);
+  const uint32_t off = ((g.iz * (uint32_t)p.ny + g.iy) * (uint32_t)p.nx + g.ix) * e;
+  const float v000 = load_grid<kElemBytes>(rsrc, off, 0u);
+  const float v100 = load_grid<kElemBytes>(rsrc, off + e, 0u);
+  const float v010 = load_grid<kElemBytes>(rsrc, off, sy);
+  const float v110 = load_grid<kElemBytes>(rsrc, off + e, sy);
+  const float v001 = load_grid<kElemBytes>(rsrc, off, sz);
+  const float v101 = load_grid<kElemBytes>(rsrc, off + e, sz);
+  const float v011 = load_grid<kElemBytes>(rsrc, off, sy + sz);
+  const float v111 = load_grid<kElemBytes>(rsrc, off + e, sy + sz);
+  const float c00 = fmaf(g.fx, v100 - v000, v000);
+  const float c10 = fmaf(g.fx, v110 - v010, v010);
+  const float c01 = fmaf(g.fx, v101 - v001, v001);
+  const float c11 = fmaf(g.fx, v111 - v011, v011);
   const float c0 = fmaf(g.fy, c10 - c00, c00);
   const float c1 = fmaf(g.fy, c11 - c01, c01);
   return fmaf(g.fz, c1 - c0, c0);
@@ -307,9 +312,17 @@ __device__ __forceinline__ float esdf_blend(const GridSample& g) {
 template <int kElemBytes>
 __device__ __forceinline__ float esdf_lookup(__amdgpu_buffer_rsrc_t rsrc, const StepParams& p,
                                              float px, float py, float pz) {
-  GridSample g;
-  esdf_fetch<kElemBytes>(rsrc, p, px, py, pz, g);
-  return esdf_blend(g);
+  return esdf_blend_at<kElemBytes>(rsrc, p, esdf_locate(p, px, py, pz));
+}
+
+// Coarse lower bound of the cell holding lookup corner g (0-filled past the buffer,
+// which only ever happens without bounds, and then it is not consulted).
+__device__ __forceinline__ float coarse_bound(__amdgpu_buffer_rsrc_t crsrc, const StepParams& p,
+                                              const GridLoc& g) {
+  const uint32_t cell =
+      ((g.iz >> kCoarseShift) * (uint32_t)p.ncy + (g.iy >> kCoarseShift)) * (uint32_t)p.ncx +
+      (g.ix >> kCoarseShift);
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(crsrc, cell * 4u, 0, 0));
 }
 
 // Forward kinematics (eq. 6) of q0 + dq with sin/cos of q0 + dq by angle addition,
@@ -357,7 +370,8 @@ __device__ __forceinline__ float state_limit_cost(const StepParams& p, const flo
 //   dq, qd : q_{k+1} - q0 and qd_{k+1};  u : u_k;  sc0 : sin(q0) then cos(q0) (LDS).
 template <int kElemBytes>
 __device__ __forceinline__ float step_cost(const DevRobot* __restrict__ rob, const StepParams& p,
-                                           __amdgpu_buffer_rsrc_t rsrc, const float* sc0,
+                                           __amdgpu_buffer_rsrc_t rsrc,
+                                           __amdgpu_buffer_rsrc_t crsrc, const float* sc0,
                                            const float (&dq)[kNdof], const float (&qd)[kNdof],
                                            const float (&u)[kNdof], bool terminal) {
   // Smoothness (eq. 23) and acceleration limit (eq. 22) on u_k.
@@ -378,12 +392,25 @@ __device__ __forceinline__ float step_cost(const DevRobot* __restrict__ rob, con
 
   if (terminal) return cost;
 
-  // Environment collision (eqs. 17, 19, 20).
+  // Environment collision (eqs. 17, 19, 20).  With coarse bounds, all spheres first
+  // fetch the bound of their lookup cell (one load each, issued together); a sphere
+  // whose bound clears its threshold has phi >= threshold, i.e. a hinge of exactly 0,
+  // and skips the trilinear lookup.
   const uint32_t active = rob->slot_active;
+  uint32_t need = active;
+  if (p.coarse_bytes != 0u) {
+    float lb[kSlots];
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s)
+      lb[s] = coarse_bound(crsrc, p, esdf_locate(p, px[s], py[s], pz[s]));
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s)
+      if (lb[s] >= p.env_thr[s]) need &= ~(1u << s);
+  }
   float c_env = 0.f;
 #pragma unroll
   for (int s = 0; s < kSlots; ++s) {
-    if (active & (1u << s)) {
+    if (need & (1u << s)) {
       const float phi = esdf_lookup<kElemBytes>(rsrc, p, px[s], py[s], pz[s]);
       const float h = fmaxf(p.env_thr[s] - phi, 0.f);
       c_env = fmaf(h, h, c_env);
@@ -612,7 +639,8 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
         u[j] = L.ubar[k * kNdof + j] + L.eps[base + j];
       }
       const __amdgpu_buffer_rsrc_t rsrc = grid_resource(q.grid, p.grid_bytes);
-      cost = step_cost<kElemBytes>(rob, p, rsrc, L.sc0, dq, qd, u, k == H - 1);
+      const __amdgpu_buffer_rsrc_t crsrc = grid_resource(q.coarse, p.coarse_bytes);
+      cost = step_cost<kElemBytes>(rob, p, rsrc, crsrc, L.sc0, dq, qd, u, k == H - 1);
     }
     L.cost[tid] = cost;
   }
@@ -1028,6 +1056,43 @@ __global__ __launch_bounds__(256) void sample_noise_kernel(uint32_t k0, uint32_t
 }
 
 // float32 -> float16 grid: clamp to [-clamp, clamp], round to nearest even.
+// Coarse lower bounds (smpc_grid_coarse_min): one wave per cell; lanes stride over
+// the cell's window of voxels [8 c, min(8 c + 8, n - 1)] per axis.  A non-finite
+// value anywhere in the window makes the bound -inf (never skip a lookup there).
+template <int kElemBytes>
+__global__ __launch_bounds__(256) void grid_coarse_min_kernel(const void* __restrict__ grid,
+                                                              uint32_t grid_bytes, int nx, int ny,
+                                                              int nz, int ncx, int ncy, int ncz,
+                                                              float* __restrict__ out) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const long long cell = (long long)blockIdx.x * 4 + (threadIdx.x / kWave);
+  const long long ncells = (long long)ncx * ncy * ncz;
+  if (cell >= ncells) return;
+  const int cx = (int)(cell % ncx), cy = (int)((cell / ncx) % ncy), cz = (int)(cell / ((long long)ncx * ncy));
+  const int x0 = cx * kCoarseCell, y0 = cy * kCoarseCell, z0 = cz * kCoarseCell;
+  const int wx = min(x0 + kCoarseCell, nx - 1) - x0 + 1;
+  const int wy = min(y0 + kCoarseCell, ny - 1) - y0 + 1;
+  const int wz = min(z0 + kCoarseCell, nz - 1) - z0 + 1;
+  const __amdgpu_buffer_rsrc_t rsrc = grid_resource(grid, grid_bytes);
+  float mn = __builtin_inff(), mx = 0.f;
+  bool bad = false;
+  for (int w = lane; w < wx * wy * wz; w += kWave) {
+    const int x = x0 + w % wx, y = y0 + (w / wx) % wy, z = z0 + w / (wx * wy);
+    const uint32_t off = (uint32_t)(((long long)z * ny + y) * nx + x) * kElemBytes;
+    const float v = load_grid<kElemBytes>(rsrc, off, 0u);
+    bad |= !isfinite(v);
+    mn = fminf(mn, v);
+    mx = fmaxf(mx, fabsf(v));
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) {
+    mn = fminf(mn, __shfl_xor(mn, off, kWave));
+    mx = fmaxf(mx, __shfl_xor(mx, off, kWave));
+  }
+  const bool any_bad = __any(bad);
+  if (lane == 0) out[cell] = any_bad ? -__builtin_inff() : mn - (1e-5f + mx * 0x1p-18f);
+}
+
 __global__ __launch_bounds__(256) void grid_to_f16_kernel(const float* __restrict__ src,
                                                           unsigned short* __restrict__ dst,
                                                           long long n, float clamp) {
@@ -1132,6 +1197,17 @@ int launch_sample_noise(uint64_t seed, int K, int H, const float* sigma, float* 
                      static_cast<hipStream_t>(stream), (uint32_t)seed, (uint32_t)(seed >> 32), K,
                      H, sg, eps, words);
   return (int)hipGetLastError();
+}
+
+int launch_grid_coarse_min(const void* grid, bool f16, int nx, int ny, int nz, float* out,
+                           void* stream) {
+  const int ncx = coarse_cells_1d(nx), ncy = coarse_cells_1d(ny), ncz = coarse_cells_1d(nz);
+  const long long ncells = (long long)ncx * ncy * ncz;
+  const uint32_t bytes = (uint32_t)((long long)nx * ny * nz * (f16 ? 2 : 4));
+  auto k = f16 ? grid_coarse_min_kernel<2> : grid_coarse_min_kernel<4>;
+  hipLaunchKernelGGL(k, dim3((unsigned)((ncells + 3) / 4)), dim3(256), 0, (hipStream_t)stream,
+                     grid, bytes, nx, ny, nz, ncx, ncy, ncz, out);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_grid_to_f16(const float* src, void* dst, long long n, float clamp, void* stream) {

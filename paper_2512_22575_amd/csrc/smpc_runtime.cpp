@@ -230,6 +230,11 @@ StepParams make_params(const smpc_ctx* ctx, const smpc_plan_args* a, const Launc
   p.nz = a->esdf.nz;
   const int elem = a->esdf.dtype == SMPC_GRID_F16 ? 2 : 4;
   p.grid_bytes = (uint32_t)((long long)a->esdf.nx * a->esdf.ny * a->esdf.nz * elem);
+  p.ncx = coarse_cells_1d(a->esdf.nx);
+  p.ncy = coarse_cells_1d(a->esdf.ny);
+  p.ncz = coarse_cells_1d(a->esdf.nz);
+  p.coarse_bytes =
+      a->esdf.coarse ? (uint32_t)((long long)p.ncx * p.ncy * p.ncz * (long long)sizeof(float)) : 0u;
   p.seed_lo = (uint32_t)a->seed;
   p.seed_hi = (uint32_t)(a->seed >> 32);
   for (int j = 0; j < kNdof; ++j) p.sigma[j] = a->sigma[j];
@@ -447,6 +452,7 @@ smpc_status smpc_plan_step(smpc_ctx* ctx, const smpc_plan_args* a, void* stream)
   std::memset(&q, 0, sizeof q);
   q.p = p;
   q.grid = a->esdf.data;
+  q.coarse = a->esdf.coarse;
   q.noise = a->noise;
   q.U_in = a->U_in;
   q.U_out = a->U_out;
@@ -469,6 +475,23 @@ smpc_status smpc_sample_noise(uint64_t seed, int32_t K, int32_t H, const float* 
   for (int j = 0; j < kNdof; ++j)
     if (!std::isfinite(sigma[j]) || sigma[j] < 0.f) return SMPC_E_INVALID_ARG;
   return launch_sample_noise(seed, K, H, sigma, eps_out, words_out, stream) == 0
+             ? SMPC_OK
+             : SMPC_E_DEVICE;
+}
+
+int64_t smpc_grid_coarse_cells(int32_t nx, int32_t ny, int32_t nz) {
+  if (nx < 2 || ny < 2 || nz < 2) return 0;
+  return (int64_t)coarse_cells_1d(nx) * coarse_cells_1d(ny) * coarse_cells_1d(nz);
+}
+
+smpc_status smpc_grid_coarse_min(const smpc_grid* g, float* coarse_out, void* stream) {
+  if (!g || !g->data || !coarse_out || g->nx < 2 || g->ny < 2 || g->nz < 2 ||
+      (g->dtype != SMPC_GRID_F32 && g->dtype != SMPC_GRID_F16))
+    return SMPC_E_INVALID_ARG;
+  const long long elem = g->dtype == SMPC_GRID_F16 ? 2 : 4;
+  if ((long long)g->nx * g->ny * g->nz * elem >= (1LL << 31)) return SMPC_E_INVALID_ARG;
+  return launch_grid_coarse_min(g->data, g->dtype == SMPC_GRID_F16, g->nx, g->ny, g->nz,
+                                coarse_out, stream) == 0
              ? SMPC_OK
              : SMPC_E_DEVICE;
 }
@@ -746,6 +769,7 @@ smpc_status launch_next(smpc_server* s, void* stream, int* launched) {
     std::memset(&q, 0, sizeof q);
     q.p = make_params(s->ctx, &a, c.lc);
     q.grid = a.esdf.data;
+    q.coarse = a.esdf.coarse;
     q.noise = nullptr;
     q.U_in = a.U_in;
     q.U_out = a.U_out;

@@ -65,6 +65,7 @@ class smpc_grid(ctypes.Structure):
         ("dtype", c_int32),
         ("origin", c_float * 3),
         ("voxel", c_float),
+        ("coarse", c_void_p),
     ]
 
 
@@ -150,6 +151,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.smpc_sample_noise.restype = c_int32
     lib.smpc_grid_to_f16.argtypes = [c_void_p, c_void_p, ctypes.c_int64, c_float, c_void_p]
     lib.smpc_grid_to_f16.restype = c_int32
+    lib.smpc_grid_coarse_cells.argtypes = [c_int32, c_int32, c_int32]
+    lib.smpc_grid_coarse_cells.restype = ctypes.c_int64
+    lib.smpc_grid_coarse_min.argtypes = [POINTER(smpc_grid), c_void_p, c_void_p]
+    lib.smpc_grid_coarse_min.restype = c_int32
     lib.smpc_plan_workspace_bytes.argtypes = [c_int32, c_int32]
     lib.smpc_edt_workspace_bytes.argtypes = [c_int32, c_int32, c_int32]
     lib.smpc_edt_workspace_bytes.restype = c_uint64
@@ -227,6 +232,19 @@ def smpc_sample_noise(seed: int, K: int, H: int, sigma, eps_out: int, words_out:
                                             c_void_p(words_out or 0), c_void_p(stream or 0))
 
 
+def smpc_grid_coarse_cells(nx: int, ny: int, nz: int) -> int:
+    return int(load_library().smpc_grid_coarse_cells(int(nx), int(ny), int(nz)))
+
+
+def smpc_grid_coarse_min(grid, dtype: int, coarse_out: int, stream: int | None) -> int:
+    """Coarse lower bounds of a device grid (torch tensor [nz][ny][nx]) into coarse_out."""
+    nz, ny, nx = (int(x) for x in grid.shape)
+    g = smpc_grid(c_void_p(_ptr(grid)), nx, ny, nz, int(dtype), (c_float * 3)(0.0, 0.0, 0.0),
+                  1.0, None)
+    return load_library().smpc_grid_coarse_min(ctypes.byref(g), c_void_p(coarse_out or 0),
+                                                c_void_p(stream or 0))
+
+
 def smpc_grid_to_f16(src: int, dst: int, n: int, clamp: float, stream: int | None) -> int:
     return load_library().smpc_grid_to_f16(c_void_p(src or 0), c_void_p(dst or 0), int(n),
                                            float(clamp), c_void_p(stream or 0))
@@ -285,7 +303,7 @@ def _ptr(t) -> int:
 
 def plan_args(q0, qd0, T_goal, grid, origin, voxel, noise, U_in, U_out, K, H, dt, lam,
               weights: dict, costs_out=None, weights_out=None, stats_out=None, seed: int = 0,
-              sigma=None, grid_dtype: int = GRID_F32) -> smpc_plan_args:
+              sigma=None, grid_dtype: int = GRID_F32, coarse=None) -> smpc_plan_args:
     """Build smpc_plan_args; tensors are torch tensors on the device (or None)."""
     a = smpc_plan_args()
     a.q0[:] = [float(x) for x in np.asarray(q0, np.float32)]
@@ -294,7 +312,7 @@ def plan_args(q0, qd0, T_goal, grid, origin, voxel, noise, U_in, U_out, K, H, dt
     nz, ny, nx = (int(s) for s in grid.shape)
     a.esdf = smpc_grid(c_void_p(_ptr(grid)), nx, ny, nz, int(grid_dtype),
                        (c_float * 3)(*[float(x) for x in np.asarray(origin, np.float32)]),
-                       float(voxel))
+                       float(voxel), c_void_p(_ptr(coarse)))
     a.noise = _ptr(noise)
     a.seed = int(seed)
     a.sigma[:] = [0.5] * NDOF if sigma is None else [float(x) for x in sigma]
@@ -349,7 +367,8 @@ class Planner:
 
     def plan_step(self, *, q0, qd0, T_goal, grid, origin, voxel, noise, U_in, U_out, dt, lam,
                   weights, costs_out=None, weights_out=None, stats_out=None, stream=None,
-                  seed: int = 0, sigma=None, grid_dtype: int = GRID_F32, K=None, H=None) -> None:
+                  seed: int = 0, sigma=None, grid_dtype: int = GRID_F32, K=None, H=None,
+                  coarse=None) -> None:
         """Enqueue one plan step on ``stream`` (default: torch's current stream)."""
         import torch
         if noise is not None:
@@ -359,7 +378,8 @@ class Planner:
         if stream is None:
             stream = torch.cuda.current_stream(self.device).cuda_stream
         a = plan_args(q0, qd0, T_goal, grid, origin, voxel, noise, U_in, U_out, K, H, dt, lam,
-                      weights, costs_out, weights_out, stats_out, seed, sigma, grid_dtype)
+                      weights, costs_out, weights_out, stats_out, seed, sigma, grid_dtype,
+                      coarse)
         st = smpc_plan_step(self._ctx, a, stream)
         if st != SMPC_OK:
             raise SMPCError(st, smpc_last_error(self._ctx))
@@ -438,12 +458,12 @@ def smpc_server_last_error(server: c_void_p) -> str:
 
 
 def controller_desc(grid, origin, voxel, K, H, dt, lam, weights, sigma,
-                    grid_dtype: int = GRID_F32) -> smpc_controller_desc:
+                    grid_dtype: int = GRID_F32, coarse=None) -> smpc_controller_desc:
     d = smpc_controller_desc()
     nz, ny, nx = (int(x) for x in grid.shape)
     d.esdf = smpc_grid(c_void_p(_ptr(grid)), nx, ny, nz, int(grid_dtype),
                        (c_float * 3)(*[float(x) for x in np.asarray(origin, np.float32)]),
-                       float(voxel))
+                       float(voxel), c_void_p(_ptr(coarse)))
     d.K, d.H = int(K), int(H)
     d.dt, d.lambda_ = float(dt), float(lam)
     d.weights = cost_weights(weights)
@@ -473,10 +493,13 @@ class Server:
         self._keep = []   # device tensors the controllers reference
 
     def add_controller(self, grid, origin, voxel, K, H, dt, lam, weights, sigma,
-                       grid_dtype: int = GRID_F32) -> int:
+                       grid_dtype: int = GRID_F32, coarse=None) -> int:
         self._keep.append(grid)
+        if coarse is not None:
+            self._keep.append(coarse)
         st, cid = smpc_server_add_controller(
-            self._h, controller_desc(grid, origin, voxel, K, H, dt, lam, weights, sigma, grid_dtype))
+            self._h, controller_desc(grid, origin, voxel, K, H, dt, lam, weights, sigma, grid_dtype,
+                                     coarse))
         if st != SMPC_OK:
             raise SMPCError(st, smpc_server_last_error(self._h))
         return cid

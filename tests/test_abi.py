@@ -53,7 +53,7 @@ int main(void) {
   F(smpc_plan_args, T_goal) F(smpc_plan_args, esdf) F(smpc_plan_args, noise)
   F(smpc_plan_args, seed) F(smpc_plan_args, K) F(smpc_plan_args, weights)
   F(smpc_plan_args, U_in) F(smpc_plan_args, stats_out)
-  F(smpc_grid, nx) F(smpc_grid, origin) F(smpc_grid, voxel)
+  F(smpc_grid, nx) F(smpc_grid, origin) F(smpc_grid, voxel) F(smpc_grid, coarse)
   printf("smpc_controller_desc sizeof %zu\n", sizeof(smpc_controller_desc));
   printf("smpc_request sizeof %zu\n", sizeof(smpc_request));
   printf("smpc_completion sizeof %zu\n", sizeof(smpc_completion));
@@ -284,6 +284,24 @@ def test_edt_validates_on_host():
            dict(d2_out=phi + 4 * nvox - 8)]           # overlaps the field
     for over in bad:
         assert S.smpc_edt(**{**ok, **over}) == S.SMPC_E_INVALID_ARG, over
+
+
+def test_coarse_bounds_validate_on_host():
+    assert S.smpc_grid_coarse_cells(200, 200, 200) == 25 ** 3
+    assert S.smpc_grid_coarse_cells(9, 10, 2) == 1 * 2 * 1
+    assert S.smpc_grid_coarse_cells(1, 5, 5) == 0
+    lib = S.load_library()
+    import ctypes
+    g = S.smpc_grid(ctypes.c_void_p(0x1000), 10, 10, 10, S.GRID_F32,
+                    (ctypes.c_float * 3)(0, 0, 0), 0.1, None)
+    assert lib.smpc_grid_coarse_min(ctypes.byref(g), ctypes.c_void_p(0), None) == S.SMPC_E_INVALID_ARG
+    assert lib.smpc_grid_coarse_min(None, ctypes.c_void_p(0x2000), None) == S.SMPC_E_INVALID_ARG
+    for field, value in (("data", None), ("nx", 1), ("dtype", 7)):
+        bad = S.smpc_grid(ctypes.c_void_p(0x1000), 10, 10, 10, S.GRID_F32,
+                          (ctypes.c_float * 3)(0, 0, 0), 0.1, None)
+        setattr(bad, field, value)
+        assert lib.smpc_grid_coarse_min(ctypes.byref(bad), ctypes.c_void_p(0x2000), None) == \
+            S.SMPC_E_INVALID_ARG, field
 
 
 def test_plan_workspace_bytes():

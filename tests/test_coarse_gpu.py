@@ -1,0 +1,165 @@
+"""GPU tests of the coarse lower bounds of the distance grid (smpc_grid.coarse).
+
+* the bounds equal their definition (window minimum minus the rounding margin,
+  -inf where the window holds a non-finite value), bit for bit;
+* plan steps with bounds are bitwise identical to plan steps without them (a
+  skipped lookup has a hinge of exactly 0), on the mid and the full-size reactive
+  workloads, a float16 grid with on-device sampling, and through the server.
+"""
+import numpy as np
+import pytest
+
+from synth import workload as W
+
+pytestmark = pytest.mark.gpu
+
+CELL = 8
+
+
+def coarse_reference(grid: np.ndarray) -> np.ndarray:
+    g = grid.astype(np.float32)
+    nz, ny, nx = g.shape
+    nc = [(n - 2) // CELL + 1 for n in (nz, ny, nx)]
+    out = np.empty(nc, np.float32)
+    for cz in range(nc[0]):
+        for cy in range(nc[1]):
+            for cx in range(nc[2]):
+                w = g[cz * CELL:min(cz * CELL + CELL, nz - 1) + 1,
+                      cy * CELL:min(cy * CELL + CELL, ny - 1) + 1,
+                      cx * CELL:min(cx * CELL + CELL, nx - 1) + 1]
+                if not np.isfinite(w).all():
+                    out[cz, cy, cx] = -np.inf
+                    continue
+                mn, mx = np.float32(w.min()), np.float32(np.abs(w).max())
+                out[cz, cy, cx] = mn - (np.float32(1e-5) + mx * np.float32(2.0 ** -18))
+    return out
+
+
+def gpu_coarse(grid_t, dtype):
+    import torch
+
+    from paper_2512_22575_amd import smpc as S
+    nz, ny, nx = grid_t.shape
+    n = S.smpc_grid_coarse_cells(nx, ny, nz)
+    out = torch.full((n,), float("nan"), device=grid_t.device)
+    st = S.smpc_grid_coarse_min(grid_t, dtype, out.data_ptr(),
+                                torch.cuda.current_stream().cuda_stream)
+    assert st == S.SMPC_OK
+    return out
+
+
+@pytest.mark.parametrize("shape", [(17, 9, 33), (2, 2, 2), (40, 41, 42)])
+def test_bounds_match_definition(shape):
+    import torch
+
+    from paper_2512_22575_amd import smpc as S
+    rng = np.random.default_rng(sum(shape))
+    grid = rng.normal(scale=0.3, size=shape).astype(np.float32)
+    if shape == (40, 41, 42):
+        grid[5, 30, 7] = np.nan
+        grid[33, 2, 40] = np.inf
+    got = gpu_coarse(torch.from_numpy(grid).cuda(), S.GRID_F32).cpu().numpy()
+    want = coarse_reference(grid).reshape(-1)
+    np.testing.assert_array_equal(got.view(np.uint32), want.view(np.uint32))
+    # float16 storage: bounds of the decoded values
+    g16 = np.clip(grid, -2, 2).astype(np.float16)
+    got16 = gpu_coarse(torch.from_numpy(g16.view(np.int16).copy()).cuda(), S.GRID_F16)
+    want16 = coarse_reference(g16.astype(np.float32)).reshape(-1)
+    np.testing.assert_array_equal(got16.cpu().numpy().view(np.uint32), want16.view(np.uint32))
+
+
+def _plan(inp, grid_t, coarse, **kw):
+    import torch
+
+    from paper_2512_22575_amd import smpc as S
+    dev = grid_t.device
+    noise = torch.from_numpy(inp.noise).to(dev) if inp.noise is not None else None
+    U_in = torch.from_numpy(inp.U_bar).to(dev)
+    U_out = torch.empty_like(U_in)
+    K = kw["K"] if "K" in kw else inp.K
+    costs = torch.empty((K,), device=dev)
+    w = torch.empty((K,), device=dev)
+    stats = torch.empty((4,), device=dev)
+    planner = S.Planner(inp.robot)
+    planner.plan_step(q0=inp.q0, qd0=inp.qd0, T_goal=inp.T_goal, grid=grid_t, origin=inp.origin,
+                      voxel=inp.voxel, noise=noise, U_in=U_in, U_out=U_out, dt=inp.dt,
+                      lam=inp.lam, weights=inp.weights, costs_out=costs, weights_out=w,
+                      stats_out=stats, coarse=coarse, **kw)
+    torch.cuda.synchronize()
+    planner.close()
+    return [t.cpu().numpy() for t in (U_out, costs, w, stats)]
+
+
+def _check_same(inp, grid_t, dtype, **kw):
+    coarse = gpu_coarse(grid_t, dtype)
+    a = _plan(inp, grid_t, None, grid_dtype=dtype, **kw)
+    b = _plan(inp, grid_t, coarse, grid_dtype=dtype, **kw)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x.view(np.uint32), y.view(np.uint32))
+
+
+def test_plan_step_identical_mid():
+    import torch
+
+    from paper_2512_22575_amd import smpc as S
+    inp = W.mid()
+    _check_same(inp, torch.from_numpy(inp.grid).cuda(), S.GRID_F32)
+
+
+def test_plan_step_identical_reactive_full_size():
+    import torch
+
+    from paper_2512_22575_amd import smpc as S
+    inp = W.ReactiveScenario(seed=3).inputs()
+    _check_same(inp, torch.from_numpy(inp.grid).cuda(), S.GRID_F32)
+
+
+def test_plan_step_identical_f16_sampling():
+    import dataclasses
+
+    import torch
+
+    from paper_2512_22575_amd import smpc as S
+    mid = W.mid()
+    inp = dataclasses.replace(mid, noise=None)
+    g16 = np.clip(inp.grid, -2, 2).astype(np.float16)
+    grid_t = torch.from_numpy(g16.view(np.int16).copy()).cuda()
+    _check_same(inp, grid_t, S.GRID_F16, seed=4, sigma=np.full(7, 0.5, np.float32), K=mid.K,
+                H=mid.H)
+
+
+def test_served_results_identical_with_bounds():
+    import torch
+
+    from paper_2512_22575_amd import smpc as S
+    fleet = [W.make_inputs(70 + i, K=256, H=16, dt=0.02, n=40, voxel=0.05, n_boxes=6,
+                           n_spheres=4, robot_seed=0) for i in range(3)]
+    grids = [torch.from_numpy(f.grid).cuda() for f in fleet]
+    out = {}
+    for use in (False, True):
+        planner = S.Planner(fleet[0].robot)
+        srv = S.Server(planner, hbm_budget_bytes=64 << 20, max_batch=8)
+        ids = [srv.add_controller(g, f.origin, f.voxel, f.K, f.H, f.dt, f.lam, f.weights,
+                                  np.full(7, 0.5, np.float32),
+                                  coarse=gpu_coarse(g, S.GRID_F32) if use else None)
+               for g, f in zip(grids, fleet)]
+        for t in range(9):
+            f = fleet[t % 3]
+            srv.submit(t, ids[t % 3], f.q0, f.qd0, f.T_goal, 100 + t)
+        done = {}
+        rounds = 0
+        while len(done) < 9:
+            rounds += 1
+            assert rounds < 10000, "server made no progress"
+            srv.pump()
+            for c in srv.poll():
+                done[c.tag] = (c.status, np.array(c.u0[:], np.float32), c.S_min, c.Z)
+            torch.cuda.synchronize()
+        srv.close()
+        planner.close()
+        out[use] = done
+    for t in range(9):
+        a, b = out[False][t], out[True][t]
+        assert a[0] == b[0] == 0
+        np.testing.assert_array_equal(a[1].view(np.uint32), b[1].view(np.uint32))
+        assert (a[2], a[3]) == (b[2], b[3])
