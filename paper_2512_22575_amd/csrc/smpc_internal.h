@@ -81,6 +81,7 @@ struct Workspace {
   float* part_Z;    // [P]   sum_m exp(-(S - part_m)/lambda)
   float* part_Z2;   // [P]   sum_m exp(-2 (S - part_m)/lambda)
   float* part_N;    // [P][HO4] sum_m exp(-(S - part_m)/lambda) eps^(m), HO4 = 7H padded to 4
+  float* c0;        // [1]   state terms of state 0 (when computed by the rollout launch)
 };
 
 // One plan step as the kernels see it (by value for a single step, in a device
@@ -100,7 +101,7 @@ struct Request {
   int32_t k1_begin;            // first rollout-cost block of this request in a batch
   int32_t k2_begin;            // first merge block of this request in a batch
   int32_t shift_out;           // 1: U_out = [u*_1 .. u*_{H-1}, 0] and u0_out = u*_0
-  int32_t pad_;
+  int32_t c0_in_ws;            // 1: an extra rollout-launch block leaves c0 in ws.c0
 };
 
 struct LaunchConfig {

@@ -470,6 +470,81 @@ __device__ __forceinline__ float step_cost(const DevRobot* __restrict__ rob, con
   return cost + fmaf(p.w_env, c_env, p.w_self * c_self);
 }
 
+// State terms of state 0 (pose, environment, self, q/qd limits, null space) are the
+// same for every rollout (reading of eq. 28 at k = 0); they are evaluated once, by
+// one whole block: one thread runs the forward-kinematics chain, one thread per
+// sphere transforms the centres, the lookups and the pairs are spread over the
+// block.  Every thread of the block must call this; all get the value.
+template <int kElemBytes>
+__device__ __forceinline__ float state0_cost(const DevRobot* __restrict__ rob,
+                                             const StepParams& p, const void* grid) {
+  __shared__ float centres[kSlots * 4];
+  __shared__ Frame frames[kNdof];
+  __shared__ float sc0[2 * kNdof];
+  __shared__ float red[1024 / kWave];
+  __shared__ float pose0;
+  const int tid = threadIdx.x, lane = tid & (kWave - 1), nthreads = blockDim.x;
+  if (tid < kNdof) {
+    float s_, c_;
+    sincosf(p.q0[tid], &s_, &c_);
+    sc0[tid] = s_;
+    sc0[kNdof + tid] = c_;
+  }
+  __syncthreads();
+  if (tid == kWave) {  // wave 0 stays free for the caller's independent loads
+    float zero[kNdof], qd0[kNdof];
+#pragma unroll
+    for (int j = 0; j < kNdof; ++j) {
+      zero[j] = 0.f;
+      qd0[j] = p.qd0[j];
+    }
+    Frame T = identity_frame();
+#pragma unroll
+    for (int i = 0; i < kNdof; ++i) {
+      mdh_step(T, rob->ca[i], rob->sa[i], rob->a[i], rob->d[i], sc0[kNdof + i], sc0[i]);
+      frames[i] = T;
+    }
+    pose0 = pose_cost(T, p, p.w_pose_t, p.w_pose_r) + state_limit_cost(p, zero, qd0);
+  }
+  __syncthreads();
+  if (tid < kSlots) {
+    float px, py, pz;
+    transform_point(frames[tid / kSpl], rob->sc[tid][0], rob->sc[tid][1], rob->sc[tid][2], px,
+                    py, pz);
+    centres[tid * 4 + 0] = px;
+    centres[tid * 4 + 1] = py;
+    centres[tid * 4 + 2] = pz;
+  }
+  __syncthreads();
+  float part = 0.f;
+  if (tid < kSlots && (rob->slot_active & (1u << tid))) {
+    const __amdgpu_buffer_rsrc_t rsrc = grid_resource(grid, p.grid_bytes);
+    const float phi = esdf_lookup<kElemBytes>(rsrc, p, centres[tid * 4], centres[tid * 4 + 1],
+                                              centres[tid * 4 + 2]);
+    const float h = fmaxf(p.env_thr[tid] - phi, 0.f);
+    part = p.w_env * h * h;
+  }
+  for (int i = tid; i < rob->n_pairs; i += nthreads) {
+    const float4 pr = rob->pair_rec[i];
+    const int a = __float_as_int(pr.x), c = __float_as_int(pr.y);
+    const float dx = centres[a * 4] - centres[c * 4];
+    const float dy = centres[a * 4 + 1] - centres[c * 4 + 1];
+    const float dz = centres[a * 4 + 2] - centres[c * 4 + 2];
+    const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    if (d2 < pr.z) {
+      const float h = pr.w - sqrt_hw(d2);
+      part = fmaf(p.w_self * h, h, part);
+    }
+  }
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) part += __shfl_xor(part, off, kWave);
+  if (lane == 0) red[tid / kWave] = part;
+  __syncthreads();
+  float c0 = pose0;
+  for (int w = 0; w < nthreads / kWave; ++w) c0 += red[w];
+  return c0;
+}
+
 // LDS layout of K1 (floats unless noted), for R rollouts of H steps.
 struct K1Lds {
   float* eps;    // [R*H*7]
@@ -706,6 +781,12 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
 template <int kElemBytes>
 __global__ __launch_bounds__(kK1Threads) __attribute__((amdgpu_waves_per_eu(3))) void
 rollout_cost_kernel(const DevRobot* __restrict__ rob, const Request q) {
+  if ((int)blockIdx.x == q.p.P) {
+    // One extra block evaluates the state-0 terms while the rollout blocks run.
+    const float c0 = state0_cost<kElemBytes>(rob, q.p, q.grid);
+    if (threadIdx.x == 0) q.ws.c0[0] = c0;
+    return;
+  }
   rollout_cost_block<kElemBytes>(rob, q, blockIdx.x);
 }
 
@@ -821,22 +902,16 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
   float* __restrict__ costs_out = q.costs_out;
   float* __restrict__ weights_out = q.weights_out;
   float* __restrict__ stats_out = q.stats_out;
-  __shared__ float centres[kSlots * 4];
-  __shared__ Frame frames[kNdof];
-  __shared__ float sc0[2 * kNdof];
   __shared__ float red[kK2Threads];
-  __shared__ float pose0;
   const int lane = threadIdx.x & (kWave - 1);
   const int tid = threadIdx.x;
   const int K = p.K, P = p.P, HO = p.H * kNdof, HO4 = (HO + 3) & ~3;
   const int n_out_blocks = (HO + kOutPerBlock - 1) / kOutPerBlock;
 
   if (kb == 0) {
-    // --- independent fetches first: pair records, the statistics rows (wave 0)
-    // and the first pass of costs to shift
-    const bool has_pair = tid < rob->n_pairs;
-    float4 pr = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (has_pair) pr = rob->pair_rec[tid];
+    if (!costs_out && !stats_out) return;
+    // --- independent fetches first: the statistics rows (wave 0) and the first
+    // pass of costs to shift
     StatRows rows;
     if (stats_out && tid < kWave) stats_load(ws, P, lane, rows);
     double sv0[kCostsAhead];
@@ -844,65 +919,7 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
 #pragma unroll
       for (int c = 0; c < kCostsAhead; ++c) sv0[c] = ws.S[min(tid + kK2Threads * c, K - 1)];
     }
-    if (tid < kNdof) {
-      float s_, c_;
-      sincosf(p.q0[tid], &s_, &c_);
-      sc0[tid] = s_;
-      sc0[kNdof + tid] = c_;
-    }
-    __syncthreads();
-    if (tid == kWave) {
-      // The joint frames of q0 (one thread: the chain is sequential); the sphere
-      // centres are then transformed by one thread each.
-      float zero[kNdof], qd0[kNdof];
-#pragma unroll
-      for (int j = 0; j < kNdof; ++j) {
-        zero[j] = 0.f;
-        qd0[j] = p.qd0[j];
-      }
-      Frame T = identity_frame();
-#pragma unroll
-      for (int i = 0; i < kNdof; ++i) {
-        mdh_step(T, rob->ca[i], rob->sa[i], rob->a[i], rob->d[i], sc0[kNdof + i], sc0[i]);
-        frames[i] = T;
-      }
-      pose0 = pose_cost(T, p, p.w_pose_t, p.w_pose_r) + state_limit_cost(p, zero, qd0);
-    }
-    __syncthreads();
-    if (tid < kSlots) {
-      float px, py, pz;
-      transform_point(frames[tid / kSpl], rob->sc[tid][0], rob->sc[tid][1], rob->sc[tid][2], px,
-                      py, pz);
-      centres[tid * 4 + 0] = px;
-      centres[tid * 4 + 1] = py;
-      centres[tid * 4 + 2] = pz;
-    }
-    __syncthreads();
-    float part = 0.f;
-    if (tid < kSlots && (rob->slot_active & (1u << tid))) {
-      const __amdgpu_buffer_rsrc_t rsrc = grid_resource(grid, p.grid_bytes);
-      const float phi = esdf_lookup<kElemBytes>(rsrc, p, centres[tid * 4], centres[tid * 4 + 1],
-                                                centres[tid * 4 + 2]);
-      const float h = fmaxf(p.env_thr[tid] - phi, 0.f);
-      part = p.w_env * h * h;
-    }
-    if (has_pair) {
-      const int a = __float_as_int(pr.x), c = __float_as_int(pr.y);
-      const float dx = centres[a * 4] - centres[c * 4];
-      const float dy = centres[a * 4 + 1] - centres[c * 4 + 1];
-      const float dz = centres[a * 4 + 2] - centres[c * 4 + 2];
-      const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-      if (d2 < pr.z) {
-        const float h = pr.w - sqrt_hw(d2);
-        part = fmaf(p.w_self * h, h, part);
-      }
-    }
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) part += __shfl_xor(part, off, kWave);
-    if (lane == 0) red[tid / kWave] = part;
-    __syncthreads();
-    float c0 = pose0;
-    for (int w = 0; w < kK2Threads / kWave; ++w) c0 += red[w];
+    const float c0 = q.c0_in_ws ? ws.c0[0] : state0_cost<kElemBytes>(rob, p, grid);
     // --- costs S = S' + c0 (eq. 28) and statistics
     if (costs_out) {
 #pragma unroll
@@ -1139,7 +1156,7 @@ static size_t padded_outputs(int H) { return ((size_t)H * kNdof + 3) & ~size_t(3
 
 size_t workspace_bytes(int K, int H, int P) {
   return align256((size_t)K * 8) + align256((size_t)P * 8) + 2 * align256((size_t)P * 4) +
-         align256(padded_outputs(H) * P * 4);
+         align256(padded_outputs(H) * P * 4) + 256;
 }
 
 Workspace carve_workspace(void* base, int K, int H, int P) {
@@ -1154,6 +1171,8 @@ Workspace carve_workspace(void* base, int K, int H, int P) {
   ws.part_Z2 = reinterpret_cast<float*>(b);
   b += align256((size_t)P * 4);
   ws.part_N = reinterpret_cast<float*>(b);
+  b += align256(padded_outputs(H) * P * 4);
+  ws.c0 = reinterpret_cast<float*>(b);
   return ws;
 }
 
@@ -1164,7 +1183,8 @@ int launch_plan_step(const DevRobot* robot, const Request& q, const LaunchConfig
   hipError_t e;
   if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return (int)e;
   auto k1 = f16 ? rollout_cost_kernel<2> : rollout_cost_kernel<4>;
-  hipLaunchKernelGGL(k1, dim3(lc.P), dim3(lc.k1_threads), lc.k1_lds, s, robot, q);
+  hipLaunchKernelGGL(k1, dim3(lc.P + (q.c0_in_ws ? 1 : 0)), dim3(lc.k1_threads), lc.k1_lds, s,
+                     robot, q);
   if ((e = hipGetLastError()) != hipSuccess) return (int)e;
   if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return (int)e;
   auto k2 = f16 ? merge_kernel<2> : merge_kernel<4>;

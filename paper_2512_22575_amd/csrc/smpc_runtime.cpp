@@ -460,6 +460,7 @@ smpc_status smpc_plan_step(smpc_ctx* ctx, const smpc_plan_args* a, void* stream)
   q.weights_out = a->weights_out;
   q.stats_out = a->stats_out;
   q.ws = ws;
+  q.c0_in_ws = (a->costs_out || a->stats_out) ? 1 : 0;
   const int e = launch_plan_step(ctx->dev_robot, q, lc, a->esdf.dtype == SMPC_GRID_F16, stream, ev);
   if (e != 0)
     return fail(ctx, SMPC_E_DEVICE, "kernel launch failed: %s",

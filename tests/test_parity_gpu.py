@@ -46,6 +46,18 @@ def small_inputs(seed, K, H, dt=0.05, n=32, voxel=0.05, **kw):
     return W.make_inputs(seed, K=K, H=H, dt=dt, n=n, voxel=voxel, n_boxes=6, n_spheres=4, **kw)
 
 
+def test_many_self_pairs_parity():
+    """336 pairs (adjacent links included, many overlapping at q0): more pairs than the
+    threads of a block, in the rollouts and in the state-0 terms of the reported costs."""
+    import dataclasses
+
+    from synth import robot as R
+    inp = small_inputs(77, 160, 12)
+    rob = R.make_robot(77, min_link_gap=1)
+    assert rob.n_pairs == 336
+    check_full(dataclasses.replace(inp, robot=rob))
+
+
 def test_tiny_workload_parity():
     check_full(W.tiny())
 
