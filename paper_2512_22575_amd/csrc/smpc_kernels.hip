@@ -722,21 +722,29 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
   __syncthreads();
 
   // S^(m) without the k = 0 state terms (eq. 28), summed over k in double, and the
-  // block's softmax partial (eqs. 29-30 regrouped per block), by wave 0: lane r
-  // holds rollout r (R <= 64); minimum and sums go through a fixed butterfly.
+  // block's softmax partial (eqs. 29-30 regrouped per block), by wave 0: G = 64 / R
+  // (rounded down to a power of 2) lanes per rollout, lane j of rollout r summing
+  // steps k = j, j + G, ... in order, then a butterfly over the G lanes; the
+  // minimum and the sums over rollouts go through further fixed butterflies.
   if (tid < kWave) {
+    int G = 1;
+    while (G * 2 * R <= kWave) G *= 2;
+    const int r = tid / G, j = tid - r * G;
     double s = 0.0;
-    if (tid < nroll) {
-      const float* c_r = L.cost + tid * H;
-      float cv[kMaxH];
+    if (r < nroll) {
+      const float* c_r = L.cost + r * H;
+      for (int c0 = 0; j + c0 * G < H; c0 += 8) {
+        float cv[8];
 #pragma unroll
-      for (int k = 0; k < kMaxH; ++k) cv[k] = c_r[min(k, H - 1)];
+        for (int c = 0; c < 8; ++c) cv[c] = c_r[min(j + (c0 + c) * G, H - 1)];
 #pragma unroll
-      for (int k = 0; k < kMaxH; ++k)
-        if (k < H) s += (double)cv[k];
-      ws.S[m0 + tid] = s;
+        for (int c = 0; c < 8; ++c)
+          if (j + (c0 + c) * G < H) s += (double)cv[c];
+      }
     }
-    const bool fin = tid < nroll && isfinite(s);
+    for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
+    if (r < nroll && j == 0) ws.S[m0 + r] = s;
+    const bool fin = r < nroll && j == 0 && isfinite(s);
     double mn = fin ? s : __builtin_inf();
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) mn = fmin(mn, __shfl_xor(mn, off, kWave));
@@ -747,7 +755,7 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
       Z += __shfl_xor(Z, off, kWave);
       Z2 += __shfl_xor(Z2, off, kWave);
     }
-    if (tid < R) L.e[tid] = e;
+    if (r < R && j == 0) L.e[r] = e;
     if (tid == 0) {
       ws.part_m[b] = mn;
       ws.part_Z[b] = Z;
