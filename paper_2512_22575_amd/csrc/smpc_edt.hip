@@ -12,8 +12,8 @@
 //
 //   pass x  (binary input): one wave per row; ballots of the sources of each
 //           64-voxel chunk give the nearest source on either side by bit scans;
-//   pass y  FH over 32 (x, z) lines per block, staged in LDS tiles;
-//   pass z  FH over 32 (x, y) lines per block, both fields, fused with the
+//   pass y  FH over 16 (x, z) lines per block, staged in LDS tiles;
+//   pass z  FH over 16 (x, y) lines per block, both fields, fused with the
 //           signed distance phi = voxel * (sqrt(D_out) - sqrt(D_in)).
 //
 // Compact intermediates: after the x and y passes a voxel's value in its own
@@ -21,8 +21,8 @@
 // value per voxel plus its occupancy bit carries both fields: 16 bits after the x
 // pass, 32 after the y pass.
 //
-// FH with 8 lanes per line.  Each lane builds the lower envelope of the samples of
-// its band of the line (FH's stack, kept as a linked list in LDS); three rounds of
+// FH with 16 lanes per line.  Each lane builds the lower envelope of the samples of
+// its band of the line (FH's stack, kept as a linked list in LDS); four rounds of
 // pairwise merges join adjacent bands.  In the dual picture the envelope is the
 // lower convex hull of the points (q, F_q), F_q = f(q) + q^2, so merging the hulls
 // of two index-separated bands only removes points near the junction: pop the left
@@ -42,8 +42,8 @@ namespace {
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;  // "no source on this line (yet)"
 constexpr uint16_t kNil = 0xFFFFu;       // end of a linked list
-constexpr int kLines = 32;               // lines per FH block
-constexpr int kG = 8;                    // lanes per line
+constexpr int kLines = 16;               // lines per FH block
+constexpr int kG = 16;                   // lanes per line
 constexpr int kFhThreads = kLines * kG;  // 256
 constexpr int kTs = kLines + 1;          // LDS tile row stride (words), padded
 constexpr int kMaxChunks = kEdtMaxSide / 64;
@@ -224,7 +224,7 @@ __device__ __forceinline__ void tile_fh(const Tile& T, int n, bool active, Emit&
   }
   __syncthreads();
 
-  // Phase B: merge groups of s bands pairwise, s = 1, 2, 4.
+  // Phase B: merge groups of s bands pairwise, s = 1, 2, 4, 8.
 #pragma unroll
   for (int s = 1; s < kG; s <<= 1) {
     const int rh = __shfl(head, lane + 1);
@@ -322,7 +322,8 @@ __device__ __forceinline__ void tile_fh(const Tile& T, int n, bool active, Emit&
 }
 
 // Stage samples q = 0..n-1 of the block's lines into the f tile: thread t takes
-// line t % kLines at q = t / kLines + 8 k.  Eight loads are issued before any is
+// line t % kLines at q = t / kLines + (kFhThreads / kLines) k.  Eight loads are
+// issued before any is
 // used (indices clamped into range, so no load sits behind a branch); decode(raw, q)
 // turns a record into the sample.  Threads of lines past the grid pass ok = false
 // and a valid base; their samples become kNone.
@@ -347,7 +348,7 @@ __device__ __forceinline__ void stage_tile(uint32_t* f, int n, const Rec* base, 
   }
 }
 
-// Pass y: block = 32 consecutive lines (x, z) of one field (blockIdx.y).
+// Pass y: block = 16 consecutive lines (x, z) of one field (blockIdx.y).
 __global__ __launch_bounds__(kFhThreads) void edt_pass_y_kernel(
     const uint16_t* __restrict__ xrec, uint32_t* __restrict__ yrec, int nx, int ny, int nz) {
   extern __shared__ uint32_t lds[];
@@ -382,7 +383,7 @@ __global__ __launch_bounds__(kFhThreads) void edt_pass_y_kernel(
   });
 }
 
-// Pass z: block = 32 consecutive lines (x, y); D_out, then D_in, then phi in a
+// Pass z: block = 16 consecutive lines (x, y); D_out, then D_in, then phi in a
 // coalesced sweep over the block's lines.  Without d2, D_out is parked in the phi
 // buffer (as bits) and D_in in the consumed y records.
 __global__ __launch_bounds__(kFhThreads) void edt_pass_z_kernel(
