@@ -323,9 +323,8 @@ __device__ __forceinline__ void tile_fh(const Tile& T, int n, bool active, Emit&
 
 // Stage samples q = 0..n-1 of the block's lines into the f tile: thread t takes
 // line t % kLines at q = t / kLines + (kFhThreads / kLines) k.  Eight loads are
-// issued before any is
-// used (indices clamped into range, so no load sits behind a branch); decode(raw, q)
-// turns a record into the sample.  Threads of lines past the grid pass ok = false
+// issued before any is used (indices clamped into range, so no load sits behind a
+// branch); decode(raw, q) turns a record into the sample.  Threads of lines past the grid pass ok = false
 // and a valid base; their samples become kNone.
 template <class Rec, class Decode>
 __device__ __forceinline__ void stage_tile(uint32_t* f, int n, const Rec* base, long long stride,
