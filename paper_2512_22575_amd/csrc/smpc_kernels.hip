@@ -785,9 +785,13 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
   }
 }
 
+// Register budget: at most 128 VGPRs (4 waves per SIMD), so that a CU holds a third
+// block next to two rollout blocks -- the extra state-0 block of a plan step runs
+// alongside them instead of waiting for a rollout block to finish.
+//
 // One plan step: the request travels by value in the kernel arguments.
 template <int kElemBytes>
-__global__ __launch_bounds__(kK1Threads) __attribute__((amdgpu_waves_per_eu(3))) void
+__global__ __launch_bounds__(kK1Threads) __attribute__((amdgpu_waves_per_eu(4))) void
 rollout_cost_kernel(const DevRobot* __restrict__ rob, const Request q) {
   if ((int)blockIdx.x == q.p.P) {
     // One extra block evaluates the state-0 terms while the rollout blocks run.
@@ -800,7 +804,7 @@ rollout_cost_kernel(const DevRobot* __restrict__ rob, const Request q) {
 
 // A batch of plan steps: block_req maps each block to its request.
 template <int kElemBytes>
-__global__ __launch_bounds__(kK1Threads) __attribute__((amdgpu_waves_per_eu(3))) void
+__global__ __launch_bounds__(kK1Threads) __attribute__((amdgpu_waves_per_eu(4))) void
 rollout_cost_batch_kernel(const DevRobot* __restrict__ rob, const Request* __restrict__ reqs,
                           const int32_t* __restrict__ block_req) {
   const Request& q = reqs[block_req[blockIdx.x]];
