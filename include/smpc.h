@@ -239,7 +239,7 @@ smpc_status smpc_grid_coarse_min(const smpc_grid* grid, float* coarse_out, void*
 #define SMPC_EDT_MAX_SIDE 512
 
 /*
- * Device workspace smpc_edt needs for an nx x ny x nz grid: six bytes per voxel.
+ * Device workspace smpc_edt needs for an nx x ny x nz grid: eight bytes per voxel.
  * Returns 0 when a side lies outside [1, SMPC_EDT_MAX_SIDE].
  */
 size_t smpc_edt_workspace_bytes(int32_t nx, int32_t ny, int32_t nz);

@@ -13,8 +13,8 @@
 //   pass x  (binary input): one wave per row; ballots of the sources of each
 //           64-voxel chunk give the nearest source on either side by bit scans;
 //   pass y  FH over 16 (x, z) lines per block, staged in LDS tiles;
-//   pass z  FH over 16 (x, y) lines per block, both fields, fused with the
-//           signed distance phi = voxel * (sqrt(D_out) - sqrt(D_in)).
+//   pass z  FH over 16 (x, y) lines per block, one field per block;
+//   phi     the signed distance phi = voxel * (sqrt(D_out) - sqrt(D_in)).
 //
 // Compact intermediates: after the x and y passes a voxel's value in its own
 // field is 0 (a free voxel is a source of D_in, an occupied one of D_out), so one
@@ -382,13 +382,15 @@ __global__ __launch_bounds__(kFhThreads) void edt_pass_y_kernel(
   });
 }
 
-// Pass z: block = 16 consecutive lines (x, y); D_out, then D_in, then phi in a
-// coalesced sweep over the block's lines.  Without d2, D_out is parked in the phi
-// buffer (as bits) and D_in in the consumed y records.
+// Pass z: block = 16 consecutive lines (x, y) of one field (blockIdx.y).  Without
+// d2, D_out is parked in the phi buffer (as bits) and D_in in the workspace region
+// of the x-pass records, which is dead once the y pass has finished; the y records
+// are only read (the blocks of the two fields run concurrently).
 __global__ __launch_bounds__(kFhThreads) void edt_pass_z_kernel(
-    uint32_t* __restrict__ yrec, int nx, int ny, int nz, uint32_t none_value, double voxel,
-    float* __restrict__ phi, uint32_t* __restrict__ d2) {
+    const uint32_t* __restrict__ yrec, int nx, int ny, int nz, uint32_t none_value, float* phi,
+    uint32_t* d2, uint32_t* d_in_scratch) {
   extern __shared__ uint32_t lds[];
+  const int fld = blockIdx.y;
   const long long plane = (long long)nx * ny;
   const long long nvox = plane * nz;
   const long long line0 = (long long)blockIdx.x * kLines;  // flattened (y, x)
@@ -396,48 +398,45 @@ __global__ __launch_bounds__(kFhThreads) void edt_pass_z_kernel(
   const int line = threadIdx.x / kG;
   const long long li = line0 + line;
   const bool active = li < plane;
-  uint32_t* dst[2] = {d2 ? d2 : reinterpret_cast<uint32_t*>(phi), d2 ? d2 + nvox : yrec};
-  for (int fld = 0; fld < 2; ++fld) {
-    {
-      const long long i = line0 + (long long)(threadIdx.x % kLines);
-      stage_tile(T.f, nz, yrec + (i < plane ? i : 0), plane, i < plane,
-                 [&](uint32_t r, int) { return field_of_y(r, fld); });
-    }
-    __syncthreads();
-    uint32_t* out = dst[fld] + li;
-    tile_fh(T, nz, active, [&](int p, uint32_t d) {
-      out[p * plane] = d == kNone ? none_value : d;
-    });
-    __syncthreads();
+  uint32_t* dst =
+      fld == 0 ? (d2 ? d2 : reinterpret_cast<uint32_t*>(phi)) : (d2 ? d2 + nvox : d_in_scratch);
+  {
+    const long long i = line0 + (long long)(threadIdx.x % kLines);
+    stage_tile(T.f, nz, yrec + (i < plane ? i : 0), plane, i < plane,
+               [&](uint32_t r, int) { return field_of_y(r, fld); });
   }
-  if (!phi) return;
-  constexpr int kRowsPerPass = kFhThreads / kLines;
-  constexpr int kBatch = 8;
-  const int l = threadIdx.x % kLines;
-  const long long i = line0 + l;
-  if (i >= plane) return;
-  for (int q0 = threadIdx.x / kLines; q0 < nz; q0 += kRowsPerPass * kBatch) {
-    uint32_t a[kBatch], b[kBatch];
-#pragma unroll
-    for (int j = 0; j < kBatch; ++j) {
-      const int q = min(q0 + j * kRowsPerPass, nz - 1);
-      a[j] = dst[0][q * plane + i];
-      b[j] = dst[1][q * plane + i];
-    }
-#pragma unroll
-    for (int j = 0; j < kBatch; ++j) {
-      const int q = q0 + j * kRowsPerPass;
-      if (q < nz)
-        phi[q * plane + i] = (float)(voxel * (__builtin_sqrt((double)a[j]) -
-                                              __builtin_sqrt((double)b[j])));
-    }
-  }
+  __syncthreads();
+  uint32_t* out = dst + li;
+  tile_fh(T, nz, active, [&](int p, uint32_t d) {
+    out[p * plane] = d == kNone ? none_value : d;
+  });
+}
+
+// phi = voxel * (sqrt(D_out) - sqrt(D_in)), in float64, rounded to float32 once.  At
+// most one of the two is nonzero (a voxel is a source of one field), and then the
+// formula is exactly +-voxel * sqrt(D) (subtracting sqrt(0) = 0 and negating are
+// exact), so one square root suffices.
+__global__ __launch_bounds__(256) void edt_phi_kernel(const uint32_t* d_out,
+                                                      const uint32_t* d_in, long long nvox,
+                                                      double voxel, float* phi) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nvox) return;
+  const uint32_t a = d_out[i], b = d_in[i];
+  double v;
+  if (a == 0u)
+    v = -(voxel * __builtin_sqrt((double)b));
+  else if (b == 0u)
+    v = voxel * __builtin_sqrt((double)a);
+  else
+    v = voxel * (__builtin_sqrt((double)a) - __builtin_sqrt((double)b));
+  phi[i] = (float)v;
 }
 
 }  // namespace
 
 size_t edt_workspace_bytes(long long nvox) {
-  return (size_t)nvox * (sizeof(uint32_t) + sizeof(uint16_t));
+  // y-pass records, then the x-pass records (u16) later reused for D_in (u32).
+  return (size_t)nvox * (2 * sizeof(uint32_t));
 }
 
 size_t edt_lds_bytes(int n_line) { return tile_bytes(n_line) + (size_t)n_line * sizeof(uint32_t); }
@@ -457,9 +456,16 @@ int launch_edt(const uint8_t* occ, int nx, int ny, int nz, float voxel, float* p
   const long long ly = (long long)nx * nz;
   hipLaunchKernelGGL(edt_pass_y_kernel, dim3((unsigned)((ly + kLines - 1) / kLines), 2),
                      dim3(kFhThreads), edt_lds_bytes(ny), stream, xrec, yrec, nx, ny, nz);
-  hipLaunchKernelGGL(edt_pass_z_kernel, dim3((unsigned)((plane + kLines - 1) / kLines)),
-                     dim3(kFhThreads), tile_bytes(nz), stream, yrec, nx, ny, nz, none_value,
-                     (double)voxel, phi, d2);
+  uint32_t* d_in_scratch = yrec + nvox;  // over the x-pass records, dead after pass y
+  hipLaunchKernelGGL(edt_pass_z_kernel, dim3((unsigned)((plane + kLines - 1) / kLines), 2),
+                     dim3(kFhThreads), tile_bytes(nz), stream, yrec, nx, ny, nz, none_value, phi,
+                     d2, d_in_scratch);
+  if (phi) {
+    const uint32_t* d_out = d2 ? d2 : reinterpret_cast<const uint32_t*>(phi);
+    const uint32_t* d_in = d2 ? d2 + nvox : d_in_scratch;
+    hipLaunchKernelGGL(edt_phi_kernel, dim3((unsigned)((nvox + 255) / 256)), dim3(256), 0, stream,
+                       d_out, d_in, nvox, (double)voxel, phi);
+  }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

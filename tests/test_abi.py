@@ -268,10 +268,10 @@ def test_server_create_without_gpu_fails_loudly(ctx):
 
 def test_edt_validates_on_host():
     need = S.smpc_edt_workspace_bytes(10, 20, 30)
-    assert need == 6 * 10 * 20 * 30
+    assert need == 8 * 10 * 20 * 30
     assert S.smpc_edt_workspace_bytes(0, 5, 5) == 0
     assert S.smpc_edt_workspace_bytes(5, 513, 5) == 0
-    assert S.smpc_edt_workspace_bytes(512, 512, 512) == 6 * 512 ** 3
+    assert S.smpc_edt_workspace_bytes(512, 512, 512) == 8 * 512 ** 3
     nvox = 6000
     occ, phi, d2, work = 0x10000000, 0x20000000, 0x30000000, 0x40000000
     ok = dict(occ=occ, nx=10, ny=20, nz=30, voxel=0.05, phi_out=phi, d2_out=d2, work=work,

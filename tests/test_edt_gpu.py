@@ -23,7 +23,7 @@ def gpu_edt(occ: np.ndarray, voxel: float, with_phi: bool = True, with_d2: bool 
     from paper_2512_22575_amd import smpc as S
     nz, ny, nx = occ.shape
     need = S.smpc_edt_workspace_bytes(nx, ny, nz)
-    assert need == 6 * occ.size
+    assert need == 8 * occ.size
     dev = torch.device("cuda:0")
     d_occ = torch.from_numpy(np.ascontiguousarray(occ, dtype=np.uint8)).to(dev)
     work = torch.full((need // 2 + 1,), -1, dtype=torch.int16, device=dev)
