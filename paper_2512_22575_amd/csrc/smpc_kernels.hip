@@ -1085,41 +1085,70 @@ __global__ __launch_bounds__(256) void sample_noise_kernel(uint32_t k0, uint32_t
 }
 
 // float32 -> float16 grid: clamp to [-clamp, clamp], round to nearest even.
-// Coarse lower bounds (smpc_grid_coarse_min): one wave per cell; lanes stride over
-// the cell's window of voxels [8 c, min(8 c + 8, n - 1)] per axis.  A non-finite
-// value anywhere in the window makes the bound -inf (never skip a lookup there).
+// Coarse lower bounds (smpc_grid_coarse_min): one block per row (cy, cz) of cells.
+// Each thread folds one x column of the rows y in [8 cy, 8 cy + 8], z in
+// [8 cz, 8 cz + 8] (clamped to the grid) -- minimum, largest |phi|, any non-finite
+// value -- with a batch of loads in flight; then each cell combines its 9 columns
+// [8 cx, 8 cx + 8] through LDS.  The x axis is covered in chunks of 31 cells (249
+// columns).  A non-finite value anywhere in a cell's window makes its bound -inf.
+constexpr int kCoarseThreads = 256;
+constexpr int kCellsPerChunk = (kCoarseThreads - 1) / kCoarseCell;  // 31
+
 template <int kElemBytes>
-__global__ __launch_bounds__(256) void grid_coarse_min_kernel(const void* __restrict__ grid,
-                                                              uint32_t grid_bytes, int nx, int ny,
-                                                              int nz, int ncx, int ncy, int ncz,
-                                                              float* __restrict__ out) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const long long cell = (long long)blockIdx.x * 4 + (threadIdx.x / kWave);
-  const long long ncells = (long long)ncx * ncy * ncz;
-  if (cell >= ncells) return;
-  const int cx = (int)(cell % ncx), cy = (int)((cell / ncx) % ncy), cz = (int)(cell / ((long long)ncx * ncy));
-  const int x0 = cx * kCoarseCell, y0 = cy * kCoarseCell, z0 = cz * kCoarseCell;
-  const int wx = min(x0 + kCoarseCell, nx - 1) - x0 + 1;
+__global__ __launch_bounds__(kCoarseThreads) void grid_coarse_min_kernel(
+    const void* __restrict__ grid, uint32_t grid_bytes, int nx, int ny, int nz, int ncx,
+    int ncy, int ncz, float* __restrict__ out) {
+  __shared__ float col_min[kCoarseThreads], col_max[kCoarseThreads];
+  __shared__ int col_bad[kCoarseThreads];
+  const int cy = blockIdx.x % ncy, cz = blockIdx.x / ncy;
+  const int y0 = cy * kCoarseCell, z0 = cz * kCoarseCell;
   const int wy = min(y0 + kCoarseCell, ny - 1) - y0 + 1;
   const int wz = min(z0 + kCoarseCell, nz - 1) - z0 + 1;
+  const int rows = wy * wz;
   const __amdgpu_buffer_rsrc_t rsrc = grid_resource(grid, grid_bytes);
-  float mn = __builtin_inff(), mx = 0.f;
-  bool bad = false;
-  for (int w = lane; w < wx * wy * wz; w += kWave) {
-    const int x = x0 + w % wx, y = y0 + (w / wx) % wy, z = z0 + w / (wx * wy);
-    const uint32_t off = (uint32_t)(((long long)z * ny + y) * nx + x) * kElemBytes;
-    const float v = load_grid<kElemBytes>(rsrc, off, 0u);
-    bad |= !isfinite(v);
-    mn = fminf(mn, v);
-    mx = fmaxf(mx, fabsf(v));
-  }
+  const int tid = threadIdx.x;
+  for (int cx0 = 0; cx0 < ncx; cx0 += kCellsPerChunk) {
+    const int x0 = cx0 * kCoarseCell;
+    const int x = min(x0 + tid, nx - 1);
+    float mn = __builtin_inff(), mx = 0.f;
+    bool bad = false;
+    constexpr int kBatch = 27;
+    for (int r0 = 0; r0 < rows; r0 += kBatch) {
+      float v[kBatch];
 #pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) {
-    mn = fminf(mn, __shfl_xor(mn, off, kWave));
-    mx = fmaxf(mx, __shfl_xor(mx, off, kWave));
+      for (int c = 0; c < kBatch; ++c) {
+        const int r = min(r0 + c, rows - 1);
+        const int y = y0 + r % wy, z = z0 + r / wy;
+        const uint32_t off = (uint32_t)(((long long)z * ny + y) * nx + x) * kElemBytes;
+        v[c] = load_grid<kElemBytes>(rsrc, off, 0u);
+      }
+#pragma unroll
+      for (int c = 0; c < kBatch; ++c) {
+        bad |= !isfinite(v[c]);
+        mn = fminf(mn, v[c]);
+        mx = fmaxf(mx, fabsf(v[c]));
+      }
+    }
+    col_min[tid] = mn;
+    col_max[tid] = mx;
+    col_bad[tid] = bad;
+    __syncthreads();
+    const int cx = cx0 + tid;
+    if (tid < kCellsPerChunk && cx < ncx) {
+      const int c_lo = tid * kCoarseCell;
+      const int c_hi = min(x0 + c_lo + kCoarseCell, nx - 1) - x0;  // last column, chunk-relative
+      float cmn = __builtin_inff(), cmx = 0.f;
+      bool cbad = false;
+      for (int c = c_lo; c <= c_hi; ++c) {
+        cmn = fminf(cmn, col_min[c]);
+        cmx = fmaxf(cmx, col_max[c]);
+        cbad |= col_bad[c] != 0;
+      }
+      out[((long long)cz * ncy + cy) * ncx + cx] =
+          cbad ? -__builtin_inff() : cmn - (1e-5f + cmx * 0x1p-18f);
+    }
+    __syncthreads();
   }
-  const bool any_bad = __any(bad);
-  if (lane == 0) out[cell] = any_bad ? -__builtin_inff() : mn - (1e-5f + mx * 0x1p-18f);
 }
 
 __global__ __launch_bounds__(256) void grid_to_f16_kernel(const float* __restrict__ src,
@@ -1237,8 +1266,9 @@ int launch_grid_coarse_min(const void* grid, bool f16, int nx, int ny, int nz, f
   const long long ncells = (long long)ncx * ncy * ncz;
   const uint32_t bytes = (uint32_t)((long long)nx * ny * nz * (f16 ? 2 : 4));
   auto k = f16 ? grid_coarse_min_kernel<2> : grid_coarse_min_kernel<4>;
-  hipLaunchKernelGGL(k, dim3((unsigned)((ncells + 3) / 4)), dim3(256), 0, (hipStream_t)stream,
-                     grid, bytes, nx, ny, nz, ncx, ncy, ncz, out);
+  (void)ncells;
+  hipLaunchKernelGGL(k, dim3((unsigned)((long long)ncy * ncz)), dim3(kCoarseThreads), 0,
+                     (hipStream_t)stream, grid, bytes, nx, ny, nz, ncx, ncy, ncz, out);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
