@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 from oracle import edt as E
+from oracle import ogm as G
 from oracle import smpc_oracle as O
 from tests import test_oracle_pins as P
 from synth import robot as R
@@ -117,6 +118,18 @@ def _signed_distance_no_inside(occ, voxel, transform=None):
     return phi.astype(np.float32), d_out, np.zeros_like(d_out)
 
 
+def _pixel_rounded(u):
+    return np.round(u)                                  # mistake: nearest pixel corner
+
+
+def _classify_free_behind(dz, tol, has):
+    return has & (np.abs(dz) <= tol), has & (dz > tol)  # mistake: free behind the surface
+
+
+def _robot_not_reset(L, margin, l_min):
+    return L                                            # mistake: robot voxels kept
+
+
 def _margin_not_applied(x, lo, hi, margin_frac):
     lo = np.asarray(lo, np.float64)
     hi = np.asarray(hi, np.float64)
@@ -169,6 +182,9 @@ MUTANTS = {
     "limit_margin_dropped": ("limit_violation", _margin_not_applied),
     "fh_intersection_without_squares": ("fh_1d", _fh_1d_no_root_square, E),
     "signed_distance_without_inside": ("signed_distance", _signed_distance_no_inside, E),
+    "ogm_pixel_rounded": ("pixel_index", _pixel_rounded, G),
+    "ogm_free_behind_surface": ("classify", _classify_free_behind, G),
+    "ogm_robot_voxels_not_reset": ("robot_reset", _robot_not_reset, G),
 }
 
 

@@ -13,6 +13,7 @@ import scipy.linalg
 from scipy.spatial.transform import Rotation
 
 from oracle import edt as E
+from oracle import ogm as G
 from oracle import smpc_oracle as O
 from synth import robot as R
 from synth import scene as SC
@@ -588,3 +589,144 @@ def test_update_excludes_zero_weight_rollouts_even_with_non_finite_noise():
     eps[1] = np.nan
     w = np.array([0.25, 0.0, 0.75])
     np.testing.assert_allclose(O.update(Ubar, eps, w), np.ones((2, 7)))
+
+
+# ---------------------------------------------------------------------------
+# Occupancy mapping by voxel projection (Sec. III-A) and the robot mask (Remark 2)
+# ---------------------------------------------------------------------------
+
+OGM_PRM = dict(tol=0.025, l_hit=0.85, l_miss=-0.4, l_min=-2.0, l_max=3.5, l_occ=0.0,
+               robot_pad=0.01)
+
+
+def _axis_camera():
+    from synth import camera as C
+    T = np.eye(4)
+    T[:3, :3] = np.array([[0.0, 0.0, 1.0], [-1.0, 0.0, 0.0], [0.0, -1.0, 0.0]])  # optical axis = +x
+    T[:3, 3] = [0.0, 0.0, 0.5]
+    return C.Camera(fx=100.0, fy=100.0, cx=40.0, cy=30.0, width=80, height=60,
+                    T_wc=T.astype(np.float32), min_depth=0.1, max_depth=4.0)
+
+
+def _wall_scene():
+    wall = SC.Primitive("box", np.array([1.1, 0.0, 0.5]), np.array([0.2, 4.0, 4.0]), np.zeros(3))
+    return [wall]
+
+
+def test_ogm_wall_closed_form_along_the_optical_axis():
+    """Wall face at x = 1.0 (depth 1.0 exactly): voxel centres at x = 0.02 + 0.04 i on the
+    axis are free up to 0.94, occupied at 0.98 and 1.02 (|x - 1| <= 0.025), unchanged behind."""
+    from synth import camera as C
+    cam = _axis_camera()
+    depth = C.render_depth(cam, _wall_scene())
+    assert np.all(depth == np.float32(1.0))
+    origin = np.array([0.0, -0.02, 0.48])
+    L0 = np.zeros((1, 1, 40), np.float32)
+    L, occ, _ = G.ogm_update(L0, depth, cam, origin, 0.04, OGM_PRM)
+    x = 0.02 + 0.04 * np.arange(40)
+    want = np.where(np.abs(x - 1.0) <= 0.025, 0.85, np.where(x < 1.0 - 0.025, -0.4, 0.0))
+    want[x < 0.1] = -0.4          # in front of the wall at any depth > 0
+    np.testing.assert_array_equal(L[0, 0], want.astype(np.float32))
+    np.testing.assert_array_equal(occ[0, 0], want > 0)
+
+
+def test_ogm_voxels_out_of_view_unchanged():
+    from synth import camera as C
+    cam = _axis_camera()
+    depth = C.render_depth(cam, _wall_scene())
+    origin = np.array([-1.0, -3.0, 0.48])
+    L0 = np.full((1, 3, 4), 0.3, np.float32)
+    L, _, _ = G.ogm_update(L0, depth, cam, origin, 0.5, OGM_PRM)
+    # x centres -0.75 (behind the camera), -0.25, 0.25, 0.75; y centres -2.75 .. -1.75:
+    # far outside the 40-pixel half width at these depths except none
+    np.testing.assert_array_equal(L, L0)
+
+
+def test_ogm_log_odds_saturate():
+    from synth import camera as C
+    cam = _axis_camera()
+    depth = C.render_depth(cam, _wall_scene())
+    origin = np.array([0.0, -0.02, 0.48])
+    L = np.zeros((1, 1, 40), np.float32)
+    for _ in range(12):
+        L, occ, _ = G.ogm_update(L, depth, cam, origin, 0.04, OGM_PRM)
+    x = 0.02 + 0.04 * np.arange(40)
+    assert np.all(L[0, 0][np.abs(x - 1.0) <= 0.025] == np.float32(3.5))
+    assert np.all(L[0, 0][(x < 0.975) & (x > 0.1)] == np.float32(-2.0))
+
+
+def test_ogm_robot_mask_discards_returns_and_clears_voxels():
+    """A robot sphere at (0.6, 0, 0.5), r = 0.1, in front of the wall: its returns are
+    discarded (no voxel occupied near it, none cleared behind it along its pixels) and
+    the voxels inside it are set to l_min."""
+    from synth import camera as C
+    cam = _axis_camera()
+    c, r = np.array([[0.6, 0.0, 0.5]]), np.array([0.1])
+    depth = C.render_depth(cam, _wall_scene(), spheres=c, radii=r)
+    cleaned, _ = G.clean_depth(depth, cam, c, r + OGM_PRM["robot_pad"])
+    on_robot = (depth > 0) & (depth < 0.9)
+    assert on_robot.sum() > 100
+    assert np.all(cleaned[on_robot] == 0) and np.all(cleaned[~on_robot] == depth[~on_robot])
+    origin = np.array([0.3, -0.3, 0.2])
+    vox = 0.03
+    L0 = np.full((20, 20, 30), 0.5, np.float32)
+    L, occ, _ = G.ogm_update(L0, depth, cam, origin, vox, OGM_PRM, c, r)
+    zi, yi, xi = np.meshgrid(*[np.arange(n) for n in L.shape], indexing="ij")
+    pw = np.stack([origin[0] + (xi + 0.5) * vox, origin[1] + (yi + 0.5) * vox,
+                   origin[2] + (zi + 0.5) * vox], -1)
+    inside = np.linalg.norm(pw - c[0], axis=-1) <= r[0] + OGM_PRM["robot_pad"]
+    assert inside.sum() > 100 and np.all(L[inside] == np.float32(-2.0))
+    # from an unknown map (log-odds 0), nothing near the robot's surface becomes occupied
+    near_surface = (np.abs(np.linalg.norm(pw - c[0], axis=-1) - r[0]) < 0.05) & ~inside
+    L1, occ1, _ = G.ogm_update(np.zeros_like(L0), depth, cam, origin, vox, OGM_PRM, c, r)
+    assert not occ1[near_surface].any()
+    # without the mask the sphere's surface is mapped as an obstacle
+    _, occ_nomask, _ = G.ogm_update(np.zeros_like(L0), depth, cam, origin, vox, OGM_PRM)
+    assert occ_nomask[near_surface].sum() >= 5
+
+
+def test_ogm_pixel_is_the_square_containing_the_projection():
+    """Depth 1.0 left of pixel column 40, 2.0 from it on; a voxel at x = 1.5 projecting to
+    u = 39.7 reads the left pixel (behind its surface: unchanged), not the right one."""
+    cam = _axis_camera()
+    depth = np.where(np.arange(80)[None, :] < 40, 1.0, 2.0) * np.ones((60, 1))
+    depth = depth.astype(np.float32)
+    y = 0.0045                                   # camera x = -y: u = 100 * 0.0045 / 1.5 ...
+    origin = np.array([1.5 - 0.005, y - 0.005, 0.5 - 0.005])
+    L, _, _ = G.ogm_update(np.zeros((1, 1, 1), np.float32), depth, cam, origin, 0.01, OGM_PRM)
+    assert L[0, 0, 0] == 0.0                     # u = 40 - 0.3 -> pixel 39 (depth 1.0)
+    origin2 = origin + np.array([0.0, -0.009, 0.0])   # u = 40 + 0.3 -> pixel 40 (depth 2.0)
+    L2, _, _ = G.ogm_update(np.zeros((1, 1, 1), np.float32), depth, cam, origin2, 0.01, OGM_PRM)
+    assert L2[0, 0, 0] == np.float32(-0.4)
+
+
+def _prim_sdf(prims, p):
+    d = np.full(p.shape[:-1], np.inf)
+    for q in prims:
+        if q.kind == "box":
+            e = np.abs(p - q.center) - 0.5 * q.size
+            out = np.linalg.norm(np.maximum(e, 0.0), axis=-1)
+            d = np.minimum(d, out + np.minimum(e.max(axis=-1), 0.0))
+        else:
+            d = np.minimum(d, np.linalg.norm(p - q.center, axis=-1) - q.size[0])
+    return d
+
+
+def test_ogm_occupied_voxels_lie_on_surfaces():
+    """Occupied voxel centres are within tol plus half a voxel and a pixel footprint of a
+    primitive surface (analytic signed distances, independent of the projection)."""
+    from synth import camera as C
+    from synth import workload as W
+    sc = W.ReactiveScenario(seed=3)
+    cam = C.default_camera(160, 120)
+    depth = C.render_depth(cam, sc.prims)
+    vox = 0.04
+    L, occ, _ = G.ogm_update(np.zeros((40, 50, 50), np.float32), depth, cam, sc.origin, vox,
+                            OGM_PRM)
+    assert occ.sum() > 50
+    zi, yi, xi = np.nonzero(occ)
+    pw = np.stack([sc.origin[0] + (xi + 0.5) * vox, sc.origin[1] + (yi + 0.5) * vox,
+                   sc.origin[2] + (zi + 0.5) * vox], -1)
+    sdf = _prim_sdf(sc.prims, pw)
+    footprint = 3.0 / cam.fx * 2.5        # a pixel's width at the farthest depth, generous
+    assert np.all(np.abs(sdf) <= OGM_PRM["tol"] + vox * np.sqrt(3) + footprint), float(np.abs(sdf).max())
