@@ -233,6 +233,60 @@ int64_t smpc_grid_coarse_cells(int32_t nx, int32_t ny, int32_t nz);
  */
 smpc_status smpc_grid_coarse_min(const smpc_grid* grid, float* coarse_out, void* stream);
 
+/* ---- Occupancy mapping (Sec. III-A) with the robot mask (Remark 2) ----------- */
+
+/* Pinhole depth camera.  Pixel (i, j) covers [i, i + 1) x [j, j + 1) in image
+ * coordinates u = fx x / z + cx, v = fy y / z + cy of a camera-frame point (x, y, z);
+ * depth is the camera-frame z of the return. */
+typedef struct {
+  float fx, fy, cx, cy;         /* intrinsics (pixels), fx, fy > 0 */
+  int32_t width, height;        /* image size, each in [1, 16384] */
+  float T_wc[16];               /* camera-to-world pose, row-major SE(3) */
+  float min_depth, max_depth;   /* returns outside [min_depth, max_depth] are no return */
+} smpc_camera;
+
+/* Occupancy update parameters (log-odds). */
+typedef struct {
+  float tol;                    /* |z - d| <= tol: the voxel is on the surface (m), >= 0 */
+  float l_hit, l_miss;          /* increments for occupied (> 0) and free (< 0) voxels */
+  float l_min, l_max;           /* clamp, l_min <= l_max */
+  float l_occ;                  /* a voxel is occupied when its log-odds exceeds l_occ */
+  float robot_pad;              /* padding of the robot sphere model (m), >= 0 */
+} smpc_ogm_params;
+
+/* Device workspace smpc_ogm_update needs for a width x height image (bytes). */
+size_t smpc_ogm_workspace_bytes(int32_t width, int32_t height);
+
+/*
+ * One occupancy update by voxel projection (Sec. III-A): every voxel centre is
+ * projected into the depth image, reads the pixel whose square contains the
+ * projection, and is classified against that pixel's depth d by its camera-frame
+ * z: |z - d| <= tol occupied (log-odds + l_hit), z < d - tol free (+ l_miss), else
+ * unknown (unchanged); voxels behind the camera, outside the image or on a pixel
+ * without a return are unknown; log-odds are clamped to [l_min, l_max].
+ * Robot mask (Remark 2), when q is given: the robot's collision spheres at joint
+ * positions q, each padded by robot_pad, are computed on the device; returns whose
+ * back-projected point (pixel centre at depth d) lies in a padded sphere are
+ * discarded before the update, and voxels whose centre lies in one are set to l_min.
+ *   ctx       : context; its robot must be set when q is given.
+ *   q         : host float[7] joint positions, or NULL (no mask).
+ *   depth     : device float [height][width] (metres; non-finite or out of range:
+ *               no return).
+ *   cam, prm  : host structs.
+ *   log_odds  : device float [nz][ny][nx] (x fastest), updated in place.
+ *   occ_out   : device uint8 [nz][ny][nx] (1 = occupied), or NULL.
+ *   origin    : host float[3], corner of voxel (0,0,0); voxel edge in metres.
+ *   work      : device scratch of smpc_ogm_workspace_bytes(width, height) bytes,
+ *               4-byte aligned; on return its first width * height floats hold the
+ *               depth image with the discarded returns set to 0.
+ * nx * ny * nz < 2^31.  Runs asynchronously on `stream`.
+ */
+smpc_status smpc_ogm_update(smpc_ctx* ctx, const float* q, const float* depth,
+                            const smpc_camera* cam, float* log_odds, uint8_t* occ_out,
+                            int32_t nx, int32_t ny, int32_t nz, const float* origin, float voxel,
+                            const smpc_ogm_params* prm, void* work, size_t work_bytes,
+                            void* stream);
+
 /* ---- Distance field construction (Sec. III-B) ------------------------------- */
 
 /* Longest grid side smpc_edt accepts, in voxels. */

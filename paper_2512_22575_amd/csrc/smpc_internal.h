@@ -142,6 +142,25 @@ inline int coarse_cells_1d(int n) { return (n - 2) / kCoarseCell + 1; }
 int launch_grid_coarse_min(const void* grid, bool f16, int nx, int ny, int nz, float* out,
                            void* stream);
 
+// Occupancy update (smpc_ogm_update): everything the two kernels need, by value.
+struct OgmArgs {
+  float fx, fy, cx, cy;
+  int32_t width, height;
+  float R[9];                  // camera-to-world rotation, row-major
+  float t[3];                  // camera position
+  float min_depth, max_depth;
+  float q[kNdof];              // joint positions of the robot mask
+  int32_t use_mask;
+  float robot_pad;
+  float origin[3];
+  float voxel;
+  int32_t nx, ny, nz;
+  float tol, l_hit, l_miss, l_min, l_max, l_occ;
+};
+constexpr int kOgmSphereFloats = kSlots * 4 + 8;  // centres, padded radius^2, bounding box
+int launch_ogm(const DevRobot* robot, const OgmArgs& a, const float* depth, float* log_odds,
+               uint8_t* occ, float* work, hipStream_t stream);
+
 constexpr int kEdtMaxSide = SMPC_EDT_MAX_SIDE;
 // Signed distance field from occupancy (smpc_edt.hip); sizes already validated.
 size_t edt_workspace_bytes(long long nvox);

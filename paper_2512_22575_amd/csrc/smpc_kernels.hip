@@ -1151,6 +1151,141 @@ __global__ __launch_bounds__(kCoarseThreads) void grid_coarse_min_kernel(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Occupancy update by voxel projection (Sec. III-A) with the robot mask (Remark 2)
+// ---------------------------------------------------------------------------
+// The robot's collision spheres at joint positions q (padded): centres and squared
+// padded radii in sph[4 s .. 4 s + 3], bounding box of the padded spheres in
+// sph[4 kSlots .. 4 kSlots + 5].  Computed by a whole block (the chain by thread 0).
+__device__ __forceinline__ void ogm_robot_spheres(const DevRobot* __restrict__ rob,
+                                                  const OgmArgs& a, float* sph) {
+  __shared__ Frame frames[kNdof];
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    Frame T = identity_frame();
+#pragma unroll
+    for (int i = 0; i < kNdof; ++i) {
+      float s_, c_;
+      sincosf(a.q[i], &s_, &c_);
+      mdh_step(T, rob->ca[i], rob->sa[i], rob->a[i], rob->d[i], c_, s_);
+      frames[i] = T;
+    }
+  }
+  __syncthreads();
+  if (tid < kSlots) {
+    float px = 0.f, py = 0.f, pz = 0.f, r2 = -1.f;  // inactive slot: never contains a point
+    if (rob->slot_active & (1u << tid)) {
+      transform_point(frames[tid / kSpl], rob->sc[tid][0], rob->sc[tid][1], rob->sc[tid][2], px,
+                      py, pz);
+      const float r = rob->sc[tid][3] + a.robot_pad;
+      r2 = r * r;
+    }
+    sph[4 * tid + 0] = px;
+    sph[4 * tid + 1] = py;
+    sph[4 * tid + 2] = pz;
+    sph[4 * tid + 3] = r2;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    float lo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
+    float hi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
+    for (int s = 0; s < kSlots; ++s) {
+      if (sph[4 * s + 3] < 0.f) continue;
+      const float r = sqrtf(sph[4 * s + 3]) * 1.0001f + 1e-6f;  // rounding slack
+      for (int k = 0; k < 3; ++k) {
+        lo[k] = fminf(lo[k], sph[4 * s + k] - r);
+        hi[k] = fmaxf(hi[k], sph[4 * s + k] + r);
+      }
+    }
+    for (int k = 0; k < 3; ++k) {
+      sph[4 * kSlots + k] = lo[k];
+      sph[4 * kSlots + 3 + k] = hi[k];
+    }
+  }
+  __syncthreads();
+}
+
+// Whether p lies in a padded robot sphere (reads the table at uniform addresses).
+__device__ __forceinline__ bool in_robot(const float* sph, float x, float y, float z) {
+  if (x < sph[4 * kSlots] || y < sph[4 * kSlots + 1] || z < sph[4 * kSlots + 2] ||
+      x > sph[4 * kSlots + 3] || y > sph[4 * kSlots + 4] || z > sph[4 * kSlots + 5])
+    return false;
+  bool in = false;
+#pragma unroll 4
+  for (int s = 0; s < kSlots; ++s) {
+    const float dx = x - sph[4 * s], dy = y - sph[4 * s + 1], dz = z - sph[4 * s + 2];
+    in |= fmaf(dx, dx, fmaf(dy, dy, dz * dz)) <= sph[4 * s + 3];
+  }
+  return in;
+}
+
+// Pass 1: valid returns not inside the robot, others 0; block 0 publishes the spheres.
+__global__ __launch_bounds__(256) void ogm_pixel_kernel(const DevRobot* __restrict__ rob,
+                                                        const OgmArgs a,
+                                                        const float* __restrict__ depth,
+                                                        float* __restrict__ work) {
+  __shared__ float sph[kOgmSphereFloats];
+  if (a.use_mask) ogm_robot_spheres(rob, a, sph);
+  const long long npix = (long long)a.width * a.height;
+  float* sph_out = work + npix;
+  if (a.use_mask && blockIdx.x == 0 && threadIdx.x < kOgmSphereFloats)
+    sph_out[threadIdx.x] = sph[threadIdx.x];
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= npix) return;
+  const float d = depth[i];
+  bool keep = isfinite(d) && d >= a.min_depth && d <= a.max_depth;
+  if (keep && a.use_mask) {
+    const int v = (int)(i / a.width), u = (int)(i - (long long)v * a.width);
+    const float xc = ((float)u + 0.5f - a.cx) * d / a.fx;
+    const float yc = ((float)v + 0.5f - a.cy) * d / a.fy;
+    const float wx = fmaf(a.R[0], xc, fmaf(a.R[1], yc, fmaf(a.R[2], d, a.t[0])));
+    const float wy = fmaf(a.R[3], xc, fmaf(a.R[4], yc, fmaf(a.R[5], d, a.t[1])));
+    const float wz = fmaf(a.R[6], xc, fmaf(a.R[7], yc, fmaf(a.R[8], d, a.t[2])));
+    keep = !in_robot(sph, wx, wy, wz);
+  }
+  work[i] = keep ? d : 0.f;
+}
+
+// Pass 2: one thread per voxel (x fastest): project, classify, update, robot reset.
+__global__ __launch_bounds__(256) void ogm_voxel_kernel(const OgmArgs a,
+                                                        const float* __restrict__ work,
+                                                        float* __restrict__ log_odds,
+                                                        uint8_t* __restrict__ occ) {
+  const long long nvox = (long long)a.nx * a.ny * a.nz;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nvox) return;
+  const long long plane = (long long)a.nx * a.ny;
+  const int iz = (int)(i / plane);
+  const long long r = i - (long long)iz * plane;
+  const int iy = (int)(r / a.nx), ix = (int)(r - (long long)iy * a.nx);
+  const float wx = a.origin[0] + ((float)ix + 0.5f) * a.voxel;
+  const float wy = a.origin[1] + ((float)iy + 0.5f) * a.voxel;
+  const float wz = a.origin[2] + ((float)iz + 0.5f) * a.voxel;
+  const float dx = wx - a.t[0], dy = wy - a.t[1], dz = wz - a.t[2];
+  // camera frame: R^T (p - t)
+  const float x = fmaf(a.R[0], dx, fmaf(a.R[3], dy, a.R[6] * dz));
+  const float y = fmaf(a.R[1], dx, fmaf(a.R[4], dy, a.R[7] * dz));
+  const float z = fmaf(a.R[2], dx, fmaf(a.R[5], dy, a.R[8] * dz));
+  float L = log_odds[i];
+  if (z > 0.f) {
+    const float u = a.fx * x / z + a.cx, v = a.fy * y / z + a.cy;
+    const float fu = floorf(u), fv = floorf(v);
+    if (fu >= 0.f && fu < (float)a.width && fv >= 0.f && fv < (float)a.height) {
+      const float d = work[(long long)fv * a.width + (long long)fu];
+      if (d > 0.f) {
+        const float e = z - d;
+        if (fabsf(e) <= a.tol)
+          L = fminf(fmaxf(L + a.l_hit, a.l_min), a.l_max);
+        else if (e < -a.tol)
+          L = fminf(fmaxf(L + a.l_miss, a.l_min), a.l_max);
+      }
+    }
+  }
+  if (a.use_mask && in_robot(work + (long long)a.width * a.height, wx, wy, wz)) L = a.l_min;
+  log_odds[i] = L;
+  if (occ) occ[i] = L > a.l_occ ? 1 : 0;
+}
+
 __global__ __launch_bounds__(256) void grid_to_f16_kernel(const float* __restrict__ src,
                                                           unsigned short* __restrict__ dst,
                                                           long long n, float clamp) {
@@ -1258,6 +1393,17 @@ int launch_sample_noise(uint64_t seed, int K, int H, const float* sigma, float* 
                      static_cast<hipStream_t>(stream), (uint32_t)seed, (uint32_t)(seed >> 32), K,
                      H, sg, eps, words);
   return (int)hipGetLastError();
+}
+
+int launch_ogm(const DevRobot* robot, const OgmArgs& a, const float* depth, float* log_odds,
+               uint8_t* occ, float* work, hipStream_t stream) {
+  const long long npix = (long long)a.width * a.height;
+  const long long nvox = (long long)a.nx * a.ny * a.nz;
+  hipLaunchKernelGGL(ogm_pixel_kernel, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, stream,
+                     robot, a, depth, work);
+  hipLaunchKernelGGL(ogm_voxel_kernel, dim3((unsigned)((nvox + 255) / 256)), dim3(256), 0, stream,
+                     a, work, log_odds, occ);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_grid_coarse_min(const void* grid, bool f16, int nx, int ny, int nz, float* out,

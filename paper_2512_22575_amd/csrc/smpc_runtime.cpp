@@ -505,6 +505,111 @@ smpc_status smpc_grid_to_f16(const float* src, void* dst, int64_t n, float clamp
                                                                         : SMPC_E_DEVICE;
 }
 
+size_t smpc_ogm_workspace_bytes(int32_t width, int32_t height) {
+  if (width < 1 || height < 1 || width > 16384 || height > 16384) return 0;
+  return ((size_t)width * height + 128) * sizeof(float);
+}
+
+smpc_status smpc_ogm_update(smpc_ctx* ctx, const float* q, const float* depth,
+                            const smpc_camera* cam, float* log_odds, uint8_t* occ_out,
+                            int32_t nx, int32_t ny, int32_t nz, const float* origin, float voxel,
+                            const smpc_ogm_params* prm, void* work, size_t work_bytes,
+                            void* stream) {
+  static_assert(kOgmSphereFloats <= 128, "sphere table fits the workspace tail");
+  if (!ctx) return SMPC_E_INVALID_ARG;
+  ctx->last_error.clear();
+  if (!depth || !cam || !log_odds || !origin || !prm || !work)
+    return fail(ctx, SMPC_E_INVALID_ARG, "null pointer argument");
+  if (q && !ctx->robot_set) return fail(ctx, SMPC_E_INVALID_ARG, "robot mask without a robot");
+  if (q && !finite_all(q, kNdof)) return fail(ctx, SMPC_E_INVALID_ARG, "non-finite q");
+  const float intr[] = {cam->fx, cam->fy, cam->cx, cam->cy};
+  if (!finite_all(intr, 4) || !(cam->fx > 0.f) || !(cam->fy > 0.f))
+    return fail(ctx, SMPC_E_INVALID_ARG, "intrinsics must be finite, fx and fy > 0");
+  const size_t need = smpc_ogm_workspace_bytes(cam->width, cam->height);
+  if (need == 0)
+    return fail(ctx, SMPC_E_INVALID_ARG, "image %dx%d outside [1, 16384]", cam->width,
+                cam->height);
+  if (work_bytes < need || ((uintptr_t)work & 3u))
+    return fail(ctx, SMPC_E_INVALID_ARG, "work needs %zu bytes, 4-byte aligned", need);
+  if (!std::isfinite(cam->min_depth) || !std::isfinite(cam->max_depth) ||
+      !(cam->min_depth > 0.f) || cam->min_depth > cam->max_depth)
+    return fail(ctx, SMPC_E_INVALID_ARG, "depth range must satisfy 0 < min <= max");
+  const float* T = cam->T_wc;
+  if (!finite_all(T, 16)) return fail(ctx, SMPC_E_INVALID_ARG, "non-finite T_wc");
+  if (T[12] != 0.f || T[13] != 0.f || T[14] != 0.f || T[15] != 1.f)
+    return fail(ctx, SMPC_E_INVALID_ARG, "T_wc last row must be [0 0 0 1]");
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double dot = 0.0;
+      for (int r = 0; r < 3; ++r) dot += (double)T[r * 4 + i] * (double)T[r * 4 + j];
+      if (std::fabs(dot - (i == j ? 1.0 : 0.0)) > 1e-4)
+        return fail(ctx, SMPC_E_INVALID_ARG, "T_wc rotation is not orthonormal");
+    }
+  if (nx < 1 || ny < 1 || nz < 1 || (long long)nx * ny * nz >= (1LL << 31))
+    return fail(ctx, SMPC_E_INVALID_ARG, "grid %dx%dx%d: sides >= 1, fewer than 2^31 voxels",
+                nx, ny, nz);
+  if (!finite_all(origin, 3) || !std::isfinite(voxel) || !(voxel > 0.f))
+    return fail(ctx, SMPC_E_INVALID_ARG, "origin/voxel must be finite, voxel > 0");
+  const float pv[] = {prm->tol, prm->l_hit, prm->l_miss, prm->l_min,
+                      prm->l_max, prm->l_occ, prm->robot_pad};
+  if (!finite_all(pv, 7) || prm->tol < 0.f || prm->robot_pad < 0.f || prm->l_min > prm->l_max)
+    return fail(ctx, SMPC_E_INVALID_ARG,
+                "parameters must be finite, tol >= 0, robot_pad >= 0, l_min <= l_max");
+  const size_t nvox = (size_t)nx * ny * nz, npix = (size_t)cam->width * cam->height;
+  struct Span {
+    uintptr_t lo, hi;
+  };
+  const Span spans[4] = {{(uintptr_t)depth, (uintptr_t)depth + 4 * npix},
+                         {(uintptr_t)work, (uintptr_t)work + need},
+                         {(uintptr_t)log_odds, (uintptr_t)log_odds + 4 * nvox},
+                         {(uintptr_t)occ_out, occ_out ? (uintptr_t)occ_out + nvox : 0}};
+  for (int a = 0; a < 4; ++a)
+    for (int b = a + 1; b < 4; ++b)
+      if (spans[a].lo < spans[b].hi && spans[b].lo < spans[a].hi)
+        return fail(ctx, SMPC_E_INVALID_ARG, "depth, work, log_odds and occ_out overlap");
+
+  OgmArgs oa;
+  std::memset(&oa, 0, sizeof oa);
+  oa.fx = cam->fx;
+  oa.fy = cam->fy;
+  oa.cx = cam->cx;
+  oa.cy = cam->cy;
+  oa.width = cam->width;
+  oa.height = cam->height;
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c) oa.R[r * 3 + c] = T[r * 4 + c];
+    oa.t[r] = T[r * 4 + 3];
+    oa.origin[r] = origin[r];
+  }
+  oa.min_depth = cam->min_depth;
+  oa.max_depth = cam->max_depth;
+  oa.use_mask = q ? 1 : 0;
+  if (q)
+    for (int j = 0; j < kNdof; ++j) oa.q[j] = q[j];
+  oa.robot_pad = prm->robot_pad;
+  oa.voxel = voxel;
+  oa.nx = nx;
+  oa.ny = ny;
+  oa.nz = nz;
+  oa.tol = prm->tol;
+  oa.l_hit = prm->l_hit;
+  oa.l_miss = prm->l_miss;
+  oa.l_min = prm->l_min;
+  oa.l_max = prm->l_max;
+  oa.l_occ = prm->l_occ;
+
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, SMPC_E_DEVICE, "hipSetDevice(%d) failed", ctx->device);
+  if (q) {
+    const smpc_status rs = ensure_device_robot(ctx);
+    if (rs != SMPC_OK) return rs;
+  }
+  if (launch_ogm(q ? ctx->dev_robot : nullptr, oa, depth, log_odds, occ_out,
+                 static_cast<float*>(work), (hipStream_t)stream) != 0)
+    return fail(ctx, SMPC_E_DEVICE, "occupancy kernel launch failed");
+  return SMPC_OK;
+}
+
 size_t smpc_edt_workspace_bytes(int32_t nx, int32_t ny, int32_t nz) {
   if (nx < 1 || ny < 1 || nz < 1 || nx > kEdtMaxSide || ny > kEdtMaxSide || nz > kEdtMaxSide)
     return 0;

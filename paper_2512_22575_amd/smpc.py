@@ -105,6 +105,20 @@ class smpc_request(ctypes.Structure):
     ]
 
 
+class smpc_camera(ctypes.Structure):
+    _fields_ = [
+        ("fx", c_float), ("fy", c_float), ("cx", c_float), ("cy", c_float),
+        ("width", c_int32), ("height", c_int32),
+        ("T_wc", c_float * 16),
+        ("min_depth", c_float), ("max_depth", c_float),
+    ]
+
+
+class smpc_ogm_params(ctypes.Structure):
+    _fields_ = [(name, c_float) for name in (
+        "tol", "l_hit", "l_miss", "l_min", "l_max", "l_occ", "robot_pad")]
+
+
 class smpc_completion(ctypes.Structure):
     _fields_ = [
         ("tag", ctypes.c_int64),
@@ -162,6 +176,13 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                              c_void_p, c_uint64, c_void_p]
     lib.smpc_edt.restype = c_int32
     lib.smpc_plan_workspace_bytes.restype = c_uint64
+    lib.smpc_ogm_workspace_bytes.argtypes = [c_int32, c_int32]
+    lib.smpc_ogm_workspace_bytes.restype = c_uint64
+    lib.smpc_ogm_update.argtypes = [c_void_p, POINTER(c_float), c_void_p, POINTER(smpc_camera),
+                                    c_void_p, c_void_p, c_int32, c_int32, c_int32,
+                                    POINTER(c_float), c_float, POINTER(smpc_ogm_params),
+                                    c_void_p, c_uint64, c_void_p]
+    lib.smpc_ogm_update.restype = c_int32
     lib.smpc_server_create.argtypes = [POINTER(c_void_p), c_void_p, c_uint64, c_int32]
     lib.smpc_server_create.restype = c_int32
     lib.smpc_server_destroy.argtypes = [c_void_p]
@@ -384,6 +405,20 @@ class Planner:
         if st != SMPC_OK:
             raise SMPCError(st, smpc_last_error(self._ctx))
 
+    def ogm_update(self, *, depth, cam: smpc_camera, log_odds, origin, voxel,
+                   prm: smpc_ogm_params, work, q=None, occ_out=None, stream=None) -> None:
+        """Enqueue one occupancy update (tensors on the device; log_odds (nz, ny, nx)
+        float32 updated in place); q given: this planner's robot masks the update."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+        nz, ny, nx = (int(s) for s in log_odds.shape)
+        st = smpc_ogm_update(self._ctx, q, _ptr(depth), cam, _ptr(log_odds), _ptr(occ_out),
+                             nx, ny, nz, origin, voxel, prm, _ptr(work),
+                             work.numel() * work.element_size(), stream)
+        if st != SMPC_OK:
+            raise SMPCError(st, smpc_last_error(self._ctx))
+
 
 def is_finite_float(x) -> bool:
     return math.isfinite(float(x))
@@ -405,6 +440,38 @@ def smpc_edt(occ: int, nx: int, ny: int, nz: int, voxel: float, phi_out: int | N
     return load_library().smpc_edt(c_void_p(occ or 0), int(nx), int(ny), int(nz), float(voxel),
                                    c_void_p(phi_out or 0), c_void_p(d2_out or 0),
                                    c_void_p(work or 0), int(work_bytes), c_void_p(stream or 0))
+
+
+def make_camera(fx, fy, cx, cy, width, height, T_wc, min_depth, max_depth) -> smpc_camera:
+    c = smpc_camera()
+    c.fx, c.fy, c.cx, c.cy = float(fx), float(fy), float(cx), float(cy)
+    c.width, c.height = int(width), int(height)
+    c.T_wc[:] = [float(x) for x in np.asarray(T_wc, np.float32).reshape(16)]
+    c.min_depth, c.max_depth = float(min_depth), float(max_depth)
+    return c
+
+
+def make_ogm_params(tol, l_hit, l_miss, l_min, l_max, l_occ, robot_pad=0.0) -> smpc_ogm_params:
+    return smpc_ogm_params(float(tol), float(l_hit), float(l_miss), float(l_min), float(l_max),
+                           float(l_occ), float(robot_pad))
+
+
+def smpc_ogm_workspace_bytes(width: int, height: int) -> int:
+    return int(load_library().smpc_ogm_workspace_bytes(int(width), int(height)))
+
+
+def smpc_ogm_update(ctx, q, depth: int, cam: smpc_camera, log_odds: int, occ_out: int | None,
+                    nx: int, ny: int, nz: int, origin, voxel: float, prm: smpc_ogm_params,
+                    work: int, work_bytes: int, stream: int | None) -> int:
+    """One occupancy update (device pointers as integers; q: 7 joint positions or None)."""
+    qa = None
+    if q is not None:
+        qa = (c_float * NDOF)(*[float(x) for x in np.asarray(q, np.float32).reshape(NDOF)])
+    oa = (c_float * 3)(*[float(x) for x in np.asarray(origin, np.float32).reshape(3)])
+    return load_library().smpc_ogm_update(
+        ctx, qa, c_void_p(depth or 0), ctypes.byref(cam), c_void_p(log_odds or 0),
+        c_void_p(occ_out or 0), int(nx), int(ny), int(nz), oa, float(voxel), ctypes.byref(prm),
+        c_void_p(work or 0), int(work_bytes), c_void_p(stream or 0))
 
 
 def smpc_server_create(ctx: c_void_p, hbm_budget_bytes: int, max_batch: int):

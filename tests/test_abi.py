@@ -60,6 +60,10 @@ int main(void) {
   F(smpc_controller_desc, K) F(smpc_controller_desc, weights) F(smpc_controller_desc, sigma)
   F(smpc_request, controller) F(smpc_request, q0) F(smpc_request, T_goal) F(smpc_request, seed)
   F(smpc_completion, status) F(smpc_completion, u0) F(smpc_completion, ess)
+  printf("smpc_camera sizeof %zu\n", sizeof(smpc_camera));
+  printf("smpc_ogm_params sizeof %zu\n", sizeof(smpc_ogm_params));
+  F(smpc_camera, width) F(smpc_camera, T_wc) F(smpc_camera, max_depth)
+  F(smpc_ogm_params, l_occ) F(smpc_ogm_params, robot_pad)
   return 0;
 }
 """
@@ -302,6 +306,62 @@ def test_coarse_bounds_validate_on_host():
         setattr(bad, field, value)
         assert lib.smpc_grid_coarse_min(ctypes.byref(bad), ctypes.c_void_p(0x2000), None) == \
             S.SMPC_E_INVALID_ARG, field
+
+
+def _ogm_call(ctx, **over):
+    cam = S.make_camera(288.0, 288.0, 160.0, 120.0, 320, 240, np.eye(4), 0.1, 4.0)
+    prm = S.make_ogm_params(0.025, 0.85, -0.4, -2.0, 3.5, 0.0, 0.01)
+    kw = dict(ctx=ctx, q=None, depth=0x10000000, cam=cam, log_odds=0x20000000,
+              occ_out=0x30000000, nx=10, ny=20, nz=30, origin=(0.0, 0.0, 0.0), voxel=0.05,
+              prm=prm, work=0x40000000, work_bytes=S.smpc_ogm_workspace_bytes(320, 240),
+              stream=None)
+    for k, v in over.items():
+        if k.startswith("cam."):
+            setattr(cam, k[4:], v)
+        elif k.startswith("prm."):
+            setattr(prm, k[4:], v)
+        else:
+            kw[k] = v
+    return S.smpc_ogm_update(**kw)
+
+
+def test_ogm_validates_on_host(ctx):
+    assert S.smpc_ogm_workspace_bytes(320, 240) == (320 * 240 + 128) * 4
+    assert S.smpc_ogm_workspace_bytes(0, 240) == 0
+    assert S.smpc_ogm_workspace_bytes(16385, 1) == 0
+    assert S.smpc_ogm_update(None, None, 0x1000, S.make_camera(1, 1, 0, 0, 1, 1, np.eye(4),
+                             0.1, 1.0), 0x2000, None, 1, 1, 1, (0, 0, 0), 1.0,
+                             S.make_ogm_params(0, 1, -1, -2, 2, 0), 0x3000, 1 << 20,
+                             None) == S.SMPC_E_INVALID_ARG
+    rot = np.eye(4)
+    rot[0, 0] = 1.1
+    shear = np.eye(4)
+    shear[3, 0] = 0.5
+    bad = [dict(depth=0), dict(log_odds=0), dict(work=0), dict(q=np.zeros(7)),  # no robot set
+           {"cam.fx": 0.0}, {"cam.cy": float("inf")}, {"cam.width": 0},
+           {"cam.height": 16385}, {"cam.min_depth": 0.0}, {"cam.max_depth": 0.05},
+           {"cam.T_wc": (ctypes.c_float * 16)(*rot.reshape(-1))},
+           {"cam.T_wc": (ctypes.c_float * 16)(*shear.reshape(-1))},
+           dict(nx=0), dict(nx=2048, ny=1024, nz=1024), dict(voxel=0.0),
+           dict(origin=(0.0, float("nan"), 0.0)), {"prm.tol": -0.1}, {"prm.robot_pad": -1e-3},
+           {"prm.l_min": 4.0}, {"prm.l_hit": float("nan")},
+           dict(work_bytes=S.smpc_ogm_workspace_bytes(320, 240) - 4), dict(work=0x40000002),
+           dict(occ_out=0x20000000 + 100),           # overlaps the log-odds grid
+           dict(work=0x10000000 + 8),                # overlaps the depth image
+           ]
+    for over in bad:
+        assert _ogm_call(ctx, **over) == S.SMPC_E_INVALID_ARG, over
+        assert S.smpc_last_error(ctx)
+    assert S.smpc_set_robot(ctx, S.robot_desc(R.make_robot(0))) == S.SMPC_OK
+    assert _ogm_call(ctx, q=np.full(7, np.nan)) == S.SMPC_E_INVALID_ARG
+    assert "q" in S.smpc_last_error(ctx)
+
+
+def test_ogm_without_gpu_fails_loudly(ctx):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present; this checks the GPU-less failure path")
+    assert _ogm_call(ctx) == S.SMPC_E_DEVICE
 
 
 def test_plan_workspace_bytes():

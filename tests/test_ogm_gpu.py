@@ -1,0 +1,259 @@
+"""Occupancy update (Sec. III-A) with the robot mask (Remark 2) on the GPU, through the
+C ABI, against the float64 oracle on the same seeded depth images.
+
+The log-odds layer is float32 on both sides, so every voxel whose decisions (pixel
+index, depth band, sphere membership) are farther than AMBIG from their thresholds
+must match bit for bit; the few within AMBIG may fall either way and are checked to
+hold one of the values a valid decision gives.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import ogm as G
+from oracle import smpc_oracle as O
+from synth import camera as C
+from synth import robot as RB
+from synth import workload as W
+
+pytestmark = pytest.mark.gpu
+
+PRM = dict(tol=0.025, l_hit=0.85, l_miss=-0.4, l_min=-2.0, l_max=3.5, l_occ=0.0,
+           robot_pad=0.01)
+# Decision margin (metres for depth and spheres, pixels for pixel borders) beyond which
+# float32 rounding of the projection (~1e-6 m, ~1e-4 px at these sizes) cannot flip it.
+AMBIG = 1e-3
+
+
+def f32(x):
+    return np.asarray(x, np.float32)
+
+
+def robot_spheres(robot, q):
+    q64 = f32(q).astype(np.float64)
+    frames = O.forward_kinematics(robot, q64[None])
+    return O.sphere_centres(robot, frames)[0], np.asarray(robot.sphere_radius, np.float64)
+
+
+def run_gpu(planner, L0, depth, cam, origin, voxel, prm, q=None, want_occ=True):
+    import torch
+
+    from paper_2512_22575_amd import smpc as S
+    dev = torch.device("cuda:0")
+    L = torch.from_numpy(np.ascontiguousarray(L0, np.float32).copy()).to(dev)
+    d = torch.from_numpy(np.ascontiguousarray(depth, np.float32)).to(dev)
+    occ = torch.full(L0.shape, 7, dtype=torch.uint8, device=dev) if want_occ else None
+    nwork = S.smpc_ogm_workspace_bytes(cam.width, cam.height) // 4
+    work = torch.full((nwork,), float("nan"), dtype=torch.float32, device=dev)
+    scam = S.make_camera(cam.fx, cam.fy, cam.cx, cam.cy, cam.width, cam.height, cam.T_wc,
+                         cam.min_depth, cam.max_depth)
+    planner.ogm_update(depth=d, cam=scam, log_odds=L, origin=f32(origin), voxel=float(voxel),
+                       prm=S.make_ogm_params(**prm), work=work, q=q, occ_out=occ)
+    torch.cuda.synchronize()
+    cleaned = work[:cam.width * cam.height].cpu().numpy().reshape(cam.height, cam.width)
+    return L.cpu().numpy(), (occ.cpu().numpy() if occ is not None else None), cleaned
+
+
+def run_oracle(L0, depth, cam, origin, voxel, prm, robot=None, q=None):
+    centres = radii = None
+    if q is not None:
+        centres, radii = robot_spheres(robot, q)
+    return G.ogm_update(L0, depth, cam, f32(origin).astype(np.float64),
+                        float(np.float32(voxel)), prm, centres, radii)
+
+
+def check(L0, L_gpu, occ_gpu, L_ref, margin, prm, max_ambiguous=0.01):
+    sure = margin > AMBIG
+    assert (~sure).mean() <= max_ambiguous, f"{(~sure).mean():.3%} voxels ambiguous"
+    bad = sure & (L_gpu.view(np.uint32) != L_ref.view(np.uint32))
+    if bad.any():
+        idx = tuple(int(i[0]) for i in np.nonzero(bad))
+        raise AssertionError(f"{int(bad.sum())} voxels differ, first at (z, y, x) = {idx}: "
+                             f"gpu {L_gpu[idx]!r} oracle {L_ref[idx]!r} from {L0[idx]!r}")
+    lo, hi = np.float32(prm["l_min"]), np.float32(prm["l_max"])
+    L0 = f32(L0)
+    options = np.stack([L0, np.clip(L0 + np.float32(prm["l_hit"]), lo, hi),
+                        np.clip(L0 + np.float32(prm["l_miss"]), lo, hi), np.full_like(L0, lo)])
+    amb = ~sure
+    assert np.all((L_gpu[amb][None] == options[:, amb]).any(axis=0)), "invalid ambiguous value"
+    if occ_gpu is not None:
+        np.testing.assert_array_equal(occ_gpu, (L_gpu > np.float32(prm["l_occ"])).astype(np.uint8))
+
+
+@pytest.fixture(scope="module")
+def scene():
+    return W.ReactiveScenario(seed=3)
+
+
+@pytest.fixture(scope="module")
+def planner(scene):
+    from paper_2512_22575_amd import smpc as S
+    p = S.Planner(scene.robot, device=0)
+    yield p
+    p.close()
+
+
+def random_log_odds(rng, shape):
+    """Prior map with values across the clamp range, some already saturated."""
+    L = rng.uniform(-2.6, 4.0, size=shape).astype(np.float32)
+    return np.clip(L, np.float32(PRM["l_min"]), np.float32(PRM["l_max"]))
+
+
+def test_update_without_mask_matches_oracle(scene, planner):
+    """160x120 image of the primitives, 61x53x47 grid at 0.04 m (several blocks and a
+    ragged tail), prior log-odds across the clamp range."""
+    rng = np.random.default_rng(11)
+    cam = C.default_camera(160, 120)
+    depth = C.render_depth(cam, scene.prims)
+    origin = np.array([-1.0, -1.0, 0.0])
+    L0 = random_log_odds(rng, (47, 53, 61))
+    L_gpu, occ_gpu, cleaned = run_gpu(planner, L0, depth, cam, origin, 0.04, PRM)
+    L_ref, _, margin = run_oracle(L0, depth, cam, origin, 0.04, PRM)
+    check(L0, L_gpu, occ_gpu, L_ref, margin, PRM)
+    assert (L_gpu != L0).sum() > 3000            # the update reached a good part of the grid
+    np.testing.assert_array_equal(cleaned, G.clean_depth(depth, cam)[0])
+
+
+def test_robot_mask_matches_oracle(scene, planner):
+    """The arm in view of the camera: its returns are discarded and the voxels inside its
+    padded spheres set to l_min, as in the oracle; the cleaned image agrees too."""
+    rng = np.random.default_rng(12)
+    cam = C.default_camera(200, 150)
+    q = scene.q0
+    centres, radii = robot_spheres(scene.robot, q)
+    depth = C.render_depth(cam, scene.prims, spheres=centres, radii=radii)
+    origin = np.array([-0.9, -0.9, 0.0])
+    voxel = 0.03
+    L0 = random_log_odds(rng, (40, 60, 60))
+    L_gpu, occ_gpu, cleaned = run_gpu(planner, L0, depth, cam, origin, voxel, PRM, q=q)
+    L_ref, _, margin = run_oracle(L0, depth, cam, origin, voxel, PRM, scene.robot, q)
+    check(L0, L_gpu, occ_gpu, L_ref, margin, PRM)
+    # the mask did something: voxels reset to l_min and returns discarded
+    clean_ref, pix_margin = G.clean_depth(depth, cam, centres, radii + PRM["robot_pad"])
+    assert (L_gpu == np.float32(PRM["l_min"])).sum() > 100
+    assert ((depth > 0) & (clean_ref == 0)).sum() > 100
+    sure = np.abs(pix_margin) > AMBIG
+    np.testing.assert_array_equal(cleaned[sure], clean_ref[sure])
+    assert np.all((cleaned[~sure] == 0) | (cleaned[~sure] == depth[~sure]))
+
+
+def test_sequence_of_views_accumulates_like_the_oracle(scene, planner):
+    """Three views in a row update one map in place; each step is checked against the
+    oracle applied to the previous GPU map (its input)."""
+    rng = np.random.default_rng(13)
+    origin = np.array([-1.0, -1.0, 0.0])
+    voxel = 0.05
+    L = np.zeros((30, 40, 40), np.float32)
+    q = scene.q0
+    centres, radii = robot_spheres(scene.robot, q)
+    for eye in [(1.2, -0.9, 0.9), (-1.1, -0.8, 1.0), (0.2, 1.3, 1.1)]:
+        cam = C.default_camera(96, 72, eye=eye)
+        depth = C.render_depth(cam, scene.prims, spheres=centres, radii=radii)
+        depth[rng.random(depth.shape) < 0.02] = 0.0          # dropouts
+        L_gpu, occ_gpu, _ = run_gpu(planner, L, depth, cam, origin, voxel, PRM, q=q)
+        L_ref, _, margin = run_oracle(L, depth, cam, origin, voxel, PRM, scene.robot, q)
+        check(L, L_gpu, occ_gpu, L_ref, margin, PRM)
+        L = L_gpu
+
+
+def test_invalid_depth_values_are_no_return(scene, planner):
+    """NaN, +-inf, negative, zero and out-of-range depths leave their voxels unknown."""
+    cam = C.default_camera(64, 48)
+    depth = C.render_depth(cam, scene.prims)
+    rng = np.random.default_rng(14)
+    bad = rng.random(depth.shape) < 0.3
+    junk = rng.choice(np.array([np.nan, np.inf, -np.inf, -1.0, 0.0, 0.05, 7.5], np.float32),
+                      size=depth.shape)
+    depth = np.where(bad, junk, depth).astype(np.float32)
+    # off the grid lines through the target: a column of voxel centres in the camera's
+    # x = 0 plane would project onto the border u = cx of two pixels
+    origin = np.array([-1.013, -0.987, 0.0])
+    L0 = random_log_odds(rng, (20, 25, 27))
+    L_gpu, occ_gpu, cleaned = run_gpu(planner, L0, depth, cam, origin, 0.08, PRM)
+    L_ref, _, margin = run_oracle(L0, depth, cam, origin, 0.08, PRM)
+    check(L0, L_gpu, occ_gpu, L_ref, margin, PRM)
+    np.testing.assert_array_equal(cleaned, G.clean_depth(depth, cam)[0])
+
+
+def test_degenerate_sizes(scene, planner):
+    """One voxel, a one-pixel image, and a camera looking away from the grid."""
+    cam = C.Camera(fx=50.0, fy=50.0, cx=0.5, cy=0.5, width=1, height=1,
+                   T_wc=C.look_at((0.0, 0.0, 2.0), (0.0, 0.0, 0.0), up=(1.0, 0.0, 0.0))
+                   .astype(np.float32))
+    depth = np.array([[1.8]], np.float32)
+    # the return lies at world z = 0.2; voxel centres at z = 0.5, 0.2, 0.0 and 2.5
+    for origin, want in (((-0.05, -0.05, 0.45), "free"), ((-0.05, -0.05, 0.15), "hit"),
+                         ((-0.05, -0.05, -0.05), "unknown"), ((-0.05, -0.05, 2.45), "unknown")):
+        L0 = np.zeros((1, 1, 1), np.float32)
+        L_gpu, occ_gpu, _ = run_gpu(planner, L0, depth, cam, origin, 0.1, PRM)
+        L_ref, _, margin = run_oracle(L0, depth, cam, origin, 0.1, PRM)
+        check(L0, L_gpu, occ_gpu, L_ref, margin, PRM)
+        expect = {"free": PRM["l_miss"], "hit": PRM["l_hit"], "unknown": 0.0}[want]
+        assert L_gpu[0, 0, 0] == np.float32(expect), (origin, L_gpu)
+    away = C.default_camera(32, 24, eye=(3.0, 3.0, 1.0), target=(6.0, 6.0, 1.0))
+    depth = np.full((24, 32), 1.0, np.float32)
+    L0 = random_log_odds(np.random.default_rng(15), (9, 10, 11))
+    L_gpu, _, _ = run_gpu(planner, L0, depth, away, (-1.0, -1.0, 0.0), 0.2, PRM)
+    np.testing.assert_array_equal(L_gpu, L0)
+
+
+def test_occupancy_output_is_optional(scene, planner):
+    cam = C.default_camera(80, 60)
+    depth = C.render_depth(cam, scene.prims)
+    L0 = random_log_odds(np.random.default_rng(16), (16, 20, 20))
+    a, occ, _ = run_gpu(planner, L0, depth, cam, (-1.0, -1.0, 0.0), 0.1, PRM, q=scene.q0)
+    b, none, _ = run_gpu(planner, L0, depth, cam, (-1.0, -1.0, 0.0), 0.1, PRM, q=scene.q0,
+                         want_occ=False)
+    assert none is None and occ is not None
+    np.testing.assert_array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_mask_outside_the_view_changes_only_robot_voxels(scene, planner):
+    """With the arm behind the camera, the mask discards no return: the update equals the
+    unmasked one except on voxels inside the padded spheres, which hold l_min."""
+    # eye off the voxel lattice: an axis-aligned view from a lattice point projects
+    # whole families of voxel centres onto pixel borders
+    cam = C.default_camera(80, 60, eye=(0.7, 0.013, 0.493), target=(2.7, 0.1, 0.55))
+    depth = C.render_depth(cam, scene.prims)
+    origin = np.array([-1.0, -1.0, 0.0])
+    L0 = random_log_odds(np.random.default_rng(17), (20, 40, 40))
+    q = np.array([0.0, -0.5, 0.0, -2.0, 0.0, 1.6, 0.0], np.float32)   # arm towards -x
+    a, _, cleaned = run_gpu(planner, L0, depth, cam, origin, 0.05, PRM, q=q)
+    b, _, _ = run_gpu(planner, L0, depth, cam, origin, 0.05, PRM)
+    centres, radii = robot_spheres(scene.robot, q)
+    L_ref, _, margin = run_oracle(L0, depth, cam, origin, 0.05, PRM, scene.robot, q)
+    check(L0, a, None, L_ref, margin, PRM)
+    np.testing.assert_array_equal(cleaned, G.clean_depth(depth, cam)[0])
+    zi, yi, xi = np.meshgrid(*[np.arange(n) for n in L0.shape], indexing="ij")
+    pw = np.stack([origin[0] + (xi + 0.5) * 0.05, origin[1] + (yi + 0.5) * 0.05,
+                   (zi + 0.5) * 0.05], -1)
+    inside = G.sphere_margin(pw, centres, radii + PRM["robot_pad"]) <= 0.0
+    assert inside.sum() > 10
+    assert np.array_equal(a[~inside], b[~inside])
+
+
+def test_full_size_grid_on_sampled_slabs(scene, planner):
+    """200^3 grid at 0.01 m and a 640x480 image with the arm in view (the mapping
+    workload): slabs of the GPU map against the oracle run on the same sub-boxes (each
+    voxel's update depends only on its own centre)."""
+    rng = np.random.default_rng(18)
+    cam = C.default_camera(640, 480)
+    q = scene.q0
+    centres, radii = robot_spheres(scene.robot, q)
+    depth = C.render_depth(cam, scene.prims, spheres=centres, radii=radii)
+    n, voxel = 200, 0.01
+    origin = f32(scene.origin).astype(np.float64)
+    L0 = random_log_odds(rng, (n, n, n))
+    L_gpu, occ_gpu, _ = run_gpu(planner, L0, depth, cam, origin, voxel, PRM, q=q)
+    np.testing.assert_array_equal(occ_gpu, (L_gpu > np.float32(PRM["l_occ"])).astype(np.uint8))
+    v32 = float(np.float32(voxel))
+    for z0, y0, x0, shape in ((0, 0, 0, (4, n, n)), (60, 0, 0, (3, n, n)),
+                              (197, 0, 0, (3, n, n)), (0, 120, 0, (n, 2, n)),
+                              (0, 0, 95, (n, n, 2))):
+        # sub-box origin: the float32 origin plus whole voxels, as the kernel's centres
+        # origin + (i + 1/2) voxel are for i = offset + local index
+        sub = tuple(slice(a, a + s) for a, s in zip((z0, y0, x0), shape))
+        sub_origin = origin + np.array([x0, y0, z0], np.float64) * v32
+        L_ref, _, margin = G.ogm_update(L0[sub], depth, cam, sub_origin, v32, PRM, centres, radii)
+        check(L0[sub], L_gpu[sub], None, L_ref, margin, PRM, max_ambiguous=0.02)
