@@ -86,6 +86,9 @@ def parse_args():
     ap.add_argument("--rate", type=float, default=2000.0, help="mean arrivals per second")
     ap.add_argument("--budget-mib", type=int, default=512, help="server HBM budget")
     ap.add_argument("--max-batch", type=int, default=64)
+    ap.add_argument("--ogm", action="store_true",
+                    help="time the occupancy update (640x480 depth image into the 200^3 map, "
+                         "robot mask on) and the mapping-to-plan pipeline instead")
     ap.add_argument("--edt", action="store_true",
                     help="time the distance-field construction (200^3 occupancy -> signed "
                          "field) and the construction + plan step pipeline instead")
@@ -318,6 +321,129 @@ def edt_bench(args) -> None:
     }), flush=True)
 
 
+# Compulsory traffic of one occupancy update: per voxel the float32 log-odds read and
+# written and the occupancy byte written; per pixel the depth read and the cleaned
+# depth written.
+OGM_BYTES_PER_VOXEL = 9.0
+OGM_BYTES_PER_PIXEL = 8.0
+
+
+def ogm_bench(args) -> None:
+    """Occupancy update of the 200^3 map from one depth image, alone and as the first
+    stage of the mapping-to-plan pipeline (map update, field, bounds, plan step).
+
+    The reactive scene is advanced by one control period per pool entry and rendered
+    from a fixed camera; images are resident in device memory.  The images hold the
+    primitives only (the input generator does no kinematics); the robot mask is on,
+    so every valid return still takes the sphere test and the voxels inside the arm
+    at q0 are reset.
+    """
+    import torch
+
+    from paper_2512_22575_amd import smpc as S
+    from synth import camera as C
+    from synth import workload as W
+
+    K, H, n = args.K, args.H, args.n
+    sc = W.ReactiveScenario(seed=3, K=K, H=H, n=n)
+    dev = torch.device("cuda:0")
+    cam = C.default_camera(640, 480)
+    pool = max(1, min(args.pool, 8))
+    planner = S.Planner(sc.robot, device=0)
+    depths = []
+    for _ in range(pool):
+        depths.append(torch.from_numpy(C.render_depth(cam, sc.prims)).to(dev))
+        sc.advance()
+    scam = S.make_camera(cam.fx, cam.fy, cam.cx, cam.cy, cam.width, cam.height, cam.T_wc,
+                         cam.min_depth, cam.max_depth)
+    prm = S.make_ogm_params(tol=0.025, l_hit=0.85, l_miss=-0.4, l_min=-2.0, l_max=3.5,
+                            l_occ=0.0, robot_pad=0.01)
+    L = torch.zeros((n, n, n), device=dev)
+    occ = torch.zeros((n, n, n), dtype=torch.uint8, device=dev)
+    work = torch.empty(S.smpc_ogm_workspace_bytes(cam.width, cam.height) // 4, device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+
+    def ogm(i):
+        planner.ogm_update(depth=depths[i % pool], cam=scam, log_odds=L, origin=sc.origin,
+                           voxel=sc.VOXEL, prm=prm, work=work, q=sc.q0, occ_out=occ,
+                           stream=stream)
+
+    for i in range(args.warmup):
+        ogm(i)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for i in range(args.steps):
+        ogm(i)
+    ev1.record()
+    torch.cuda.synchronize()
+    ogm_ms = ev0.elapsed_time(ev1) / args.steps
+
+    # Map update, distance field of the new occupancy, bounds, warm-started plan step.
+    nvox = n ** 3
+    need = S.smpc_edt_workspace_bytes(n, n, n)
+    ework = torch.empty((need + 3) // 4, dtype=torch.int32, device=dev)
+    phi = torch.empty((n, n, n), device=dev)
+    coarse = torch.empty(S.smpc_grid_coarse_cells(n, n, n), device=dev)
+    noise = [torch.from_numpy(sc.noise()).to(dev) for _ in range(4)]
+    U = [torch.zeros((H, 7), device=dev), torch.zeros((H, 7), device=dev)]
+    plans = [S.plan_args(sc.q0, sc.qd0, sc.target(), phi, sc.origin, sc.VOXEL, noise[i % 4],
+                         U[i % 2], U[(i + 1) % 2], K, H, sc.DT, 1.0, sc.weights, coarse=coarse)
+             for i in range(args.steps)]
+
+    def pipeline(i):
+        ogm(i)
+        st = S.smpc_edt(occ.data_ptr(), n, n, n, sc.VOXEL, phi.data_ptr(), None,
+                        ework.data_ptr(), need, stream)
+        if st != S.SMPC_OK:
+            raise S.SMPCError(st, "smpc_edt")
+        st = S.smpc_grid_coarse_min(phi, S.GRID_F32, coarse.data_ptr(), stream)
+        if st != S.SMPC_OK:
+            raise S.SMPCError(st, "smpc_grid_coarse_min")
+        st = S.smpc_plan_step(planner._ctx, plans[i], stream)
+        if st != S.SMPC_OK:
+            raise S.SMPCError(st, S.smpc_last_error(planner._ctx))
+
+    for i in range(min(args.warmup, args.steps)):
+        pipeline(i)
+    torch.cuda.synchronize()
+    ev0.record()
+    for i in range(args.steps):
+        pipeline(i)
+    ev1.record()
+    torch.cuda.synchronize()
+    pipe_ms = ev0.elapsed_time(ev1) / args.steps
+    planner.close()
+
+    npix = cam.width * cam.height
+    bytes_ = OGM_BYTES_PER_VOXEL * nvox + OGM_BYTES_PER_PIXEL * npix
+    achieved = bytes_ / (ogm_ms * 1e-3) / 1e9
+    print(json.dumps({
+        "metric": "voxels/s of occupancy update (one depth image into the log-odds map)",
+        "value": round(nvox / (ogm_ms * 1e-3), 1),
+        "unit": "voxels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ogm_ms, 6),
+        "higher_is_better": True,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"reactive scene {n}^3 log-odds map at 0.01 m, 640x480 depth "
+                               f"images of 20 boxes and 20 spheres, robot mask on at q0, "
+                               f"{pool} consecutive periods",
+                   "grid": [n] * 3, "image": [cam.width, cam.height]},
+        "roofline": {"bound": "hbm", "kernel": "smpc_ogm_update (2 kernels)",
+                     "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None,
+                     "bytes_per_voxel": OGM_BYTES_PER_VOXEL,
+                     "bytes_per_pixel": OGM_BYTES_PER_PIXEL},
+        "pipeline_ms_per_step": round(pipe_ms, 5),
+        "pipeline": f"smpc_ogm_update, smpc_edt on its occupancy, smpc_grid_coarse_min, then "
+                    f"smpc_plan_step (K={K}, H={H}) on the new field",
+    }), flush=True)
+
+
 def cpu_baseline(sc, grid, noise, K, H):
     """Time the FP64 oracle on one full plan step of the same workload, one thread."""
     from threadpoolctl import threadpool_limits
@@ -339,16 +465,19 @@ def main():
     if args.calibrate_copy_mib:
         calibrate_copy(args.calibrate_copy_mib)
         return
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the plan step is not sharded "
+              "across GPUs); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
     if args.serving:
         serving_bench(args)
         return
     if args.edt:
         edt_bench(args)
         return
-    if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the plan step is not sharded "
-              "across GPUs); run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
+    if args.ogm:
+        ogm_bench(args)
+        return
     import torch
 
     from paper_2512_22575_amd import smpc as S

@@ -254,7 +254,8 @@ typedef struct {
   float robot_pad;              /* padding of the robot sphere model (m), >= 0 */
 } smpc_ogm_params;
 
-/* Device workspace smpc_ogm_update needs for a width x height image (bytes). */
+/* Device workspace smpc_ogm_update needs for a width x height image (bytes); 0 when
+ * a size is out of range. */
 size_t smpc_ogm_workspace_bytes(int32_t width, int32_t height);
 
 /*

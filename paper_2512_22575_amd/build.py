@@ -33,7 +33,7 @@ def hipcc() -> str:
 
 def compile_command(out_path: str = LIB_PATH, extra: list[str] | None = None) -> list[str]:
     return ([hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-             "-Wall", "-Wno-unused-function", f"-I{INCLUDE}", f"-I{CSRC}"] + DEVICE_FLAGS
+             "-Wall", "-Wshadow", "-Wno-unused-function", f"-I{INCLUDE}", f"-I{CSRC}"] + DEVICE_FLAGS
             + (extra or []) + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", out_path])
 
 

@@ -156,8 +156,22 @@ struct OgmArgs {
   float voxel;
   int32_t nx, ny, nz;
   float tol, l_hit, l_miss, l_min, l_max, l_occ;
+  // Voxel (ix, iy, iz) -> (X, Y, Z) = M (ix, iy, iz) + m: Z is the camera-frame depth
+  // of the voxel centre and (X / Z, Y / Z) its image coordinates (u, v).
+  float M[9], m[3];
+  double inv_nx, inv_plane;    // 1 / nx and 1 / (nx ny) for the voxel index split
+  // n / d = umulhi(n, mul) >> shift for n < 2^31 (d = nx and nx ny; set when nx >= 2)
+  uint32_t nx_mul, nx_shift, plane_mul, plane_shift;
 };
-constexpr int kOgmSphereFloats = kSlots * 4 + 8;  // centres, padded radius^2, bounding box
+// Sphere table after the cleaned image: per slot centre and padded radius^2, the
+// bounding box of the padded spheres in metres (6 floats) and in voxel indices
+// widened by one voxel (6 int32: x, y, z lower bounds, then upper bounds).
+// Workspace: cleaned image (npix floats), then the sphere table (kOgmTableFloats).
+constexpr int kOgmTableFloats = 128;
+constexpr int kOgmBox = kSlots * 4;
+constexpr int kOgmIndexBox = kOgmBox + 6;
+constexpr int kOgmSphereFloats = kOgmIndexBox + 6;
+static_assert(kOgmSphereFloats <= kOgmTableFloats, "sphere table fits its slot");
 int launch_ogm(const DevRobot* robot, const OgmArgs& a, const float* depth, float* log_odds,
                uint8_t* occ, float* work, hipStream_t stream);
 

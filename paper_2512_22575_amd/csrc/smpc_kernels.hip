@@ -1154,62 +1154,78 @@ __global__ __launch_bounds__(kCoarseThreads) void grid_coarse_min_kernel(
 // ---------------------------------------------------------------------------
 // Occupancy update by voxel projection (Sec. III-A) with the robot mask (Remark 2)
 // ---------------------------------------------------------------------------
-// The robot's collision spheres at joint positions q (padded): centres and squared
-// padded radii in sph[4 s .. 4 s + 3], bounding box of the padded spheres in
-// sph[4 kSlots .. 4 kSlots + 5].  Computed by a whole block (the chain by thread 0).
+constexpr int kOgmThreads = 256;
+constexpr int kOgmPerThread = 4;  // pixels or voxels per thread, kOgmThreads apart
+constexpr int kOgmTile = kOgmThreads * kOgmPerThread;
+
+// The robot's collision spheres at joint positions q, padded: centres and squared
+// padded radii in sph[4 s .. 4 s + 3] (inactive slots get radius^2 = -1, which no
+// point is within), bounding box of the padded spheres in sph[4 kSlots .. + 5]
+// (min x, y, z, then max x, y, z).  Called by every thread of the block.
 __device__ __forceinline__ void ogm_robot_spheres(const DevRobot* __restrict__ rob,
                                                   const OgmArgs& a, float* sph) {
+  __shared__ float sincos_q[2 * kNdof];
   __shared__ Frame frames[kNdof];
   const int tid = threadIdx.x;
+  if (tid < kNdof) sincosf(a.q[tid], &sincos_q[tid], &sincos_q[kNdof + tid]);
+  __syncthreads();
   if (tid == 0) {
     Frame T = identity_frame();
 #pragma unroll
     for (int i = 0; i < kNdof; ++i) {
-      float s_, c_;
-      sincosf(a.q[i], &s_, &c_);
-      mdh_step(T, rob->ca[i], rob->sa[i], rob->a[i], rob->d[i], c_, s_);
+      mdh_step(T, rob->ca[i], rob->sa[i], rob->a[i], rob->d[i], sincos_q[kNdof + i],
+               sincos_q[i]);
       frames[i] = T;
     }
   }
   __syncthreads();
-  if (tid < kSlots) {
-    float px = 0.f, py = 0.f, pz = 0.f, r2 = -1.f;  // inactive slot: never contains a point
-    if (rob->slot_active & (1u << tid)) {
-      transform_point(frames[tid / kSpl], rob->sc[tid][0], rob->sc[tid][1], rob->sc[tid][2], px,
-                      py, pz);
-      const float r = rob->sc[tid][3] + a.robot_pad;
-      r2 = r * r;
-    }
-    sph[4 * tid + 0] = px;
-    sph[4 * tid + 1] = py;
-    sph[4 * tid + 2] = pz;
-    sph[4 * tid + 3] = r2;
-  }
-  __syncthreads();
-  if (tid == 0) {
+  if (tid < kWave) {
+    // lanes 0..kSlots-1 hold one slot each; the box is reduced over the first 32 lanes
     float lo[3] = {__builtin_inff(), __builtin_inff(), __builtin_inff()};
     float hi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
-    for (int s = 0; s < kSlots; ++s) {
-      if (sph[4 * s + 3] < 0.f) continue;
-      const float r = sqrtf(sph[4 * s + 3]) * 1.0001f + 1e-6f;  // rounding slack
-      for (int k = 0; k < 3; ++k) {
-        lo[k] = fminf(lo[k], sph[4 * s + k] - r);
-        hi[k] = fmaxf(hi[k], sph[4 * s + k] + r);
+    if (tid < kSlots) {
+      float p[3] = {0.f, 0.f, 0.f}, r2 = -1.f;
+      if (rob->slot_active & (1u << tid)) {
+        transform_point(frames[tid / kSpl], rob->sc[tid][0], rob->sc[tid][1], rob->sc[tid][2],
+                        p[0], p[1], p[2]);
+        const float r = rob->sc[tid][3] + a.robot_pad;
+        r2 = r * r;
+        const float rb = r * 1.0001f + 1e-6f;  // slack over the rounding of r^2 and |p - c|^2
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          lo[k] = p[k] - rb;
+          hi[k] = p[k] + rb;
+        }
       }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) sph[4 * tid + k] = p[k];
+      sph[4 * tid + 3] = r2;
     }
-    for (int k = 0; k < 3; ++k) {
-      sph[4 * kSlots + k] = lo[k];
-      sph[4 * kSlots + 3 + k] = hi[k];
-    }
+    static_assert(kSlots <= 32, "box reduction covers 32 lanes");
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        lo[k] = fminf(lo[k], __shfl_xor(lo[k], off, kWave));
+        hi[k] = fmaxf(hi[k], __shfl_xor(hi[k], off, kWave));
+      }
+    if (tid == 0)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        sph[kOgmBox + k] = lo[k];
+        sph[kOgmBox + 3 + k] = hi[k];
+        // voxel indices whose centre origin + (i + 1/2) voxel may lie in the box
+        const float il = floorf((lo[k] - a.origin[k]) / a.voxel - 0.5f) - 1.f;
+        const float ih = ceilf((hi[k] - a.origin[k]) / a.voxel - 0.5f) + 1.f;
+        sph[kOgmIndexBox + k] = __int_as_float((int32_t)fminf(fmaxf(il, -2.f), 2.0e9f));
+        sph[kOgmIndexBox + 3 + k] = __int_as_float((int32_t)fminf(fmaxf(ih, -2.f), 2.0e9f));
+      }
   }
   __syncthreads();
 }
 
-// Whether p lies in a padded robot sphere (reads the table at uniform addresses).
-__device__ __forceinline__ bool in_robot(const float* sph, float x, float y, float z) {
-  if (x < sph[4 * kSlots] || y < sph[4 * kSlots + 1] || z < sph[4 * kSlots + 2] ||
-      x > sph[4 * kSlots + 3] || y > sph[4 * kSlots + 4] || z > sph[4 * kSlots + 5])
-    return false;
+// Whether p lies in a padded robot sphere (entries read at uniform addresses).
+__device__ __forceinline__ bool in_robot_spheres(const float* sph, float x, float y, float z) {
   bool in = false;
 #pragma unroll 4
   for (int s = 0; s < kSlots; ++s) {
@@ -1219,71 +1235,177 @@ __device__ __forceinline__ bool in_robot(const float* sph, float x, float y, flo
   return in;
 }
 
-// Pass 1: valid returns not inside the robot, others 0; block 0 publishes the spheres.
-__global__ __launch_bounds__(256) void ogm_pixel_kernel(const DevRobot* __restrict__ rob,
-                                                        const OgmArgs a,
-                                                        const float* __restrict__ depth,
-                                                        float* __restrict__ work) {
-  __shared__ float sph[kOgmSphereFloats];
-  if (a.use_mask) ogm_robot_spheres(rob, a, sph);
-  const long long npix = (long long)a.width * a.height;
-  float* sph_out = work + npix;
-  if (a.use_mask && blockIdx.x == 0 && threadIdx.x < kOgmSphereFloats)
-    sph_out[threadIdx.x] = sph[threadIdx.x];
-  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (i >= npix) return;
-  const float d = depth[i];
-  bool keep = isfinite(d) && d >= a.min_depth && d <= a.max_depth;
-  if (keep && a.use_mask) {
-    const int v = (int)(i / a.width), u = (int)(i - (long long)v * a.width);
-    const float xc = ((float)u + 0.5f - a.cx) * d / a.fx;
-    const float yc = ((float)v + 0.5f - a.cy) * d / a.fy;
-    const float wx = fmaf(a.R[0], xc, fmaf(a.R[1], yc, fmaf(a.R[2], d, a.t[0])));
-    const float wy = fmaf(a.R[3], xc, fmaf(a.R[4], yc, fmaf(a.R[5], d, a.t[1])));
-    const float wz = fmaf(a.R[6], xc, fmaf(a.R[7], yc, fmaf(a.R[8], d, a.t[2])));
-    keep = !in_robot(sph, wx, wy, wz);
-  }
-  work[i] = keep ? d : 0.f;
+// The same, first tested against the table's bounding box: the sphere entries are
+// read only when some lane of the wave is inside the box.
+__device__ __forceinline__ bool in_robot(const float* sph, float x, float y, float z) {
+  const float* box = sph + kOgmBox;
+  const bool in_box = (x >= box[0]) & (y >= box[1]) & (z >= box[2]) & (x <= box[3]) &
+                      (y <= box[4]) & (z <= box[5]);
+  return in_box && in_robot_spheres(sph, x, y, z);
 }
 
-// Pass 2: one thread per voxel (x fastest): project, classify, update, robot reset.
-__global__ __launch_bounds__(256) void ogm_voxel_kernel(const OgmArgs a,
-                                                        const float* __restrict__ work,
-                                                        float* __restrict__ log_odds,
-                                                        uint8_t* __restrict__ occ) {
-  const long long nvox = (long long)a.nx * a.ny * a.nz;
-  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (i >= nvox) return;
-  const long long plane = (long long)a.nx * a.ny;
-  const int iz = (int)(i / plane);
-  const long long r = i - (long long)iz * plane;
-  const int iy = (int)(r / a.nx), ix = (int)(r - (long long)iy * a.nx);
-  const float wx = a.origin[0] + ((float)ix + 0.5f) * a.voxel;
-  const float wy = a.origin[1] + ((float)iy + 0.5f) * a.voxel;
-  const float wz = a.origin[2] + ((float)iz + 0.5f) * a.voxel;
-  const float dx = wx - a.t[0], dy = wy - a.t[1], dz = wz - a.t[2];
-  // camera frame: R^T (p - t)
-  const float x = fmaf(a.R[0], dx, fmaf(a.R[3], dy, a.R[6] * dz));
-  const float y = fmaf(a.R[1], dx, fmaf(a.R[4], dy, a.R[7] * dz));
-  const float z = fmaf(a.R[2], dx, fmaf(a.R[5], dy, a.R[8] * dz));
-  float L = log_odds[i];
-  if (z > 0.f) {
-    const float u = a.fx * x / z + a.cx, v = a.fy * y / z + a.cy;
-    const float fu = floorf(u), fv = floorf(v);
-    if (fu >= 0.f && fu < (float)a.width && fv >= 0.f && fv < (float)a.height) {
-      const float d = work[(long long)fv * a.width + (long long)fu];
-      if (d > 0.f) {
-        const float e = z - d;
-        if (fabsf(e) <= a.tol)
-          L = fminf(fmaxf(L + a.l_hit, a.l_min), a.l_max);
-        else if (e < -a.tol)
-          L = fminf(fmaxf(L + a.l_miss, a.l_min), a.l_max);
-      }
-    }
+// Pass 1: valid returns not inside the robot, others 0.  Each block takes a tile of
+// kOgmTile pixels; block 0 also publishes the sphere table after the image.
+__global__ __launch_bounds__(kOgmThreads) void ogm_pixel_kernel(
+    const DevRobot* __restrict__ rob, const OgmArgs a, const float* __restrict__ depth,
+    float* __restrict__ work) {
+  __shared__ float sph[kOgmSphereFloats];
+  const uint32_t npix = (uint32_t)a.width * (uint32_t)a.height;
+  const uint32_t base = blockIdx.x * (uint32_t)kOgmTile + threadIdx.x;
+  float d[kOgmPerThread];
+#pragma unroll
+  for (int k = 0; k < kOgmPerThread; ++k) {
+    const uint32_t i = base + k * kOgmThreads;
+    d[k] = i < npix ? depth[i] : 0.f;
   }
-  if (a.use_mask && in_robot(work + (long long)a.width * a.height, wx, wy, wz)) L = a.l_min;
-  log_odds[i] = L;
-  if (occ) occ[i] = L > a.l_occ ? 1 : 0;
+  if (a.use_mask) {
+    ogm_robot_spheres(rob, a, sph);
+    if (blockIdx.x == 0 && threadIdx.x < kOgmSphereFloats)
+      work[npix + threadIdx.x] = sph[threadIdx.x];
+  }
+#pragma unroll
+  for (int k = 0; k < kOgmPerThread; ++k) {
+    const uint32_t i = base + k * kOgmThreads;
+    if (i >= npix) break;
+    bool keep = isfinite(d[k]) && d[k] >= a.min_depth && d[k] <= a.max_depth;
+    if (keep && a.use_mask) {
+      const uint32_t v = i / (uint32_t)a.width, u = i - v * (uint32_t)a.width;
+      const float xc = ((float)u + 0.5f - a.cx) * d[k] / a.fx;
+      const float yc = ((float)v + 0.5f - a.cy) * d[k] / a.fy;
+      const float wx = fmaf(a.R[0], xc, fmaf(a.R[1], yc, fmaf(a.R[2], d[k], a.t[0])));
+      const float wy = fmaf(a.R[3], xc, fmaf(a.R[4], yc, fmaf(a.R[5], d[k], a.t[1])));
+      const float wz = fmaf(a.R[6], xc, fmaf(a.R[7], yc, fmaf(a.R[8], d[k], a.t[2])));
+      keep = !in_robot(sph, wx, wy, wz);
+    }
+    work[i] = keep ? d[k] : 0.f;
+  }
+}
+
+// n / d for n < 2^31 and 1 <= d < 2^31: the double quotient is within one of the
+// truth, and one correction step makes it exact.
+__device__ __forceinline__ uint32_t ogm_div(uint32_t n, uint32_t d, double inv_d) {
+  const uint32_t q = (uint32_t)((double)n * inv_d);
+  const int64_t r = (int64_t)n - (int64_t)q * d;
+  return r < 0 ? q - 1u : (r >= (int64_t)d ? q + 1u : q);
+}
+
+// Raw buffer over `bytes` bytes at p: accesses past the end read 0 and write nothing.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t ogm_buffer(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)bytes, 0x00020000);
+}
+
+// Pass 2: a block takes kOgmTile consecutive voxels (x fastest), each wave 64 of them
+// per step, kOgmThreads apart over kOgmPerThread steps.  The log-odds and occupancy
+// are accessed through buffers bounded at the block's last voxel, so the ragged end
+// needs no branch.  A wave's first voxel is split into (x, y, z) on the scalar unit;
+// a lane past the end of that row wraps into the next one (at most once, as nx >= 64;
+// narrower grids split every voxel).  The centre maps to (X, Y, Z) by the affine map
+// M, m: Z is its depth and floor(X / Z), floor(Y / Z) its pixel, read through a
+// bounded buffer, so that a voxel out of view reads past the end of the image and
+// gets 0 ("no return").  Then the log-odds are updated, voxels inside the robot
+// reset and the occupancy written.
+__global__ __launch_bounds__(kOgmThreads) void ogm_voxel_kernel(
+    const OgmArgs a, const float* __restrict__ work, float* __restrict__ log_odds,
+    uint8_t* __restrict__ occ) {
+  const uint32_t nx = (uint32_t)a.nx, ny = (uint32_t)a.ny;
+  const uint32_t plane = nx * ny, nvox = plane * (uint32_t)a.nz;
+  const uint32_t width = (uint32_t)a.width, height = (uint32_t)a.height;
+  const uint32_t npix = width * height;
+  const __amdgpu_buffer_rsrc_t img = ogm_buffer(work, npix * 4u);
+  const float* sph = work + npix;
+  const uint32_t blk0 = blockIdx.x * (uint32_t)kOgmTile;
+  const uint32_t nblk = min(nvox - blk0, (uint32_t)kOgmTile);
+  const __amdgpu_buffer_rsrc_t lbuf = ogm_buffer(log_odds + blk0, nblk * 4u);
+  const uint32_t lane = threadIdx.x & (kWave - 1);
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const uint32_t loc = wave * kWave + lane;  // voxel blk0 + loc + k kOgmThreads
+  // Robot bounding box in voxel indices (empty without the mask).
+  int32_t blo[3] = {1, 1, 1}, bhi[3] = {0, 0, 0};
+  if (a.use_mask)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      blo[k] = __float_as_int(sph[kOgmIndexBox + k]);
+      bhi[k] = __float_as_int(sph[kOgmIndexBox + 3 + k]);
+    }
+  float L[kOgmPerThread], d[kOgmPerThread], z[kOgmPerThread];
+  uint32_t vx[kOgmPerThread], vy[kOgmPerThread], vz[kOgmPerThread];
+  bool in_box[kOgmPerThread];
+#pragma unroll
+  for (int k = 0; k < kOgmPerThread; ++k)
+    L[k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                         lbuf, (int)((loc + k * kOgmThreads) * 4u), 0, 0));
+#pragma unroll
+  for (int k = 0; k < kOgmPerThread; ++k) {
+    uint32_t ix, iy, iz;
+    bool box;
+    if (nx >= (uint32_t)kWave) {
+      // wave-uniform split of the wave's first voxel (scalar unit)
+      const uint32_t w0 = min(blk0 + wave * kWave + k * kOgmThreads, nvox - 1u);
+      const uint32_t bz = __umulhi(w0, a.plane_mul) >> a.plane_shift;
+      const uint32_t rem = w0 - bz * plane;
+      const uint32_t by = __umulhi(rem, a.nx_mul) >> a.nx_shift;
+      const uint32_t bx = rem - by * nx;
+      const bool last_y = by + 1u >= ny;
+      const uint32_t ny1 = last_y ? 0u : by + 1u, nz1 = last_y ? bz + 1u : bz;
+      const bool row0 = ((int32_t)by >= blo[1]) & ((int32_t)by <= bhi[1]) &
+                        ((int32_t)bz >= blo[2]) & ((int32_t)bz <= bhi[2]);
+      const bool row1 = ((int32_t)ny1 >= blo[1]) & ((int32_t)ny1 <= bhi[1]) &
+                        ((int32_t)nz1 >= blo[2]) & ((int32_t)nz1 <= bhi[2]);
+      ix = bx + lane;
+      const bool wrap = ix >= nx;
+      ix = wrap ? ix - nx : ix;
+      iy = wrap ? ny1 : by;
+      iz = wrap ? nz1 : bz;
+      box = false;
+      if (row0 | row1)
+        box = (wrap ? row1 : row0) & ((int32_t)ix >= blo[0]) & ((int32_t)ix <= bhi[0]);
+    } else {
+      const uint32_t i = min(blk0 + loc + k * kOgmThreads, nvox - 1u);
+      iz = ogm_div(i, plane, a.inv_plane);
+      iy = ogm_div(i - iz * plane, nx, a.inv_nx);
+      ix = i - iz * plane - iy * nx;
+      box = ((int32_t)ix >= blo[0]) & ((int32_t)ix <= bhi[0]) & ((int32_t)iy >= blo[1]) &
+            ((int32_t)iy <= bhi[1]) & ((int32_t)iz >= blo[2]) & ((int32_t)iz <= bhi[2]);
+    }
+    const float fx = (float)ix, fy = (float)iy, fz = (float)iz;
+    const float X = fmaf(a.M[0], fx, fmaf(a.M[1], fy, fmaf(a.M[2], fz, a.m[0])));
+    const float Y = fmaf(a.M[3], fx, fmaf(a.M[4], fy, fmaf(a.M[5], fz, a.m[1])));
+    const float Z = fmaf(a.M[6], fx, fmaf(a.M[7], fy, fmaf(a.M[8], fz, a.m[2])));
+    // In front: Z above the smallest normal float, so 1 / Z and X / Z stay finite.
+    const float inv_z = __builtin_amdgcn_rcpf(Z);
+    const int32_t pu = __float2int_rd(X * inv_z), pv = __float2int_rd(Y * inv_z);
+    const bool in_view =
+        (Z > 1.17549435e-38f) & ((uint32_t)pu < width) & ((uint32_t)pv < height);
+    // pixel row and column are below 2^14: a 24-bit multiply is exact
+    const uint32_t off = in_view ? __umul24((uint32_t)pv, width) + (uint32_t)pu : npix;
+    d[k] = __builtin_bit_cast(float,
+                              __builtin_amdgcn_raw_buffer_load_b32(img, (int)(off * 4u), 0, 0));
+    z[k] = Z;
+    vx[k] = ix;
+    vy[k] = iy;
+    vz[k] = iz;
+    in_box[k] = box;
+  }
+#pragma unroll
+  for (int k = 0; k < kOgmPerThread; ++k) {
+    float l = L[k];
+    const float e = z[k] - d[k];
+    const bool hit = fabsf(e) <= a.tol, free = e < -a.tol;
+    if ((d[k] > 0.f) & (hit | free))
+      l = fminf(fmaxf(l + (hit ? a.l_hit : a.l_miss), a.l_min), a.l_max);
+    if (in_box[k]) {
+      const float wx = a.origin[0] + ((float)vx[k] + 0.5f) * a.voxel;
+      const float wy = a.origin[1] + ((float)vy[k] + 0.5f) * a.voxel;
+      const float wz = a.origin[2] + ((float)vz[k] + 0.5f) * a.voxel;
+      if (in_robot_spheres(sph, wx, wy, wz)) l = a.l_min;
+    }
+    const uint32_t o = loc + k * kOgmThreads;
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, l), lbuf, (int)(o * 4u),
+                                          0, 0);
+    if (occ)
+      __builtin_amdgcn_raw_buffer_store_b8((uint8_t)(l > a.l_occ ? 1 : 0),
+                                           ogm_buffer(occ + blk0, nblk), (int)o, 0, 0);
+  }
 }
 
 __global__ __launch_bounds__(256) void grid_to_f16_kernel(const float* __restrict__ src,
@@ -1399,10 +1521,10 @@ int launch_ogm(const DevRobot* robot, const OgmArgs& a, const float* depth, floa
                uint8_t* occ, float* work, hipStream_t stream) {
   const long long npix = (long long)a.width * a.height;
   const long long nvox = (long long)a.nx * a.ny * a.nz;
-  hipLaunchKernelGGL(ogm_pixel_kernel, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, stream,
-                     robot, a, depth, work);
-  hipLaunchKernelGGL(ogm_voxel_kernel, dim3((unsigned)((nvox + 255) / 256)), dim3(256), 0, stream,
-                     a, work, log_odds, occ);
+  hipLaunchKernelGGL(ogm_pixel_kernel, dim3((unsigned)((npix + kOgmTile - 1) / kOgmTile)),
+                     dim3(kOgmThreads), 0, stream, robot, a, depth, work);
+  hipLaunchKernelGGL(ogm_voxel_kernel, dim3((unsigned)((nvox + kOgmTile - 1) / kOgmTile)),
+                     dim3(kOgmThreads), 0, stream, a, work, log_odds, occ);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -409,8 +409,8 @@ smpc_status smpc_set_robot(smpc_ctx* ctx, const smpc_robot_desc* d) {
     r.lp_rs[lp][bit] = (float)rs;
     const double bt = bound_r[la] + bound_r[lb];
     r.lp_bthr[lp] = (float)(bt * bt);
-    const double st = ctx->slot_radius[a] + bound_r[lb];
-    r.lp_sthr[lp][a % kSpl] = (float)(st * st);
+    const double sb = ctx->slot_radius[a] + bound_r[lb];
+    r.lp_sthr[lp][a % kSpl] = (float)(sb * sb);
   }
   r.n_pairs = n_unique;
   ctx->host_robot = r;
@@ -507,7 +507,7 @@ smpc_status smpc_grid_to_f16(const float* src, void* dst, int64_t n, float clamp
 
 size_t smpc_ogm_workspace_bytes(int32_t width, int32_t height) {
   if (width < 1 || height < 1 || width > 16384 || height > 16384) return 0;
-  return ((size_t)width * height + 128) * sizeof(float);
+  return ((size_t)width * height + kOgmTableFloats) * sizeof(float);
 }
 
 smpc_status smpc_ogm_update(smpc_ctx* ctx, const float* q, const float* depth,
@@ -515,7 +515,6 @@ smpc_status smpc_ogm_update(smpc_ctx* ctx, const float* q, const float* depth,
                             int32_t nx, int32_t ny, int32_t nz, const float* origin, float voxel,
                             const smpc_ogm_params* prm, void* work, size_t work_bytes,
                             void* stream) {
-  static_assert(kOgmSphereFloats <= 128, "sphere table fits the workspace tail");
   if (!ctx) return SMPC_E_INVALID_ARG;
   ctx->last_error.clear();
   if (!depth || !cam || !log_odds || !origin || !prm || !work)
@@ -525,12 +524,9 @@ smpc_status smpc_ogm_update(smpc_ctx* ctx, const float* q, const float* depth,
   const float intr[] = {cam->fx, cam->fy, cam->cx, cam->cy};
   if (!finite_all(intr, 4) || !(cam->fx > 0.f) || !(cam->fy > 0.f))
     return fail(ctx, SMPC_E_INVALID_ARG, "intrinsics must be finite, fx and fy > 0");
-  const size_t need = smpc_ogm_workspace_bytes(cam->width, cam->height);
-  if (need == 0)
+  if (cam->width < 1 || cam->height < 1 || cam->width > 16384 || cam->height > 16384)
     return fail(ctx, SMPC_E_INVALID_ARG, "image %dx%d outside [1, 16384]", cam->width,
                 cam->height);
-  if (work_bytes < need || ((uintptr_t)work & 3u))
-    return fail(ctx, SMPC_E_INVALID_ARG, "work needs %zu bytes, 4-byte aligned", need);
   if (!std::isfinite(cam->min_depth) || !std::isfinite(cam->max_depth) ||
       !(cam->min_depth > 0.f) || cam->min_depth > cam->max_depth)
     return fail(ctx, SMPC_E_INVALID_ARG, "depth range must satisfy 0 < min <= max");
@@ -548,6 +544,9 @@ smpc_status smpc_ogm_update(smpc_ctx* ctx, const float* q, const float* depth,
   if (nx < 1 || ny < 1 || nz < 1 || (long long)nx * ny * nz >= (1LL << 31))
     return fail(ctx, SMPC_E_INVALID_ARG, "grid %dx%dx%d: sides >= 1, fewer than 2^31 voxels",
                 nx, ny, nz);
+  const size_t need = smpc_ogm_workspace_bytes(cam->width, cam->height);
+  if (work_bytes < need || ((uintptr_t)work & 3u))
+    return fail(ctx, SMPC_E_INVALID_ARG, "work needs %zu bytes, 4-byte aligned", need);
   if (!finite_all(origin, 3) || !std::isfinite(voxel) || !(voxel > 0.f))
     return fail(ctx, SMPC_E_INVALID_ARG, "origin/voxel must be finite, voxel > 0");
   const float pv[] = {prm->tol, prm->l_hit, prm->l_miss, prm->l_min,
@@ -597,6 +596,47 @@ smpc_status smpc_ogm_update(smpc_ctx* ctx, const float* q, const float* depth,
   oa.l_min = prm->l_min;
   oa.l_max = prm->l_max;
   oa.l_occ = prm->l_occ;
+  {
+    // K R^T applied to origin + (i + 1/2) voxel - t, as one affine map of the index.
+    const double Kc[3][3] = {{cam->fx, 0.0, cam->cx}, {0.0, cam->fy, cam->cy}, {0.0, 0.0, 1.0}};
+    double KRt[3][3];
+    for (int r = 0; r < 3; ++r)
+      for (int c = 0; c < 3; ++c) {
+        double acc = 0.0;
+        for (int k = 0; k < 3; ++k) acc += Kc[r][k] * (double)T[c * 4 + k];  // (R^T)[k][c] = R[c][k]
+        KRt[r][c] = acc;
+      }
+    double p0[3];
+    for (int c = 0; c < 3; ++c)
+      p0[c] = (double)origin[c] + 0.5 * (double)voxel - (double)T[c * 4 + 3];
+    for (int r = 0; r < 3; ++r) {
+      double acc = 0.0;
+      for (int c = 0; c < 3; ++c) {
+        oa.M[r * 3 + c] = (float)(KRt[r][c] * (double)voxel);
+        acc += KRt[r][c] * p0[c];
+      }
+      oa.m[r] = (float)acc;
+    }
+  }
+  oa.inv_nx = 1.0 / (double)nx;
+  {
+    // Division by an invariant d >= 2 for numerators below 2^31: with l = ceil(log2 d)
+    // and mul = ceil(2^(31 + l) / d) < 2^32, n / d = (n * mul) >> (31 + l).
+    auto magic = [](uint64_t d, uint32_t& mul, uint32_t& shift) {
+      if (d < 2) {
+        mul = 0;
+        shift = 0;
+        return;
+      }
+      uint32_t l = 0;
+      while ((1ull << l) < d) ++l;
+      mul = (uint32_t)(((1ull << (31 + l)) + d - 1) / d);
+      shift = l - 1;
+    };
+    magic((uint64_t)nx, oa.nx_mul, oa.nx_shift);
+    magic((uint64_t)nx * (uint64_t)ny, oa.plane_mul, oa.plane_shift);
+  }
+  oa.inv_plane = 1.0 / ((double)nx * (double)ny);
 
   DeviceGuard g(ctx->device);
   if (!g.ok) return fail(ctx, SMPC_E_DEVICE, "hipSetDevice(%d) failed", ctx->device);

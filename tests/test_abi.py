@@ -326,6 +326,7 @@ def _ogm_call(ctx, **over):
 
 
 def test_ogm_validates_on_host(ctx):
+    # cleaned image, then the 128-float sphere table
     assert S.smpc_ogm_workspace_bytes(320, 240) == (320 * 240 + 128) * 4
     assert S.smpc_ogm_workspace_bytes(0, 240) == 0
     assert S.smpc_ogm_workspace_bytes(16385, 1) == 0
@@ -345,7 +346,8 @@ def test_ogm_validates_on_host(ctx):
            dict(nx=0), dict(nx=2048, ny=1024, nz=1024), dict(voxel=0.0),
            dict(origin=(0.0, float("nan"), 0.0)), {"prm.tol": -0.1}, {"prm.robot_pad": -1e-3},
            {"prm.l_min": 4.0}, {"prm.l_hit": float("nan")},
-           dict(work_bytes=S.smpc_ogm_workspace_bytes(320, 240) - 4), dict(work=0x40000002),
+           dict(work_bytes=S.smpc_ogm_workspace_bytes(320, 240) - 4),
+           dict(work=0x40000002),                    # not 4-byte aligned
            dict(occ_out=0x20000000 + 100),           # overlaps the log-odds grid
            dict(work=0x10000000 + 8),                # overlaps the depth image
            ]

@@ -100,22 +100,27 @@ def random_log_odds(rng, shape):
     return np.clip(L, np.float32(PRM["l_min"]), np.float32(PRM["l_max"]))
 
 
-def test_update_without_mask_matches_oracle(scene, planner):
-    """160x120 image of the primitives, 61x53x47 grid at 0.04 m (several blocks and a
-    ragged tail), prior log-odds across the clamp range."""
+# Grid widths on both sides of 64: rows of 64 or more voxels take the per-wave index
+# split (a wave wraps into the next row at most once), narrower ones split per voxel.
+@pytest.mark.parametrize("shape,voxel", [((47, 53, 67), 0.04), ((40, 30, 64), 0.06),
+                                         ((30, 40, 63), 0.06), ((16, 24, 130), 0.05)])
+def test_update_without_mask_matches_oracle(scene, planner, shape, voxel):
+    """160x120 image of the primitives, grids of several blocks with a ragged tail, prior
+    log-odds across the clamp range."""
     rng = np.random.default_rng(11)
     cam = C.default_camera(160, 120)
     depth = C.render_depth(cam, scene.prims)
     origin = np.array([-1.0, -1.0, 0.0])
-    L0 = random_log_odds(rng, (47, 53, 61))
-    L_gpu, occ_gpu, cleaned = run_gpu(planner, L0, depth, cam, origin, 0.04, PRM)
-    L_ref, _, margin = run_oracle(L0, depth, cam, origin, 0.04, PRM)
+    L0 = random_log_odds(rng, shape)
+    L_gpu, occ_gpu, cleaned = run_gpu(planner, L0, depth, cam, origin, voxel, PRM)
+    L_ref, _, margin = run_oracle(L0, depth, cam, origin, voxel, PRM)
     check(L0, L_gpu, occ_gpu, L_ref, margin, PRM)
-    assert (L_gpu != L0).sum() > 3000            # the update reached a good part of the grid
+    assert (L_gpu != L0).sum() > 0.01 * L0.size  # the update reached part of the grid
     np.testing.assert_array_equal(cleaned, G.clean_depth(depth, cam)[0])
 
 
-def test_robot_mask_matches_oracle(scene, planner):
+@pytest.mark.parametrize("shape", [(40, 60, 60), (40, 60, 70)])
+def test_robot_mask_matches_oracle(scene, planner, shape):
     """The arm in view of the camera: its returns are discarded and the voxels inside its
     padded spheres set to l_min, as in the oracle; the cleaned image agrees too."""
     rng = np.random.default_rng(12)
@@ -125,7 +130,7 @@ def test_robot_mask_matches_oracle(scene, planner):
     depth = C.render_depth(cam, scene.prims, spheres=centres, radii=radii)
     origin = np.array([-0.9, -0.9, 0.0])
     voxel = 0.03
-    L0 = random_log_odds(rng, (40, 60, 60))
+    L0 = random_log_odds(rng, shape)
     L_gpu, occ_gpu, cleaned = run_gpu(planner, L0, depth, cam, origin, voxel, PRM, q=q)
     L_ref, _, margin = run_oracle(L0, depth, cam, origin, voxel, PRM, scene.robot, q)
     check(L0, L_gpu, occ_gpu, L_ref, margin, PRM)
@@ -198,12 +203,16 @@ def test_degenerate_sizes(scene, planner):
     np.testing.assert_array_equal(L_gpu, L0)
 
 
-def test_occupancy_output_is_optional(scene, planner):
+@pytest.mark.parametrize("masked", [True, False])
+@pytest.mark.parametrize("shape", [(16, 20, 20), (16, 20, 90)])
+def test_occupancy_output_is_optional(scene, planner, masked, shape):
+    """The log-odds are the same whether or not the occupancy output is requested."""
     cam = C.default_camera(80, 60)
     depth = C.render_depth(cam, scene.prims)
-    L0 = random_log_odds(np.random.default_rng(16), (16, 20, 20))
-    a, occ, _ = run_gpu(planner, L0, depth, cam, (-1.0, -1.0, 0.0), 0.1, PRM, q=scene.q0)
-    b, none, _ = run_gpu(planner, L0, depth, cam, (-1.0, -1.0, 0.0), 0.1, PRM, q=scene.q0,
+    L0 = random_log_odds(np.random.default_rng(16), shape)
+    q = scene.q0 if masked else None
+    a, occ, _ = run_gpu(planner, L0, depth, cam, (-1.0, -1.0, 0.0), 0.1, PRM, q=q)
+    b, none, _ = run_gpu(planner, L0, depth, cam, (-1.0, -1.0, 0.0), 0.1, PRM, q=q,
                          want_occ=False)
     assert none is None and occ is not None
     np.testing.assert_array_equal(a.view(np.uint32), b.view(np.uint32))
