@@ -62,6 +62,27 @@ def assert_controls_close(U_gpu, U_ref, atol=U_ATOL):
     assert np.all(err <= atol), f"U* mismatch: max abs err {float(err.max()):.3g} > {atol}"
 
 
+# One float32 rounding, relative: the least error any float32 evaluation of a cost has.
+F32_ROUNDING = 2.0 ** -24
+
+
+def control_conditioning_tolerance(ref, noise):
+    """Change of U* that one float32 rounding of every cost can cause (oracle values only).
+
+    U* - U_bar = sum_j w_j eps_j with w = softmax(-S / lambda), so to first order
+    dU* = -sum_j (w_j / lambda) (eps_j - sum_i w_i eps_i) dS_j.  With |dS_j| <=
+    F32_ROUNDING |S_j| this is at most sum_j (w_j / lambda) |eps_j - mean| |S_j|
+    F32_ROUNDING per control.  It is negligible for spread-out weights and exceeds
+    U_ATOL only when two or three rollouts with large S nearly tie for the minimum.
+    """
+    S = np.where(np.isfinite(ref["S"]), ref["S"], 0.0)
+    w = ref["w"]
+    eps = np.asarray(noise, np.float64)
+    mean = np.tensordot(w, eps, axes=1)
+    sens = np.tensordot(w * np.abs(S) / ref["lam"], np.abs(eps - mean[None]), axes=1)
+    return sens * F32_ROUNDING
+
+
 def weight_tolerance(ref):
     """Bound on |w_gpu - w_ref| implied by the cost bar.
 
