@@ -1158,23 +1158,53 @@ constexpr int kOgmThreads = 256;
 constexpr int kOgmPerThread = 4;  // pixels or voxels per thread, kOgmThreads apart
 constexpr int kOgmTile = kOgmThreads * kOgmPerThread;
 
+// Robot data one thread needs for the sphere table, fetched before anything else so
+// that its latency overlaps the caller's own loads: the DH constants (wave-uniform,
+// scalar loads), this lane's joint angle (lanes below kNdof) and sphere slot (lanes
+// below kSlots; radius -1 when the slot is empty).
+struct OgmRobotFetch {
+  float ca[kNdof], sa[kNdof], a[kNdof], d[kNdof];
+  float q;
+  float4 slot;
+};
+
+__device__ __forceinline__ OgmRobotFetch ogm_fetch_robot(const DevRobot* __restrict__ rob,
+                                                         const OgmArgs& a) {
+  OgmRobotFetch f;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int i = 0; i < kNdof; ++i) {
+    f.ca[i] = rob->ca[i];
+    f.sa[i] = rob->sa[i];
+    f.a[i] = rob->a[i];
+    f.d[i] = rob->d[i];
+  }
+  f.q = a.q[0];
+#pragma unroll
+  for (int i = 1; i < kNdof; ++i) f.q = tid == i ? a.q[i] : f.q;
+  f.slot = make_float4(0.f, 0.f, 0.f, -1.f);
+  if (tid < kSlots && (rob->slot_active & (1u << tid)))
+    f.slot = *reinterpret_cast<const float4*>(rob->sc[tid]);
+  return f;
+}
+
 // The robot's collision spheres at joint positions q, padded: centres and squared
 // padded radii in sph[4 s .. 4 s + 3] (inactive slots get radius^2 = -1, which no
-// point is within), bounding box of the padded spheres in sph[4 kSlots .. + 5]
-// (min x, y, z, then max x, y, z).  Called by every thread of the block.
-__device__ __forceinline__ void ogm_robot_spheres(const DevRobot* __restrict__ rob,
-                                                  const OgmArgs& a, float* sph) {
+// point is within), bounding box of the padded spheres in sph[kOgmBox .. + 5] (min x,
+// y, z, then max x, y, z) and in voxel indices in sph[kOgmIndexBox .. + 5].  Called
+// by every thread of the block.
+__device__ __forceinline__ void ogm_robot_spheres(const OgmRobotFetch& f, const OgmArgs& a,
+                                                  float* sph) {
   __shared__ float sincos_q[2 * kNdof];
   __shared__ Frame frames[kNdof];
   const int tid = threadIdx.x;
-  if (tid < kNdof) sincosf(a.q[tid], &sincos_q[tid], &sincos_q[kNdof + tid]);
+  if (tid < kNdof) sincosf(f.q, &sincos_q[tid], &sincos_q[kNdof + tid]);
   __syncthreads();
   if (tid == 0) {
     Frame T = identity_frame();
 #pragma unroll
     for (int i = 0; i < kNdof; ++i) {
-      mdh_step(T, rob->ca[i], rob->sa[i], rob->a[i], rob->d[i], sincos_q[kNdof + i],
-               sincos_q[i]);
+      mdh_step(T, f.ca[i], f.sa[i], f.a[i], f.d[i], sincos_q[kNdof + i], sincos_q[i]);
       frames[i] = T;
     }
   }
@@ -1185,10 +1215,9 @@ __device__ __forceinline__ void ogm_robot_spheres(const DevRobot* __restrict__ r
     float hi[3] = {-__builtin_inff(), -__builtin_inff(), -__builtin_inff()};
     if (tid < kSlots) {
       float p[3] = {0.f, 0.f, 0.f}, r2 = -1.f;
-      if (rob->slot_active & (1u << tid)) {
-        transform_point(frames[tid / kSpl], rob->sc[tid][0], rob->sc[tid][1], rob->sc[tid][2],
-                        p[0], p[1], p[2]);
-        const float r = rob->sc[tid][3] + a.robot_pad;
+      if (f.slot.w >= 0.f) {
+        transform_point(frames[tid / kSpl], f.slot.x, f.slot.y, f.slot.z, p[0], p[1], p[2]);
+        const float r = f.slot.w + a.robot_pad;
         r2 = r * r;
         const float rb = r * 1.0001f + 1e-6f;  // slack over the rounding of r^2 and |p - c|^2
 #pragma unroll
@@ -1252,6 +1281,8 @@ __global__ __launch_bounds__(kOgmThreads) void ogm_pixel_kernel(
   __shared__ float sph[kOgmSphereFloats];
   const uint32_t npix = (uint32_t)a.width * (uint32_t)a.height;
   const uint32_t base = blockIdx.x * (uint32_t)kOgmTile + threadIdx.x;
+  OgmRobotFetch rf;
+  if (a.use_mask) rf = ogm_fetch_robot(rob, a);
   float d[kOgmPerThread];
 #pragma unroll
   for (int k = 0; k < kOgmPerThread; ++k) {
@@ -1259,7 +1290,7 @@ __global__ __launch_bounds__(kOgmThreads) void ogm_pixel_kernel(
     d[k] = i < npix ? depth[i] : 0.f;
   }
   if (a.use_mask) {
-    ogm_robot_spheres(rob, a, sph);
+    ogm_robot_spheres(rf, a, sph);
     if (blockIdx.x == 0 && threadIdx.x < kOgmSphereFloats)
       work[npix + threadIdx.x] = sph[threadIdx.x];
   }
