@@ -44,9 +44,13 @@ PEAK_FP32_TFLOPS = 157.3
 # reads half the bytes copied: x2; WRITE_SIZE reads them all: x1).  Valid only for
 # the kernel sources it was taken on: bench.py reports null traffic when their
 # hash differs.
-ROLLOUT_TRAFFIC = {"sources_sha256": "da09281131dc41097b025e37ca21bb12890e157984f49a00cc9e6bb4123a398d",
-                   "fetch_kib": 2867.95, "fetch_scale": 2.0,
-                   "write_kib": 640.0, "write_scale": 1.0}
+ROLLOUT_TRAFFIC = {"sources_sha256": "73dfa0b5480321a49885bab2de7dc1074fcd52d0404e6825c4102c3f4f34cc97",
+                   "fetch_kib": 2789.55, "fetch_scale": 2.0,
+                   "write_kib": 640.03, "write_scale": 1.0}
+# The same for one occupancy update (pixel and voxel pass together) at 200^3, 640x480.
+OGM_TRAFFIC = {"sources_sha256": "73dfa0b5480321a49885bab2de7dc1074fcd52d0404e6825c4102c3f4f34cc97",
+               "fetch_kib": 674.54 + 20391.88, "fetch_scale": 2.0,
+               "write_kib": 1200.5 + 39066.74, "write_scale": 1.0}
 
 
 def kernel_sources_sha256() -> str:
@@ -58,11 +62,14 @@ def kernel_sources_sha256() -> str:
     return h.hexdigest()
 
 
-def rollout_traffic_bytes():
-    t = ROLLOUT_TRAFFIC
+def traffic_bytes(t):
     if t is None or t["sources_sha256"] != kernel_sources_sha256():
         return None
     return round(1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]))
+
+
+def rollout_traffic_bytes():
+    return traffic_bytes(ROLLOUT_TRAFFIC)
 
 
 def parse_args():
@@ -435,7 +442,8 @@ def ogm_bench(args) -> None:
                    "grid": [n] * 3, "image": [cam.width, cam.height]},
         "roofline": {"bound": "hbm", "kernel": "smpc_ogm_update (2 kernels)",
                      "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_HBM_GBPS, 4),
+                     "traffic": traffic_bytes(OGM_TRAFFIC) if (n, cam.width) == (200, 640) else None,
                      "bytes_per_voxel": OGM_BYTES_PER_VOXEL,
                      "bytes_per_pixel": OGM_BYTES_PER_PIXEL},
         "pipeline_ms_per_step": round(pipe_ms, 5),
