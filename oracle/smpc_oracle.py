@@ -384,6 +384,24 @@ def plan_step(robot, q0, qd0, T_goal, grid, origin, voxel, noise, U_bar, dt, lam
     return dict(U_star=U_star, S=S, w=w, S_min=S_min, Z=Z, ess=ess, numeric_ok=ok)
 
 
+def merge_shards(results, U_bar, lam):
+    """Combine plan_step results of disjoint rollout subsets into the result over their
+    union (eqs. 29-30 regrouped): with S_min and Z of each subset, the overall minimum
+    is the least S_min, each subset's normaliser is rescaled by exp(-(S_min_g - m)/lam)
+    and its weighted disturbance sum (U*_g - Ubar) Z_g likewise.  Returns (U_star, S_min,
+    Z); subsets without a finite cost contribute nothing.
+    """
+    parts = [r for r in results if r["numeric_ok"]]
+    U_bar = np.asarray(U_bar, np.float64)
+    if not parts:
+        return U_bar.copy(), float("nan"), 0.0
+    m = min(r["S_min"] for r in parts)
+    scale = [np.exp(-(r["S_min"] - m) / lam) for r in parts]
+    Z = sum(r["Z"] * c for r, c in zip(parts, scale))
+    N = sum((np.asarray(r["U_star"]) - U_bar) * r["Z"] * c for r, c in zip(parts, scale))
+    return U_bar + N / Z, float(m), float(Z)
+
+
 def plan_step_inputs(inp):
     """plan_step on a synth.workload.PlanInputs bundle (robot rounded like the GPU's)."""
     return plan_step(inp.robot.rounded_f32(), inp.q0, inp.qd0, inp.T_goal, inp.grid,

@@ -730,3 +730,20 @@ def test_ogm_occupied_voxels_lie_on_surfaces():
     sdf = _prim_sdf(sc.prims, pw)
     footprint = 3.0 / cam.fx * 2.5        # a pixel's width at the farthest depth, generous
     assert np.all(np.abs(sdf) <= OGM_PRM["tol"] + vox * np.sqrt(3) + footprint), float(np.abs(sdf).max())
+
+
+def test_merging_rollout_shards_equals_the_whole_plan_step():
+    """Splitting the K rollouts into disjoint subsets and merging their (S_min, Z, U*)
+    gives the plan step over all of them (eqs. 29-30 are sums over rollouts)."""
+    from synth import workload as W
+    inp = W.make_inputs(21, K=90, H=8, dt=0.05, n=24, voxel=0.05, n_boxes=4, n_spheres=2)
+    full = O.plan_step_inputs(inp)
+    parts = []
+    for lo, hi in ((0, 7), (7, 50), (50, 90)):
+        parts.append(O.plan_step(inp.robot.rounded_f32(), inp.q0, inp.qd0, inp.T_goal, inp.grid,
+                                 inp.origin, inp.voxel, inp.noise[lo:hi], inp.U_bar, inp.dt,
+                                 inp.lam, inp.weights))
+    U, m, Z = O.merge_shards(parts, inp.U_bar, inp.lam)
+    np.testing.assert_allclose(U, full["U_star"], rtol=0, atol=1e-12)
+    assert m == full["S_min"]
+    assert Z == pytest.approx(full["Z"], rel=1e-12)
