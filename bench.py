@@ -474,8 +474,8 @@ def main():
         calibrate_copy(args.calibrate_copy_mib)
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the plan step is not sharded "
-              "across GPUs); run with --gpus 1", file=sys.stderr)
+        print("bench.py runs on one GPU only (the plan step is not sharded across GPUs); "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.serving:
         serving_bench(args)

@@ -51,7 +51,7 @@ enum {
   SMPC_E_OOM = -2,         /* device workspace allocation failed                      */
   SMPC_E_DEVICE = -3,      /* a HIP runtime call or kernel launch failed              */
   SMPC_E_NUMERIC = -4,     /* every rollout cost is non-finite (reported in stats)    */
-  SMPC_E_UNSUPPORTED = -5  /* valid request outside what this build implements        */
+  SMPC_E_UNSUPPORTED = -5  /* valid request outside what this library implements      */
 };
 
 #define SMPC_NDOF 7
