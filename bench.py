@@ -303,6 +303,19 @@ def edt_bench(args) -> None:
     planner.close()
 
     achieved = EDT_BYTES_PER_VOXEL * nvox / (edt_ms * 1e-3) / 1e9
+    extra = {}
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_limits
+
+        from oracle import edt as E
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            E.signed_distance(occs_np[0], float(np.float32(sc.VOXEL)))
+            dt = time.perf_counter() - t0
+        extra["cpu_baseline"] = {
+            "value": round(nvox / dt, 1), "unit": "voxels/s", "cores": 1, "kind": "oracle",
+            "sample": f"one {n}^3 construction of the same scene (separable FH in float64 "
+                      f"numpy, both fields and phi), {dt:.2f} s on one host thread"}
     print(json.dumps({
         "metric": "voxels/s of signed distance field construction (occupancy -> field)",
         "value": round(nvox / (edt_ms * 1e-3), 1),
@@ -325,6 +338,7 @@ def edt_bench(args) -> None:
         "pipeline_ms_per_step": round(pipe_ms, 5),
         "pipeline": f"smpc_edt, smpc_grid_coarse_min, then smpc_plan_step (K={K}, H={H}) "
                     "on the new field",
+        **extra,
     }), flush=True)
 
 
@@ -357,10 +371,11 @@ def ogm_bench(args) -> None:
     cam = C.default_camera(640, 480)
     pool = max(1, min(args.pool, 8))
     planner = S.Planner(sc.robot, device=0)
-    depths = []
+    depths_np = []
     for _ in range(pool):
-        depths.append(torch.from_numpy(C.render_depth(cam, sc.prims)).to(dev))
+        depths_np.append(C.render_depth(cam, sc.prims))
         sc.advance()
+    depths = [torch.from_numpy(d).to(dev) for d in depths_np]
     scam = S.make_camera(cam.fx, cam.fy, cam.cx, cam.cy, cam.width, cam.height, cam.T_wc,
                          cam.min_depth, cam.max_depth)
     prm = S.make_ogm_params(tol=0.025, l_hit=0.85, l_miss=-0.4, l_min=-2.0, l_max=3.5,
@@ -425,6 +440,27 @@ def ogm_bench(args) -> None:
     npix = cam.width * cam.height
     bytes_ = OGM_BYTES_PER_VOXEL * nvox + OGM_BYTES_PER_PIXEL * npix
     achieved = bytes_ / (ogm_ms * 1e-3) / 1e9
+    extra = {}
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_limits
+
+        from oracle import ogm as G
+        from oracle import smpc_oracle as O
+        robot = sc.robot.rounded_f32()
+        q = np.asarray(sc.q0, np.float32).astype(np.float64)
+        centres = O.sphere_centres(robot, O.forward_kinematics(robot, q[None]))[0]
+        prm_d = dict(tol=0.025, l_hit=0.85, l_miss=-0.4, l_min=-2.0, l_max=3.5, l_occ=0.0,
+                     robot_pad=0.01)
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            G.ogm_update(np.zeros((n, n, n), np.float32), depths_np[0], cam,
+                         np.asarray(sc.origin, np.float64), float(np.float32(sc.VOXEL)), prm_d,
+                         centres, robot.sphere_radius)
+            dt = time.perf_counter() - t0
+        extra["cpu_baseline"] = {
+            "value": round(nvox / dt, 1), "unit": "voxels/s", "cores": 1, "kind": "oracle",
+            "sample": f"one update of the {n}^3 map from one 640x480 image with the robot mask "
+                      f"(float64 numpy), {dt:.2f} s on one host thread"}
     print(json.dumps({
         "metric": "voxels/s of occupancy update (one depth image into the log-odds map)",
         "value": round(nvox / (ogm_ms * 1e-3), 1),
@@ -449,6 +485,7 @@ def ogm_bench(args) -> None:
         "pipeline_ms_per_step": round(pipe_ms, 5),
         "pipeline": f"smpc_ogm_update, smpc_edt on its occupancy, smpc_grid_coarse_min, then "
                     f"smpc_plan_step (K={K}, H={H}) on the new field",
+        **extra,
     }), flush=True)
 
 
