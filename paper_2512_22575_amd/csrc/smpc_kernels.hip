@@ -1439,6 +1439,109 @@ __global__ __launch_bounds__(kOgmThreads) void ogm_voxel_kernel(
   }
 }
 
+// Pass 2 for rows of a multiple of four voxels (16-byte aligned log-odds, 4-byte
+// aligned occupancy): each lane takes kOgmGroups groups of four consecutive voxels of
+// one row, 16 bytes of log-odds and one occupancy word per group (plain global
+// accesses guarded by the group count: groups are whole); the index split and the
+// affine map are evaluated once per group (X, Y, Z of the next voxel differ by the
+// first column of M).  Otherwise as ogm_voxel_kernel.
+constexpr int kOgmGroups = 2;
+constexpr int kOgmGroupTile = kOgmThreads * kOgmGroups;  // groups per block
+
+__global__ __launch_bounds__(kOgmThreads) void ogm_voxel4_kernel(
+    const OgmArgs a, const float* __restrict__ work, float* __restrict__ log_odds,
+    uint8_t* __restrict__ occ) {
+  const uint32_t nx = (uint32_t)a.nx, plane = nx * (uint32_t)a.ny;
+  const uint32_t ngroups = plane * (uint32_t)a.nz / 4u;
+  const uint32_t width = (uint32_t)a.width, height = (uint32_t)a.height;
+  const uint32_t npix = width * height;
+  const __amdgpu_buffer_rsrc_t img = ogm_buffer(work, npix * 4u);
+  const float* sph = work + npix;
+  const uint32_t blk_g = blockIdx.x * (uint32_t)kOgmGroupTile;
+  float4* __restrict__ L4 = reinterpret_cast<float4*>(log_odds);
+  uint32_t* __restrict__ occ4 = reinterpret_cast<uint32_t*>(occ);
+  int32_t blo[3] = {1, 1, 1}, bhi[3] = {0, 0, 0};
+  if (a.use_mask)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      blo[k] = __float_as_int(sph[kOgmIndexBox + k]);
+      bhi[k] = __float_as_int(sph[kOgmIndexBox + 3 + k]);
+    }
+  const uint32_t tid = threadIdx.x;
+  float L[kOgmGroups][4], d[kOgmGroups][4], z[kOgmGroups][4];
+  uint32_t gx[kOgmGroups], gy[kOgmGroups], gz[kOgmGroups];
+  bool row_box[kOgmGroups];
+#pragma unroll
+  for (int k = 0; k < kOgmGroups; ++k) {
+    const uint32_t g = blk_g + tid + k * kOgmThreads;
+    const float4 v = g < ngroups ? L4[g] : make_float4(0.f, 0.f, 0.f, 0.f);
+    L[k][0] = v.x;
+    L[k][1] = v.y;
+    L[k][2] = v.z;
+    L[k][3] = v.w;
+  }
+#pragma unroll
+  for (int k = 0; k < kOgmGroups; ++k) {
+    const uint32_t i0 = 4u * min(blk_g + tid + k * kOgmThreads, ngroups - 1u);
+    const uint32_t iz = __umulhi(i0, a.plane_mul) >> a.plane_shift;
+    const uint32_t rem = i0 - iz * plane;
+    const uint32_t iy = __umulhi(rem, a.nx_mul) >> a.nx_shift;
+    const uint32_t ix = rem - iy * nx;
+    gx[k] = ix;
+    gy[k] = iy;
+    gz[k] = iz;
+    row_box[k] = ((int32_t)iy >= blo[1]) & ((int32_t)iy <= bhi[1]) & ((int32_t)iz >= blo[2]) &
+                 ((int32_t)iz <= bhi[2]);
+    const float fx = (float)ix, fy = (float)iy, fz = (float)iz;
+    const float X0 = fmaf(a.M[0], fx, fmaf(a.M[1], fy, fmaf(a.M[2], fz, a.m[0])));
+    const float Y0 = fmaf(a.M[3], fx, fmaf(a.M[4], fy, fmaf(a.M[5], fz, a.m[1])));
+    const float Z0 = fmaf(a.M[6], fx, fmaf(a.M[7], fy, fmaf(a.M[8], fz, a.m[2])));
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float X = fmaf((float)j, a.M[0], X0);
+      const float Y = fmaf((float)j, a.M[3], Y0);
+      const float Z = fmaf((float)j, a.M[6], Z0);
+      // In front: Z above the smallest normal float, so 1 / Z and X / Z stay finite.
+      const float inv_z = __builtin_amdgcn_rcpf(Z);
+      const int32_t pu = __float2int_rd(X * inv_z), pv = __float2int_rd(Y * inv_z);
+      const bool in_view =
+          (Z > 1.17549435e-38f) & ((uint32_t)pu < width) & ((uint32_t)pv < height);
+      // pixel row and column are below 2^14: a 24-bit multiply is exact
+      const uint32_t off = in_view ? __umul24((uint32_t)pv, width) + (uint32_t)pu : npix;
+      d[k][j] = __builtin_bit_cast(
+          float, __builtin_amdgcn_raw_buffer_load_b32(img, (int)(off * 4u), 0, 0));
+      z[k][j] = Z;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < kOgmGroups; ++k) {
+    uint32_t bits = 0u;
+    float out[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float l = L[k][j];
+      const float e = z[k][j] - d[k][j];
+      const bool hit = fabsf(e) <= a.tol, free = e < -a.tol;
+      if ((d[k][j] > 0.f) & (hit | free))
+        l = fminf(fmaxf(l + (hit ? a.l_hit : a.l_miss), a.l_min), a.l_max);
+      const int32_t ix = (int32_t)(gx[k] + j);
+      if (row_box[k] & (ix >= blo[0]) & (ix <= bhi[0])) {
+        const float wx = a.origin[0] + ((float)ix + 0.5f) * a.voxel;
+        const float wy = a.origin[1] + ((float)gy[k] + 0.5f) * a.voxel;
+        const float wz = a.origin[2] + ((float)gz[k] + 0.5f) * a.voxel;
+        if (in_robot_spheres(sph, wx, wy, wz)) l = a.l_min;
+      }
+      out[j] = l;
+      bits |= (l > a.l_occ ? 1u : 0u) << (8 * j);
+    }
+    const uint32_t g = blk_g + tid + k * kOgmThreads;
+    if (g < ngroups) {
+      L4[g] = make_float4(out[0], out[1], out[2], out[3]);
+      if (occ) occ4[g] = bits;
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void grid_to_f16_kernel(const float* __restrict__ src,
                                                           unsigned short* __restrict__ dst,
                                                           long long n, float clamp) {
@@ -1554,8 +1657,17 @@ int launch_ogm(const DevRobot* robot, const OgmArgs& a, const float* depth, floa
   const long long nvox = (long long)a.nx * a.ny * a.nz;
   hipLaunchKernelGGL(ogm_pixel_kernel, dim3((unsigned)((npix + kOgmTile - 1) / kOgmTile)),
                      dim3(kOgmThreads), 0, stream, robot, a, depth, work);
-  hipLaunchKernelGGL(ogm_voxel_kernel, dim3((unsigned)((nvox + kOgmTile - 1) / kOgmTile)),
-                     dim3(kOgmThreads), 0, stream, a, work, log_odds, occ);
+  const bool grouped = a.nx % 4 == 0 && ((uintptr_t)log_odds & 15u) == 0 &&
+                       ((uintptr_t)occ & 3u) == 0;
+  if (grouped) {
+    const long long ngroups = nvox / 4;
+    hipLaunchKernelGGL(ogm_voxel4_kernel,
+                       dim3((unsigned)((ngroups + kOgmGroupTile - 1) / kOgmGroupTile)),
+                       dim3(kOgmThreads), 0, stream, a, work, log_odds, occ);
+  } else {
+    hipLaunchKernelGGL(ogm_voxel_kernel, dim3((unsigned)((nvox + kOgmTile - 1) / kOgmTile)),
+                       dim3(kOgmThreads), 0, stream, a, work, log_odds, occ);
+  }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

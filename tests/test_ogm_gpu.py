@@ -266,3 +266,33 @@ def test_full_size_grid_on_sampled_slabs(scene, planner):
         sub_origin = origin + np.array([x0, y0, z0], np.float64) * v32
         L_ref, _, margin = G.ogm_update(L0[sub], depth, cam, sub_origin, v32, PRM, centres, radii)
         check(L0[sub], L_gpu[sub], None, L_ref, margin, PRM, max_ambiguous=0.02)
+
+
+def test_map_not_16_byte_aligned_takes_the_general_kernel(scene, planner):
+    """A log-odds map at an offset of one float (rows of 60 voxels, a multiple of four)
+    cannot take the four-voxel kernel; the update is still the oracle's."""
+    import torch
+
+    from paper_2512_22575_amd import smpc as S
+    rng = np.random.default_rng(19)
+    cam = C.default_camera(160, 120)
+    depth = C.render_depth(cam, scene.prims)
+    origin = np.array([-1.0, -1.0, 0.0])
+    shape = (20, 30, 60)
+    L0 = random_log_odds(rng, shape)
+    dev = torch.device("cuda:0")
+    backing = torch.zeros(L0.size + 4, dtype=torch.float32, device=dev)
+    L = backing[1:1 + L0.size].view(shape)
+    assert L.data_ptr() % 16 == 4
+    L.copy_(torch.from_numpy(L0))
+    d = torch.from_numpy(depth).to(dev)
+    work = torch.empty(S.smpc_ogm_workspace_bytes(cam.width, cam.height) // 4, device=dev)
+    scam = S.make_camera(cam.fx, cam.fy, cam.cx, cam.cy, cam.width, cam.height, cam.T_wc,
+                         cam.min_depth, cam.max_depth)
+    planner.ogm_update(depth=d, cam=scam, log_odds=L, origin=f32(origin), voxel=0.05,
+                       prm=S.make_ogm_params(**PRM), work=work, q=scene.q0)
+    torch.cuda.synchronize()
+    L_gpu = L.cpu().numpy()
+    L_ref, _, margin = run_oracle(L0, depth, cam, origin, 0.05, PRM, scene.robot, scene.q0)
+    check(L0, L_gpu, None, L_ref, margin, PRM)
+    assert float(backing[0]) == 0.0 and float(backing[-1]) == 0.0   # neighbours untouched
