@@ -259,3 +259,24 @@ def test_scene_with_no_obstacles():
     occ = np.zeros((32, 32, 32), bool)
     inp.grid = SC.signed_distance_grid(occ, inp.voxel)
     check_full(inp)
+
+
+def test_large_batch_longest_horizon_sampled():
+    """K = 65536 rollouts at the longest horizon H = 64 (13108 rollout blocks): the costs
+    of 64 sampled rollouts match the oracle (each rollout's cost depends on nothing
+    else); the rest is checked by properties that hold at any size — the weights are
+    the softmax of the returned costs (eq. 29) and sum to 1, and U* is U_bar plus the
+    weighted disturbances (eq. 30), evaluated in float64 from the returned weights."""
+    inp = small_inputs(77, 65536, 64, dt=0.02)
+    got = run_gpu(inp)
+    idx = np.sort(np.random.default_rng(5).choice(inp.K, size=64, replace=False))
+    sub = dataclasses.replace(inp, noise=inp.noise[idx].copy())
+    ref = oracle(sub)
+    assert_costs_close(got["S"][idx], ref["S"])
+    S = got["S"]
+    w = got["w"]
+    e = np.exp(-(S - S.min()) / inp.lam)
+    np.testing.assert_allclose(w, e / e.sum(), rtol=1e-4, atol=1e-9)
+    assert abs(w.sum() - 1.0) < 1e-4
+    U = inp.U_bar.astype(np.float64) + np.tensordot(w, inp.noise.astype(np.float64), axes=1)
+    assert_controls_close(got["U_star"], U)
