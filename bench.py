@@ -93,6 +93,9 @@ def parse_args():
     ap.add_argument("--rate", type=float, default=2000.0, help="mean arrivals per second")
     ap.add_argument("--budget-mib", type=int, default=512, help="server HBM budget")
     ap.add_argument("--max-batch", type=int, default=64)
+    ap.add_argument("--variants", action="store_true",
+                    help="time the float16-grid and on-device-sampling variants of the plan "
+                         "step against the float32 path (mid and reactive workloads)")
     ap.add_argument("--ogm", action="store_true",
                     help="time the occupancy update (640x480 depth image into the 200^3 map, "
                          "robot mask on) and the mapping-to-plan pipeline instead")
@@ -489,6 +492,80 @@ def ogm_bench(args) -> None:
     }), flush=True)
 
 
+def variants_bench(args) -> None:
+    """Plan-step time with the grid in float16 (clamped to +-2 m) and/or the disturbances
+    sampled on the device (Philox, sigma 0.5), against float32 grid + disturbance
+    buffer, on the mid workload (K=1024, H=32, 64^3) and the reactive one (K=4096,
+    H=40, 200^3).  Coarse bounds are built for each grid outside the timed region.
+    Warm-started back-to-back steps, events on the launch stream."""
+    import torch
+
+    from paper_2512_22575_amd import smpc as S
+    from synth import workload as W
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    cases = {"mid K=1024 H=32 64^3 at 0.03 m": W.mid(),
+             "reactive K=4096 H=40 200^3 at 0.01 m": W.ReactiveScenario(seed=3).inputs()}
+    out = {}
+    for name, inp in cases.items():
+        K, H = inp.K, inp.H
+        g32 = torch.from_numpy(np.ascontiguousarray(inp.grid)).to(dev)
+        g16 = torch.empty(g32.shape, dtype=torch.int16, device=dev)
+        ncells = S.smpc_grid_coarse_cells(*reversed(tuple(g32.shape)))
+        c32 = torch.empty(ncells, device=dev)
+        c16 = torch.empty(ncells, device=dev)
+        for st in (S.smpc_grid_to_f16(g32.data_ptr(), g16.data_ptr(), g32.numel(), 2.0, stream),
+                   S.smpc_grid_coarse_min(g32, S.GRID_F32, c32.data_ptr(), stream),
+                   S.smpc_grid_coarse_min(g16, S.GRID_F16, c16.data_ptr(), stream)):
+            if st != S.SMPC_OK:
+                raise S.SMPCError(st, "grid preparation")
+        noise = torch.from_numpy(np.ascontiguousarray(inp.noise)).to(dev)
+        U = [torch.zeros((H, 7), device=dev), torch.zeros((H, 7), device=dev)]
+        planner = S.Planner(inp.robot, device=0)
+        sigma = [0.5] * 7
+
+        def step(i, f16, sample):
+            planner.plan_step(q0=inp.q0, qd0=inp.qd0, T_goal=inp.T_goal,
+                              grid=g16 if f16 else g32, origin=inp.origin, voxel=inp.voxel,
+                              noise=None if sample else noise, U_in=U[i % 2],
+                              U_out=U[(i + 1) % 2], dt=inp.dt, lam=inp.lam,
+                              weights=inp.weights, stream=stream, seed=1000 + i, sigma=sigma,
+                              grid_dtype=S.GRID_F16 if f16 else S.GRID_F32, K=K, H=H,
+                              coarse=c16 if f16 else c32)
+
+        row = {}
+        for label, f16, sample in (("f32 grid, noise buffer", False, False),
+                                   ("f16 grid, noise buffer", True, False),
+                                   ("f32 grid, device sampling", False, True),
+                                   ("f16 grid, device sampling", True, True)):
+            for i in range(args.warmup):
+                step(i, f16, sample)
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            ev0.record()
+            for i in range(args.steps):
+                step(i, f16, sample)
+            ev1.record()
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1) / args.steps
+            row[label] = {"ms_per_step": round(ms, 6),
+                          "rollout_steps_per_s": round(K * H / (ms * 1e-3), 1)}
+        base = row["f32 grid, noise buffer"]["ms_per_step"]
+        for v in row.values():
+            v["speedup_vs_f32_buffer"] = round(base / v["ms_per_step"], 4)
+        out[name] = row
+        planner.close()
+    print(json.dumps({
+        "metric": "plan-step time of the float16-grid and device-sampling variants",
+        "unit": "ms per step", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "higher_is_better": False, "data": "synthetic", "dtype": "f32 arithmetic, f16 grid",
+        "variants": out,
+        "errors": "stated by tests/test_variants_gpu.py against the FP64 oracle",
+    }), flush=True)
+
+
 def cpu_baseline(sc, grid, noise, K, H):
     """Time the FP64 oracle on one full plan step of the same workload, one thread."""
     from threadpoolctl import threadpool_limits
@@ -522,6 +599,9 @@ def main():
         return
     if args.ogm:
         ogm_bench(args)
+        return
+    if args.variants:
+        variants_bench(args)
         return
     import torch
 

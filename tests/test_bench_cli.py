@@ -9,7 +9,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-@pytest.mark.parametrize("mode", [[], ["--edt"], ["--ogm"], ["--serving"]])
+@pytest.mark.parametrize("mode", [[], ["--edt"], ["--ogm"], ["--serving"], ["--variants"]])
 def test_more_than_one_gpu_is_refused(mode):
     res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"] + mode,
                          capture_output=True, text=True, timeout=120)
