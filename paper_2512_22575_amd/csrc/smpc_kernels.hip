@@ -315,13 +315,19 @@ __device__ __forceinline__ float esdf_lookup(__amdgpu_buffer_rsrc_t rsrc, const 
   return esdf_blend_at<kElemBytes>(rsrc, p, esdf_locate(p, px, py, pz));
 }
 
-// Coarse lower bound of the cell holding lookup corner g (0-filled past the buffer,
-// which only ever happens without bounds, and then it is not consulted).
+// Coarse lower bound of the cell holding the lookup corner of p (0-filled past the
+// buffer, which only ever happens without bounds, and then it is not consulted).  The
+// corner is min(floor(u), n - 2) per axis with u clamped to [0, n - 1] (as in
+// esdf_locate), so its cell is min(trunc(u) >> 3, nc - 1).
 __device__ __forceinline__ float coarse_bound(__amdgpu_buffer_rsrc_t crsrc, const StepParams& p,
-                                              const GridLoc& g) {
-  const uint32_t cell =
-      ((g.iz >> kCoarseShift) * (uint32_t)p.ncy + (g.iy >> kCoarseShift)) * (uint32_t)p.ncx +
-      (g.ix >> kCoarseShift);
+                                              float px, float py, float pz) {
+  const float ux = __builtin_amdgcn_fmed3f(fmaf(px, p.inv_voxel, p.gcx), 0.f, (float)(p.nx - 1));
+  const float uy = __builtin_amdgcn_fmed3f(fmaf(py, p.inv_voxel, p.gcy), 0.f, (float)(p.ny - 1));
+  const float uz = __builtin_amdgcn_fmed3f(fmaf(pz, p.inv_voxel, p.gcz), 0.f, (float)(p.nz - 1));
+  const uint32_t cx = min((uint32_t)ux >> kCoarseShift, (uint32_t)p.ncx - 1u);
+  const uint32_t cy = min((uint32_t)uy >> kCoarseShift, (uint32_t)p.ncy - 1u);
+  const uint32_t cz = min((uint32_t)uz >> kCoarseShift, (uint32_t)p.ncz - 1u);
+  const uint32_t cell = (cz * (uint32_t)p.ncy + cy) * (uint32_t)p.ncx + cx;
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(crsrc, cell * 4u, 0, 0));
 }
 
@@ -401,8 +407,7 @@ __device__ __forceinline__ float step_cost(const DevRobot* __restrict__ rob, con
   if (p.coarse_bytes != 0u) {
     float lb[kSlots];
 #pragma unroll
-    for (int s = 0; s < kSlots; ++s)
-      lb[s] = coarse_bound(crsrc, p, esdf_locate(p, px[s], py[s], pz[s]));
+    for (int s = 0; s < kSlots; ++s) lb[s] = coarse_bound(crsrc, p, px[s], py[s], pz[s]);
 #pragma unroll
     for (int s = 0; s < kSlots; ++s)
       if (lb[s] >= p.env_thr[s]) need &= ~(1u << s);
