@@ -296,3 +296,25 @@ def test_map_not_16_byte_aligned_takes_the_general_kernel(scene, planner):
     L_ref, _, margin = run_oracle(L0, depth, cam, origin, 0.05, PRM, scene.robot, scene.q0)
     check(L0, L_gpu, None, L_ref, margin, PRM)
     assert float(backing[0]) == 0.0 and float(backing[-1]) == 0.0   # neighbours untouched
+
+
+@pytest.mark.parametrize("nx", [60, 61])
+def test_robot_reaching_out_of_the_map(scene, planner, nx):
+    """A small map around the arm's middle links: the robot's bounding box extends past
+    the grid on several sides (its voxel-index box is clamped), with both voxel
+    kernels (rows of 60 take the four-voxel one, rows of 61 the per-voxel one)."""
+    rng = np.random.default_rng(20)
+    cam = C.default_camera(120, 90)
+    q = scene.q0
+    centres, radii = robot_spheres(scene.robot, q)
+    depth = C.render_depth(cam, scene.prims, spheres=centres, radii=radii)
+    mid = centres[8:16].mean(axis=0)
+    voxel = 0.005
+    origin = mid - 0.5 * voxel * np.array([nx, 40, 30])
+    L0 = random_log_odds(rng, (30, 40, nx))
+    L_gpu, occ_gpu, _ = run_gpu(planner, L0, depth, cam, origin, voxel, PRM, q=q)
+    L_ref, _, margin = run_oracle(L0, depth, cam, origin, voxel, PRM, scene.robot, q)
+    # the arm fills much of this 5 mm map: ~2.3 % of the voxel centres lie within 1 mm of
+    # a padded sphere surface
+    check(L0, L_gpu, occ_gpu, L_ref, margin, PRM, max_ambiguous=0.05)
+    assert (L_gpu == np.float32(PRM["l_min"])).sum() > 1000   # inside the arm
