@@ -398,28 +398,17 @@ __device__ __forceinline__ float step_cost(const DevRobot* __restrict__ rob, con
 
   if (terminal) return cost;
 
-  // Environment collision (eqs. 17, 19, 20).  With coarse bounds, all spheres first
+  // Environment collision (eqs. 17, 19, 20), with the self-collision terms evaluated
+  // while the coarse bounds are in flight.  With coarse bounds, all spheres first
   // fetch the bound of their lookup cell (one load each, issued together); a sphere
   // whose bound clears its threshold has phi >= threshold, i.e. a hinge of exactly 0,
   // and skips the trilinear lookup.
   const uint32_t active = rob->slot_active;
   uint32_t need = active;
+  float lb[kSlots];
   if (p.coarse_bytes != 0u) {
-    float lb[kSlots];
 #pragma unroll
     for (int s = 0; s < kSlots; ++s) lb[s] = coarse_bound(crsrc, p, px[s], py[s], pz[s]);
-#pragma unroll
-    for (int s = 0; s < kSlots; ++s)
-      if (lb[s] >= p.env_thr[s]) need &= ~(1u << s);
-  }
-  float c_env = 0.f;
-#pragma unroll
-  for (int s = 0; s < kSlots; ++s) {
-    if (need & (1u << s)) {
-      const float phi = esdf_lookup<kElemBytes>(rsrc, p, px[s], py[s], pz[s]);
-      const float h = fmaxf(p.env_thr[s] - phi, 0.f);
-      c_env = fmaf(h, h, c_env);
-    }
   }
 
   // Self collision (eqs. 18-20), grouped by link pair.  When no lane's link bounding
@@ -470,6 +459,20 @@ __device__ __forceinline__ float step_cost(const DevRobot* __restrict__ rob, con
           }
         }
       }
+    }
+  }
+  if (p.coarse_bytes != 0u) {
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s)
+      if (lb[s] >= p.env_thr[s]) need &= ~(1u << s);
+  }
+  float c_env = 0.f;
+#pragma unroll
+  for (int s = 0; s < kSlots; ++s) {
+    if (need & (1u << s)) {
+      const float phi = esdf_lookup<kElemBytes>(rsrc, p, px[s], py[s], pz[s]);
+      const float h = fmaxf(p.env_thr[s] - phi, 0.f);
+      c_env = fmaf(h, h, c_env);
     }
   }
   return cost + fmaf(p.w_env, c_env, p.w_self * c_self);
