@@ -405,10 +405,10 @@ __device__ __forceinline__ float step_cost(const DevRobot* __restrict__ rob, con
   // and skips the trilinear lookup.
   const uint32_t active = rob->slot_active;
   uint32_t need = active;
-  float lb[kSlots];
+  float bound[kSlots];
   if (p.coarse_bytes != 0u) {
 #pragma unroll
-    for (int s = 0; s < kSlots; ++s) lb[s] = coarse_bound(crsrc, p, px[s], py[s], pz[s]);
+    for (int s = 0; s < kSlots; ++s) bound[s] = coarse_bound(crsrc, p, px[s], py[s], pz[s]);
   }
 
   // Self collision (eqs. 18-20), grouped by link pair.  When no lane's link bounding
@@ -464,7 +464,7 @@ __device__ __forceinline__ float step_cost(const DevRobot* __restrict__ rob, con
   if (p.coarse_bytes != 0u) {
 #pragma unroll
     for (int s = 0; s < kSlots; ++s)
-      if (lb[s] >= p.env_thr[s]) need &= ~(1u << s);
+      if (bound[s] >= p.env_thr[s]) need &= ~(1u << s);
   }
   float c_env = 0.f;
 #pragma unroll
