@@ -44,11 +44,11 @@ PEAK_FP32_TFLOPS = 157.3
 # reads half the bytes copied: x2; WRITE_SIZE reads them all: x1).  Valid only for
 # the kernel sources it was taken on: bench.py reports null traffic when their
 # hash differs.
-ROLLOUT_TRAFFIC = {"sources_sha256": "c5da2b1f0493fbe41e6f52a53ca83ac1c399d138bfd8c8e8b72c9121941f0ab8",
-                   "fetch_kib": 2779.57, "fetch_scale": 2.0,
+ROLLOUT_TRAFFIC = {"sources_sha256": "578bcf58ccf36d0e8adf0b931f77c1100deab1a3f38558deced67601a38b34e2",
+                   "fetch_kib": 2782.55, "fetch_scale": 2.0,
                    "write_kib": 640.03, "write_scale": 1.0}
 # The same for one occupancy update (pixel and voxel pass together) at 200^3, 640x480.
-OGM_TRAFFIC = {"sources_sha256": "c5da2b1f0493fbe41e6f52a53ca83ac1c399d138bfd8c8e8b72c9121941f0ab8",
+OGM_TRAFFIC = {"sources_sha256": "578bcf58ccf36d0e8adf0b931f77c1100deab1a3f38558deced67601a38b34e2",
                "fetch_kib": 674.54 + 20301.44, "fetch_scale": 2.0,
                "write_kib": 1200.5 + 39062.5, "write_scale": 1.0}
 
