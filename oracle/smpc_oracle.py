@@ -225,7 +225,7 @@ def esdf_lookup(grid, origin, voxel, p):
     base corner i0 = min(floor(u), n-2), fraction f = u - i0.  A non-finite query
     point has no distance: the result is nan there.
     """
-    grid = np.asarray(grid, np.float64)
+    grid = np.asarray(grid)          # corners are widened to float64 as they are read
     nz, ny, nx = grid.shape
     p = np.asarray(p, np.float64)
     bad = ~np.all(np.isfinite(p), axis=-1)
@@ -244,7 +244,7 @@ def esdf_lookup(grid, origin, voxel, p):
             wy = fy if by else 1.0 - fy
             for bx in (0, 1):
                 wx = fx if bx else 1.0 - fx
-                phi += wx * wy * wz * grid[iz + bz, iy + by, ix + bx]
+                phi += wx * wy * wz * grid[iz + bz, iy + by, ix + bx].astype(np.float64)
     return np.where(bad, np.nan, phi)
 
 
@@ -382,6 +382,30 @@ def plan_step(robot, q0, qd0, T_goal, grid, origin, voxel, noise, U_bar, dt, lam
     U_star = update(U_bar, eps, w) if ok else np.asarray(U_bar, np.float64).copy()
     ess = float(1.0 / np.sum(w * w)) if ok else 0.0
     return dict(U_star=U_star, S=S, w=w, S_min=S_min, Z=Z, ess=ess, numeric_ok=ok)
+
+
+# ---------------------------------------------------------------------------
+# Receding horizon (Sec. IV-C, last paragraph; Algorithm 1 initialisation)
+# ---------------------------------------------------------------------------
+
+def execute_first_control(q0, qd0, U_star, dt):
+    """State one control period later when the first control of U* is applied: the
+    same semi-implicit Euler step the rollouts use (eq. 7), qd' = qd0 + u*_0 dt, then
+    q' = q0 + qd' dt.  Returns (q', qd') in float64."""
+    u0 = np.asarray(U_star, np.float64)[0]
+    qd1 = np.asarray(qd0, np.float64) + u0 * dt
+    q1 = np.asarray(q0, np.float64) + qd1 * dt
+    return q1, qd1
+
+
+def shift_nominal(U_star):
+    """Nominal sequence of the next period: u*_0 has been executed, the remaining
+    controls move one step forward and the last one is zero (the value Algorithm 1
+    starts the sequence from)."""
+    U = np.asarray(U_star, np.float64)
+    out = np.zeros_like(U)
+    out[:-1] = U[1:]
+    return out
 
 
 def merge_shards(results, U_bar, lam):

@@ -136,6 +136,19 @@ def _margin_not_applied(x, lo, hi, margin_frac):
     return np.maximum(0.0, x - hi) + np.minimum(0.0, x - lo)
 
 
+def _execute_explicit(q0, qd0, U_star, dt):
+    u0 = np.asarray(U_star, np.float64)[0]
+    q1 = np.asarray(q0, np.float64) + np.asarray(qd0, np.float64) * dt   # mistake: old velocity
+    return q1, np.asarray(qd0, np.float64) + u0 * dt
+
+
+def _shift_backwards(U_star):
+    U = np.asarray(U_star, np.float64)
+    out = np.zeros_like(U)
+    out[1:] = U[:-1]                                    # mistake: shifted the wrong way
+    return out
+
+
 _orig_lookup = O.esdf_lookup
 
 ROBOT = R.make_robot(0)
@@ -185,6 +198,8 @@ MUTANTS = {
     "ogm_pixel_rounded": ("pixel_index", _pixel_rounded, G),
     "ogm_free_behind_surface": ("classify", _classify_free_behind, G),
     "ogm_robot_voxels_not_reset": ("robot_reset", _robot_not_reset, G),
+    "executed_control_explicit_euler": ("execute_first_control", _execute_explicit),
+    "nominal_shifted_backwards": ("shift_nominal", _shift_backwards),
 }
 
 

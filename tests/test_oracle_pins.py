@@ -732,6 +732,46 @@ def test_ogm_occupied_voxels_lie_on_surfaces():
     assert np.all(np.abs(sdf) <= OGM_PRM["tol"] + vox * np.sqrt(3) + footprint), float(np.abs(sdf).max())
 
 
+# ---------------------------------------------------------------------------
+# Receding horizon (Sec. IV-C, last paragraph): execute u*_0, shift the rest
+# ---------------------------------------------------------------------------
+
+def test_executing_a_constant_control_follows_the_closed_form():
+    """n periods that each execute the same control a move the arm as the closed
+    form of constant acceleration under the semi-implicit Euler reading:
+    qd_n = qd0 + n a dt, q_n = q0 + n dt qd0 + a dt^2 n (n + 1) / 2."""
+    rng = np.random.default_rng(5)
+    q0, qd0, a = rng.normal(size=7), rng.normal(size=7), rng.normal(size=7)
+    dt = 0.02
+    q, qd = q0.copy(), qd0.copy()
+    for n in range(1, 31):
+        q, qd = O.execute_first_control(q, qd, np.vstack([a, rng.normal(size=(3, 7))]), dt)
+        np.testing.assert_allclose(qd, qd0 + n * a * dt, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(q, q0 + n * dt * qd0 + a * dt * dt * n * (n + 1) / 2,
+                                   rtol=0, atol=1e-12)
+
+
+def test_zero_disturbance_loop_replays_the_nominal_sequence_then_zeros():
+    """With every disturbance zero the update returns U* = Ubar (eq. 30), so the
+    receding-horizon loop executes the first nominal sequence control by control and
+    then zero controls (the shifted-in tail): after n periods the state is state n of
+    the open-loop rollout of [Ubar_0, 0, 0, ...]."""
+    rng = np.random.default_rng(6)
+    H, dt, n_periods = 5, 0.05, 9
+    U0 = rng.normal(size=(H, 7))
+    q0, qd0 = rng.normal(size=7), rng.normal(size=7)
+    ref_q, ref_qd = O.rollout(q0, qd0, np.vstack([U0, np.zeros((n_periods - H, 7))])[None], dt)
+    U, q, qd = U0.copy(), q0.copy(), qd0.copy()
+    for n in range(1, n_periods + 1):
+        U_star = O.update(U, np.zeros((4, H, 7)), np.full(4, 0.25))
+        q, qd = O.execute_first_control(q, qd, U_star, dt)
+        U = O.shift_nominal(U_star)
+        np.testing.assert_allclose(q, ref_q[0, n], rtol=0, atol=1e-12)
+        np.testing.assert_allclose(qd, ref_qd[0, n], rtol=0, atol=1e-12)
+    assert np.all(U == 0.0)
+    assert O.shift_nominal(np.ones((1, 7))).tolist() == [[0.0] * 7]
+
+
 def test_merging_rollout_shards_equals_the_whole_plan_step():
     """Splitting the K rollouts into disjoint subsets and merging their (S_min, Z, U*)
     gives the plan step over all of them (eqs. 29-30 are sums over rollouts)."""
