@@ -3,19 +3,24 @@
 
 Workload (the reactive-replanning configuration): K = 4096 rollouts, H = 40
 steps, dt = 0.02 s, a 200^3 float32 signed distance grid at 0.01 m built from 20
-boxes and 20 spheres, the 7-DoF arm with 28 collision spheres and 240
-self-collision pairs, temperature 1.  All inputs are seeded synthetic data and
-are resident in device memory before timing starts.
+boxes and 20 spheres drifting at 0.2 m/s, a target moving on a 0.3 m circle, the
+7-DoF arm with 28 collision spheres and 240 self-collision pairs, temperature 1.
+All inputs are seeded synthetic data and are resident in device memory before
+timing starts.
 
-One step = one call of smpc_plan_step (both kernels: rollout costs and the
-softmax update).  Consecutive steps are warm-started (U* of one step is the
-nominal sequence of the next) and the target moves on its circle; the
-disturbances cycle through a pool of pre-sampled buffers.
+One step = one control period of the closed loop on a fresh grid: the coarse
+lower bounds of that period's grid (smpc_grid_coarse_min) and one plan step
+(smpc_plan_step, both kernels) that reads the joint state and nominal sequence the
+previous period left on the device, executes u*_0 for one period and shifts the
+nominal sequence (receding horizon).  The grids of consecutive periods (built on
+the device from the scene's occupancy) and the disturbances cycle through pools of
+distinct device buffers.
 
 Printed: one JSON line with rollout-steps/s (K*H per second) from back-to-back
-steps, per-step latency percentiles (each step synchronised on its own), the
-rollout-cost kernel's duration against the FP32 VALU peak, and the FP64 oracle's
-rate on the host cores (one full plan step).
+periods, per-period latency percentiles (each period synchronised on its own), the
+rollout-cost kernel's duration against the FP32 VALU peak (and the L2 side when its
+counters match the sources), the same plan steps on one static grid, and the FP64
+oracle's closed loop on one host thread.
 """
 from __future__ import annotations
 
@@ -53,6 +58,23 @@ OGM_TRAFFIC = {"sources_sha256": "578bcf58ccf36d0e8adf0b931f77c1100deab1a3f38558
                "write_kib": 1200.5 + 39062.5, "write_scale": 1.0}
 
 
+# L2 requests of one rollout-cost launch on the default workload (rocprofv3 --pmc
+# TCC_REQ_sum, per dispatch), taken on the kernel sources named by the hash.  The L2
+# side of the roofline counts 128 B per request against the L2 peak of
+# PEAK_L2_GBPS: 8 XCDs x 16 channels x 128 B per clock x 2.4 GHz.
+ROLLOUT_L2 = {"sources_sha256": "", "tcc_req": 0.0}
+PEAK_L2_GBPS = 8 * 16 * 128 * 2.4
+
+
+def rollout_l2(k1_ms):
+    if not ROLLOUT_L2["sources_sha256"] or ROLLOUT_L2["sources_sha256"] != kernel_sources_sha256():
+        return None
+    gbs = ROLLOUT_L2["tcc_req"] * 128.0 / (k1_ms * 1e-3) / 1e9
+    return {"achieved": round(gbs, 1), "peak": round(PEAK_L2_GBPS, 1), "unit": "GB/s",
+            "frac": round(gbs / PEAK_L2_GBPS, 4), "requests_per_launch": ROLLOUT_L2["tcc_req"],
+            "bytes_per_request": 128}
+
+
 def kernel_sources_sha256() -> str:
     import hashlib
     h = hashlib.sha256()
@@ -80,6 +102,10 @@ def parse_args():
     ap.add_argument("--latency-steps", type=int, default=300)
     ap.add_argument("--profile-steps", type=int, default=200)
     ap.add_argument("--pool", type=int, default=16, help="distinct noise buffers cycled")
+    ap.add_argument("--grids", type=int, default=16,
+                    help="distinct consecutive-period grids cycled by the closed loop")
+    ap.add_argument("--static-steps", type=int, default=200,
+                    help="extra figure: plan steps on one grid with its bounds built once")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-coarse", action="store_true",
                     help="plan without the coarse lower bounds of the grid")
@@ -566,20 +592,54 @@ def variants_bench(args) -> None:
     }), flush=True)
 
 
-def cpu_baseline(sc, grid, noise, K, H):
-    """Time the FP64 oracle on one full plan step of the same workload, one thread."""
+def cpu_baseline(sc, grids_np, noises_np, K, H, periods):
+    """The FP64 oracle's closed loop on the host: ``periods`` control periods of the
+    same scene (plan step, execution of u*_0, shift), one thread."""
     from threadpoolctl import threadpool_limits
 
     from oracle import smpc_oracle as O
-    inp = sc.inputs(grid=grid)
+    rob = sc.robot.rounded_f32()
+    q, qd = sc.q0.astype(np.float64), sc.qd0.astype(np.float64)
+    U = np.zeros((H, 7))
+    t_sc = sc.t
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        O.plan_step(inp.robot.rounded_f32(), inp.q0, inp.qd0, inp.T_goal, grid, inp.origin,
-                    inp.voxel, noise, inp.U_bar, inp.dt, inp.lam, inp.weights)
+        for i in range(periods):
+            ref = O.plan_step(rob, q, qd, sc.target(), grids_np[i], sc.origin,
+                              np.float32(sc.VOXEL), noises_np[i], U, np.float32(sc.DT), 1.0,
+                              sc.weights)
+            q, qd = O.execute_first_control(q, qd, ref["U_star"], np.float32(sc.DT))
+            U = O.shift_nominal(ref["U_star"])
+            sc.t += sc.DT
         dt = time.perf_counter() - t0
-    return {"value": K * H / dt, "unit": "rollout-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"one full plan step (K={K}, H={H}) of the same scene, float64 numpy, "
-                      f"{dt:.2f} s on one host thread"}
+    sc.t = t_sc
+    return {"value": round(periods * K * H / dt, 1), "unit": "rollout-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{periods} closed-loop periods (K={K}, H={H}) of the same scene on its "
+                      f"first grids, float64 numpy, {dt:.2f} s on one host thread"}
+
+
+def build_grid_pool(S, sc, n_grids, dev, stream):
+    """Signed distance grids of consecutive control periods of the scene: occupancy on
+    the host, the exact field on the device (smpc_edt), resident in HBM."""
+    import torch
+    n = sc.N
+    need = S.smpc_edt_workspace_bytes(n, n, n)
+    work = torch.empty((need + 3) // 4, dtype=torch.int32, device=dev)
+    occs, grids = [], []
+    for _ in range(n_grids):
+        occ = torch.from_numpy(sc.occupancy().astype(np.uint8)).to(dev)
+        phi = torch.empty((n, n, n), device=dev)
+        st = S.smpc_edt(occ.data_ptr(), n, n, n, sc.VOXEL, phi.data_ptr(), None, work.data_ptr(),
+                        need, stream)
+        if st != S.SMPC_OK:
+            raise S.SMPCError(st, "smpc_edt")
+        occs.append(occ)
+        grids.append(phi)
+        sc.advance()
+    torch.cuda.synchronize()
+    del occs, work
+    return grids
 
 
 def main():
@@ -603,60 +663,74 @@ def main():
     if args.variants:
         variants_bench(args)
         return
+    import ctypes
+
     import torch
 
     from paper_2512_22575_amd import smpc as S
     from synth import workload as W
 
-    K, H = args.K, args.H
-    sc = W.ReactiveScenario(seed=3, K=K, H=H, n=args.n)
-    grid_np = sc.grid()
+    K, H, n = args.K, args.H, args.n
+    sc = W.ReactiveScenario(seed=3, K=K, H=H, n=n)
     dev = torch.device("cuda:0")
-    grid = torch.from_numpy(grid_np).to(dev)
-    stream0 = torch.cuda.current_stream(dev).cuda_stream
-    coarse = None
-    coarse_ms = None
-    if not args.no_coarse:
-        # Coarse lower bounds of the grid: built once per grid, like the grid itself.
-        coarse = torch.empty(S.smpc_grid_coarse_cells(args.n, args.n, args.n), device=dev)
-        for rep in range(4):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            st = S.smpc_grid_coarse_min(grid, S.GRID_F32, coarse.data_ptr(), stream0)
-            e1.record()
-            torch.cuda.synchronize()
-            if st != S.SMPC_OK:
-                raise S.SMPCError(st, "smpc_grid_coarse_min")
-            coarse_ms = e0.elapsed_time(e1)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    lib = S.load_library()
+    t_setup = time.perf_counter()
+    n_grids = max(1, args.grids)
+    grids = build_grid_pool(S, sc, n_grids, dev, stream)
+    sc.t = 0.0
     n_pool = max(1, args.pool)
     noise_np = [sc.noise() for _ in range(n_pool)]
     noise = [torch.from_numpy(x).to(dev) for x in noise_np]
-    U = [torch.zeros((H, 7), device=dev), torch.zeros((H, 7), device=dev)]
+    t_setup = time.perf_counter() - t_setup
+    use_coarse = not args.no_coarse
+    coarse = torch.empty(S.smpc_grid_coarse_cells(n, n, n), device=dev) if use_coarse else None
     costs = torch.empty((K,), device=dev)
     stats = torch.empty((4,), device=dev)
     planner = S.Planner(sc.robot, device=0)
     ctx = planner._ctx
-    stream = torch.cuda.current_stream(dev).cuda_stream
+    # Closed loop on the device: two nominal sequences and two joint states alternate.
+    U = [torch.zeros((H, 7), device=dev), torch.zeros((H, 7), device=dev)]
+    X0 = torch.from_numpy(np.concatenate([sc.q0, sc.qd0]).astype(np.float32)).to(dev)
+    X = [X0.clone(), torch.zeros_like(X0)]
+    u0 = torch.zeros((7,), device=dev)
+    u0_host = torch.zeros((7,), pin_memory=True)
 
     total = args.warmup + args.steps + args.latency_steps + args.profile_steps
-    plan = []
+    plans, grid_structs = [], []
     for i in range(total):
-        plan.append(S.plan_args(sc.q0, sc.qd0, sc.target(), grid, sc.origin, sc.VOXEL,
-                                noise[i % n_pool], U[i % 2], U[(i + 1) % 2], K, H, sc.DT, 1.0,
-                                sc.weights, costs_out=costs, stats_out=stats, coarse=coarse))
+        g = grids[i % n_grids]
+        plans.append(S.plan_args(sc.q0, sc.qd0, sc.target(), g, sc.origin, sc.VOXEL,
+                                 noise[i % n_pool], U[i % 2], U[(i + 1) % 2], K, H, sc.DT, 1.0,
+                                 sc.weights, costs_out=costs, stats_out=stats, coarse=coarse,
+                                 receding=True, u0_out=u0, state_in=X[i % 2],
+                                 state_out=X[(i + 1) % 2]))
         sc.t += sc.DT
+    for g in grids:
+        grid_structs.append(S.smpc_grid(ctypes.c_void_p(g.data_ptr()), n, n, n, S.GRID_F32,
+                                        (ctypes.c_float * 3)(0.0, 0.0, 0.0), 1.0, None))
+    plan_ptrs = [ctypes.byref(a) for a in plans]
+    grid_ptrs = [ctypes.byref(g) for g in grid_structs]
+    coarse_ptr = ctypes.c_void_p(coarse.data_ptr() if use_coarse else 0)
+    sp = ctypes.c_void_p(stream)
 
-    def step(i):
-        st = S.smpc_plan_step(ctx, plan[i], stream)
+    def period(i):
+        """One control period on a fresh grid: bounds of the new grid, then the plan step
+        (which executes u*_0 and shifts the nominal sequence on the device)."""
+        if use_coarse:
+            st = lib.smpc_grid_coarse_min(grid_ptrs[i % n_grids], coarse_ptr, sp)
+            if st != S.SMPC_OK:
+                raise S.SMPCError(st, "smpc_grid_coarse_min")
+        st = lib.smpc_plan_step(ctx, plan_ptrs[i], sp)
         if st != S.SMPC_OK:
             raise S.SMPCError(st, S.smpc_last_error(ctx))
 
     # Warm-up (untimed).
     for i in range(args.warmup):
-        step(i)
+        period(i)
     torch.cuda.synchronize()
 
-    # Throughput: K steps back to back on one stream.
+    # Throughput: periods back to back on one stream.
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     base = args.warmup
@@ -664,7 +738,7 @@ def main():
     t0 = time.perf_counter()
     ev0.record()
     for i in range(base, base + args.steps):
-        step(i)
+        period(i)
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -673,8 +747,12 @@ def main():
     s = stats.cpu().numpy()
     if s[3] != 0.0:
         raise RuntimeError(f"plan step reported status {s[3]}")
+    x_end = X[(base + args.steps) % 2].cpu().numpy()
+    if not np.all(np.isfinite(x_end)):
+        raise RuntimeError("closed-loop state is not finite")
 
-    # Latency: each step alone (device time between events, host time to completion).
+    # Latency: each period alone, with u*_0 copied to pinned host memory (device time
+    # between events; host time from the first call to u*_0 on the host).
     base += args.steps
     lat_dev, lat_host = [], []
     for i in range(base, base + args.latency_steps):
@@ -682,7 +760,8 @@ def main():
         b = torch.cuda.Event(enable_timing=True)
         h0 = time.perf_counter()
         a.record()
-        step(i)
+        period(i)
+        u0_host.copy_(u0, non_blocking=True)
         b.record()
         b.synchronize()
         lat_host.append((time.perf_counter() - h0) * 1e3)
@@ -690,18 +769,61 @@ def main():
     lat_dev = np.array(lat_dev)
     lat_host = np.array(lat_host)
 
-    # Per-kernel durations from events recorded by the library on the launch stream.
+    # Per-kernel durations from events recorded by the library on the launch stream;
+    # the bounds build between events of its own.
     base += args.latency_steps
     planner.profile_enable(args.profile_steps)
+    cb = []
     for i in range(base, base + args.profile_steps):
-        step(i)
+        if use_coarse:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            st = lib.smpc_grid_coarse_min(grid_ptrs[i % n_grids], coarse_ptr, sp)
+            e1.record()
+            cb.append((e0, e1))
+        st = lib.smpc_plan_step(ctx, plan_ptrs[i], sp)
+        if st != S.SMPC_OK:
+            raise S.SMPCError(st, S.smpc_last_error(ctx))
     torch.cuda.synchronize()
     k1_ms, k2_ms = planner.profile_read(args.profile_steps)
     planner.profile_enable(0)
+    coarse_ms = float(np.mean([a.elapsed_time(b) for a, b in cb])) if cb else 0.0
     k1_avg = float(np.mean(k1_ms))
     flop = FLOP_PER_ROLLOUT_STEP * K * H
     achieved = flop / (k1_avg * 1e-3) / 1e12
     gather_gbs = GATHER_BYTES_PER_ROLLOUT_STEP * K * H / (k1_avg * 1e-3) / 1e9
+
+    # The same plan steps on one static grid whose bounds are built once (cache-warm).
+    static = None
+    if args.static_steps > 0:
+        g0 = grids[0]
+        c0 = None
+        if use_coarse:
+            c0 = torch.empty_like(coarse)
+            st = lib.smpc_grid_coarse_min(grid_ptrs[0], ctypes.c_void_p(c0.data_ptr()), sp)
+            if st != S.SMPC_OK:
+                raise S.SMPCError(st, "smpc_grid_coarse_min")
+        splans = [S.plan_args(sc.q0, sc.qd0, plans[i].T_goal, g0, sc.origin, sc.VOXEL,
+                              noise[i % n_pool], U[i % 2], U[(i + 1) % 2], K, H, sc.DT, 1.0,
+                              sc.weights, costs_out=costs, stats_out=stats, coarse=c0,
+                              receding=True, u0_out=u0, state_in=X[i % 2],
+                              state_out=X[(i + 1) % 2])
+                  for i in range(args.warmup + args.static_steps)]
+        for i in range(args.warmup):
+            lib.smpc_plan_step(ctx, ctypes.byref(splans[i]), sp)
+        torch.cuda.synchronize()
+        ev0.record()
+        for i in range(args.warmup, args.warmup + args.static_steps):
+            st = lib.smpc_plan_step(ctx, ctypes.byref(splans[i]), sp)
+            if st != S.SMPC_OK:
+                raise S.SMPCError(st, S.smpc_last_error(ctx))
+        ev1.record()
+        torch.cuda.synchronize()
+        sms = ev0.elapsed_time(ev1) / args.static_steps
+        static = {"ms_per_step": round(sms, 6), "rollout_steps_per_s": round(K * H / (sms * 1e-3), 1),
+                  "steps": args.static_steps,
+                  "what": "plan steps (receding, state on the device) on one grid whose bounds "
+                          "are built once, outside the timed region"}
 
     out = {
         "metric": METRIC,
@@ -717,14 +839,19 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"reactive replanning plan step: K={K} rollouts x H={H} steps, "
-                        f"dt=0.02 s, {args.n}^3 f32 ESDF at 0.01 m from 40 primitives, "
-                        f"7-DoF arm, 28 spheres, {sc.robot.n_pairs} self pairs",
-            "K": K, "H": H, "grid": [args.n] * 3, "voxel_m": 0.01, "lambda": 1.0,
-            "noise": "pre-sampled device buffers (float32)",
-            "coarse_bounds": None if coarse is None else
-            f"8^3-cell lower bounds of the grid, built once per grid in {coarse_ms:.4f} ms "
-            "(outside the timed region, like the grid)",
+            "workload": f"reactive replanning closed loop, fresh grid per period: K={K} "
+                        f"rollouts x H={H} steps, dt=0.02 s, {n}^3 f32 ESDF at 0.01 m from 40 "
+                        f"primitives drifting 0.2 m/s, target on a 0.3 m circle, 7-DoF arm, "
+                        f"28 spheres, {sc.robot.n_pairs} self pairs",
+            "K": K, "H": H, "grid": [n] * 3, "voxel_m": 0.01, "lambda": 1.0,
+            "period": ("coarse bounds of the period's grid + plan step that executes u*_0 and "
+                       "shifts the nominal sequence on the device" if use_coarse else
+                       "plan step that executes u*_0 and shifts the nominal sequence on the "
+                       "device (no coarse bounds)"),
+            "grids": f"{n_grids} distinct consecutive-period grids resident in HBM "
+                     f"({n_grids * n ** 3 * 4 / 2 ** 20:.0f} MiB), cycled",
+            "noise": f"{n_pool} pre-sampled device buffers (float32), cycled",
+            "setup_s": round(t_setup, 1),
         },
         "latency_ms": {
             "p50": round(float(np.percentile(lat_dev, 50)), 5),
@@ -733,9 +860,12 @@ def main():
             "host_p50": round(float(np.percentile(lat_host, 50)), 5),
             "host_p99": round(float(np.percentile(lat_host, 99)), 5),
             "steps": int(args.latency_steps),
+            "what": "one period alone on the device (events), and on the host until u*_0 "
+                    "is in host memory",
         },
         "host_ms_per_step": round(wall * 1e3 / args.steps, 5),
-        "kernels_ms": {"rollout_cost": round(k1_avg, 6),
+        "kernels_ms": {"coarse_bounds": round(coarse_ms, 6),
+                       "rollout_cost": round(k1_avg, 6),
                        "merge": round(float(np.mean(k2_ms)), 6)},
         "roofline": {
             "bound": "alu",
@@ -748,11 +878,18 @@ def main():
             "flop_per_launch": flop,
             "gather_GBps": round(gather_gbs, 1),
         },
+        "static_grid": static,
         "paper_context": "5.322 ms per replanning iteration at M=512 on an RTX 3090 "
                          "(H not stated); not the same workload",
     }
+    l2 = rollout_l2(k1_avg)
+    if l2 is not None:
+        out["roofline"]["l2"] = l2
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sc, grid_np, noise_np[0], K, H)
+        sc2 = W.ReactiveScenario(seed=3, K=K, H=H, n=n)
+        periods = 2
+        grids_np = [g.cpu().numpy() for g in grids[:periods]]
+        out["cpu_baseline"] = cpu_baseline(sc2, grids_np, noise_np, K, H, periods)
     print(json.dumps(out), flush=True)
     planner.close()
 

@@ -142,13 +142,26 @@ typedef struct {
  *   dt        : control period (s), finite and > 0.
  *   lambda    : temperature of eq. 29, finite and > 0.
  *   U_in      : device float [H][7], nominal sequence Ubar.
- *   U_out     : device float [H][7], receives U*; may alias U_in.
+ *   U_out     : device float [H][7], receives U*; may alias U_in (not when receding).
  *   costs_out : device float [K] receiving S^(m), or NULL.
  *   weights_out: device float [K] receiving w^(m), or NULL.
  *   stats_out : device float [4] receiving {S_min, Z, ESS, status}, or NULL;
  *               status is 0, or SMPC_E_NUMERIC when every cost is non-finite (then
  *               U_out = U_in and the weights are 0).  Z = sum_m exp(-(S-S_min)/lambda),
  *               ESS = 1 / sum_m w^2.
+ * Receding-horizon execution (Sec. IV-C, last paragraph: the first control of U* is
+ * applied for one period and the rest warm-starts the next period; Algorithm 1
+ * starts the nominal sequence from zero, so the control shifted in last is 0):
+ *   receding  : 0: U_out receives U*.  1: U_out receives [u*_1 .. u*_{H-1}, 0], the
+ *               nominal sequence of the next period; U_out must then not overlap U_in.
+ *   u0_out    : device float [7] receiving u*_0, or NULL.
+ *   state_in  : device float [14] holding (q0, qd0), or NULL to use q0 and qd0 above.
+ *               Lets a loop keep its state on the device with no host round trip.
+ *   state_out : device float [14] receiving the state one period dt later when u*_0
+ *               is applied with the rollouts' integrator: qd' = qd0 + u*_0 dt,
+ *               q' = q0 + qd' dt; or NULL.
+ *   No output (u0_out, state_out) may overlap an input (U_in, state_in).  When no
+ *   cost is finite u*_0 = ubar_0 is executed.
  * All work is enqueued on `stream` (a hipStream_t; NULL = default stream) and the
  * call returns without waiting for it.
  */
@@ -170,6 +183,10 @@ typedef struct {
   float* costs_out;
   float* weights_out;
   float* stats_out;
+  int32_t receding;
+  float* u0_out;
+  const float* state_in;
+  float* state_out;
 } smpc_plan_args;
 
 /* Create a context on HIP device `hip_device`.  *out receives the handle. */

@@ -96,11 +96,13 @@ struct Request {
   float* costs_out;            // device [K] or null
   float* weights_out;          // device [K] or null
   float* stats_out;            // device [4] or null
-  float* u0_out;               // device [7] or null (shift_out only)
+  float* u0_out;               // device [7] or null: receives u*_0
+  const float* state_in;       // device [14] (q0, qd0), or null: p.q0 and p.qd0
+  float* state_out;            // device [14] or null: state after executing u*_0 for dt
   Workspace ws;
   int32_t k1_begin;            // first rollout-cost block of this request in a batch
   int32_t k2_begin;            // first merge block of this request in a batch
-  int32_t shift_out;           // 1: U_out = [u*_1 .. u*_{H-1}, 0] and u0_out = u*_0
+  int32_t shift_out;           // 1: U_out = [u*_1 .. u*_{H-1}, 0] (receding horizon)
   int32_t c0_in_ws;            // 1: an extra rollout-launch block leaves c0 in ws.c0
 };
 

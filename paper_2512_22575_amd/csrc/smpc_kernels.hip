@@ -355,13 +355,15 @@ __device__ __forceinline__ Frame fk_spheres(const DevRobot* __restrict__ rob, co
   return T;
 }
 
-// Position / velocity limits (eq. 22) and null-space term (eq. 24) of one state.
-__device__ __forceinline__ float state_limit_cost(const StepParams& p, const float (&dq)[kNdof],
+// Position / velocity limits (eq. 22) and null-space term (eq. 24) of one state
+// q0 + dq, qd.
+__device__ __forceinline__ float state_limit_cost(const StepParams& p, const float (&q0)[kNdof],
+                                                  const float (&dq)[kNdof],
                                                   const float (&qd)[kNdof]) {
   float c_q = 0.f, c_qd = 0.f, c_ns = 0.f;
 #pragma unroll
   for (int j = 0; j < kNdof; ++j) {
-    const float q = p.q0[j] + dq[j];
+    const float q = q0[j] + dq[j];
     const float vq = limit_violation(q, p.qlo[j], p.qhi[j]);
     const float vqd = limit_violation(qd[j], p.qdlo[j], p.qdhi[j]);
     const float e = q - p.qref[j];
@@ -373,11 +375,13 @@ __device__ __forceinline__ float state_limit_cost(const StepParams& p, const flo
 }
 
 // Cost charged by thread (m, k): control terms of u_k and state terms of state k+1.
-//   dq, qd : q_{k+1} - q0 and qd_{k+1};  u : u_k;  sc0 : sin(q0) then cos(q0) (LDS).
+//   q0 : start positions (wave-uniform);  dq, qd : q_{k+1} - q0 and qd_{k+1};  u : u_k;
+//   sc0 : sin(q0) then cos(q0) (LDS).
 template <int kElemBytes>
 __device__ __forceinline__ float step_cost(const DevRobot* __restrict__ rob, const StepParams& p,
                                            __amdgpu_buffer_rsrc_t rsrc,
                                            __amdgpu_buffer_rsrc_t crsrc, const float* sc0,
+                                           const float (&q0)[kNdof],
                                            const float (&dq)[kNdof], const float (&qd)[kNdof],
                                            const float (&u)[kNdof], bool terminal) {
   // Smoothness (eq. 23) and acceleration limit (eq. 22) on u_k.
@@ -389,7 +393,7 @@ __device__ __forceinline__ float step_cost(const DevRobot* __restrict__ rob, con
     c_ulim = fmaf(v, v, c_ulim);
   }
   float cost = fmaf(p.w_smooth, c_u2, p.w_qdd * c_ulim);
-  if (!terminal) cost += state_limit_cost(p, dq, qd);
+  if (!terminal) cost += state_limit_cost(p, q0, dq, qd);
 
   float px[kSlots], py[kSlots], pz[kSlots];
   const Frame T = fk_spheres(rob, sc0, dq, px, py, pz);
@@ -485,7 +489,8 @@ __device__ __forceinline__ float step_cost(const DevRobot* __restrict__ rob, con
 // block.  Every thread of the block must call this; all get the value.
 template <int kElemBytes>
 __device__ __forceinline__ float state0_cost(const DevRobot* __restrict__ rob,
-                                             const StepParams& p, const void* grid) {
+                                             const StepParams& p, const void* grid,
+                                             const float* __restrict__ state_in) {
   __shared__ float centres[kSlots * 4];
   __shared__ Frame frames[kNdof];
   __shared__ float sc0[2 * kNdof];
@@ -494,17 +499,18 @@ __device__ __forceinline__ float state0_cost(const DevRobot* __restrict__ rob,
   const int tid = threadIdx.x, lane = tid & (kWave - 1), nthreads = blockDim.x;
   if (tid < kNdof) {
     float s_, c_;
-    sincosf(p.q0[tid], &s_, &c_);
+    sincosf(state_in ? state_in[tid] : p.q0[tid], &s_, &c_);
     sc0[tid] = s_;
     sc0[kNdof + tid] = c_;
   }
   __syncthreads();
   if (tid == kWave) {  // wave 0 stays free for the caller's independent loads
-    float zero[kNdof], qd0[kNdof];
+    float zero[kNdof], q0[kNdof], qd0[kNdof];
 #pragma unroll
     for (int j = 0; j < kNdof; ++j) {
       zero[j] = 0.f;
-      qd0[j] = p.qd0[j];
+      q0[j] = state_in ? state_in[j] : p.q0[j];
+      qd0[j] = state_in ? state_in[kNdof + j] : p.qd0[j];
     }
     Frame T = identity_frame();
 #pragma unroll
@@ -512,7 +518,7 @@ __device__ __forceinline__ float state0_cost(const DevRobot* __restrict__ rob,
       mdh_step(T, rob->ca[i], rob->sa[i], rob->a[i], rob->d[i], sc0[kNdof + i], sc0[i]);
       frames[i] = T;
     }
-    pose0 = pose_cost(T, p, p.w_pose_t, p.w_pose_r) + state_limit_cost(p, zero, qd0);
+    pose0 = pose_cost(T, p, p.w_pose_t, p.w_pose_r) + state_limit_cost(p, q0, zero, qd0);
   }
   __syncthreads();
   if (tid < kSlots) {
@@ -561,6 +567,7 @@ struct K1Lds {
   float* ubar;   // [H*7]
   float* cost;   // [R*H]
   float* sc0;    // [16]     sin(q0), cos(q0)
+  float* x0;     // [16]     q0, qd0
   float* e;      // [R]      exp(-(S - m_b)/lambda)
   float* seg;    // [R*7*nseg*2] velocity / displacement increments of 8-step segments
 };
@@ -578,7 +585,8 @@ __device__ __forceinline__ K1Lds k1_lds(unsigned char* base, int R, int H) {
   L.ubar = L.qd + rh7;
   L.cost = L.ubar + H * kNdof;
   L.sc0 = L.cost + R * H;
-  L.e = L.sc0 + 16;
+  L.x0 = L.sc0 + 16;
+  L.e = L.x0 + 16;
   L.seg = L.e + R;
   return L;
 }
@@ -631,11 +639,16 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
     }
   }
   for (int i = tid; i < H * kNdof; i += nthreads) L.ubar[i] = U_in[i];
-  if (tid < kNdof) {
-    float s, c;
-    sincosf(p.q0[tid], &s, &c);
-    L.sc0[tid] = s;
-    L.sc0[kNdof + tid] = c;
+  // Start state (q0, qd0): read from the device when the request carries it there.
+  if (tid < 2 * kNdof) {
+    const float x = q.state_in ? q.state_in[tid] : (tid < kNdof ? p.q0[tid] : p.qd0[tid - kNdof]);
+    L.x0[tid] = x;
+    if (tid < kNdof) {
+      float s, c;
+      sincosf(x, &s, &c);
+      L.sc0[tid] = s;
+      L.sc0[kNdof + tid] = c;
+    }
   }
   __syncthreads();
 
@@ -650,7 +663,7 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
   for (int w = tid; w < n_items; w += nthreads) {
     const int sg = w % nseg, rj = w / nseg, r = rj / kNdof, j = rj - r * kNdof;
     if (r < nroll) {
-      const float dt = p.dt, qd0 = p.qd0[j];
+      const float dt = p.dt, qd0 = L.x0[kNdof + j];
       const int k0 = sg * kSeg;
       const float* eps_r = L.eps + r * H * kNdof + j;
       float u[kSeg];
@@ -675,7 +688,7 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
   for (int w = tid; w < n_items; w += nthreads) {
     const int sg = w % nseg, rj = w / nseg, r = rj / kNdof, j = rj - r * kNdof;
     if (r < nroll) {
-      const float dt = p.dt, qd0 = p.qd0[j];
+      const float dt = p.dt, qd0 = L.x0[kNdof + j];
       const int k0 = sg * kSeg;
       const float* eps_r = L.eps + r * H * kNdof + j;
       float u[kSeg];
@@ -721,9 +734,14 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
         qd[j] = L.qd[base + j];
         u[j] = L.ubar[k * kNdof + j] + L.eps[base + j];
       }
+      float q0[kNdof];  // wave-uniform: moved to scalar registers
+#pragma unroll
+      for (int j = 0; j < kNdof; ++j)
+        q0[j] = __builtin_bit_cast(
+            float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, L.x0[j])));
       const __amdgpu_buffer_rsrc_t rsrc = grid_resource(q.grid, p.grid_bytes);
       const __amdgpu_buffer_rsrc_t crsrc = grid_resource(q.coarse, p.coarse_bytes);
-      cost = step_cost<kElemBytes>(rob, p, rsrc, crsrc, L.sc0, dq, qd, u, k == H - 1);
+      cost = step_cost<kElemBytes>(rob, p, rsrc, crsrc, L.sc0, q0, dq, qd, u, k == H - 1);
     }
     L.cost[tid] = cost;
   }
@@ -803,7 +821,7 @@ __global__ __launch_bounds__(kK1Threads) __attribute__((amdgpu_waves_per_eu(4)))
 rollout_cost_kernel(const DevRobot* __restrict__ rob, const Request q) {
   if ((int)blockIdx.x == q.p.P) {
     // One extra block evaluates the state-0 terms while the rollout blocks run.
-    const float c0 = state0_cost<kElemBytes>(rob, q.p, q.grid);
+    const float c0 = state0_cost<kElemBytes>(rob, q.p, q.grid, q.state_in);
     if (threadIdx.x == 0) q.ws.c0[0] = c0;
     return;
   }
@@ -939,7 +957,7 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
 #pragma unroll
       for (int c = 0; c < kCostsAhead; ++c) sv0[c] = ws.S[min(tid + kK2Threads * c, K - 1)];
     }
-    const float c0 = q.c0_in_ws ? ws.c0[0] : state0_cost<kElemBytes>(rob, p, grid);
+    const float c0 = q.c0_in_ws ? ws.c0[0] : state0_cost<kElemBytes>(rob, p, grid, q.state_in);
     // --- costs S = S' + c0 (eq. 28) and statistics
     if (costs_out) {
 #pragma unroll
@@ -1032,15 +1050,23 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
 #pragma unroll
       for (int r = 0; r < kRowGroups; ++r) n += red[r * kOutPerBlock + oi];
       const float u = ok ? U_in[o] + n / st.Z : U_in[o];
+      if (o < kNdof) {
+        if (q.u0_out) q.u0_out[o] = u;
+        if (q.state_out) {
+          // Execute u*_0 for one period with the rollouts' integrator (eq. 7):
+          // qd' = qd0 + u*_0 dt, q' = q0 + qd' dt.
+          const float q0 = q.state_in ? q.state_in[o] : p.q0[o];
+          const float qd0 = q.state_in ? q.state_in[kNdof + o] : p.qd0[o];
+          const float qd1 = fmaf(u, p.dt, qd0);
+          q.state_out[o] = fmaf(qd1, p.dt, q0);
+          q.state_out[kNdof + o] = qd1;
+        }
+      }
       if (!q.shift_out) {
         U_out[o] = u;
       } else {
-        // Receding-horizon warm start: U_out = [u*_1 .. u*_{H-1}, 0], u0_out = u*_0.
-        if (o < kNdof) {
-          if (q.u0_out) q.u0_out[o] = u;
-        } else {
-          U_out[o - kNdof] = u;
-        }
+        // Receding-horizon warm start: U_out = [u*_1 .. u*_{H-1}, 0].
+        if (o >= kNdof) U_out[o - kNdof] = u;
         if (o >= HO - kNdof) U_out[o] = 0.f;
       }
     }
@@ -1568,7 +1594,7 @@ __global__ __launch_bounds__(256) void grid_to_f16_kernel(const float* __restric
 // ---------------------------------------------------------------------------
 
 static size_t k1_lds_bytes(int R, int H) {
-  const size_t floats = (size_t)R * H * kNdof * 3 + (size_t)H * kNdof + (size_t)R * H + 16 + R +
+  const size_t floats = (size_t)R * H * kNdof * 3 + (size_t)H * kNdof + (size_t)R * H + 32 + R +
                         (size_t)R * kNdof * k1_segments(H) * 2;
   return floats * 4;
 }

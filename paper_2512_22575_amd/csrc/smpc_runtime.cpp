@@ -7,6 +7,7 @@
 
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -59,6 +60,13 @@ bool finite_all(const float* x, int n) {
   for (int i = 0; i < n; ++i)
     if (!std::isfinite(x[i])) return false;
   return true;
+}
+
+// Two device byte ranges [a, a + na) and [b, b + nb) share a byte (NULL: never).
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+  if (!a || !b) return false;
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return x < y + nb && y < x + na;
 }
 
 bool finite_all(const double* x, int n) {
@@ -167,6 +175,15 @@ smpc_status validate_args(smpc_ctx* ctx, const smpc_plan_args* a) {
   if (!finite_all(g.origin, 3) || !std::isfinite(g.voxel) || !(g.voxel > 0.f))
     return fail(ctx, SMPC_E_INVALID_ARG, "grid origin/voxel must be finite, voxel > 0");
   if (!a->U_in || !a->U_out) return fail(ctx, SMPC_E_INVALID_ARG, "U_in/U_out is NULL");
+  if (a->receding != 0 && a->receding != 1)
+    return fail(ctx, SMPC_E_INVALID_ARG, "receding must be 0 or 1");
+  const size_t ub = (size_t)a->H * kNdof * sizeof(float), sb = 2 * kNdof * sizeof(float);
+  if (a->receding && overlaps(a->U_out, ub, a->U_in, ub))
+    return fail(ctx, SMPC_E_INVALID_ARG, "receding: U_out overlaps U_in");
+  if (overlaps(a->u0_out, kNdof * sizeof(float), a->U_in, ub) ||
+      overlaps(a->u0_out, kNdof * sizeof(float), a->state_in, sb) ||
+      overlaps(a->state_out, sb, a->U_in, ub) || overlaps(a->state_out, sb, a->state_in, sb))
+    return fail(ctx, SMPC_E_INVALID_ARG, "u0_out/state_out overlaps an input");
   if (!a->noise) {
     for (int j = 0; j < kNdof; ++j)
       if (!std::isfinite(a->sigma[j]) || a->sigma[j] < 0.f)
@@ -459,6 +476,10 @@ smpc_status smpc_plan_step(smpc_ctx* ctx, const smpc_plan_args* a, void* stream)
   q.costs_out = a->costs_out;
   q.weights_out = a->weights_out;
   q.stats_out = a->stats_out;
+  q.u0_out = a->u0_out;
+  q.state_in = a->state_in;
+  q.state_out = a->state_out;
+  q.shift_out = a->receding;
   q.ws = ws;
   q.c0_in_ws = (a->costs_out || a->stats_out) ? 1 : 0;
   const int e = launch_plan_step(ctx->dev_robot, q, lc, a->esdf.dtype == SMPC_GRID_F16, stream, ev);

@@ -82,6 +82,8 @@ class smpc_plan_args(ctypes.Structure):
         ("weights", smpc_cost_weights),
         ("U_in", c_void_p), ("U_out", c_void_p),
         ("costs_out", c_void_p), ("weights_out", c_void_p), ("stats_out", c_void_p),
+        ("receding", c_int32),
+        ("u0_out", c_void_p), ("state_in", c_void_p), ("state_out", c_void_p),
     ]
 
 
@@ -324,7 +326,8 @@ def _ptr(t) -> int:
 
 def plan_args(q0, qd0, T_goal, grid, origin, voxel, noise, U_in, U_out, K, H, dt, lam,
               weights: dict, costs_out=None, weights_out=None, stats_out=None, seed: int = 0,
-              sigma=None, grid_dtype: int = GRID_F32, coarse=None) -> smpc_plan_args:
+              sigma=None, grid_dtype: int = GRID_F32, coarse=None, receding: bool = False,
+              u0_out=None, state_in=None, state_out=None) -> smpc_plan_args:
     """Build smpc_plan_args; tensors are torch tensors on the device (or None)."""
     a = smpc_plan_args()
     a.q0[:] = [float(x) for x in np.asarray(q0, np.float32)]
@@ -342,6 +345,8 @@ def plan_args(q0, qd0, T_goal, grid, origin, voxel, noise, U_in, U_out, K, H, dt
     a.weights = cost_weights(weights)
     a.U_in, a.U_out = _ptr(U_in), _ptr(U_out)
     a.costs_out, a.weights_out, a.stats_out = _ptr(costs_out), _ptr(weights_out), _ptr(stats_out)
+    a.receding = 1 if receding else 0
+    a.u0_out, a.state_in, a.state_out = _ptr(u0_out), _ptr(state_in), _ptr(state_out)
     return a
 
 
@@ -389,7 +394,8 @@ class Planner:
     def plan_step(self, *, q0, qd0, T_goal, grid, origin, voxel, noise, U_in, U_out, dt, lam,
                   weights, costs_out=None, weights_out=None, stats_out=None, stream=None,
                   seed: int = 0, sigma=None, grid_dtype: int = GRID_F32, K=None, H=None,
-                  coarse=None) -> None:
+                  coarse=None, receding: bool = False, u0_out=None, state_in=None,
+                  state_out=None) -> None:
         """Enqueue one plan step on ``stream`` (default: torch's current stream)."""
         import torch
         if noise is not None:
@@ -400,7 +406,7 @@ class Planner:
             stream = torch.cuda.current_stream(self.device).cuda_stream
         a = plan_args(q0, qd0, T_goal, grid, origin, voxel, noise, U_in, U_out, K, H, dt, lam,
                       weights, costs_out, weights_out, stats_out, seed, sigma, grid_dtype,
-                      coarse)
+                      coarse, receding, u0_out, state_in, state_out)
         st = smpc_plan_step(self._ctx, a, stream)
         if st != SMPC_OK:
             raise SMPCError(st, smpc_last_error(self._ctx))
@@ -418,6 +424,64 @@ class Planner:
                              work.numel() * work.element_size(), stream)
         if st != SMPC_OK:
             raise SMPCError(st, smpc_last_error(self._ctx))
+
+
+class RecedingHorizon:
+    """Closed-loop plan steps of one controller with its state on the device.
+
+    Each ``step`` enqueues one plan step from the device-resident joint state and
+    nominal sequence; the library executes u*_0 for one period (the rollouts'
+    integrator) and shifts the sequence to [u*_1 .. u*_{H-1}, 0] (the receding-horizon
+    execution of the paper's Sec. IV-C), so consecutive periods need no host round
+    trip.  Two state and two sequence buffers alternate: a step reads one and writes
+    the other.  ``state``, ``U`` and ``u0`` are the current device tensors.
+    """
+
+    def __init__(self, planner: "Planner", H: int, q0, qd0, U0=None):
+        import torch
+        dev = torch.device("cuda", planner.device)
+        self.planner = planner
+        self.H = int(H)
+        self._q0 = np.asarray(q0, np.float32)
+        self._qd0 = np.asarray(qd0, np.float32)
+        self._U = [torch.zeros((self.H, NDOF), device=dev) for _ in range(2)]
+        self._X = [torch.zeros((2 * NDOF,), device=dev) for _ in range(2)]
+        self.u0 = torch.zeros((NDOF,), device=dev)
+        self._cur = 0
+        self.set_state(q0, qd0)
+        if U0 is not None:
+            self.set_nominal(U0)
+
+    @property
+    def state(self):
+        return self._X[self._cur]
+
+    @property
+    def U(self):
+        return self._U[self._cur]
+
+    def set_state(self, q, qd) -> None:
+        import torch
+        x = np.concatenate([np.asarray(q, np.float32), np.asarray(qd, np.float32)])
+        self._X[self._cur].copy_(torch.from_numpy(x))
+
+    def set_nominal(self, U) -> None:
+        import torch
+        self._U[self._cur].copy_(torch.from_numpy(np.asarray(U, np.float32).reshape(self.H, NDOF)))
+
+    def step(self, *, T_goal, grid, origin, voxel, dt, lam, weights, noise=None, seed: int = 0,
+             sigma=None, K=None, coarse=None, costs_out=None, weights_out=None, stats_out=None,
+             grid_dtype: int = GRID_F32, stream=None) -> None:
+        """Enqueue one control period on ``stream`` (default: torch's current stream)."""
+        nxt = 1 - self._cur
+        self.planner.plan_step(q0=self._q0, qd0=self._qd0, T_goal=T_goal, grid=grid,
+                               origin=origin, voxel=voxel, noise=noise, U_in=self._U[self._cur],
+                               U_out=self._U[nxt], dt=dt, lam=lam, weights=weights,
+                               costs_out=costs_out, weights_out=weights_out, stats_out=stats_out,
+                               stream=stream, seed=seed, sigma=sigma, grid_dtype=grid_dtype, K=K,
+                               H=self.H, coarse=coarse, receding=True, u0_out=self.u0,
+                               state_in=self._X[self._cur], state_out=self._X[nxt])
+        self._cur = nxt
 
 
 def is_finite_float(x) -> bool:

@@ -160,10 +160,11 @@ class ReactiveScenario:
     K, H, DT, N, VOXEL = 4096, 40, 0.02, 200, 0.01
 
     def __init__(self, seed: int = 3, K: int | None = None, H: int | None = None,
-                 n: int | None = None):
+                 n: int | None = None, voxel: float | None = None):
         self.K = K or self.K
         self.H = H or self.H
         self.N = n or self.N
+        self.VOXEL = voxel or self.VOXEL
         self.rng = np.random.default_rng(seed)
         self.robot = robot_mod.make_robot(seed)
         self.origin = f32(scene_mod.grid_origin(self.N, self.VOXEL))

@@ -52,7 +52,8 @@ int main(void) {
   F(smpc_robot_desc, sphere_center) F(smpc_robot_desc, n_pairs) F(smpc_robot_desc, pairs)
   F(smpc_plan_args, T_goal) F(smpc_plan_args, esdf) F(smpc_plan_args, noise)
   F(smpc_plan_args, seed) F(smpc_plan_args, K) F(smpc_plan_args, weights)
-  F(smpc_plan_args, U_in) F(smpc_plan_args, stats_out)
+  F(smpc_plan_args, U_in) F(smpc_plan_args, stats_out) F(smpc_plan_args, receding)
+  F(smpc_plan_args, u0_out) F(smpc_plan_args, state_in) F(smpc_plan_args, state_out)
   F(smpc_grid, nx) F(smpc_grid, origin) F(smpc_grid, voxel) F(smpc_grid, coarse)
   printf("smpc_controller_desc sizeof %zu\n", sizeof(smpc_controller_desc));
   printf("smpc_request sizeof %zu\n", sizeof(smpc_request));
@@ -203,6 +204,47 @@ def test_plan_step_requires_robot(ctx):
 def test_plan_step_rejects_invalid_arguments(ctx, over, status, msg):
     assert S.smpc_set_robot(ctx, S.robot_desc(R.make_robot(0))) == S.SMPC_OK
     _expect(ctx, _args(**over), status, msg)
+
+
+_H = W.tiny().H
+_UB = 7 * 4 * _H  # bytes of one nominal sequence
+
+
+@pytest.mark.parametrize("over,msg", [
+    # The shifted sequence is written while other blocks still read U_in.
+    (dict(receding=True), "U_out overlaps U_in"),
+    (dict(receding=True, U_out=_FakeTensor((_H, 7), ptr=0x1000 + _UB - 4)), "U_out overlaps U_in"),
+    (dict(receding=True, U_out=_FakeTensor((_H, 7), ptr=0x1000 - _UB + 4)), "U_out overlaps U_in"),
+    (dict(u0_out=_FakeTensor((7,), ptr=0x1000 + 8)), "overlaps an input"),
+    (dict(state_in=_FakeTensor((14,), ptr=0x9000), state_out=_FakeTensor((14,), ptr=0x9000 + 52)),
+     "overlaps an input"),
+    (dict(state_in=_FakeTensor((14,), ptr=0x9000), u0_out=_FakeTensor((7,), ptr=0x9000 - 24)),
+     "overlaps an input"),
+    (dict(state_out=_FakeTensor((14,), ptr=0x1000 + _UB - 8)), "overlaps an input"),
+])
+def test_receding_outputs_must_not_overlap_inputs(ctx, over, msg):
+    assert S.smpc_set_robot(ctx, S.robot_desc(R.make_robot(0))) == S.SMPC_OK
+    _expect(ctx, _args(**over), S.SMPC_E_INVALID_ARG, msg)
+
+
+def test_receding_flag_is_boolean(ctx):
+    assert S.smpc_set_robot(ctx, S.robot_desc(R.make_robot(0))) == S.SMPC_OK
+    a = _args(U_out=_FakeTensor((_H, 7), ptr=0x1000 + _UB))
+    a.receding = 2
+    _expect(ctx, a, S.SMPC_E_INVALID_ARG, "receding")
+
+
+def test_adjacent_receding_buffers_pass_validation(ctx):
+    # Touching but disjoint ranges are valid: the call gets past validation and, with
+    # no GPU, fails at the first device call.
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present; this checks the GPU-less failure path")
+    assert S.smpc_set_robot(ctx, S.robot_desc(R.make_robot(0))) == S.SMPC_OK
+    a = _args(receding=True, U_out=_FakeTensor((_H, 7), ptr=0x1000 + _UB),
+              u0_out=_FakeTensor((7,), ptr=0x1000 - 28), state_in=_FakeTensor((14,), ptr=0x9000),
+              state_out=_FakeTensor((14,), ptr=0x9000 + 56))
+    assert S.smpc_plan_step(ctx, a, None) == S.SMPC_E_DEVICE
 
 
 @pytest.mark.parametrize("field,value", [

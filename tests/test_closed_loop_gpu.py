@@ -1,0 +1,184 @@
+"""Receding-horizon closed loop on the GPU against the oracle's own chain.
+
+Sec. IV-C (last paragraph) applies the first control of U* for one period and
+warm-starts the next period with the remaining controls; Algorithm 1 starts the
+nominal sequence from zero, so the control shifted in last is zero.  The library
+does both on the device (``receding``, ``state_in``/``state_out``): each period
+reads the state and nominal sequence the previous period wrote.
+
+The oracle runs its own chain from the same seeds, grids and targets: its own U*,
+executed state and shifted sequence (float64 throughout).  Each period compares
+the costs (1e-4 relative), u*_0 and the shifted sequence (1e-5 rad/s^2 plus the
+float32 conditioning term of near-tied rollouts), and the executed state against a
+bound accumulated from the control bar.  When the conditioning term alone exceeds
+the control bar the two chains may legitimately part, and the GPU chain is
+re-seeded from the oracle's state and sequence (never the reverse).
+"""
+import numpy as np
+import pytest
+
+from oracle import smpc_oracle as O
+from synth import workload as W
+from tests.gpu_helpers import (U_ATOL, assert_costs_close, control_conditioning_tolerance)
+
+pytestmark = pytest.mark.gpu
+
+F32_EPS = 2.0 ** -23
+
+
+def _oracle_step(sc, rob64, q, qd, U_bar, grid, noise, T_goal):
+    ref = O.plan_step(rob64, q, qd, T_goal, grid, sc.origin, W.f32s(sc.VOXEL), noise, U_bar,
+                      W.f32s(sc.DT), 1.0, sc.weights)
+    ref["lam"] = 1.0
+    return ref
+
+
+@pytest.mark.parametrize("n,voxel,periods", [(100, 0.02, 20), (200, 0.01, 3)])
+def test_closed_loop_chain_matches_oracle_chain(n, voxel, periods):
+    """The reactive scene (2 m cube, drifting primitives, circling target), K = 512,
+    H = 40: fresh grid and coarse bounds every period, state and nominal sequence kept
+    on the device between periods."""
+    import torch
+
+    from paper_2512_22575_amd import smpc as S
+    sc = W.ReactiveScenario(seed=3, K=512, n=n, voxel=voxel)
+    K, H, dt = sc.K, sc.H, W.f32s(sc.DT)
+    dev = torch.device("cuda:0")
+    rob64 = sc.robot.rounded_f32()
+    planner = S.Planner(sc.robot, device=0)
+    loop = S.RecedingHorizon(planner, H, sc.q0, sc.qd0)
+    costs = torch.empty((K,), device=dev)
+    stats = torch.empty((4,), device=dev)
+    coarse = torch.empty((S.smpc_grid_coarse_cells(n, n, n),), device=dev)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+
+    q_ref = sc.q0.astype(np.float64)
+    qd_ref = sc.qd0.astype(np.float64)
+    U_ref = np.zeros((H, 7))
+    bq = bqd = 0.0          # accumulated bound on the executed-state difference
+    reseeds = 0
+    worst_u = worst_x = 0.0
+    for t in range(periods):
+        grid_np = sc.grid()
+        noise_np = sc.noise()
+        T_goal = sc.target()
+        grid = torch.from_numpy(grid_np).to(dev)
+        noise = torch.from_numpy(noise_np).to(dev)
+        assert S.smpc_grid_coarse_min(grid, S.GRID_F32, coarse.data_ptr(), stream) == S.SMPC_OK
+        print(f"period {t}: n={n} K={K} H={H}", flush=True)
+        loop.step(T_goal=T_goal, grid=grid, origin=sc.origin, voxel=sc.VOXEL, dt=dt, lam=1.0,
+                  weights=sc.weights, noise=noise, coarse=coarse, costs_out=costs,
+                  stats_out=stats)
+        torch.cuda.synchronize()
+        S_gpu = costs.cpu().numpy().astype(np.float64)
+        u0_gpu = loop.u0.cpu().numpy().astype(np.float64)
+        U_next_gpu = loop.U.cpu().numpy().astype(np.float64)
+        x_gpu = loop.state.cpu().numpy().astype(np.float64)
+        assert stats.cpu().numpy()[3] == 0.0
+
+        ref = _oracle_step(sc, rob64, q_ref, qd_ref, U_ref, grid_np, noise_np, T_goal)
+        q_next, qd_next = O.execute_first_control(q_ref, qd_ref, ref["U_star"], dt)
+        U_next = O.shift_nominal(ref["U_star"])
+
+        assert_costs_close(S_gpu, ref["S"])
+        cond = control_conditioning_tolerance(ref, noise_np)
+        tol = U_ATOL + cond
+        err0 = np.abs(u0_gpu - ref["U_star"][0])
+        assert np.all(err0 <= tol[0]), (t, float(err0.max()))
+        errU = np.abs(U_next_gpu - U_next)
+        assert np.all(U_next_gpu[-1] == 0.0)
+        assert np.all(errU[:-1] <= tol[1:]), (t, float(errU.max()))
+        # Executed state: the control bar enters through dt; one float32 rounding of
+        # each fused update on top.
+        bqd = bqd + float(np.max(tol[0])) * dt + F32_EPS * float(np.max(np.abs(qd_next))) + 1e-9
+        bq = bq + bqd * dt + F32_EPS * float(np.max(np.abs(q_next))) + 1e-9
+        ex_q = np.abs(x_gpu[:7] - q_next)
+        ex_qd = np.abs(x_gpu[7:] - qd_next)
+        assert np.all(ex_q <= bq), (t, float(ex_q.max()), bq)
+        assert np.all(ex_qd <= bqd), (t, float(ex_qd.max()), bqd)
+        worst_u = max(worst_u, float(err0.max()), float(errU.max()))
+        worst_x = max(worst_x, float(ex_q.max()), float(ex_qd.max()))
+
+        q_ref, qd_ref, U_ref = q_next, qd_next, U_next
+        if float(np.max(cond)) > U_ATOL:
+            # Near-tied rollouts: the chains may part legitimately; follow the oracle.
+            loop.set_state(q_ref, qd_ref)
+            loop.set_nominal(U_ref)
+            bq = bqd = 0.0
+            reseeds += 1
+        sc.advance()
+    print(f"closed loop n={n}: {periods} periods, worst control err {worst_u:.3g}, "
+          f"worst state err {worst_x:.3g}, re-seeds {reseeds}")
+    planner.close()
+
+
+def test_receding_outputs_by_value_and_device_state_agree():
+    """The same period with the start state passed by value and read from the device:
+    bitwise the same U*, shifted sequence, u*_0 and executed state; the executed state
+    is one semi-implicit Euler step of u*_0 (eq. 7) and the shift drops u*_0."""
+    import torch
+
+    from paper_2512_22575_amd import smpc as S
+    inp = W.tiny()
+    rng = np.random.default_rng(5)
+    inp.U_bar = W.f32(0.4 * rng.standard_normal(inp.U_bar.shape))
+    inp.qd0 = W.f32(0.2 * rng.standard_normal(7))
+    dev = torch.device("cuda:0")
+    grid = torch.from_numpy(inp.grid).to(dev)
+    noise = torch.from_numpy(inp.noise).to(dev)
+    planner = S.Planner(inp.robot, device=0)
+    U_in = torch.from_numpy(inp.U_bar).to(dev)
+
+    def run(receding, state_on_device):
+        U_out = torch.full_like(U_in, float("nan"))
+        u0 = torch.full((7,), float("nan"), device=dev)
+        x_out = torch.full((14,), float("nan"), device=dev)
+        x_in = torch.from_numpy(np.concatenate([inp.q0, inp.qd0])).to(dev) \
+            if state_on_device else None
+        q0 = np.zeros(7, np.float32) if state_on_device else inp.q0
+        qd0 = np.zeros(7, np.float32) if state_on_device else inp.qd0
+        planner.plan_step(q0=q0, qd0=qd0, T_goal=inp.T_goal, grid=grid, origin=inp.origin,
+                          voxel=inp.voxel, noise=noise, U_in=U_in, U_out=U_out, dt=inp.dt,
+                          lam=inp.lam, weights=inp.weights, receding=receding, u0_out=u0,
+                          state_in=x_in, state_out=x_out)
+        torch.cuda.synchronize()
+        return U_out.cpu().numpy(), u0.cpu().numpy(), x_out.cpu().numpy()
+
+    U_plain, u0_plain, x_plain = run(False, False)
+    U_a, u0_a, x_a = run(True, False)
+    U_b, u0_b, x_b = run(True, True)
+    np.testing.assert_array_equal(u0_plain, U_plain[0])
+    np.testing.assert_array_equal(U_a[:-1], U_plain[1:])
+    assert np.all(U_a[-1] == 0.0)
+    for x, y in ((U_a, U_b), (u0_a, u0_b), (x_a, x_b), (x_plain, x_a)):
+        np.testing.assert_array_equal(x, y)
+    q1, qd1 = O.execute_first_control(inp.q0, inp.qd0, U_plain.astype(np.float64), inp.dt)
+    np.testing.assert_allclose(x_a[7:], qd1, rtol=0, atol=4 * F32_EPS * max(1.0, np.abs(qd1).max()))
+    np.testing.assert_allclose(x_a[:7], q1, rtol=0, atol=4 * F32_EPS * max(1.0, np.abs(q1).max()))
+    ref = O.plan_step_inputs(inp)
+    assert np.max(np.abs(u0_b - ref["U_star"][0])) <= U_ATOL
+    planner.close()
+
+
+def test_receding_horizon_one_step():
+    """H = 1: the shifted sequence is the single zero control."""
+    import torch
+
+    from paper_2512_22575_amd import smpc as S
+    inp = W.make_inputs(31, K=40, H=1, dt=0.05, n=32, voxel=0.05, n_boxes=4, n_spheres=2)
+    dev = torch.device("cuda:0")
+    planner = S.Planner(inp.robot, device=0)
+    loop = S.RecedingHorizon(planner, 1, inp.q0, inp.qd0, U0=np.full((1, 7), 0.25, np.float32))
+    loop.step(T_goal=inp.T_goal, grid=torch.from_numpy(inp.grid).to(dev), origin=inp.origin,
+              voxel=inp.voxel, dt=inp.dt, lam=inp.lam, weights=inp.weights,
+              noise=torch.from_numpy(inp.noise).to(dev))
+    torch.cuda.synchronize()
+    assert np.all(loop.U.cpu().numpy() == 0.0)
+    inp.U_bar = np.full((1, 7), 0.25, np.float32)
+    ref = O.plan_step_inputs(inp)
+    assert np.max(np.abs(loop.u0.cpu().numpy() - ref["U_star"][0])) <= U_ATOL
+    q1, qd1 = O.execute_first_control(inp.q0, inp.qd0, ref["U_star"], inp.dt)
+    x = loop.state.cpu().numpy()
+    assert np.max(np.abs(x[7:] - qd1)) <= U_ATOL * inp.dt + 1e-6
+    assert np.max(np.abs(x[:7] - q1)) <= 1e-6
+    planner.close()

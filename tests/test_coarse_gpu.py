@@ -163,3 +163,39 @@ def test_served_results_identical_with_bounds():
         assert a[0] == b[0] == 0
         np.testing.assert_array_equal(a[1].view(np.uint32), b[1].view(np.uint32))
         assert (a[2], a[3]) == (b[2], b[3])
+
+
+def test_plan_step_identical_ragged_grid_spheres_outside_every_face():
+    """Sides 41 x 33 x 17 (each 1 mod 8, so the last lookup corner n - 2 sits in the
+    last cell with floor(u) = n - 1 clamped to it) and an origin that puts the grid
+    across the arm, so that rollout spheres leave it through all six faces: bounds on
+    and off give bitwise the same plan step, for float32 and float16 storage."""
+    import dataclasses
+
+    import torch
+
+    from oracle import smpc_oracle as O
+    from paper_2512_22575_amd import smpc as S
+    from synth import scene as SC
+    nx, ny, nz, voxel = 41, 33, 17, 0.012
+    origin = W.f32([-0.566, -0.098, 0.453])
+    rng = np.random.default_rng(1741)
+    lo = origin + 0.02
+    hi = origin + np.array([nx, ny, nz]) * voxel - 0.02
+    prims = SC.random_primitives(rng, lo, hi, 5, 3, speed=0.0)
+    grid = SC.signed_distance_grid(SC.occupancy(prims, (nx, ny, nz), origin, voxel), voxel)
+    assert grid.shape == (nz, ny, nx)
+    base = W.make_inputs(1741, K=384, H=24, dt=0.04, n=16, voxel=0.03, n_boxes=2, n_spheres=0)
+    inp = dataclasses.replace(base, grid=grid, origin=origin, voxel=W.f32s(voxel))
+    # Every face is crossed by some rollout sphere (oracle kinematics on the inputs).
+    rob = inp.robot.rounded_f32()
+    q = O.rollout(inp.q0, inp.qd0, inp.U_bar[None] + inp.noise, inp.dt)[0]
+    centres = O.sphere_centres(rob, O.forward_kinematics(rob, q.reshape(-1, 7)))
+    u = (centres.reshape(-1, 3) - origin) / voxel
+    ext = np.array([nx, ny, nz])
+    for ax in range(3):
+        assert (u[:, ax] < 0).any() and (u[:, ax] > ext[ax]).any(), ax
+    grid_t = torch.from_numpy(grid).cuda()
+    _check_same(inp, grid_t, S.GRID_F32)
+    g16 = np.clip(grid, -2, 2).astype(np.float16)
+    _check_same(inp, torch.from_numpy(g16.view(np.int16).copy()).cuda(), S.GRID_F16)
