@@ -1185,6 +1185,117 @@ __global__ __launch_bounds__(kCoarseThreads) void grid_coarse_min_kernel(
   }
 }
 
+// Coarse lower bounds, wide path: rows whose byte length is a multiple of 16 in a
+// 16-byte-aligned grid.  A block covers one row (cy, cz) of cells and a chunk of
+// kCoarseChunkGroups - 1 sixteen-byte groups of columns (31 cells of float32, 63 of
+// float16) plus the next group, whose first column closes the chunk's last window.
+// Thread (s, g) loads group g of rows s, s + 5, ... of the cell row's window (all
+// its loads issued at once; row and group indices are clamped instead of masked,
+// since a repeated value changes neither a minimum nor a maximum) and folds, per
+// group, the minimum and the largest |phi| (+inf for a non-finite value) of all its
+// columns and of its first column alone.  The five row subsets meet in LDS, then
+// each cell combines its groups: the window [8 cx, 8 cx + 8] is two whole groups of
+// float32 (one of float16) plus the first column of the next one, or ends at the
+// last column of the row.  Blocks are laid out by XCD (block b runs on XCD b mod 8,
+// and takes work item (b mod 8) * per + b / 8), so windows that share rows or
+// planes are read through the same L2.
+constexpr int kCoarseChunkGroups = 64;
+constexpr int kCoarseSubsets = 5;
+constexpr int kCoarseWideThreads = kCoarseChunkGroups * kCoarseSubsets;  // 320
+constexpr int kCoarseRowsPerThread =
+    ((kCoarseCell + 1) * (kCoarseCell + 1) + kCoarseSubsets - 1) / kCoarseSubsets;  // 17
+constexpr int kXcds = 8;
+typedef uint32_t U32x4 __attribute__((ext_vector_type(4)));
+
+template <int kElemBytes>
+__global__ __launch_bounds__(kCoarseWideThreads) void grid_coarse_min_wide_kernel(
+    const unsigned char* __restrict__ grid, int nx, int ny, int nz, int ncx, int ncy,
+    int nchunks, int nwork, float* __restrict__ out) {
+  constexpr int kCols = 16 / kElemBytes;                               // columns per group
+  constexpr int kCells = (kCoarseChunkGroups - 1) * kCols / kCoarseCell;  // cells per chunk
+  __shared__ float s_mn[kCoarseSubsets][kCoarseChunkGroups];
+  __shared__ float s_mx[kCoarseSubsets][kCoarseChunkGroups];
+  __shared__ float s_fmn[kCoarseSubsets][kCoarseChunkGroups];
+  __shared__ float s_fmx[kCoarseSubsets][kCoarseChunkGroups];
+  const int per = (nwork + kXcds - 1) / kXcds;
+  const int w = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+  if (w >= nwork) return;
+  const int ch = w % nchunks, cyz = w / nchunks;
+  const int cy = cyz % ncy, cz = cyz / ncy;
+  const int y0 = cy * kCoarseCell, z0 = cz * kCoarseCell;
+  const int wy = min(y0 + kCoarseCell, ny - 1) - y0 + 1;
+  const int rows = wy * (min(z0 + kCoarseCell, nz - 1) - z0 + 1);
+  const int x0 = ch * kCells * kCoarseCell;                     // first column of the chunk
+  const int n_groups = nx / kCols;                              // groups per grid row
+  const int tid = threadIdx.x;
+  const int s = tid / kCoarseChunkGroups, g = tid - s * kCoarseChunkGroups;
+  const int gg = min(x0 / kCols + g, n_groups - 1);             // clamped group of the row
+  // Non-temporal loads: the grid streams through once and does not displace what the
+  // plan step that follows keeps in L2 (robot constants, instructions).
+  U32x4 v[kCoarseRowsPerThread];
+#pragma unroll
+  for (int j = 0; j < kCoarseRowsPerThread; ++j) {
+    const int r = min(s + kCoarseSubsets * j, rows - 1);
+    const int y = y0 + r % wy, z = z0 + r / wy;
+    const size_t row = ((size_t)z * (size_t)ny + (size_t)y) * (size_t)nx * kElemBytes;
+    v[j] = __builtin_nontemporal_load(
+        reinterpret_cast<const U32x4*>(grid + row + (size_t)gg * 16u));
+  }
+  float mn = __builtin_inff(), mx = 0.f, fmn = __builtin_inff(), fmx = 0.f;
+#pragma unroll
+  for (int j = 0; j < kCoarseRowsPerThread; ++j) {
+    const uint32_t wd[4] = {v[j][0], v[j][1], v[j][2], v[j][3]};
+#pragma unroll
+    for (int c = 0; c < kCols; ++c) {
+      float x;
+      if constexpr (kElemBytes == 4) {
+        x = __uint_as_float(wd[c]);
+      } else {
+        const unsigned short h = (unsigned short)(wd[c >> 1] >> ((c & 1) * 16));
+        x = (float)__builtin_bit_cast(_Float16, h);
+      }
+      const float a = isfinite(x) ? fabsf(x) : __builtin_inff();
+      mn = fminf(mn, x);
+      mx = fmaxf(mx, a);
+      if (c == 0) {
+        fmn = fminf(fmn, x);
+        fmx = fmaxf(fmx, a);
+      }
+    }
+  }
+  s_mn[s][g] = mn;
+  s_mx[s][g] = mx;
+  s_fmn[s][g] = fmn;
+  s_fmx[s][g] = fmx;
+  __syncthreads();
+  const int cx = ch * kCells + tid;
+  if (tid < kCells && cx < ncx) {
+    const int c_lo = tid * kCoarseCell;                          // chunk-relative columns
+    const int c_hi = min(c_lo + kCoarseCell, nx - 1 - x0);
+    // Whole groups [c_lo / kCols, g_end); the window's last column opens group g_end
+    // when it is a group's first column (c_hi = c_lo + 8), else it closes g_end - 1.
+    const bool first_only = (c_hi % kCols) == 0;
+    const int g_end = first_only ? c_hi / kCols : c_hi / kCols + 1;
+    float cmn = __builtin_inff(), cmx = 0.f;
+    for (int gi = c_lo / kCols; gi < g_end; ++gi) {
+#pragma unroll
+      for (int t = 0; t < kCoarseSubsets; ++t) {
+        cmn = fminf(cmn, s_mn[t][gi]);
+        cmx = fmaxf(cmx, s_mx[t][gi]);
+      }
+    }
+    if (first_only) {
+#pragma unroll
+      for (int t = 0; t < kCoarseSubsets; ++t) {
+        cmn = fminf(cmn, s_fmn[t][g_end]);
+        cmx = fmaxf(cmx, s_fmx[t][g_end]);
+      }
+    }
+    out[((size_t)cz * ncy + cy) * ncx + cx] =
+        cmx == __builtin_inff() ? -__builtin_inff() : cmn - (1e-5f + cmx * 0x1p-18f);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Occupancy update by voxel projection (Sec. III-A) with the robot mask (Remark 2)
 // ---------------------------------------------------------------------------
@@ -1709,11 +1820,23 @@ int launch_grid_coarse_min(const void* grid, bool f16, int nx, int ny, int nz, f
                            void* stream) {
   const int ncx = coarse_cells_1d(nx), ncy = coarse_cells_1d(ny), ncz = coarse_cells_1d(nz);
   const long long ncells = (long long)ncx * ncy * ncz;
-  const uint32_t bytes = (uint32_t)((long long)nx * ny * nz * (f16 ? 2 : 4));
-  auto k = f16 ? grid_coarse_min_kernel<2> : grid_coarse_min_kernel<4>;
+  const int elem = f16 ? 2 : 4;
   (void)ncells;
-  hipLaunchKernelGGL(k, dim3((unsigned)((long long)ncy * ncz)), dim3(kCoarseThreads), 0,
-                     (hipStream_t)stream, grid, bytes, nx, ny, nz, ncx, ncy, ncz, out);
+  if (((long long)nx * elem) % 16 == 0 && reinterpret_cast<uintptr_t>(grid) % 16 == 0) {
+    const int cells_per_chunk = (kCoarseChunkGroups - 1) * (16 / elem) / kCoarseCell;
+    const int nchunks = (ncx + cells_per_chunk - 1) / cells_per_chunk;
+    const long long nwork = (long long)nchunks * ncy * ncz;
+    const long long blocks = (nwork + kXcds - 1) / kXcds * kXcds;
+    auto k = f16 ? grid_coarse_min_wide_kernel<2> : grid_coarse_min_wide_kernel<4>;
+    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kCoarseWideThreads), 0,
+                       (hipStream_t)stream, static_cast<const unsigned char*>(grid), nx, ny, nz,
+                       ncx, ncy, nchunks, (int)nwork, out);
+  } else {
+    const uint32_t bytes = (uint32_t)((long long)nx * ny * nz * elem);
+    auto k = f16 ? grid_coarse_min_kernel<2> : grid_coarse_min_kernel<4>;
+    hipLaunchKernelGGL(k, dim3((unsigned)((long long)ncy * ncz)), dim3(kCoarseThreads), 0,
+                       (hipStream_t)stream, grid, bytes, nx, ny, nz, ncx, ncy, ncz, out);
+  }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

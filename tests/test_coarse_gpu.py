@@ -48,20 +48,57 @@ def gpu_coarse(grid_t, dtype):
     return out
 
 
-@pytest.mark.parametrize("shape", [(17, 9, 33), (2, 2, 2), (40, 41, 42)])
+# Rows of 16-byte multiples take the wide kernel (several x chunks at 520 columns);
+# the others, and a grid that does not start on a 16-byte boundary, the row kernel.
+@pytest.mark.parametrize("shape", [(17, 9, 33), (2, 2, 2), (40, 41, 42), (17, 9, 48), (2, 2, 8),
+                                   (10, 12, 520), (40, 41, 200)])
 def test_bounds_match_definition(shape):
     import torch
 
     from paper_2512_22575_amd import smpc as S
     rng = np.random.default_rng(sum(shape))
     grid = rng.normal(scale=0.3, size=shape).astype(np.float32)
-    if shape == (40, 41, 42):
+    if shape in ((40, 41, 42), (40, 41, 200)):
         grid[5, 30, 7] = np.nan
         grid[33, 2, 40] = np.inf
+        grid[39, 40, shape[2] - 1] = -np.inf
     got = gpu_coarse(torch.from_numpy(grid).cuda(), S.GRID_F32).cpu().numpy()
     want = coarse_reference(grid).reshape(-1)
     np.testing.assert_array_equal(got.view(np.uint32), want.view(np.uint32))
     # float16 storage: bounds of the decoded values
+    g16 = np.clip(grid, -2, 2).astype(np.float16)
+    got16 = gpu_coarse(torch.from_numpy(g16.view(np.int16).copy()).cuda(), S.GRID_F16)
+    want16 = coarse_reference(g16.astype(np.float32)).reshape(-1)
+    np.testing.assert_array_equal(got16.cpu().numpy().view(np.uint32), want16.view(np.uint32))
+
+
+def test_bounds_unaligned_grid_start():
+    """A grid whose data starts 4 bytes past a 16-byte boundary (row kernel)."""
+    import torch
+
+    from paper_2512_22575_amd import smpc as S
+    shape = (12, 10, 24)
+    rng = np.random.default_rng(7)
+    grid = rng.normal(scale=0.3, size=shape).astype(np.float32)
+    buf = torch.zeros(grid.size + 1, device="cuda")
+    buf[1:] = torch.from_numpy(grid.reshape(-1)).cuda()
+    view = buf[1:].view(shape)
+    assert view.data_ptr() % 16 == 4
+    got = gpu_coarse(view, S.GRID_F32).cpu().numpy()
+    np.testing.assert_array_equal(got.view(np.uint32),
+                                  coarse_reference(grid).reshape(-1).view(np.uint32))
+
+
+def test_bounds_full_size_reactive_grid():
+    """The 200^3 grid of the reactive workload, float32 and float16 (wide kernel)."""
+    import torch
+
+    from paper_2512_22575_amd import smpc as S
+    sc = W.ReactiveScenario(seed=3, K=64)
+    grid = sc.grid()
+    got = gpu_coarse(torch.from_numpy(grid).cuda(), S.GRID_F32).cpu().numpy()
+    np.testing.assert_array_equal(got.view(np.uint32),
+                                  coarse_reference(grid).reshape(-1).view(np.uint32))
     g16 = np.clip(grid, -2, 2).astype(np.float16)
     got16 = gpu_coarse(torch.from_numpy(g16.view(np.int16).copy()).cuda(), S.GRID_F16)
     want16 = coarse_reference(g16.astype(np.float32)).reshape(-1)
