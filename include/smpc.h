@@ -195,11 +195,32 @@ smpc_status smpc_create(smpc_ctx** out, int32_t hip_device);
 /* Destroy a context and free its device memory (waits for the device). NULL is a no-op. */
 void smpc_destroy(smpc_ctx* ctx);
 
-/* Validate and copy a robot description to the device (synchronous). */
+/* Validate a robot description and copy it into the context (host memory; no device
+ * call).  The next smpc_plan_step uploads it to the device. */
 smpc_status smpc_set_robot(smpc_ctx* ctx, const smpc_robot_desc* desc);
 
 /* Validate `args` and enqueue one plan step on `stream` (asynchronous). */
 smpc_status smpc_plan_step(smpc_ctx* ctx, const smpc_plan_args* args, void* stream);
+
+/* Bytes of the static device array that smpc_plan_step_noalloc takes its workspace from. */
+#define SMPC_NOALLOC_SCRATCH_BYTES (4u << 20)
+
+/*
+ * smpc_plan_step for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  Same validation,
+ * kernels and results as smpc_plan_step, but the workspace is a static device array of
+ * SMPC_NOALLOC_SCRATCH_BYTES per device (held until the process ends) instead of the
+ * context's arena, and no hipMalloc or hipFree is called.
+ *   - The robot must already be on the device: smpc_plan_step has run on this context
+ *     since its last smpc_set_robot.  Otherwise SMPC_E_INVALID_ARG.
+ *   - smpc_plan_workspace_bytes(K, H) <= SMPC_NOALLOC_SCRATCH_BYTES (K up to 27952 at
+ *     H = 40, 11345 at H = 64), else SMPC_E_INVALID_ARG; nothing is enqueued on any
+ *     error.
+ *   - All calls on one device share that device's array and it keeps the last call's
+ *     contents (nothing in it needs to start at zero): calls that may overlap on one
+ *     device (other streams, other contexts) race and must be ordered by the caller.
+ */
+smpc_status smpc_plan_step_noalloc(smpc_ctx* ctx, const smpc_plan_args* args, void* stream);
 
 /* Static description of a status code. */
 const char* smpc_status_string(smpc_status status);

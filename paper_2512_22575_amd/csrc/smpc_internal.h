@@ -118,6 +118,13 @@ LaunchConfig plan_launch_config(int K, int H);
 size_t workspace_bytes(int K, int H, int P);
 Workspace carve_workspace(void* base, int K, int H, int P);
 
+// Static device scratch of smpc_plan_step_noalloc (one per device).
+constexpr size_t kScratchBytes = SMPC_NOALLOC_SCRATCH_BYTES;
+constexpr int kScratchDevices = 64;
+// Device address of the scratch on `device`, which must be current (looked up once per
+// device).  Returns a hipError_t value (0 = success).
+int scratch_address(int device, void** out);
+
 // Enqueue both kernels of one plan step.  Returns a hipError_t value (0 = success).
 // When `events` is non-null, events[0..2] (hipEvent_t) are recorded before the
 // rollout-cost kernel, between the kernels and after the merge kernel.

@@ -18,6 +18,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <mutex>
+
 #include "smpc_internal.h"
 
 namespace smpc {
@@ -1751,6 +1753,28 @@ Workspace carve_workspace(void* base, int K, int H, int P) {
   b += align256(padded_outputs(H) * P * 4);
   ws.c0 = reinterpret_cast<float*>(b);
   return ws;
+}
+
+// Workspace of the allocation-free plan step: one static array per device, held until
+// the process ends.  Host code never hands `scratch` itself to a kernel or a copy (its
+// host-side name is not a device address): it uses the address hipGetSymbolAddress
+// returns on each device, looked up once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+int scratch_address(int device, void** out) {
+  static std::mutex mu;
+  static void* addr[kScratchDevices] = {};
+  if (device < 0 || device >= kScratchDevices) return (int)hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return (int)e;
+    if (!ptr) return (int)hipErrorInvalidSymbol;
+    addr[device] = ptr;
+  }
+  *out = addr[device];
+  return 0;
 }
 
 int launch_plan_step(const DevRobot* robot, const Request& q, const LaunchConfig& lc,

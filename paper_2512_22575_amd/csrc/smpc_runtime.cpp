@@ -264,6 +264,28 @@ StepParams make_params(const smpc_ctx* ctx, const smpc_plan_args* a, const Launc
   return p;
 }
 
+// The request descriptor of one plan step (by value in the kernel arguments).
+Request single_request(const smpc_plan_args* a, const StepParams& p, const Workspace& ws) {
+  Request q;
+  std::memset(&q, 0, sizeof q);
+  q.p = p;
+  q.grid = a->esdf.data;
+  q.coarse = a->esdf.coarse;
+  q.noise = a->noise;
+  q.U_in = a->U_in;
+  q.U_out = a->U_out;
+  q.costs_out = a->costs_out;
+  q.weights_out = a->weights_out;
+  q.stats_out = a->stats_out;
+  q.u0_out = a->u0_out;
+  q.state_in = a->state_in;
+  q.state_out = a->state_out;
+  q.shift_out = a->receding;
+  q.ws = ws;
+  q.c0_in_ws = (a->costs_out || a->stats_out) ? 1 : 0;
+  return q;
+}
+
 // Allocates the device robot buffer if needed and uploads a changed robot.  The
 // caller has made the context's device current.
 smpc_status ensure_device_robot(smpc_ctx* ctx) {
@@ -465,24 +487,40 @@ smpc_status smpc_plan_step(smpc_ctx* ctx, const smpc_plan_args* a, void* stream)
   const Workspace ws = carve_workspace(ctx->workspace, a->K, a->H, lc.P);
   hipEvent_t* ev = nullptr;
   if (ctx->prof_recorded < ctx->prof_capacity) ev = &ctx->prof_events[3 * ctx->prof_recorded++];
-  Request q;
-  std::memset(&q, 0, sizeof q);
-  q.p = p;
-  q.grid = a->esdf.data;
-  q.coarse = a->esdf.coarse;
-  q.noise = a->noise;
-  q.U_in = a->U_in;
-  q.U_out = a->U_out;
-  q.costs_out = a->costs_out;
-  q.weights_out = a->weights_out;
-  q.stats_out = a->stats_out;
-  q.u0_out = a->u0_out;
-  q.state_in = a->state_in;
-  q.state_out = a->state_out;
-  q.shift_out = a->receding;
-  q.ws = ws;
-  q.c0_in_ws = (a->costs_out || a->stats_out) ? 1 : 0;
-  const int e = launch_plan_step(ctx->dev_robot, q, lc, a->esdf.dtype == SMPC_GRID_F16, stream, ev);
+  const int e = launch_plan_step(ctx->dev_robot, single_request(a, p, ws), lc,
+                                 a->esdf.dtype == SMPC_GRID_F16, stream, ev);
+  if (e != 0)
+    return fail(ctx, SMPC_E_DEVICE, "kernel launch failed: %s",
+                hipGetErrorString(static_cast<hipError_t>(e)));
+  return SMPC_OK;
+}
+
+smpc_status smpc_plan_step_noalloc(smpc_ctx* ctx, const smpc_plan_args* a, void* stream) {
+  if (!ctx) return SMPC_E_INVALID_ARG;
+  if (!a) return fail(ctx, SMPC_E_INVALID_ARG, "args is NULL");
+  ctx->last_error.clear();
+  const smpc_status st = validate_args(ctx, a);
+  if (st != SMPC_OK) return st;
+  const LaunchConfig lc = plan_launch_config(a->K, a->H);
+  const size_t need = workspace_bytes(a->K, a->H, lc.P);
+  if (need > kScratchBytes)
+    return fail(ctx, SMPC_E_INVALID_ARG,
+                "K=%d, H=%d needs a %zu-byte workspace; the static scratch holds %zu bytes", a->K,
+                a->H, need, kScratchBytes);
+  if (!ctx->dev_robot || ctx->robot_dirty)
+    return fail(ctx, SMPC_E_INVALID_ARG,
+                "robot is not on the device yet: run smpc_plan_step once after smpc_set_robot");
+  const StepParams p = make_params(ctx, a, lc);
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return fail(ctx, SMPC_E_DEVICE, "hipSetDevice(%d) failed", ctx->device);
+  void* base = nullptr;
+  const int se = scratch_address(ctx->device, &base);
+  if (se != 0)
+    return fail(ctx, SMPC_E_DEVICE, "static scratch lookup failed: %s",
+                hipGetErrorString(static_cast<hipError_t>(se)));
+  const Workspace ws = carve_workspace(base, a->K, a->H, lc.P);
+  const int e = launch_plan_step(ctx->dev_robot, single_request(a, p, ws), lc,
+                                 a->esdf.dtype == SMPC_GRID_F16, stream, nullptr);
   if (e != 0)
     return fail(ctx, SMPC_E_DEVICE, "kernel launch failed: %s",
                 hipGetErrorString(static_cast<hipError_t>(e)));

@@ -156,6 +156,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.smpc_set_robot.restype = c_int32
     lib.smpc_plan_step.argtypes = [c_void_p, POINTER(smpc_plan_args), c_void_p]
     lib.smpc_plan_step.restype = c_int32
+    lib.smpc_plan_step_noalloc.argtypes = [c_void_p, POINTER(smpc_plan_args), c_void_p]
+    lib.smpc_plan_step_noalloc.restype = c_int32
     lib.smpc_status_string.argtypes = [c_int32]
     lib.smpc_status_string.restype = c_char_p
     lib.smpc_last_error.argtypes = [c_void_p]
@@ -233,6 +235,10 @@ def smpc_set_robot(ctx: c_void_p, desc: smpc_robot_desc) -> int:
 
 def smpc_plan_step(ctx: c_void_p, args: smpc_plan_args, stream: int | None) -> int:
     return load_library().smpc_plan_step(ctx, ctypes.byref(args), c_void_p(stream or 0))
+
+
+def smpc_plan_step_noalloc(ctx: c_void_p, args: smpc_plan_args, stream: int | None) -> int:
+    return load_library().smpc_plan_step_noalloc(ctx, ctypes.byref(args), c_void_p(stream or 0))
 
 
 def smpc_status_string(status: int) -> str:
@@ -395,8 +401,9 @@ class Planner:
                   weights, costs_out=None, weights_out=None, stats_out=None, stream=None,
                   seed: int = 0, sigma=None, grid_dtype: int = GRID_F32, K=None, H=None,
                   coarse=None, receding: bool = False, u0_out=None, state_in=None,
-                  state_out=None) -> None:
-        """Enqueue one plan step on ``stream`` (default: torch's current stream)."""
+                  state_out=None, noalloc: bool = False) -> None:
+        """Enqueue one plan step on ``stream`` (default: torch's current stream);
+        ``noalloc`` takes the workspace from the library's static device scratch."""
         import torch
         if noise is not None:
             K, H = int(noise.shape[0]), int(noise.shape[1])
@@ -407,7 +414,7 @@ class Planner:
         a = plan_args(q0, qd0, T_goal, grid, origin, voxel, noise, U_in, U_out, K, H, dt, lam,
                       weights, costs_out, weights_out, stats_out, seed, sigma, grid_dtype,
                       coarse, receding, u0_out, state_in, state_out)
-        st = smpc_plan_step(self._ctx, a, stream)
+        st = (smpc_plan_step_noalloc if noalloc else smpc_plan_step)(self._ctx, a, stream)
         if st != SMPC_OK:
             raise SMPCError(st, smpc_last_error(self._ctx))
 

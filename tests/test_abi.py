@@ -267,6 +267,39 @@ def test_valid_request_without_gpu_fails_loudly(ctx):
     assert S.smpc_last_error(ctx)
 
 
+def _expect_noalloc(ctx, args, status, msg):
+    st = S.smpc_plan_step_noalloc(ctx, args, None)
+    assert st == status, (st, S.smpc_last_error(ctx))
+    assert msg in S.smpc_last_error(ctx)
+
+
+def test_noalloc_validates_like_plan_step(ctx):
+    _expect_noalloc(ctx, _args(), S.SMPC_E_INVALID_ARG, "no robot")
+    assert S.smpc_set_robot(ctx, S.robot_desc(R.make_robot(0))) == S.SMPC_OK
+    _expect_noalloc(ctx, _args(K=0), S.SMPC_E_INVALID_ARG, "K=0")
+    _expect_noalloc(ctx, _args(lam=-1.0), S.SMPC_E_INVALID_ARG, "lambda")
+    _expect_noalloc(ctx, _args(receding=True), S.SMPC_E_INVALID_ARG, "U_out overlaps U_in")
+
+
+def test_noalloc_rejects_a_workspace_beyond_the_static_scratch(ctx):
+    assert S.smpc_set_robot(ctx, S.robot_desc(R.make_robot(0))) == S.SMPC_OK
+    lib = S.load_library()
+    limit = 4 << 20
+    assert lib.smpc_plan_workspace_bytes(27953, 40) > limit >= lib.smpc_plan_workspace_bytes(27952, 40)
+    big = dict(K=27953, H=40, noise=_FakeTensor((27953, 40, 7)), U_in=_FakeTensor((40, 7)),
+               U_out=_FakeTensor((40, 7), ptr=0x100000))
+    _expect_noalloc(ctx, _args(**big), S.SMPC_E_INVALID_ARG, "static scratch")
+    # One rollout fewer fits, and the call stops at the next check (robot not resident).
+    fits = dict(big, K=27952, noise=_FakeTensor((27952, 40, 7)))
+    _expect_noalloc(ctx, _args(**fits), S.SMPC_E_INVALID_ARG, "not on the device")
+
+
+def test_noalloc_requires_the_robot_on_the_device(ctx):
+    # Setting a robot makes no device call, so nothing is resident until a plan step.
+    assert S.smpc_set_robot(ctx, S.robot_desc(R.make_robot(0))) == S.SMPC_OK
+    _expect_noalloc(ctx, _args(), S.SMPC_E_INVALID_ARG, "run smpc_plan_step once")
+
+
 def test_planner_raises_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(S, "_lib", None)
     with pytest.raises(OSError, match="missing"):
