@@ -409,6 +409,11 @@ typedef struct {
   float lambda;
   smpc_cost_weights weights;
   float sigma[SMPC_NDOF];
+  /* Optional device outputs (NULL: not written), overwritten by each served request of
+   * this controller and valid once its completion has been polled: U* before the
+   * receding-horizon shift, [H][7], and the rollout costs, [K]. */
+  float* U_star_out;
+  float* costs_out;
 } smpc_controller_desc;
 
 typedef struct {

@@ -99,6 +99,7 @@ struct Request {
   float* u0_out;               // device [7] or null: receives u*_0
   const float* state_in;       // device [14] (q0, qd0), or null: p.q0 and p.qd0
   float* state_out;            // device [14] or null: state after executing u*_0 for dt
+  float* U_star_out;           // device [H][7] or null: U* (unshifted) besides U_out
   Workspace ws;
   int32_t k1_begin;            // first rollout-cost block of this request in a batch
   int32_t k2_begin;            // first merge block of this request in a batch
@@ -131,11 +132,18 @@ int scratch_address(int device, void** out);
 int launch_plan_step(const DevRobot* robot, const Request& q, const LaunchConfig& lc, bool f16,
                      void* stream, void* events);
 
-// Enqueue both kernels for a batch of requests (device array `reqs`, block maps
-// k1_map [k1_blocks] and k2_map [k2_blocks] giving each block's request index).
-int launch_batch(const DevRobot* robot, const Request* reqs, const int32_t* k1_map,
-                 int k1_blocks, const int32_t* k2_map, int k2_blocks, size_t k1_lds, bool f16,
-                 void* stream);
+// A batch of requests (device array `reqs`; block maps k1_map [k1_blocks] and k2_map
+// [k2_blocks] give each block's request index) as one HIP graph (descriptor upload,
+// both batch kernels, result download),
+// created at the first launch and re-parameterised for every later one.  `*graph` is
+// the slot's handle (null before the first launch); the caller relaunches it only after
+// the previous launch has completed.  up: host -> device bytes (descriptors and maps);
+// res: device -> host result bytes.  Returns a hipError_t value.
+int launch_batch_graph(void** graph, const DevRobot* robot, void* d_up, const void* h_up,
+                       size_t up_bytes, const Request* reqs, const int32_t* k1_map,
+                       int k1_blocks, const int32_t* k2_map, int k2_blocks, size_t k1_lds,
+                       bool f16, void* h_res, const void* d_res, size_t res_bytes, void* stream);
+void destroy_batch_graph(void* graph);
 
 // Disturbances of the sampling mode written to memory (eps [K][H][7], words [K][H][8];
 // either may be null).  Returns a hipError_t value.

@@ -18,7 +18,9 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <cstring>
 #include <mutex>
+#include <new>
 
 #include "smpc_internal.h"
 
@@ -1064,6 +1066,7 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
           q.state_out[kNdof + o] = qd1;
         }
       }
+      if (q.U_star_out) q.U_star_out[o] = u;
       if (!q.shift_out) {
         U_out[o] = u;
       } else {
@@ -1795,17 +1798,80 @@ int launch_plan_step(const DevRobot* robot, const Request& q, const LaunchConfig
   return 0;
 }
 
-int launch_batch(const DevRobot* robot, const Request* reqs, const int32_t* k1_map,
-                 int k1_blocks, const int32_t* k2_map, int k2_blocks, size_t k1_lds, bool f16,
-                 void* stream) {
-  hipStream_t s = static_cast<hipStream_t>(stream);
+namespace {
+struct BatchGraph {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipGraphNode_t up = nullptr, k1 = nullptr, k2 = nullptr, down = nullptr;
+  bool f16 = false;
+};
+
+hipKernelNodeParams kernel_node(void* func, int blocks, int threads, size_t lds, void** args) {
+  hipKernelNodeParams p;
+  std::memset(&p, 0, sizeof p);
+  p.func = func;
+  p.gridDim = dim3((unsigned)blocks);
+  p.blockDim = dim3((unsigned)threads);
+  p.sharedMemBytes = (unsigned)lds;
+  p.kernelParams = args;
+  p.extra = nullptr;
+  return p;
+}
+}  // namespace
+
+void destroy_batch_graph(void* handle) {
+  BatchGraph* g = static_cast<BatchGraph*>(handle);
+  if (!g) return;
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
+}
+
+int launch_batch_graph(void** handle, const DevRobot* robot, void* d_up, const void* h_up,
+                       size_t up_bytes, const Request* reqs, const int32_t* k1_map,
+                       int k1_blocks, const int32_t* k2_map, int k2_blocks, size_t k1_lds,
+                       bool f16, void* h_res, const void* d_res, size_t res_bytes, void* stream) {
+  void* f1 = f16 ? reinterpret_cast<void*>(rollout_cost_batch_kernel<2>)
+                 : reinterpret_cast<void*>(rollout_cost_batch_kernel<4>);
+  void* f2 = f16 ? reinterpret_cast<void*>(merge_batch_kernel<2>)
+                 : reinterpret_cast<void*>(merge_batch_kernel<4>);
+  const DevRobot* rob = robot;
+  const Request* rq = reqs;
+  const int32_t* m1 = k1_map;
+  const int32_t* m2 = k2_map;
+  void* a1[] = {&rob, &rq, &m1};
+  void* a2[] = {&rob, &rq, &m2};
+  const hipKernelNodeParams p1 = kernel_node(f1, k1_blocks, kK1Threads, k1_lds, a1);
+  const hipKernelNodeParams p2 = kernel_node(f2, k2_blocks, kK2Threads, 0, a2);
+  BatchGraph* g = static_cast<BatchGraph*>(*handle);
   hipError_t e;
-  auto k1 = f16 ? rollout_cost_batch_kernel<2> : rollout_cost_batch_kernel<4>;
-  hipLaunchKernelGGL(k1, dim3(k1_blocks), dim3(kK1Threads), k1_lds, s, robot, reqs, k1_map);
-  if ((e = hipGetLastError()) != hipSuccess) return (int)e;
-  auto k2 = f16 ? merge_batch_kernel<2> : merge_batch_kernel<4>;
-  hipLaunchKernelGGL(k2, dim3(k2_blocks), dim3(kK2Threads), 0, s, robot, reqs, k2_map);
-  return (int)hipGetLastError();
+  if (!g) {
+    g = new (std::nothrow) BatchGraph();
+    if (!g) return (int)hipErrorOutOfMemory;
+    g->f16 = f16;
+    if ((e = hipGraphCreate(&g->graph, 0)) != hipSuccess ||
+        (e = hipGraphAddMemcpyNode1D(&g->up, g->graph, nullptr, 0, d_up, h_up, up_bytes,
+                                     hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipGraphAddKernelNode(&g->k1, g->graph, &g->up, 1, &p1)) != hipSuccess ||
+        (e = hipGraphAddKernelNode(&g->k2, g->graph, &g->k1, 1, &p2)) != hipSuccess ||
+        (e = hipGraphAddMemcpyNode1D(&g->down, g->graph, &g->k2, 1, h_res, d_res, res_bytes,
+                                     hipMemcpyDeviceToHost)) != hipSuccess ||
+        (e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0)) != hipSuccess) {
+      destroy_batch_graph(g);
+      return (int)e;
+    }
+    *handle = g;
+  } else {
+    if (g->f16 != f16) return (int)hipErrorInvalidValue;
+    if ((e = hipGraphExecMemcpyNodeSetParams1D(g->exec, g->up, d_up, h_up, up_bytes,
+                                               hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipGraphExecKernelNodeSetParams(g->exec, g->k1, &p1)) != hipSuccess ||
+        (e = hipGraphExecKernelNodeSetParams(g->exec, g->k2, &p2)) != hipSuccess ||
+        (e = hipGraphExecMemcpyNodeSetParams1D(g->exec, g->down, h_res, d_res, res_bytes,
+                                               hipMemcpyDeviceToHost)) != hipSuccess)
+      return (int)e;
+  }
+  return (int)hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream));
 }
 
 int launch_sample_noise(uint64_t seed, int K, int H, const float* sigma, float* eps,

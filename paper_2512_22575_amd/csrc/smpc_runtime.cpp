@@ -810,13 +810,15 @@ struct BatchSlot {
   std::vector<int32_t> ctls;
   hipEvent_t done = nullptr;
   void* ws = nullptr;                   // half of the budget
-  size_t req_cap = 0, map_cap = 0;
-  Request* h_reqs = nullptr;            // pinned
-  Request* d_reqs = nullptr;
-  int32_t* h_maps = nullptr;            // pinned [k1 blocks + k2 blocks]
-  int32_t* d_maps = nullptr;
-  float* h_res = nullptr;               // pinned [req_cap * kResultStride]
+  // Upload buffers: the batch's request descriptors, then its block maps
+  // (k1 blocks + k2 blocks int32), copied host -> device by one graph node.
+  size_t up_cap = 0;
+  unsigned char* h_up = nullptr;        // pinned
+  unsigned char* d_up = nullptr;
+  size_t res_cap = 0;                   // requests the result buffers hold
+  float* h_res = nullptr;               // pinned [res_cap * kResultStride]
   float* d_res = nullptr;
+  void* graph = nullptr;                // the slot's batch graph (launch_batch_graph)
 };
 
 }  // namespace
@@ -843,46 +845,41 @@ smpc_status sfail(smpc_server* s, smpc_status st, const std::string& msg) {
 }
 
 void free_slot(BatchSlot& b) {
+  destroy_batch_graph(b.graph);
   if (b.done) (void)hipEventDestroy(b.done);
   if (b.ws) (void)hipFree(b.ws);
-  if (b.d_reqs) (void)hipFree(b.d_reqs);
-  if (b.d_maps) (void)hipFree(b.d_maps);
+  if (b.d_up) (void)hipFree(b.d_up);
   if (b.d_res) (void)hipFree(b.d_res);
-  if (b.h_reqs) (void)hipHostFree(b.h_reqs);
-  if (b.h_maps) (void)hipHostFree(b.h_maps);
+  if (b.h_up) (void)hipHostFree(b.h_up);
   if (b.h_res) (void)hipHostFree(b.h_res);
   b = BatchSlot();
 }
 
-// Grow a slot's descriptor, map and result buffers (only while the slot is free).
-bool reserve_slot(BatchSlot& b, size_t reqs, size_t maps) {
-  if (reqs > b.req_cap) {
-    if (b.h_reqs) (void)hipHostFree(b.h_reqs);
-    if (b.d_reqs) (void)hipFree(b.d_reqs);
+// Grow a slot's upload and result buffers (only while the slot is free; the graph
+// takes the new addresses at its next launch).
+bool reserve_slot(BatchSlot& b, size_t up_bytes, size_t reqs) {
+  if (up_bytes > b.up_cap) {
+    const size_t cap = std::max(up_bytes, 2 * b.up_cap);
+    if (b.h_up) (void)hipHostFree(b.h_up);
+    if (b.d_up) (void)hipFree(b.d_up);
+    b.h_up = nullptr;
+    b.d_up = nullptr;
+    b.up_cap = 0;
+    if (hipHostMalloc(reinterpret_cast<void**>(&b.h_up), cap) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&b.d_up), cap) != hipSuccess)
+      return false;
+    b.up_cap = cap;
+  }
+  if (reqs > b.res_cap) {
     if (b.h_res) (void)hipHostFree(b.h_res);
     if (b.d_res) (void)hipFree(b.d_res);
-    b.h_reqs = nullptr;
-    b.d_reqs = nullptr;
     b.h_res = nullptr;
     b.d_res = nullptr;
-    b.req_cap = 0;
-    if (hipHostMalloc(reinterpret_cast<void**>(&b.h_reqs), reqs * sizeof(Request)) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void**>(&b.d_reqs), reqs * sizeof(Request)) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&b.h_res), reqs * kResultStride * 4) != hipSuccess ||
+    b.res_cap = 0;
+    if (hipHostMalloc(reinterpret_cast<void**>(&b.h_res), reqs * kResultStride * 4) != hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&b.d_res), reqs * kResultStride * 4) != hipSuccess)
       return false;
-    b.req_cap = reqs;
-  }
-  if (maps > b.map_cap) {
-    if (b.h_maps) (void)hipHostFree(b.h_maps);
-    if (b.d_maps) (void)hipFree(b.d_maps);
-    b.h_maps = nullptr;
-    b.d_maps = nullptr;
-    b.map_cap = 0;
-    if (hipHostMalloc(reinterpret_cast<void**>(&b.h_maps), maps * 4) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void**>(&b.d_maps), maps * 4) != hipSuccess)
-      return false;
-    b.map_cap = maps;
+    b.res_cap = reqs;
   }
   return true;
 }
@@ -905,6 +902,7 @@ smpc_plan_args request_args(const Controller& c, const smpc_request& r) {
   a.weights = c.desc.weights;
   a.U_in = c.ubar[c.cur];
   a.U_out = c.ubar[1 - c.cur];
+  a.costs_out = c.desc.costs_out;
   return a;
 }
 
@@ -959,8 +957,14 @@ smpc_status launch_next(smpc_server* s, void* stream, int* launched) {
     k2_total += (size_t)c.lc.k2_blocks;
   }
   if (take.empty()) return SMPC_OK;
-  if (!reserve_slot(b, (size_t)s->max_batch, k1_total + k2_total))
+  const size_t req_bytes = take.size() * sizeof(Request);
+  const size_t up_bytes = req_bytes + (k1_total + k2_total) * sizeof(int32_t);
+  if (!reserve_slot(b, up_bytes, (size_t)s->max_batch))
     return sfail(s, SMPC_E_OOM, "batch buffer allocation failed");
+  Request* h_reqs = reinterpret_cast<Request*>(b.h_up);
+  int32_t* h_maps = reinterpret_cast<int32_t*>(b.h_up + req_bytes);
+  const Request* d_reqs = reinterpret_cast<const Request*>(b.d_up);
+  const int32_t* d_maps = reinterpret_cast<const int32_t*>(b.d_up + req_bytes);
 
   size_t lds = 0;
   int k1 = 0, k2 = 0;
@@ -970,7 +974,7 @@ smpc_status launch_next(smpc_server* s, void* stream, int* launched) {
     const smpc_request& r = s->queue[take[t]];
     Controller& c = s->ctl[r.controller];
     const smpc_plan_args a = request_args(c, r);
-    Request& q = b.h_reqs[t];
+    Request& q = h_reqs[t];
     std::memset(&q, 0, sizeof q);
     q.p = make_params(s->ctx, &a, c.lc);
     q.grid = a.esdf.data;
@@ -978,6 +982,8 @@ smpc_status launch_next(smpc_server* s, void* stream, int* launched) {
     q.noise = nullptr;
     q.U_in = a.U_in;
     q.U_out = a.U_out;
+    q.U_star_out = c.desc.U_star_out;
+    q.costs_out = c.desc.costs_out;
     q.u0_out = b.d_res + t * kResultStride;
     q.stats_out = b.d_res + t * kResultStride + kNdof;
     q.ws = carve_workspace(static_cast<unsigned char*>(b.ws) + ws_off[t], c.desc.K, c.desc.H,
@@ -985,8 +991,8 @@ smpc_status launch_next(smpc_server* s, void* stream, int* launched) {
     q.k1_begin = k1;
     q.k2_begin = k2;
     q.shift_out = 1;
-    for (int j = 0; j < c.lc.P; ++j) b.h_maps[k1 + j] = (int32_t)t;
-    for (int j = 0; j < c.lc.k2_blocks; ++j) b.h_maps[k1_total + k2 + j] = (int32_t)t;
+    for (int j = 0; j < c.lc.P; ++j) h_maps[k1 + j] = (int32_t)t;
+    for (int j = 0; j < c.lc.k2_blocks; ++j) h_maps[k1_total + k2 + j] = (int32_t)t;
     k1 += c.lc.P;
     k2 += c.lc.k2_blocks;
     lds = std::max(lds, c.lc.k1_lds);
@@ -994,21 +1000,15 @@ smpc_status launch_next(smpc_server* s, void* stream, int* launched) {
     b.tags[t] = r.tag;
     b.ctls[t] = r.controller;
   }
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  if (hipMemcpyAsync(b.d_reqs, b.h_reqs, take.size() * sizeof(Request), hipMemcpyHostToDevice,
-                     st) != hipSuccess ||
-      hipMemcpyAsync(b.d_maps, b.h_maps, (k1_total + k2_total) * 4, hipMemcpyHostToDevice, st) !=
-          hipSuccess)
-    return sfail(s, SMPC_E_DEVICE, "descriptor upload failed");
-  const int e = launch_batch(s->ctx->dev_robot, b.d_reqs, b.d_maps, (int)k1_total,
-                             b.d_maps + k1_total, (int)k2_total, lds,
-                             s->elem_dtype == SMPC_GRID_F16, stream);
+  // One graph launch: descriptors and maps up, both batch kernels, results down.
+  const int e = launch_batch_graph(&b.graph, s->ctx->dev_robot, b.d_up, b.h_up, up_bytes, d_reqs,
+                                   d_maps, (int)k1_total, d_maps + k1_total, (int)k2_total, lds,
+                                   s->elem_dtype == SMPC_GRID_F16, b.h_res, b.d_res,
+                                   take.size() * kResultStride * 4, stream);
   if (e != 0) return sfail(s, SMPC_E_DEVICE, std::string("batch launch failed: ") +
                                                  hipGetErrorString(static_cast<hipError_t>(e)));
-  if (hipMemcpyAsync(b.h_res, b.d_res, take.size() * kResultStride * 4, hipMemcpyDeviceToHost,
-                     st) != hipSuccess ||
-      hipEventRecord(b.done, st) != hipSuccess)
-    return sfail(s, SMPC_E_DEVICE, "result download failed");
+  if (hipEventRecord(b.done, static_cast<hipStream_t>(stream)) != hipSuccess)
+    return sfail(s, SMPC_E_DEVICE, "batch event record failed");
   b.n = (int)take.size();
   for (int t = (int)take.size() - 1; t >= 0; --t) s->queue.erase(s->queue.begin() + take[t]);
   ++s->n_in_flight;

@@ -94,6 +94,8 @@ class smpc_controller_desc(ctypes.Structure):
         ("dt", c_float), ("lambda_", c_float),
         ("weights", smpc_cost_weights),
         ("sigma", c_float * NDOF),
+        ("U_star_out", c_void_p),
+        ("costs_out", c_void_p),
     ]
 
 
@@ -596,7 +598,8 @@ def smpc_server_last_error(server: c_void_p) -> str:
 
 
 def controller_desc(grid, origin, voxel, K, H, dt, lam, weights, sigma,
-                    grid_dtype: int = GRID_F32, coarse=None) -> smpc_controller_desc:
+                    grid_dtype: int = GRID_F32, coarse=None, U_star_out=None,
+                    costs_out=None) -> smpc_controller_desc:
     d = smpc_controller_desc()
     nz, ny, nx = (int(x) for x in grid.shape)
     d.esdf = smpc_grid(c_void_p(_ptr(grid)), nx, ny, nz, int(grid_dtype),
@@ -606,6 +609,8 @@ def controller_desc(grid, origin, voxel, K, H, dt, lam, weights, sigma,
     d.dt, d.lambda_ = float(dt), float(lam)
     d.weights = cost_weights(weights)
     d.sigma[:] = [float(x) for x in np.broadcast_to(np.asarray(sigma, np.float32), (NDOF,))]
+    d.U_star_out = c_void_p(_ptr(U_star_out))
+    d.costs_out = c_void_p(_ptr(costs_out))
     return d
 
 
@@ -631,13 +636,16 @@ class Server:
         self._keep = []   # device tensors the controllers reference
 
     def add_controller(self, grid, origin, voxel, K, H, dt, lam, weights, sigma,
-                       grid_dtype: int = GRID_F32, coarse=None) -> int:
-        self._keep.append(grid)
-        if coarse is not None:
-            self._keep.append(coarse)
+                       grid_dtype: int = GRID_F32, coarse=None, U_star_out=None,
+                       costs_out=None) -> int:
+        """Register a controller; the optional device tensors U_star_out [H][7] and
+        costs_out [K] receive each served request's U* and rollout costs."""
+        for t in (grid, coarse, U_star_out, costs_out):
+            if t is not None:
+                self._keep.append(t)
         st, cid = smpc_server_add_controller(
             self._h, controller_desc(grid, origin, voxel, K, H, dt, lam, weights, sigma, grid_dtype,
-                                     coarse))
+                                     coarse, U_star_out, costs_out))
         if st != SMPC_OK:
             raise SMPCError(st, smpc_server_last_error(self._h))
         return cid

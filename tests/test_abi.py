@@ -59,6 +59,7 @@ int main(void) {
   printf("smpc_request sizeof %zu\n", sizeof(smpc_request));
   printf("smpc_completion sizeof %zu\n", sizeof(smpc_completion));
   F(smpc_controller_desc, K) F(smpc_controller_desc, weights) F(smpc_controller_desc, sigma)
+  F(smpc_controller_desc, U_star_out) F(smpc_controller_desc, costs_out)
   F(smpc_request, controller) F(smpc_request, q0) F(smpc_request, T_goal) F(smpc_request, seed)
   F(smpc_completion, status) F(smpc_completion, u0) F(smpc_completion, ess)
   printf("smpc_camera sizeof %zu\n", sizeof(smpc_camera));

@@ -134,3 +134,68 @@ def test_first_step_of_each_controller_matches_oracle():
                           np.zeros((f.H, 7)), f.dt, f.lam, f.weights)
         np.testing.assert_allclose(served[tag][1], ref["U_star"][0], atol=1e-5)
         assert served[tag][2] == pytest.approx(ref["S_min"], rel=1e-4)
+
+
+def test_serving_sizes_match_oracle_through_the_server():
+    """One request per (K, H) class of the serving workload, K in {256, 1024, 2048, 4096}
+    and H in {16, 32, 64}, on grids of 64^3 at 0.03 m, 112^3 at 0.02 m and 160^3 at
+    0.01 m (10 to 60 primitives), all submitted together so they share batches: every
+    rollout cost, the whole U* before the shift and u*_0 against the oracle run on the
+    same counter-based disturbances."""
+    import torch
+
+    from paper_2512_22575_amd import smpc as S
+    from synth import robot as RB
+    from tests.gpu_helpers import U_ATOL, assert_costs_close, control_conditioning_tolerance
+
+    rng = np.random.default_rng(55)
+    rob = RB.make_robot(0)
+    dev = torch.device("cuda:0")
+    grids = []
+    for n, voxel, n_prim in ((64, 0.03, 10), (112, 0.02, 30), (160, 0.01, 60)):
+        g, origin, _, _ = W.make_scene_grid(rng, n, voxel, n_prim // 2, n_prim - n_prim // 2)
+        grids.append((g, origin, W.f32s(voxel), torch.from_numpy(g).to(dev)))
+    weights = {k: W.f32s(v) for k, v in W.DEFAULT_WEIGHTS.items()}
+    dt, lam, sigma = W.f32s(0.02), 1.0, np.full(7, 0.5, np.float32)
+    planner = S.Planner(rob)
+    srv = S.Server(planner, hbm_budget_bytes=512 << 20, max_batch=64)
+    cases = []
+    for i, (K, H) in enumerate((K, H) for K in (256, 1024, 2048, 4096) for H in (16, 32, 64)):
+        g, origin, voxel, gt = grids[i % 3]
+        U_star = torch.full((H, 7), float("nan"), device=dev)
+        costs = torch.full((K,), float("nan"), device=dev)
+        cid = srv.add_controller(gt, origin, voxel, K, H, dt, lam, weights, sigma,
+                                 U_star_out=U_star, costs_out=costs)
+        q0 = W.f32(RB.random_joint_config(rng, rob))
+        qd0 = W.f32(rng.normal(scale=0.1, size=7))
+        T = W.f32(W.random_target_pose(rng))
+        seed = int(rng.integers(1 << 40))
+        srv.submit(i, cid, q0, qd0, T, seed)
+        cases.append((K, H, g, origin, voxel, q0, qd0, T, seed, U_star, costs))
+    done = {}
+    for _ in range(10000):
+        if not (srv.queued() or srv.in_flight()):
+            break
+        srv.pump()
+        for comp in srv.poll():
+            done[comp.tag] = comp
+        torch.cuda.synchronize()
+    for comp in srv.poll():
+        done[comp.tag] = comp
+    assert set(done) == set(range(len(cases)))
+    for i, (K, H, g, origin, voxel, q0, qd0, T, seed, U_star, costs) in enumerate(cases):
+        print(f"serving class K={K} H={H} grid {g.shape[0]}^3", flush=True)
+        eps = ORNG.sample_noise(seed, K, H, sigma.astype(np.float64))
+        ref = O.plan_step(rob.rounded_f32(), q0, qd0, T, g, origin, voxel, eps,
+                          np.zeros((H, 7)), dt, lam, weights)
+        ref["lam"] = lam
+        U = U_star.cpu().numpy().astype(np.float64)
+        assert done[i].status == 0
+        assert_costs_close(costs.cpu().numpy().astype(np.float64), ref["S"])
+        tol = U_ATOL + control_conditioning_tolerance(ref, eps)
+        err = np.abs(U - ref["U_star"])
+        assert np.all(err <= tol), (K, H, float(err.max()))
+        np.testing.assert_array_equal(np.array(done[i].u0[:], np.float32), U[0].astype(np.float32))
+        assert done[i].S_min == pytest.approx(ref["S_min"], rel=1e-4)
+    srv.close()
+    planner.close()
