@@ -213,8 +213,8 @@ smpc_status smpc_plan_step(smpc_ctx* ctx, const smpc_plan_args* args, void* stre
  * context's arena, and no hipMalloc or hipFree is called.
  *   - The robot must already be on the device: smpc_plan_step has run on this context
  *     since its last smpc_set_robot.  Otherwise SMPC_E_INVALID_ARG.
- *   - smpc_plan_workspace_bytes(K, H) <= SMPC_NOALLOC_SCRATCH_BYTES (K up to 27952 at
- *     H = 40, 11345 at H = 64), else SMPC_E_INVALID_ARG; nothing is enqueued on any
+ *   - smpc_plan_workspace_bytes(K, H) <= SMPC_NOALLOC_SCRATCH_BYTES (K up to 21246 at
+ *     H = 40, 9116 at H = 64), else SMPC_E_INVALID_ARG; nothing is enqueued on any
  *     error.
  *   - All calls on one device share that device's array and it keeps the last call's
  *     contents (nothing in it needs to start at zero): calls that may overlap on one

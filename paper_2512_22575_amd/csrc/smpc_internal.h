@@ -14,10 +14,22 @@ constexpr int kSpl = SMPC_SPHERES_PER_LINK;   // sphere slots per link
 constexpr int kSlots = kNdof * kSpl;          // slot s = (link - 1) * kSpl + j
 constexpr int kMaxPairs = SMPC_MAX_PAIRS;
 constexpr int kMaxH = SMPC_MAX_H;
-constexpr int kK1Threads = 320;               // rollout-cost block size (5 waves)
+constexpr int kK1Threads = 256;               // rollout-cost block size (4 waves)
 constexpr int kK2Threads = 256;               // reduce/update block size
 constexpr int kOutPerBlock = 8;               // U* outputs merged per K2 block
 constexpr int kWeightsPerBlock = 1024;        // weights_out elements per K2 block
+
+// Self-collision constants of one link pair (la <= lb): bit i * kSpl + j of mask marks
+// the pair (slot la*kSpl+i, slot lb*kSpl+j).  One record, so that a group's constants
+// arrive in a few wide scalar loads.
+struct alignas(16) LinkPair {
+  uint32_t mask;
+  float bthr;                  // (R_la + R_lb)^2 of the link bounding spheres
+  uint32_t pad_[2];
+  float sthr[kSpl];            // (r_i + R_lb)^2: sphere i of la vs lb's bound
+  float rr2[kSpl * kSpl];      // (r_i + r_j)^2 per pair (0 if not a pair)
+  float rs[kSpl * kSpl];       // r_i + r_j
+};
 
 // Robot constants in device memory.  Every field is read at a wave-uniform
 // address, so the kernels fetch it with scalar loads.
@@ -26,13 +38,9 @@ struct DevRobot {
   float a[kNdof], d[kNdof];
   float sc[kSlots][4];         // sphere slot centre (x, y, z) in its link frame, radius
   uint32_t slot_active;        // bit s set when slot s holds a sphere
-  // Self-collision pairs grouped by link pair (la <= lb, index la * kNdof + lb): bit
-  // i * kSpl + j of lp_mask marks the pair (slot la*kSpl+i, slot lb*kSpl+j).
-  uint32_t lp_mask[kNdof * kNdof];
-  float lp_bthr[kNdof * kNdof];              // (R_la + R_lb)^2 of the link bounding spheres
-  float lp_sthr[kNdof * kNdof][kSpl];        // (r_i + R_lb)^2: sphere i of la vs lb's bound
-  float lp_rr2[kNdof * kNdof][kSpl * kSpl];  // (r_i + r_j)^2 per pair (0 if not a pair)
-  float lp_rs[kNdof * kNdof][kSpl * kSpl];   // r_i + r_j
+  uint32_t pad0_[3];
+  // Self-collision pairs grouped by link pair, index la * kNdof + lb.
+  LinkPair lp[kNdof * kNdof];
   float lbound[kNdof];         // bounding radius of each link's spheres about its slot-0 sphere
   int32_t n_pairs;             // distinct pairs after de-duplication
   int32_t pad_[3];
@@ -63,6 +71,8 @@ struct StepParams {
   uint32_t grid_bytes;
   int32_t ncx, ncy, ncz;       // coarse bound cells per axis
   uint32_t coarse_bytes;       // 0: no coarse bounds
+  float cmax[3];               // ncx - 1, ncy - 1, ncz - 1
+  float cstride[2];            // ncx, ncx * ncy (cell index strides)
   int32_t K, H, R, P;          // samples, horizon, rollouts per K1 block, K1 blocks
   float dt;
   float inv_lambda;

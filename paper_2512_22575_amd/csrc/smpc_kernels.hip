@@ -321,17 +321,20 @@ __device__ __forceinline__ float esdf_lookup(__amdgpu_buffer_rsrc_t rsrc, const 
 
 // Coarse lower bound of the cell holding the lookup corner of p (0-filled past the
 // buffer, which only ever happens without bounds, and then it is not consulted).  The
-// corner is min(floor(u), n - 2) per axis with u clamped to [0, n - 1] (as in
-// esdf_locate), so its cell is min(trunc(u) >> 3, nc - 1).
+// corner is i0 = min(floor(u), n - 2) per axis with u clamped to [0, n - 1] (as in
+// esdf_locate), and its cell i0 >> 3 equals floor(u / 8) clamped to [0, nc - 1]:
+// u / 8 is exact, floor(u / 8) = floor(floor(u) / 8) for u >= 0, and the clamped ends
+// agree because nc - 1 = floor((n - 2) / 8) <= floor((n - 1) / 8).  The cell index is
+// formed in float (exact below 2^24).
 __device__ __forceinline__ float coarse_bound(__amdgpu_buffer_rsrc_t crsrc, const StepParams& p,
                                               float px, float py, float pz) {
-  const float ux = __builtin_amdgcn_fmed3f(fmaf(px, p.inv_voxel, p.gcx), 0.f, (float)(p.nx - 1));
-  const float uy = __builtin_amdgcn_fmed3f(fmaf(py, p.inv_voxel, p.gcy), 0.f, (float)(p.ny - 1));
-  const float uz = __builtin_amdgcn_fmed3f(fmaf(pz, p.inv_voxel, p.gcz), 0.f, (float)(p.nz - 1));
-  const uint32_t cx = min((uint32_t)ux >> kCoarseShift, (uint32_t)p.ncx - 1u);
-  const uint32_t cy = min((uint32_t)uy >> kCoarseShift, (uint32_t)p.ncy - 1u);
-  const uint32_t cz = min((uint32_t)uz >> kCoarseShift, (uint32_t)p.ncz - 1u);
-  const uint32_t cell = (cz * (uint32_t)p.ncy + cy) * (uint32_t)p.ncx + cx;
+  const float cx = __builtin_amdgcn_fmed3f(floorf(fmaf(px, p.inv_voxel, p.gcx) * 0.125f), 0.f,
+                                           p.cmax[0]);
+  const float cy = __builtin_amdgcn_fmed3f(floorf(fmaf(py, p.inv_voxel, p.gcy) * 0.125f), 0.f,
+                                           p.cmax[1]);
+  const float cz = __builtin_amdgcn_fmed3f(floorf(fmaf(pz, p.inv_voxel, p.gcz) * 0.125f), 0.f,
+                                           p.cmax[2]);
+  const uint32_t cell = (uint32_t)fmaf(cz, p.cstride[1], fmaf(cy, p.cstride[0], cx));
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(crsrc, cell * 4u, 0, 0));
 }
 
@@ -429,20 +432,26 @@ __device__ __forceinline__ float step_cost(const DevRobot* __restrict__ rob, con
   for (int la = 0; la < kNdof; ++la) {
 #pragma unroll
     for (int lb = la; lb < kNdof; ++lb) {
-      const int lp = la * kNdof + lb;
-      const uint32_t mask = rob->lp_mask[lp];
+      const LinkPair& G = rob->lp[la * kNdof + lb];
+      const uint32_t mask = G.mask;
       if (mask == 0u) continue;
       bool near = true;
       if (la != lb) {
         // A link's bounding sphere is centred on the sphere in its first slot.
         const int ca = la * kSpl, cb = lb * kSpl;
         const float dx = px[ca] - px[cb], dy = py[ca] - py[cb], dz = pz[ca] - pz[cb];
-        near = fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rob->lp_bthr[lp];
+        near = fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < G.bthr;
       }
       if (near) {
-        float rr2[kSpl * kSpl];
+        // The group's constants, fetched together before any of them is used.
+        float sthr[kSpl], rr2[kSpl * kSpl], rs[kSpl * kSpl];
 #pragma unroll
-        for (int b = 0; b < kSpl * kSpl; ++b) rr2[b] = rob->lp_rr2[lp][b];
+        for (int i = 0; i < kSpl; ++i) sthr[i] = G.sthr[i];
+#pragma unroll
+        for (int b = 0; b < kSpl * kSpl; ++b) {
+          rr2[b] = G.rr2[b];
+          rs[b] = G.rs[b];
+        }
 #pragma unroll
         for (int i = 0; i < kSpl; ++i) {
           if (!(mask & (0xFu << (i * kSpl)))) continue;
@@ -451,7 +460,7 @@ __device__ __forceinline__ float step_cost(const DevRobot* __restrict__ rob, con
           if (la != lb) {
             const int sa = la * kSpl + i, cb = lb * kSpl;
             const float dx = px[sa] - px[cb], dy = py[sa] - py[cb], dz = pz[sa] - pz[cb];
-            if (!(fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < rob->lp_sthr[lp][i])) continue;
+            if (!(fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < sthr[i])) continue;
           }
 #pragma unroll
           for (int j = 0; j < kSpl; ++j) {
@@ -461,7 +470,7 @@ __device__ __forceinline__ float step_cost(const DevRobot* __restrict__ rob, con
             const float dx = px[sa] - px[sb], dy = py[sa] - py[sb], dz = pz[sa] - pz[sb];
             const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
             if (d2 < rr2[bit]) {
-              const float h = rob->lp_rs[lp][bit] - sqrt_hw(d2);
+              const float h = rs[bit] - sqrt_hw(d2);
               c_self = fmaf(h, h, c_self);
             }
           }
@@ -573,7 +582,9 @@ struct K1Lds {
   float* sc0;    // [16]     sin(q0), cos(q0)
   float* x0;     // [16]     q0, qd0
   float* e;      // [R]      exp(-(S - m_b)/lambda)
-  float* seg;    // [R*7*nseg*2] velocity / displacement increments of 8-step segments
+  float* seg;    // [R*7*nseg*2 + 2*kSeg] velocity / displacement increments of 8-step
+                 //          segments (the tail pads reads of absent segments)
+  double* sr;    // [R]      per-rollout cost sums
 };
 
 constexpr int kSeg = 8;  // integration segment length
@@ -591,8 +602,17 @@ __device__ __forceinline__ K1Lds k1_lds(unsigned char* base, int R, int H) {
   L.sc0 = L.cost + R * H;
   L.x0 = L.sc0 + 16;
   L.e = L.x0 + 16;
-  L.seg = L.e + R;
+  // 8-byte aligned (read as float2).
+  L.seg = reinterpret_cast<float*>((reinterpret_cast<uintptr_t>(L.e + R) + 7) & ~uintptr_t(7));
+  const uintptr_t end = reinterpret_cast<uintptr_t>(L.seg + R * kNdof * k1_segments(H) * 2 + 2 * kSeg);
+  L.sr = reinterpret_cast<double*>((end + 7) & ~uintptr_t(7));
   return L;
+}
+
+// q / d for 0 <= q < 2^12 and 1 <= d <= 64 by a float reciprocal: (q + 1/2) / d lies at
+// least 1/(2d) from an integer and the product's rounding error is far below that.
+__device__ __forceinline__ int div_small(int q, float inv_d) {
+  return (int)(((float)q + 0.5f) * inv_d);
 }
 
 // Rollout-cost work of block b (counted within its request) of request q.
@@ -664,23 +684,30 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
   // dx + n dt v) and replays its steps.
   const int nseg = k1_segments(H);
   const int n_items = R * kNdof * nseg;
-  for (int w = tid; w < n_items; w += nthreads) {
-    const int sg = w % nseg, rj = w / nseg, r = rj / kNdof, j = rj - r * kNdof;
-    if (r < nroll) {
+  const float inv_nseg = 1.f / (float)nseg;
+  // Item w = ((r * 7 + j) * nseg + sg): rollout r, joint j, segment sg.  Its controls are
+  // read at a constant stride from the segment's first row (rows past H - 1 read padding
+  // or the next rollout and are never used).  A thread keeps its items' controls in
+  // registers for the second pass (at most kMaxItems items per thread).
+  constexpr int kMaxItems = 2;
+  float uk[kMaxItems][kSeg];
+#pragma unroll
+  for (int it = 0; it < kMaxItems; ++it) {
+    const int w = tid + it * nthreads;
+    const int rj = div_small(w, inv_nseg), sg = w - rj * nseg;
+    const int r = div_small(rj, 1.f / 7.f), j = rj - r * kNdof;
+    if (w < n_items && r < nroll) {
       const float dt = p.dt, qd0 = L.x0[kNdof + j];
       const int k0 = sg * kSeg;
-      const float* eps_r = L.eps + r * H * kNdof + j;
-      float u[kSeg];
+      const float* e_p = L.eps + (__mul24(r, H) + k0) * kNdof + j;
+      const float* u_p = L.ubar + k0 * kNdof + j;
 #pragma unroll
-      for (int c = 0; c < kSeg; ++c) {
-        const int k = min(k0 + c, H - 1);
-        u[c] = L.ubar[k * kNdof + j] + eps_r[k * kNdof];  // eq. 27
-      }
+      for (int c = 0; c < kSeg; ++c) uk[it][c] = u_p[c * kNdof] + e_p[c * kNdof];  // eq. 27
       float dv = 0.f, dx = 0.f;
 #pragma unroll
       for (int c = 0; c < kSeg; ++c) {
         if (k0 + c < H) {
-          dv = fmaf(u[c], dt, dv);
+          dv = fmaf(uk[it][c], dt, dv);
           dx = fmaf(qd0 + dv, dt, dx);
         }
       }
@@ -689,36 +716,37 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
     }
   }
   __syncthreads();
-  for (int w = tid; w < n_items; w += nthreads) {
-    const int sg = w % nseg, rj = w / nseg, r = rj / kNdof, j = rj - r * kNdof;
-    if (r < nroll) {
+#pragma unroll
+  for (int it = 0; it < kMaxItems; ++it) {
+    const int w = tid + it * nthreads;
+    const int rj = div_small(w, inv_nseg), sg = w - rj * nseg;
+    const int r = div_small(rj, 1.f / 7.f), j = rj - r * kNdof;
+    if (w < n_items && r < nroll) {
       const float dt = p.dt, qd0 = L.x0[kNdof + j];
       const int k0 = sg * kSeg;
-      const float* eps_r = L.eps + r * H * kNdof + j;
-      float u[kSeg];
+      const float2* sp = reinterpret_cast<const float2*>(L.seg) + rj * nseg;
+      float2 pvx[kSeg - 1];
 #pragma unroll
-      for (int c = 0; c < kSeg; ++c) {
-        const int k = min(k0 + c, H - 1);
-        u[c] = L.ubar[k * kNdof + j] + eps_r[k * kNdof];
-      }
+      for (int c = 0; c < kSeg - 1; ++c) pvx[c] = sp[c];  // earlier segments (c < sg used)
       float dqd = 0.f, dq = 0.f;
       const float full = (float)kSeg * dt;
-      for (int s2 = 0; s2 < sg; ++s2) {  // earlier segments are full
-        const float dv = L.seg[2 * (rj * nseg + s2)], dx = L.seg[2 * (rj * nseg + s2) + 1];
-        dq = fmaf(full, dqd, dq + dx);
-        dqd += dv;
+#pragma unroll
+      for (int c = 0; c < kSeg - 1; ++c) {  // earlier segments are full
+        if (c < sg) {
+          dq = fmaf(full, dqd, dq + pvx[c].y);
+          dqd += pvx[c].x;
+        }
       }
-      float* dq_r = L.dq + r * H * kNdof + j;
-      float* qd_r = L.qd + r * H * kNdof + j;
+      float* dq_r = L.dq + (__mul24(r, H) + k0) * kNdof + j;
+      float* qd_r = L.qd + (__mul24(r, H) + k0) * kNdof + j;
 #pragma unroll
       for (int c = 0; c < kSeg; ++c) {
-        const int k = k0 + c;
-        if (k < H) {
-          dqd = fmaf(u[c], dt, dqd);
+        if (k0 + c < H) {
+          dqd = fmaf(uk[it][c], dt, dqd);
           const float qd = qd0 + dqd;
           dq = fmaf(qd, dt, dq);
-          dq_r[k * kNdof] = dq;
-          qd_r[k * kNdof] = qd;
+          dq_r[c * kNdof] = dq;
+          qd_r[c * kNdof] = qd;
         }
       }
     }
@@ -727,10 +755,10 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
 
   // Per-(rollout, step) cost.
   if (tid < RH) {
-    const int r = tid / H, k = tid - r * H;
+    const int r = div_small(tid, 1.f / (float)H), k = tid - __mul24(r, H);
     float cost = 0.f;
     if (r < nroll) {
-      const int base = (r * H + k) * kNdof;
+      const int base = tid * kNdof;
       float dq[kNdof], qd[kNdof], u[kNdof];
 #pragma unroll
       for (int j = 0; j < kNdof; ++j) {
@@ -754,8 +782,11 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
   // S^(m) without the k = 0 state terms (eq. 28), summed over k in double, and the
   // block's softmax partial (eqs. 29-30 regrouped per block), by wave 0: G = 64 / R
   // (rounded down to a power of 2) lanes per rollout, lane j of rollout r summing
-  // steps k = j, j + G, ... in order, then a butterfly over the G lanes; the
-  // minimum and the sums over rollouts go through further fixed butterflies.
+  // steps k = j, j + G, ... in order, then a butterfly over the G lanes.  The block
+  // minimum and the sums of exponentials then run over the rollouts in order, every lane
+  // reading the per-rollout values back from LDS (one wave's LDS accesses complete in
+  // program order, so no barrier is needed).  The global stores come last, so that no
+  // wait for them delays the exchange.
   if (tid < kWave) {
     int G = 1;
     while (G * 2 * R <= kWave) G *= 2;
@@ -773,19 +804,36 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
       }
     }
     for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
-    if (r < nroll && j == 0) ws.S[m0 + r] = s;
-    const bool fin = r < nroll && j == 0 && isfinite(s);
-    double mn = fin ? s : __builtin_inf();
+    if (r < nroll && j == 0) L.sr[r] = s;
+    __builtin_amdgcn_wave_barrier();
+    constexpr int kBatch = 8;  // LDS reads in flight at once
+    double mn = __builtin_inf();
+    for (int r0 = 0; r0 < nroll; r0 += kBatch) {
+      double v[kBatch];
 #pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) mn = fmin(mn, __shfl_xor(mn, off, kWave));
-    const float e = (fin && isfinite(mn)) ? expf(-(float)(s - mn) * p.inv_lambda) : 0.f;
-    float Z = e, Z2 = e * e;
+      for (int c = 0; c < kBatch; ++c) v[c] = L.sr[min(r0 + c, nroll - 1)];
 #pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-      Z += __shfl_xor(Z, off, kWave);
-      Z2 += __shfl_xor(Z2, off, kWave);
+      for (int c = 0; c < kBatch; ++c)
+        if (isfinite(v[c])) mn = fmin(mn, v[c]);  // a repeated last value changes nothing
     }
+    const bool fin = r < nroll && j == 0 && isfinite(s);
+    const float e = (fin && isfinite(mn)) ? expf(-(float)(s - mn) * p.inv_lambda) : 0.f;
     if (r < R && j == 0) L.e[r] = e;
+    __builtin_amdgcn_wave_barrier();
+    float Z = 0.f, Z2 = 0.f;
+    for (int r0 = 0; r0 < nroll; r0 += kBatch) {
+      float v[kBatch];
+#pragma unroll
+      for (int c = 0; c < kBatch; ++c) v[c] = L.e[min(r0 + c, nroll - 1)];
+#pragma unroll
+      for (int c = 0; c < kBatch; ++c) {
+        if (r0 + c < nroll) {
+          Z += v[c];
+          Z2 = fmaf(v[c], v[c], Z2);
+        }
+      }
+    }
+    if (r < nroll && j == 0) ws.S[m0 + r] = s;
     if (tid == 0) {
       ws.part_m[b] = mn;
       ws.part_Z[b] = Z;
@@ -793,25 +841,33 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
     }
   }
   __syncthreads();
-  // N_b[o] = sum_r e_r eps_r[o], one contiguous row per block (padded to 4 floats).
+  // N_b[o] = sum_r e_r eps_r[o], one contiguous row per block (padded to 4 floats), two
+  // consecutive outputs per thread.
   const int HO = H * kNdof, HO4 = (HO + 3) & ~3;
-  for (int o = tid; o < HO4; o += nthreads) {
-    float acc = 0.f;
+  for (int o = 2 * tid; o < HO4; o += 2 * nthreads) {
+    float acc0 = 0.f, acc1 = 0.f;
+    const int o1 = min(o + 1, HO - 1);
     if (o < HO) {
       for (int r0 = 0; r0 < nroll; r0 += 8) {
-        float ev[8], xv[8];
+        float ev[8], xv0[8], xv1[8];
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
           const int r = min(r0 + c, nroll - 1);
           ev[c] = L.e[r];
-          xv[c] = L.eps[r * HO + o];
+          xv0[c] = L.eps[r * HO + o];
+          xv1[c] = L.eps[r * HO + o1];
         }
 #pragma unroll
-        for (int c = 0; c < 8; ++c)  // weight-0 rollouts excluded
-          if (r0 + c < nroll && ev[c] > 0.f) acc = fmaf(ev[c], xv[c], acc);
+        for (int c = 0; c < 8; ++c) {  // weight-0 rollouts excluded
+          if (r0 + c < nroll && ev[c] > 0.f) {
+            acc0 = fmaf(ev[c], xv0[c], acc0);
+            acc1 = fmaf(ev[c], xv1[c], acc1);
+          }
+        }
       }
     }
-    ws.part_N[(size_t)b * HO4 + o] = acc;
+    ws.part_N[(size_t)b * HO4 + o] = acc0;
+    ws.part_N[(size_t)b * HO4 + o + 1] = o + 1 < HO ? acc1 : 0.f;
   }
 }
 
@@ -823,13 +879,16 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
 template <int kElemBytes>
 __global__ __launch_bounds__(kK1Threads) __attribute__((amdgpu_waves_per_eu(4))) void
 rollout_cost_kernel(const DevRobot* __restrict__ rob, const Request q) {
-  if ((int)blockIdx.x == q.p.P) {
-    // One extra block evaluates the state-0 terms while the rollout blocks run.
+  // With the state-0 terms requested, block 0 evaluates them and the rollout blocks
+  // follow: the dispatcher places blocks in index order and fills each CU with two
+  // rollout blocks, so an extra block at the end would only start when one of them ends.
+  const int b = (int)blockIdx.x - q.c0_in_ws;
+  if (b < 0) {
     const float c0 = state0_cost<kElemBytes>(rob, q.p, q.grid, q.state_in);
     if (threadIdx.x == 0) q.ws.c0[0] = c0;
     return;
   }
-  rollout_cost_block<kElemBytes>(rob, q, blockIdx.x);
+  rollout_cost_block<kElemBytes>(rob, q, b);
 }
 
 // A batch of plan steps: block_req maps each block to its request.
@@ -857,7 +916,7 @@ struct GlobalStats {
   double m;
   float Z, Z2;
 };
-constexpr int kStatRows = 8;
+constexpr int kStatRows = 12;
 
 // Rows of the first round, loaded by stats_load and folded by stats_finish (so a
 // caller can issue the loads early and overlap their latency with other work).
@@ -930,7 +989,7 @@ __device__ __forceinline__ GlobalStats wave_stats(const Workspace& ws, int P, fl
 constexpr int kCostsPerThread = 32;   // costs per thread per later pass
 constexpr int kCostsAhead = 16;       // costs per thread loaded before c0 (K <= 4096)
 constexpr int kRowGroups = kK2Threads / kOutPerBlock;
-constexpr int kRowsAhead = 16;  // partial rows per thread loaded before the statistics
+constexpr int kRowsAhead = 24;  // partial rows per thread loaded before the statistics
 constexpr int kWeightsPerThread = kWeightsPerBlock / kK2Threads;
 
 template <int kElemBytes>
@@ -1711,14 +1770,20 @@ __global__ __launch_bounds__(256) void grid_to_f16_kernel(const float* __restric
 
 static size_t k1_lds_bytes(int R, int H) {
   const size_t floats = (size_t)R * H * kNdof * 3 + (size_t)H * kNdof + (size_t)R * H + 32 + R +
-                        (size_t)R * kNdof * k1_segments(H) * 2;
-  return floats * 4;
+                        (size_t)R * kNdof * k1_segments(H) * 2 + 2 * kSeg;
+  return floats * 4 + 4 + 8 + (size_t)R * 8;  // seg aligned; R doubles 8-byte aligned
 }
+
+static_assert(kK1Threads == 256, "the integration keeps at most two items per thread: "
+              "R * 7 * ceil(H / 8) <= 512 for R = min(64, 256 / H), 1 <= H <= 64");
 
 LaunchConfig plan_launch_config(int K, int H) {
   // Every block has kK1Threads threads and holds R = kK1Threads / H whole rollouts
   // (at most 64), whatever else shares the launch: a request's arithmetic is the
-  // same alone and in a batch.  320 = 5 waves fits H = 16, 32, 40 and 64 exactly.
+  // same alone and in a batch.  Four waves put one wave of every block on each SIMD
+  // of a CU, so the SIMDs of a CU carry equal work (a five-wave block doubles up on one
+  // SIMD, and two such blocks on the same one leave it with twice the others' work).
+  // 256 fits H = 16, 32 and 64 exactly and uses 240 lanes at H = 40.
   int R = kK1Threads / H;
   if (R > 64) R = 64;
   if (R < 1) R = 1;

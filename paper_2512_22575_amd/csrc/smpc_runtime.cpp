@@ -252,6 +252,11 @@ StepParams make_params(const smpc_ctx* ctx, const smpc_plan_args* a, const Launc
   p.ncz = coarse_cells_1d(a->esdf.nz);
   p.coarse_bytes =
       a->esdf.coarse ? (uint32_t)((long long)p.ncx * p.ncy * p.ncz * (long long)sizeof(float)) : 0u;
+  p.cmax[0] = (float)(p.ncx - 1);
+  p.cmax[1] = (float)(p.ncy - 1);
+  p.cmax[2] = (float)(p.ncz - 1);
+  p.cstride[0] = (float)p.ncx;
+  p.cstride[1] = (float)((long long)p.ncx * p.ncy);
   p.seed_lo = (uint32_t)a->seed;
   p.seed_hi = (uint32_t)(a->seed >> 32);
   for (int j = 0; j < kNdof; ++j) p.sigma[j] = a->sigma[j];
@@ -443,13 +448,13 @@ smpc_status smpc_set_robot(smpc_ctx* ctx, const smpc_robot_desc* d) {
     ++n_unique;
     const int la = a / kSpl, lb = b / kSpl, lp = la * kNdof + lb;
     const int bit = (a % kSpl) * kSpl + (b % kSpl);
-    r.lp_mask[lp] |= 1u << bit;
-    r.lp_rr2[lp][bit] = (float)(rs * rs);
-    r.lp_rs[lp][bit] = (float)rs;
+    r.lp[lp].mask |= 1u << bit;
+    r.lp[lp].rr2[bit] = (float)(rs * rs);
+    r.lp[lp].rs[bit] = (float)rs;
     const double bt = bound_r[la] + bound_r[lb];
-    r.lp_bthr[lp] = (float)(bt * bt);
+    r.lp[lp].bthr = (float)(bt * bt);
     const double sb = ctx->slot_radius[a] + bound_r[lb];
-    r.lp_sthr[lp][a % kSpl] = (float)(sb * sb);
+    r.lp[lp].sthr[a % kSpl] = (float)(sb * sb);
   }
   r.n_pairs = n_unique;
   ctx->host_robot = r;

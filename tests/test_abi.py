@@ -286,12 +286,12 @@ def test_noalloc_rejects_a_workspace_beyond_the_static_scratch(ctx):
     assert S.smpc_set_robot(ctx, S.robot_desc(R.make_robot(0))) == S.SMPC_OK
     lib = S.load_library()
     limit = 4 << 20
-    assert lib.smpc_plan_workspace_bytes(27953, 40) > limit >= lib.smpc_plan_workspace_bytes(27952, 40)
-    big = dict(K=27953, H=40, noise=_FakeTensor((27953, 40, 7)), U_in=_FakeTensor((40, 7)),
+    assert lib.smpc_plan_workspace_bytes(21247, 40) > limit >= lib.smpc_plan_workspace_bytes(21246, 40)
+    big = dict(K=21247, H=40, noise=_FakeTensor((21247, 40, 7)), U_in=_FakeTensor((40, 7)),
                U_out=_FakeTensor((40, 7), ptr=0x100000))
     _expect_noalloc(ctx, _args(**big), S.SMPC_E_INVALID_ARG, "static scratch")
     # One rollout fewer fits, and the call stops at the next check (robot not resident).
-    fits = dict(big, K=27952, noise=_FakeTensor((27952, 40, 7)))
+    fits = dict(big, K=21246, noise=_FakeTensor((21246, 40, 7)))
     _expect_noalloc(ctx, _args(**fits), S.SMPC_E_INVALID_ARG, "not on the device")
 
 
