@@ -9,7 +9,8 @@ All inputs are seeded synthetic data and are resident in device memory before
 timing starts.
 
 One step = one control period of the closed loop on a fresh grid: the coarse
-lower bounds of that period's grid (smpc_grid_coarse_min) and one plan step
+lower bounds of that period's grid over the cells the arm can reach
+(smpc_grid_coarse_min_ball with smpc_robot_reach) and one plan step
 (smpc_plan_step, both kernels) that reads the joint state and nominal sequence the
 previous period left on the device, executes u*_0 for one period and shifts the
 nominal sequence (receding horizon).  The grids of consecutive periods (built on
@@ -313,9 +314,10 @@ def edt_bench(args) -> None:
 
     def pipeline(i):
         edt(i)
-        st = S.smpc_grid_coarse_min(phi, S.GRID_F32, coarse.data_ptr(), stream)
+        st = S.smpc_grid_coarse_min_ball(phi, S.GRID_F32, sc.origin, sc.VOXEL, *planner.robot_reach(),
+                                         coarse.data_ptr(), stream)
         if st != S.SMPC_OK:
-            raise S.SMPCError(st, "smpc_grid_coarse_min")
+            raise S.SMPCError(st, "smpc_grid_coarse_min_ball")
         st = S.smpc_plan_step(planner._ctx, plans[i], stream)
         if st != S.SMPC_OK:
             raise S.SMPCError(st, S.smpc_last_error(planner._ctx))
@@ -365,7 +367,7 @@ def edt_bench(args) -> None:
                      "bytes_per_voxel": EDT_BYTES_PER_VOXEL},
         "occupancy_h2d_ms": round(h2d_ms, 5),
         "pipeline_ms_per_step": round(pipe_ms, 5),
-        "pipeline": f"smpc_edt, smpc_grid_coarse_min, then smpc_plan_step (K={K}, H={H}) "
+        "pipeline": f"smpc_edt, smpc_grid_coarse_min_ball, then smpc_plan_step (K={K}, H={H}) "
                     "on the new field",
         **extra,
     }), flush=True)
@@ -448,9 +450,10 @@ def ogm_bench(args) -> None:
                         ework.data_ptr(), need, stream)
         if st != S.SMPC_OK:
             raise S.SMPCError(st, "smpc_edt")
-        st = S.smpc_grid_coarse_min(phi, S.GRID_F32, coarse.data_ptr(), stream)
+        st = S.smpc_grid_coarse_min_ball(phi, S.GRID_F32, sc.origin, sc.VOXEL, *planner.robot_reach(),
+                                         coarse.data_ptr(), stream)
         if st != S.SMPC_OK:
-            raise S.SMPCError(st, "smpc_grid_coarse_min")
+            raise S.SMPCError(st, "smpc_grid_coarse_min_ball")
         st = S.smpc_plan_step(planner._ctx, plans[i], stream)
         if st != S.SMPC_OK:
             raise S.SMPCError(st, S.smpc_last_error(planner._ctx))
@@ -512,7 +515,7 @@ def ogm_bench(args) -> None:
                      "bytes_per_voxel": OGM_BYTES_PER_VOXEL,
                      "bytes_per_pixel": OGM_BYTES_PER_PIXEL},
         "pipeline_ms_per_step": round(pipe_ms, 5),
-        "pipeline": f"smpc_ogm_update, smpc_edt on its occupancy, smpc_grid_coarse_min, then "
+        "pipeline": f"smpc_ogm_update, smpc_edt on its occupancy, smpc_grid_coarse_min_ball, then "
                     f"smpc_plan_step (K={K}, H={H}) on the new field",
         **extra,
     }), flush=True)
@@ -689,6 +692,10 @@ def main():
     stats = torch.empty((4,), device=dev)
     planner = S.Planner(sc.robot, device=0)
     ctx = planner._ctx
+    # The bounds are built for the cells the arm's spheres can reach (smpc_robot_reach);
+    # the other cells get -inf, so plan steps are exact whatever the arm does.
+    reach_c, reach_r = planner.robot_reach()
+    reach_cp = (ctypes.c_float * 3)(*[float(x) for x in reach_c])
     # Closed loop on the device: two nominal sequences and two joint states alternate.
     U = [torch.zeros((H, 7), device=dev), torch.zeros((H, 7), device=dev)]
     X0 = torch.from_numpy(np.concatenate([sc.q0, sc.qd0]).astype(np.float32)).to(dev)
@@ -708,7 +715,8 @@ def main():
         sc.t += sc.DT
     for g in grids:
         grid_structs.append(S.smpc_grid(ctypes.c_void_p(g.data_ptr()), n, n, n, S.GRID_F32,
-                                        (ctypes.c_float * 3)(0.0, 0.0, 0.0), 1.0, None))
+                                        (ctypes.c_float * 3)(*[float(x) for x in sc.origin]),
+                                        float(sc.VOXEL), None))
     plan_ptrs = [ctypes.byref(a) for a in plans]
     grid_ptrs = [ctypes.byref(g) for g in grid_structs]
     coarse_ptr = ctypes.c_void_p(coarse.data_ptr() if use_coarse else 0)
@@ -718,9 +726,10 @@ def main():
         """One control period on a fresh grid: bounds of the new grid, then the plan step
         (which executes u*_0 and shifts the nominal sequence on the device)."""
         if use_coarse:
-            st = lib.smpc_grid_coarse_min(grid_ptrs[i % n_grids], coarse_ptr, sp)
+            st = lib.smpc_grid_coarse_min_ball(grid_ptrs[i % n_grids], reach_cp, reach_r,
+                                               coarse_ptr, sp)
             if st != S.SMPC_OK:
-                raise S.SMPCError(st, "smpc_grid_coarse_min")
+                raise S.SMPCError(st, "smpc_grid_coarse_min_ball")
         st = lib.smpc_plan_step(ctx, plan_ptrs[i], sp)
         if st != S.SMPC_OK:
             raise S.SMPCError(st, S.smpc_last_error(ctx))
@@ -778,7 +787,8 @@ def main():
         if use_coarse:
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
-            st = lib.smpc_grid_coarse_min(grid_ptrs[i % n_grids], coarse_ptr, sp)
+            st = lib.smpc_grid_coarse_min_ball(grid_ptrs[i % n_grids], reach_cp, reach_r,
+                                               coarse_ptr, sp)
             e1.record()
             cb.append((e0, e1))
         st = lib.smpc_plan_step(ctx, plan_ptrs[i], sp)
@@ -800,9 +810,10 @@ def main():
         c0 = None
         if use_coarse:
             c0 = torch.empty_like(coarse)
-            st = lib.smpc_grid_coarse_min(grid_ptrs[0], ctypes.c_void_p(c0.data_ptr()), sp)
+            st = lib.smpc_grid_coarse_min_ball(grid_ptrs[0], reach_cp, reach_r,
+                                               ctypes.c_void_p(c0.data_ptr()), sp)
             if st != S.SMPC_OK:
-                raise S.SMPCError(st, "smpc_grid_coarse_min")
+                raise S.SMPCError(st, "smpc_grid_coarse_min_ball")
         splans = [S.plan_args(sc.q0, sc.qd0, plans[i].T_goal, g0, sc.origin, sc.VOXEL,
                               noise[i % n_pool], U[i % 2], U[(i + 1) % 2], K, H, sc.DT, 1.0,
                               sc.weights, costs_out=costs, stats_out=stats, coarse=c0,
@@ -844,8 +855,9 @@ def main():
                         f"primitives drifting 0.2 m/s, target on a 0.3 m circle, 7-DoF arm, "
                         f"28 spheres, {sc.robot.n_pairs} self pairs",
             "K": K, "H": H, "grid": [n] * 3, "voxel_m": 0.01, "lambda": 1.0,
-            "period": ("coarse bounds of the period's grid + plan step that executes u*_0 and "
-                       "shifts the nominal sequence on the device" if use_coarse else
+            "period": ("coarse bounds of the period's grid (cells within the arm's reach) + "
+                       "plan step that executes u*_0 and shifts the nominal sequence on the "
+                       "device" if use_coarse else
                        "plan step that executes u*_0 and shifts the nominal sequence on the "
                        "device (no coarse bounds)"),
             "grids": f"{n_grids} distinct consecutive-period grids resident in HBM "

@@ -271,6 +271,28 @@ int64_t smpc_grid_coarse_cells(int32_t nx, int32_t ny, int32_t nz);
  */
 smpc_status smpc_grid_coarse_min(const smpc_grid* grid, float* coarse_out, void* stream);
 
+/*
+ * smpc_grid_coarse_min for the lookups of points within `radius` metres of `center`
+ * (world frame, the frame of grid->origin; grid->origin and grid->voxel are used):
+ * cells that no such lookup reaches (R5's clamping included) get -inf, which never lets
+ * a lookup be skipped, so a plan step stays exact wherever its spheres go; the others
+ * get smpc_grid_coarse_min's bound.  Rows of cells outside the ball are not read.
+ * radius = +inf gives smpc_grid_coarse_min's table; center finite, radius >= 0.
+ * With smpc_robot_reach's ball a table holds a bound for every cell the arm can query.
+ * Runs on the device current to the calling thread, asynchronously on `stream`.
+ */
+smpc_status smpc_grid_coarse_min_ball(const smpc_grid* grid, const float center[3],
+                                      float radius, float* coarse_out, void* stream);
+
+/*
+ * A ball holding every sphere centre of the context's robot at any joint values: the
+ * base (the world origin, R3) and radius max over spheres s on link l of
+ * sum_{i <= l} sqrt(a_i^2 + d_i^2) + |c_s|, plus 1 mm (with modified DH each joint moves
+ * the frame origin by exactly sqrt(a_i^2 + d_i^2)).
+ * SMPC_E_INVALID_ARG when no robot is set.  Host only.
+ */
+smpc_status smpc_robot_reach(const smpc_ctx* ctx, float center_out[3], float* radius_out);
+
 /* ---- Occupancy mapping (Sec. III-A) with the robot mask (Remark 2) ----------- */
 
 /* Pinhole depth camera.  Pixel (i, j) covers [i, i + 1) x [j, j + 1) in image

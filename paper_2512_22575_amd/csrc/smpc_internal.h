@@ -166,8 +166,10 @@ constexpr int kCoarseCell = SMPC_COARSE_CELL;
 constexpr int kCoarseShift = 3;  // log2(kCoarseCell)
 static_assert((1 << kCoarseShift) == kCoarseCell, "coarse cell edge");
 inline int coarse_cells_1d(int n) { return (n - 2) / kCoarseCell + 1; }
-int launch_grid_coarse_min(const void* grid, bool f16, int nx, int ny, int nz, float* out,
-                           void* stream);
+// Coarse bounds; ball_c (3 floats, continuous-index units) and ball_r2 restrict them to
+// the cells the lookups of a ball reach (the others get -inf); ball_c null: every cell.
+int launch_grid_coarse_min(const void* grid, bool f16, int nx, int ny, int nz,
+                           const float* ball_c, float ball_r2, float* out, void* stream);
 
 // Occupancy update (smpc_ogm_update): everything the two kernels need, by value.
 struct OgmArgs {

@@ -1189,13 +1189,31 @@ __global__ __launch_bounds__(256) void sample_noise_kernel(uint32_t k0, uint32_t
 // value -- with a batch of loads in flight; then each cell combines its 9 columns
 // [8 cx, 8 cx + 8] through LDS.  The x axis is covered in chunks of 31 cells (249
 // columns).  A non-finite value anywhere in a cell's window makes its bound -inf.
+// A ball of query points in continuous-index units (u = (p - origin) / voxel - 1/2
+// per axis): centre c and radius r; r = inf takes every cell.  Cell k along an axis
+// (nk cells) holds the lookups with u in [8k, 8k + 8), extended to -inf for k = 0 and
+// to +inf for k = nk - 1 by the clamping of the lookup (R5).
+struct CoarseBall {
+  float c[3];
+  float r2;
+};
+
+// Squared distance, along one axis, from the ball centre to the u-range of cells
+// [k0, k1].
+__device__ __forceinline__ float coarse_axis_gap(float c, int k0, int k1, int nk) {
+  const float lo = k0 == 0 ? -__builtin_inff() : 8.f * (float)k0;
+  const float hi = k1 == nk - 1 ? __builtin_inff() : 8.f * (float)(k1 + 1);
+  const float d = fmaxf(fmaxf(lo - c, c - hi), 0.f);
+  return d * d;
+}
+
 constexpr int kCoarseThreads = 256;
 constexpr int kCellsPerChunk = (kCoarseThreads - 1) / kCoarseCell;  // 31
 
 template <int kElemBytes>
 __global__ __launch_bounds__(kCoarseThreads) void grid_coarse_min_kernel(
     const void* __restrict__ grid, uint32_t grid_bytes, int nx, int ny, int nz, int ncx,
-    int ncy, int ncz, float* __restrict__ out) {
+    int ncy, int ncz, CoarseBall ball, float* __restrict__ out) {
   __shared__ float col_min[kCoarseThreads], col_max[kCoarseThreads];
   __shared__ int col_bad[kCoarseThreads];
   const int cy = blockIdx.x % ncy, cz = blockIdx.x / ncy;
@@ -1205,6 +1223,13 @@ __global__ __launch_bounds__(kCoarseThreads) void grid_coarse_min_kernel(
   const int rows = wy * wz;
   const __amdgpu_buffer_rsrc_t rsrc = grid_resource(grid, grid_bytes);
   const int tid = threadIdx.x;
+  if (coarse_axis_gap(ball.c[0], 0, ncx - 1, ncx) + coarse_axis_gap(ball.c[1], cy, cy, ncy) +
+          coarse_axis_gap(ball.c[2], cz, cz, ncz) > ball.r2) {
+    // No lookup from the ball reaches this row of cells: no bound (never skips).
+    for (int cx = tid; cx < ncx; cx += kCoarseThreads)
+      out[((long long)cz * ncy + cy) * ncx + cx] = -__builtin_inff();
+    return;
+  }
   for (int cx0 = 0; cx0 < ncx; cx0 += kCellsPerChunk) {
     const int x0 = cx0 * kCoarseCell;
     const int x = min(x0 + tid, nx - 1);
@@ -1253,11 +1278,12 @@ __global__ __launch_bounds__(kCoarseThreads) void grid_coarse_min_kernel(
 // 16-byte-aligned grid.  A block covers one row (cy, cz) of cells and a chunk of
 // kCoarseChunkGroups - 1 sixteen-byte groups of columns (31 cells of float32, 63 of
 // float16) plus the next group, whose first column closes the chunk's last window.
-// Thread (s, g) loads group g of rows s, s + 5, ... of the cell row's window (all
-// its loads issued at once; row and group indices are clamped instead of masked,
-// since a repeated value changes neither a minimum nor a maximum) and folds, per
-// group, the minimum and the largest |phi| (+inf for a non-finite value) of all its
-// columns and of its first column alone.  The five row subsets meet in LDS, then
+// Wave s of the block loads group g (its lane) of the 9 rows of planes s and s + 5 of
+// the cell row's window (all loads issued at once, at wave-uniform row starts; plane,
+// row and group indices are clamped instead of masked, since a repeated value changes
+// neither a minimum nor a maximum) and folds, per group, the minimum and the largest
+// |phi| (with non-finite values flagged) of all its columns and of its first column
+// alone.  The five waves' partial results meet in LDS, then
 // each cell combines its groups: the window [8 cx, 8 cx + 8] is two whole groups of
 // float32 (one of float16) plus the first column of the next one, or ends at the
 // last column of the row.  Blocks are laid out by XCD (block b runs on XCD b mod 8,
@@ -1266,49 +1292,70 @@ __global__ __launch_bounds__(kCoarseThreads) void grid_coarse_min_kernel(
 constexpr int kCoarseChunkGroups = 64;
 constexpr int kCoarseSubsets = 5;
 constexpr int kCoarseWideThreads = kCoarseChunkGroups * kCoarseSubsets;  // 320
-constexpr int kCoarseRowsPerThread =
-    ((kCoarseCell + 1) * (kCoarseCell + 1) + kCoarseSubsets - 1) / kCoarseSubsets;  // 17
+static_assert(2 * kCoarseSubsets >= kCoarseCell + 1, "two planes per wave cover a window");
 constexpr int kXcds = 8;
 typedef uint32_t U32x4 __attribute__((ext_vector_type(4)));
 
 template <int kElemBytes>
 __global__ __launch_bounds__(kCoarseWideThreads) void grid_coarse_min_wide_kernel(
     const unsigned char* __restrict__ grid, int nx, int ny, int nz, int ncx, int ncy,
-    int nchunks, int nwork, float* __restrict__ out) {
+    int ncz, int nchunks, int nwork, CoarseBall ball, float* __restrict__ out) {
   constexpr int kCols = 16 / kElemBytes;                               // columns per group
   constexpr int kCells = (kCoarseChunkGroups - 1) * kCols / kCoarseCell;  // cells per chunk
   __shared__ float s_mn[kCoarseSubsets][kCoarseChunkGroups];
-  __shared__ float s_mx[kCoarseSubsets][kCoarseChunkGroups];
+  __shared__ uint32_t s_mx[kCoarseSubsets][kCoarseChunkGroups];
   __shared__ float s_fmn[kCoarseSubsets][kCoarseChunkGroups];
-  __shared__ float s_fmx[kCoarseSubsets][kCoarseChunkGroups];
+  __shared__ uint32_t s_fmx[kCoarseSubsets][kCoarseChunkGroups];
   const int per = (nwork + kXcds - 1) / kXcds;
   const int w = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
   if (w >= nwork) return;
-  const int ch = w % nchunks, cyz = w / nchunks;
-  const int cy = cyz % ncy, cz = cyz / ncy;
+  const int cyz = w / nchunks, ch = w - cyz * nchunks;
+  const int cz = cyz / ncy, cy = cyz - cz * ncy;
   const int y0 = cy * kCoarseCell, z0 = cz * kCoarseCell;
   const int wy = min(y0 + kCoarseCell, ny - 1) - y0 + 1;
-  const int rows = wy * (min(z0 + kCoarseCell, nz - 1) - z0 + 1);
+  const int wz = min(z0 + kCoarseCell, nz - 1) - z0 + 1;
   const int x0 = ch * kCells * kCoarseCell;                     // first column of the chunk
   const int n_groups = nx / kCols;                              // groups per grid row
   const int tid = threadIdx.x;
-  const int s = tid / kCoarseChunkGroups, g = tid - s * kCoarseChunkGroups;
+  const int cx_last = min(ch * kCells + kCells, ncx) - 1;
+  if (coarse_axis_gap(ball.c[0], ch * kCells, cx_last, ncx) +
+          coarse_axis_gap(ball.c[1], cy, cy, ncy) + coarse_axis_gap(ball.c[2], cz, cz, ncz) >
+      ball.r2) {
+    // No lookup from the ball reaches these cells: no bound (never skips), no loads.
+    if (tid <= cx_last - ch * kCells)
+      out[((size_t)cz * ncy + cy) * ncx + ch * kCells + tid] = -__builtin_inff();
+    return;
+  }
+  // Wave s takes planes s and s + 5 of the cell row's window and all 9 of its rows (plane
+  // and row clamped to the window: a repeated row changes nothing), so every address is a
+  // wave-uniform row start plus the lane's 16-byte group.
+  const int s = __builtin_amdgcn_readfirstlane(tid / kCoarseChunkGroups);
+  const int g = tid & (kCoarseChunkGroups - 1);
   const int gg = min(x0 / kCols + g, n_groups - 1);             // clamped group of the row
+  const uint32_t lane_off = (uint32_t)gg * 16u;
+  const size_t row_bytes = (size_t)nx * kElemBytes, plane_bytes = row_bytes * (size_t)ny;
   // Non-temporal loads: the grid streams through once and does not displace what the
   // plan step that follows keeps in L2 (robot constants, instructions).
-  U32x4 v[kCoarseRowsPerThread];
+  U32x4 v[2][kCoarseCell + 1];
 #pragma unroll
-  for (int j = 0; j < kCoarseRowsPerThread; ++j) {
-    const int r = min(s + kCoarseSubsets * j, rows - 1);
-    const int y = y0 + r % wy, z = z0 + r / wy;
-    const size_t row = ((size_t)z * (size_t)ny + (size_t)y) * (size_t)nx * kElemBytes;
-    v[j] = __builtin_nontemporal_load(
-        reinterpret_cast<const U32x4*>(grid + row + (size_t)gg * 16u));
+  for (int zi = 0; zi < 2; ++zi) {
+    const int z = z0 + min(s + kCoarseSubsets * zi, wz - 1);
+#pragma unroll
+    for (int yy = 0; yy <= kCoarseCell; ++yy) {
+      const int y = y0 + min(yy, wy - 1);
+      const unsigned char* row = grid + (size_t)z * plane_bytes + (size_t)y * row_bytes;
+      v[zi][yy] = __builtin_nontemporal_load(reinterpret_cast<const U32x4*>(row + lane_off));
+    }
   }
-  float mn = __builtin_inff(), mx = 0.f, fmn = __builtin_inff(), fmx = 0.f;
+  // The minimum, and the largest |phi| as the bits of |phi|: for a float the bits with the
+  // sign cleared order like |phi| when finite and are >= 0x7f800000 for +-inf and NaN, so
+  // one unsigned maximum gives max |phi| and flags any non-finite value.
+  float mn = __builtin_inff(), fmn = __builtin_inff();
+  uint32_t mxb = 0u, fmxb = 0u;
 #pragma unroll
-  for (int j = 0; j < kCoarseRowsPerThread; ++j) {
-    const uint32_t wd[4] = {v[j][0], v[j][1], v[j][2], v[j][3]};
+  for (int j = 0; j < 2 * (kCoarseCell + 1); ++j) {
+    const U32x4& vj = v[j / (kCoarseCell + 1)][j % (kCoarseCell + 1)];
+    const uint32_t wd[4] = {vj[0], vj[1], vj[2], vj[3]};
 #pragma unroll
     for (int c = 0; c < kCols; ++c) {
       float x;
@@ -1318,19 +1365,19 @@ __global__ __launch_bounds__(kCoarseWideThreads) void grid_coarse_min_wide_kerne
         const unsigned short h = (unsigned short)(wd[c >> 1] >> ((c & 1) * 16));
         x = (float)__builtin_bit_cast(_Float16, h);
       }
-      const float a = isfinite(x) ? fabsf(x) : __builtin_inff();
+      const uint32_t ab = __float_as_uint(x) & 0x7fffffffu;
       mn = fminf(mn, x);
-      mx = fmaxf(mx, a);
+      mxb = max(mxb, ab);
       if (c == 0) {
         fmn = fminf(fmn, x);
-        fmx = fmaxf(fmx, a);
+        fmxb = max(fmxb, ab);
       }
     }
   }
   s_mn[s][g] = mn;
-  s_mx[s][g] = mx;
+  s_mx[s][g] = mxb;
   s_fmn[s][g] = fmn;
-  s_fmx[s][g] = fmx;
+  s_fmx[s][g] = fmxb;
   __syncthreads();
   const int cx = ch * kCells + tid;
   if (tid < kCells && cx < ncx) {
@@ -1340,23 +1387,25 @@ __global__ __launch_bounds__(kCoarseWideThreads) void grid_coarse_min_wide_kerne
     // when it is a group's first column (c_hi = c_lo + 8), else it closes g_end - 1.
     const bool first_only = (c_hi % kCols) == 0;
     const int g_end = first_only ? c_hi / kCols : c_hi / kCols + 1;
-    float cmn = __builtin_inff(), cmx = 0.f;
+    float cmn = __builtin_inff();
+    uint32_t cmxb = 0u;
     for (int gi = c_lo / kCols; gi < g_end; ++gi) {
 #pragma unroll
       for (int t = 0; t < kCoarseSubsets; ++t) {
         cmn = fminf(cmn, s_mn[t][gi]);
-        cmx = fmaxf(cmx, s_mx[t][gi]);
+        cmxb = max(cmxb, s_mx[t][gi]);
       }
     }
     if (first_only) {
 #pragma unroll
       for (int t = 0; t < kCoarseSubsets; ++t) {
         cmn = fminf(cmn, s_fmn[t][g_end]);
-        cmx = fmaxf(cmx, s_fmx[t][g_end]);
+        cmxb = max(cmxb, s_fmx[t][g_end]);
       }
     }
     out[((size_t)cz * ncy + cy) * ncx + cx] =
-        cmx == __builtin_inff() ? -__builtin_inff() : cmn - (1e-5f + cmx * 0x1p-18f);
+        cmxb >= 0x7f800000u ? -__builtin_inff()
+                            : cmn - (1e-5f + __uint_as_float(cmxb) * 0x1p-18f);
   }
 }
 
@@ -1971,12 +2020,15 @@ int launch_ogm(const DevRobot* robot, const OgmArgs& a, const float* depth, floa
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_grid_coarse_min(const void* grid, bool f16, int nx, int ny, int nz, float* out,
-                           void* stream) {
+int launch_grid_coarse_min(const void* grid, bool f16, int nx, int ny, int nz,
+                           const float* ball_c, float ball_r2, float* out, void* stream) {
   const int ncx = coarse_cells_1d(nx), ncy = coarse_cells_1d(ny), ncz = coarse_cells_1d(nz);
   const long long ncells = (long long)ncx * ncy * ncz;
   const int elem = f16 ? 2 : 4;
   (void)ncells;
+  CoarseBall ball;
+  for (int a = 0; a < 3; ++a) ball.c[a] = ball_c ? ball_c[a] : 0.f;
+  ball.r2 = ball_c ? ball_r2 : __builtin_inff();
   if (((long long)nx * elem) % 16 == 0 && reinterpret_cast<uintptr_t>(grid) % 16 == 0) {
     const int cells_per_chunk = (kCoarseChunkGroups - 1) * (16 / elem) / kCoarseCell;
     const int nchunks = (ncx + cells_per_chunk - 1) / cells_per_chunk;
@@ -1985,12 +2037,12 @@ int launch_grid_coarse_min(const void* grid, bool f16, int nx, int ny, int nz, f
     auto k = f16 ? grid_coarse_min_wide_kernel<2> : grid_coarse_min_wide_kernel<4>;
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kCoarseWideThreads), 0,
                        (hipStream_t)stream, static_cast<const unsigned char*>(grid), nx, ny, nz,
-                       ncx, ncy, nchunks, (int)nwork, out);
+                       ncx, ncy, ncz, nchunks, (int)nwork, ball, out);
   } else {
     const uint32_t bytes = (uint32_t)((long long)nx * ny * nz * elem);
     auto k = f16 ? grid_coarse_min_kernel<2> : grid_coarse_min_kernel<4>;
     hipLaunchKernelGGL(k, dim3((unsigned)((long long)ncy * ncz)), dim3(kCoarseThreads), 0,
-                       (hipStream_t)stream, grid, bytes, nx, ny, nz, ncx, ncy, ncz, out);
+                       (hipStream_t)stream, grid, bytes, nx, ny, nz, ncx, ncy, ncz, ball, out);
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }

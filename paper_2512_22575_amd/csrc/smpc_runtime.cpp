@@ -556,9 +556,52 @@ smpc_status smpc_grid_coarse_min(const smpc_grid* g, float* coarse_out, void* st
   const long long elem = g->dtype == SMPC_GRID_F16 ? 2 : 4;
   if ((long long)g->nx * g->ny * g->nz * elem >= (1LL << 31)) return SMPC_E_INVALID_ARG;
   return launch_grid_coarse_min(g->data, g->dtype == SMPC_GRID_F16, g->nx, g->ny, g->nz,
+                                nullptr, 0.f, coarse_out, stream) == 0
+             ? SMPC_OK
+             : SMPC_E_DEVICE;
+}
+
+smpc_status smpc_grid_coarse_min_ball(const smpc_grid* g, const float* center, float radius,
+                                      float* coarse_out, void* stream) {
+  if (!g || !g->data || !coarse_out || !center || g->nx < 2 || g->ny < 2 || g->nz < 2 ||
+      (g->dtype != SMPC_GRID_F32 && g->dtype != SMPC_GRID_F16))
+    return SMPC_E_INVALID_ARG;
+  const long long elem = g->dtype == SMPC_GRID_F16 ? 2 : 4;
+  if ((long long)g->nx * g->ny * g->nz * elem >= (1LL << 31)) return SMPC_E_INVALID_ARG;
+  if (!finite_all(center, 3) || !finite_all(g->origin, 3) || !std::isfinite(g->voxel) ||
+      !(g->voxel > 0.f) || std::isnan(radius) || radius < 0.f)
+    return SMPC_E_INVALID_ARG;
+  // The ball in continuous-index units, its radius widened by one voxel, which covers
+  // the float32 rounding of the sphere positions and of the cell test.
+  float c[3];
+  for (int a = 0; a < 3; ++a)
+    c[a] = (float)(((double)center[a] - (double)g->origin[a]) / (double)g->voxel - 0.5);
+  const double r = std::isinf(radius) ? HUGE_VAL : (double)radius / (double)g->voxel + 1.0;
+  const float r2 = std::isinf(r) ? HUGE_VALF : (float)(r * r);
+  return launch_grid_coarse_min(g->data, g->dtype == SMPC_GRID_F16, g->nx, g->ny, g->nz, c, r2,
                                 coarse_out, stream) == 0
              ? SMPC_OK
              : SMPC_E_DEVICE;
+}
+
+smpc_status smpc_robot_reach(const smpc_ctx* ctx, float* center_out, float* radius_out) {
+  if (!ctx || !center_out || !radius_out || !ctx->robot_set) return SMPC_E_INVALID_ARG;
+  // With modified DH the origin of frame i moves by TransX(a_i) and then by d_i along a
+  // direction orthogonal to it, so |O_i - O_{i-1}| = sqrt(a_i^2 + d_i^2) exactly, and a
+  // sphere centre lies |c| from its frame's origin.  Computed from the float32 values
+  // the device uses, with 1 mm for the device's rounding.
+  const DevRobot& r = ctx->host_robot;
+  double chain[kNdof + 1] = {0.0};  // chain[l]: bound on |O_l|, the origin of frame l
+  for (int i = 0; i < kNdof; ++i) chain[i + 1] = chain[i] + std::hypot((double)r.a[i], (double)r.d[i]);
+  double reach = 0.0;
+  for (int s = 0; s < kSlots; ++s)
+    if (r.slot_active & (1u << s))
+      reach = std::max(reach, chain[s / kSpl + 1] + std::sqrt((double)r.sc[s][0] * r.sc[s][0] +
+                                                             (double)r.sc[s][1] * r.sc[s][1] +
+                                                             (double)r.sc[s][2] * r.sc[s][2]));
+  for (int a = 0; a < 3; ++a) center_out[a] = 0.f;  // the base is at the world origin
+  *radius_out = (float)(reach + 1e-3);
+  return SMPC_OK;
 }
 
 smpc_status smpc_grid_to_f16(const float* src, void* dst, int64_t n, float clamp, void* stream) {

@@ -174,6 +174,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.smpc_grid_coarse_cells.argtypes = [c_int32, c_int32, c_int32]
     lib.smpc_grid_coarse_cells.restype = ctypes.c_int64
     lib.smpc_grid_coarse_min.argtypes = [POINTER(smpc_grid), c_void_p, c_void_p]
+    lib.smpc_grid_coarse_min_ball.argtypes = [POINTER(smpc_grid), POINTER(c_float), c_float,
+                                              c_void_p, c_void_p]
+    lib.smpc_grid_coarse_min_ball.restype = c_int32
+    lib.smpc_robot_reach.argtypes = [c_void_p, POINTER(c_float), POINTER(c_float)]
+    lib.smpc_robot_reach.restype = c_int32
     lib.smpc_grid_coarse_min.restype = c_int32
     lib.smpc_plan_workspace_bytes.argtypes = [c_int32, c_int32]
     lib.smpc_edt_workspace_bytes.argtypes = [c_int32, c_int32, c_int32]
@@ -276,6 +281,28 @@ def smpc_grid_coarse_min(grid, dtype: int, coarse_out: int, stream: int | None) 
                                                 c_void_p(stream or 0))
 
 
+def smpc_grid_coarse_min_ball(grid, dtype: int, origin, voxel: float, center, radius: float,
+                              coarse_out: int, stream: int | None) -> int:
+    """Coarse lower bounds restricted to the cells the lookups of a ball reach (the others
+    -inf); grid is a device tensor [nz][ny][nx] at `origin` / `voxel`."""
+    nz, ny, nx = (int(x) for x in grid.shape)
+    g = smpc_grid(c_void_p(_ptr(grid)), nx, ny, nz, int(dtype),
+                  (c_float * 3)(*[float(x) for x in np.asarray(origin, np.float32)]),
+                  float(voxel), None)
+    c = (c_float * 3)(*[float(x) for x in np.asarray(center, np.float32)])
+    return load_library().smpc_grid_coarse_min_ball(ctypes.byref(g), c, float(radius),
+                                                    c_void_p(coarse_out or 0),
+                                                    c_void_p(stream or 0))
+
+
+def smpc_robot_reach(ctx: c_void_p):
+    """(status, centre (3,), radius) of the ball holding every sphere centre of the robot."""
+    c = (c_float * 3)()
+    r = c_float()
+    st = load_library().smpc_robot_reach(ctx, c, ctypes.byref(r))
+    return st, np.array(c[:], np.float32), float(r.value)
+
+
 def smpc_grid_to_f16(src: int, dst: int, n: int, clamp: float, stream: int | None) -> int:
     return load_library().smpc_grid_to_f16(c_void_p(src or 0), c_void_p(dst or 0), int(n),
                                            float(clamp), c_void_p(stream or 0))
@@ -375,6 +402,13 @@ class Planner:
         st = smpc_set_robot(self._ctx, robot_desc(robot))
         if st != SMPC_OK:
             raise SMPCError(st, smpc_last_error(self._ctx))
+
+    def robot_reach(self):
+        """(centre, radius) of a ball holding every sphere centre at any joint values."""
+        st, c, r = smpc_robot_reach(self._ctx)
+        if st != SMPC_OK:
+            raise SMPCError(st, "smpc_robot_reach")
+        return c, r
 
     def profile_enable(self, n_steps: int) -> None:
         st = smpc_profile_enable(self._ctx, n_steps)

@@ -301,6 +301,47 @@ def test_noalloc_requires_the_robot_on_the_device(ctx):
     _expect_noalloc(ctx, _args(), S.SMPC_E_INVALID_ARG, "run smpc_plan_step once")
 
 
+def test_robot_reach_holds_every_sphere_centre(ctx):
+    """The reach ball: the closed form of the modified-DH chain, and every sphere centre of
+    the oracle's kinematics inside it at random joint values (limits ignored)."""
+    from oracle import smpc_oracle as O
+    st, c, r = S.smpc_robot_reach(ctx)
+    assert st == S.SMPC_E_INVALID_ARG  # no robot yet
+    rob = R.make_robot(0)
+    assert S.smpc_set_robot(ctx, S.robot_desc(rob)) == S.SMPC_OK
+    st, c, r = S.smpc_robot_reach(ctx)
+    assert st == S.SMPC_OK and np.all(c == 0.0)
+    f = rob.rounded_f32()
+    chain = np.concatenate([[0.0], np.cumsum(np.hypot(f.a, f.d))])
+    want = max(chain[f.sphere_link[i]] + np.linalg.norm(f.sphere_center[i])
+               for i in range(f.n_spheres))
+    assert r == pytest.approx(want + 1e-3, abs=1e-6)
+    q = np.random.default_rng(3).uniform(-np.pi, np.pi, size=(2000, 7))
+    centres = O.sphere_centres(f, O.forward_kinematics(f, q))
+    reach = np.linalg.norm(centres, axis=-1).max()
+    assert reach <= r - 1e-3 + 1e-9
+    assert reach > 0.8 * (r - 1e-3)  # the bound is not loose by construction of the test
+
+
+def test_coarse_ball_validates_on_host():
+    lib = S.load_library()
+    f3 = ctypes.c_float * 3
+
+    def grid(voxel):
+        return S.smpc_grid(ctypes.c_void_p(0x1000), 16, 16, 16, S.GRID_F32, f3(0.0, 0.0, 0.0),
+                           voxel, None)
+
+    def call(g, c, r, out=0x2000):
+        return lib.smpc_grid_coarse_min_ball(ctypes.byref(g), c, r, ctypes.c_void_p(out), None)
+
+    ok, bad = f3(0.0, 0.0, 0.0), f3(0.0, float("nan"), 0.0)
+    assert call(grid(0.05), bad, 1.0) == S.SMPC_E_INVALID_ARG
+    assert call(grid(0.05), ok, -1.0) == S.SMPC_E_INVALID_ARG
+    assert call(grid(0.05), ok, float("nan")) == S.SMPC_E_INVALID_ARG
+    assert call(grid(0.0), ok, 1.0) == S.SMPC_E_INVALID_ARG
+    assert call(grid(0.05), ok, 1.0, out=0) == S.SMPC_E_INVALID_ARG
+
+
 def test_planner_raises_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(S, "_lib", None)
     with pytest.raises(OSError, match="missing"):

@@ -2,9 +2,13 @@
 
 * the bounds equal their definition (window minimum minus the rounding margin,
   -inf where the window holds a non-finite value), bit for bit;
-* plan steps with bounds are bitwise identical to plan steps without them (a
-  skipped lookup has a hinge of exactly 0), on the mid and the full-size reactive
-  workloads, a float16 grid with on-device sampling, and through the server.
+* plan steps with bounds -- the whole table, or the table restricted to the robot's
+  reach -- are bitwise identical to plan steps without them (a skipped lookup has a
+  hinge of exactly 0), on the mid and the full-size reactive workloads, a float16 grid
+  with on-device sampling, a ragged grid the arm leaves through every face, and through
+  the server;
+* a table restricted to a ball holds the full bound in every cell a lookup from the
+  ball reaches, and the full bound or -inf elsewhere.
 """
 import numpy as np
 import pytest
@@ -105,6 +109,67 @@ def test_bounds_full_size_reactive_grid():
     np.testing.assert_array_equal(got16.cpu().numpy().view(np.uint32), want16.view(np.uint32))
 
 
+def cells_reached(shape, origin, voxel, center, radius):
+    """Cells (cz, cy, cx) holding lookups of points within `radius` of `center` (float64):
+    cell k along an axis covers u in [8k, 8k + 8), extended to -inf for k = 0 and to +inf
+    for the last cell, u = (p - origin) / voxel - 1/2 (R5's clamping)."""
+    nz, ny, nx = shape
+    u = (np.asarray(center, np.float64) - np.asarray(origin, np.float64)) / voxel - 0.5
+    gaps = []
+    for ax, n in enumerate((nx, ny, nz)):
+        k = np.arange((n - 2) // CELL + 1)
+        lo = np.where(k == 0, -np.inf, 8.0 * k)
+        hi = np.where(k == k[-1], np.inf, 8.0 * (k + 1))
+        gaps.append(np.maximum(np.maximum(lo - u[ax], u[ax] - hi), 0.0) ** 2)
+    g2 = gaps[2][:, None, None] + gaps[1][None, :, None] + gaps[0][None, None, :]
+    return g2 <= (radius / voxel) ** 2
+
+
+def gpu_coarse_ball(grid_t, dtype, origin, voxel, center, radius):
+    import torch
+
+    from paper_2512_22575_amd import smpc as S
+    nz, ny, nx = grid_t.shape
+    out = torch.full((S.smpc_grid_coarse_cells(nx, ny, nz),), float("nan"), device=grid_t.device)
+    st = S.smpc_grid_coarse_min_ball(grid_t, dtype, origin, voxel, center, radius, out.data_ptr(),
+                                     torch.cuda.current_stream().cuda_stream)
+    assert st == S.SMPC_OK
+    return out
+
+
+@pytest.mark.parametrize("shape", [(40, 41, 200), (17, 9, 33), (10, 12, 520)])
+def test_ball_bounds_cover_every_reached_cell(shape):
+    """Cells a lookup from the ball reaches hold the full bound bit for bit; every other
+    cell holds the full bound or -inf; an infinite radius gives the full table."""
+    import torch
+
+    from paper_2512_22575_amd import smpc as S
+    rng = np.random.default_rng(sum(shape) + 1)
+    grid = rng.normal(scale=0.3, size=shape).astype(np.float32)
+    origin, voxel = W.f32([-0.4, -0.3, 0.1]), W.f32s(0.01)
+    extent = np.array(shape[::-1]) * voxel
+    center = W.f32(origin + extent * np.array([0.3, 0.6, 0.5]))
+    radius = float(0.35 * extent.min())
+    full = coarse_reference(grid)
+    reached = cells_reached(shape, origin, voxel, center, radius)
+    assert 0 < reached.sum() < reached.size
+    for dtype, g in ((S.GRID_F32, grid), (S.GRID_F16, np.clip(grid, -2, 2).astype(np.float16))):
+        if dtype == S.GRID_F16:
+            full = coarse_reference(g.astype(np.float32))
+            gt = torch.from_numpy(g.view(np.int16).copy()).cuda()
+        else:
+            gt = torch.from_numpy(g).cuda()
+        got = gpu_coarse_ball(gt, dtype, origin, voxel, center, radius).cpu().numpy()
+        got = got.reshape(full.shape)
+        np.testing.assert_array_equal(got[reached].view(np.uint32), full[reached].view(np.uint32))
+        rest = got[~reached]
+        assert np.all((rest == -np.inf) | (rest.view(np.uint32) == full[~reached].view(np.uint32)))
+        if shape == (40, 41, 200):  # rows of cells wholly outside the ball are skipped
+            assert np.any(rest == -np.inf)
+        inf = gpu_coarse_ball(gt, dtype, origin, voxel, center, float("inf")).cpu().numpy()
+        np.testing.assert_array_equal(inf.view(np.uint32), full.reshape(-1).view(np.uint32))
+
+
 def _plan(inp, grid_t, coarse, **kw):
     import torch
 
@@ -128,11 +193,18 @@ def _plan(inp, grid_t, coarse, **kw):
 
 
 def _check_same(inp, grid_t, dtype, **kw):
-    coarse = gpu_coarse(grid_t, dtype)
+    """Plan steps without bounds, with the full table and with the table restricted to
+    the robot's reach: bitwise the same."""
+    from paper_2512_22575_amd import smpc as S
+    planner = S.Planner(inp.robot)
+    center, radius = planner.robot_reach()
+    planner.close()
     a = _plan(inp, grid_t, None, grid_dtype=dtype, **kw)
-    b = _plan(inp, grid_t, coarse, grid_dtype=dtype, **kw)
-    for x, y in zip(a, b):
-        np.testing.assert_array_equal(x.view(np.uint32), y.view(np.uint32))
+    for coarse in (gpu_coarse(grid_t, dtype),
+                   gpu_coarse_ball(grid_t, dtype, inp.origin, inp.voxel, center, radius)):
+        b = _plan(inp, grid_t, coarse, grid_dtype=dtype, **kw)
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x.view(np.uint32), y.view(np.uint32))
 
 
 def test_plan_step_identical_mid():
