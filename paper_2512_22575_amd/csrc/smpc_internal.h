@@ -75,7 +75,7 @@ struct StepParams {
   float cstride[2];            // ncx, ncx * ncy (cell index strides)
   int32_t K, H, R, P;          // samples, horizon, rollouts per K1 block, K1 blocks
   float dt;
-  float inv_lambda;
+  float k_lambda;              // log2(e) / lambda (softmax factors by exp2)
   uint32_t seed_lo, seed_hi;   // sampling mode: Philox key
   float sigma[kNdof];          // sampling mode: per-joint standard deviation
 };

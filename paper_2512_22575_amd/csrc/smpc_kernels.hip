@@ -183,6 +183,14 @@ __device__ __forceinline__ void step_normals(uint64_t n0, uint32_t k0, uint32_t 
 
 __device__ __forceinline__ float sqrt_hw(float x) { return __builtin_amdgcn_sqrtf(x); }
 
+// exp(-d / lambda) for d >= 0 (weights and softmax rescaling, eq. 29) as
+// 2^(-d * log2(e) / lambda) on the hardware exp2, with k = log2(e) / lambda.  Rounding
+// the product costs at most |d / lambda| * 2^-24 relative, below 1e-6 for every factor
+// larger than e^-16; smaller factors carry no weight that matters.
+__device__ __forceinline__ float softmax_factor(float d, float k) {
+  return __builtin_amdgcn_exp2f(-d * k);
+}
+
 // g(theta) = (x^2 - sin^2 x) / (2 sin^4 x), x = theta / 2, for theta in [0, pi].
 // With it |v|^2 = |t|^2 + g(theta) t^T (I - R) t for the translational part v of
 // log(T) (eqs. 12-14): V(theta) acts as the identity along the rotation axis and
@@ -817,7 +825,7 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
         if (isfinite(v[c])) mn = fmin(mn, v[c]);  // a repeated last value changes nothing
     }
     const bool fin = r < nroll && j == 0 && isfinite(s);
-    const float e = (fin && isfinite(mn)) ? expf(-(float)(s - mn) * p.inv_lambda) : 0.f;
+    const float e = (fin && isfinite(mn)) ? softmax_factor((float)(s - mn), p.k_lambda) : 0.f;
     if (r < R && j == 0) L.e[r] = e;
     __builtin_amdgcn_wave_barrier();
     float Z = 0.f, Z2 = 0.f;
@@ -935,7 +943,7 @@ __device__ __forceinline__ void stats_load(const Workspace& ws, int P, int lane,
   }
 }
 
-__device__ __forceinline__ GlobalStats stats_finish(const Workspace& ws, int P, float inv_lambda,
+__device__ __forceinline__ GlobalStats stats_finish(const Workspace& ws, int P, float k_lambda,
                                                     int lane, const StatRows& r) {
   double mn = __builtin_inf();
 #pragma unroll
@@ -949,14 +957,14 @@ __device__ __forceinline__ GlobalStats stats_finish(const Workspace& ws, int P, 
 #pragma unroll
     for (int c = 0; c < kStatRows; ++c) {
       if (lane + kWave * c >= P || !isfinite(r.m[c])) continue;
-      const float e = expf(-(float)(r.m[c] - mn) * inv_lambda);
+      const float e = softmax_factor((float)(r.m[c] - mn), k_lambda);
       Z = fmaf(r.z[c], e, Z);
       Z2 = fmaf(r.z2[c], e * e, Z2);
     }
     for (int b = lane + kWave * kStatRows; b < P; b += kWave) {
       const double mb = ws.part_m[b];
       if (!isfinite(mb)) continue;
-      const float e = expf(-(float)(mb - mn) * inv_lambda);
+      const float e = softmax_factor((float)(mb - mn), k_lambda);
       Z = fmaf(ws.part_Z[b], e, Z);
       Z2 = fmaf(ws.part_Z2[b], e * e, Z2);
     }
@@ -969,11 +977,11 @@ __device__ __forceinline__ GlobalStats stats_finish(const Workspace& ws, int P, 
   return {mn, Z, Z2};
 }
 
-__device__ __forceinline__ GlobalStats wave_stats(const Workspace& ws, int P, float inv_lambda,
+__device__ __forceinline__ GlobalStats wave_stats(const Workspace& ws, int P, float k_lambda,
                                                   int lane) {
   StatRows r;
   stats_load(ws, P, lane, r);
-  return stats_finish(ws, P, inv_lambda, lane, r);
+  return stats_finish(ws, P, k_lambda, lane, r);
 }
 
 // State terms of state 0 (pose, environment, self, q/qd limits, null space) are the
@@ -1043,7 +1051,7 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
       }
     }
     GlobalStats st{__builtin_inf(), 0.f, 0.f};
-    if (stats_out && tid < kWave) st = stats_finish(ws, P, p.inv_lambda, lane, rows);
+    if (stats_out && tid < kWave) st = stats_finish(ws, P, p.k_lambda, lane, rows);
     if (stats_out && tid == 0) {
       const bool ok = isfinite(st.m);
       stats_out[0] = ok ? (float)(st.m + (double)c0) : __builtin_nanf("");
@@ -1077,7 +1085,7 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
 #pragma unroll
     for (int c = 0; c < kWeightsPerThread; ++c) sv[c] = ws.S[min(lo + tid + kK2Threads * c, K - 1)];
   }
-  const GlobalStats st = wave_stats(ws, P, p.inv_lambda, lane);
+  const GlobalStats st = wave_stats(ws, P, p.k_lambda, lane);
   const bool ok = isfinite(st.m);
 
   if (is_out) {
@@ -1087,7 +1095,7 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
 #pragma unroll
       for (int c = 0; c < kRowsAhead; ++c) {
         if (g + kRowGroups * c < P && isfinite(mv[c]))
-          acc = fmaf(nv[c], expf(-(float)(mv[c] - st.m) * p.inv_lambda), acc);
+          acc = fmaf(nv[c], softmax_factor((float)(mv[c] - st.m), p.k_lambda), acc);
       }
       constexpr int kBatch = 8;
       for (int b0 = g + kRowGroups * kRowsAhead; b0 < P; b0 += kRowGroups * kBatch) {
@@ -1102,7 +1110,7 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
 #pragma unroll
         for (int c = 0; c < kBatch; ++c) {
           if (b0 + kRowGroups * c < P && isfinite(mb[c]))
-            acc = fmaf(nb[c], expf(-(float)(mb[c] - st.m) * p.inv_lambda), acc);
+            acc = fmaf(nb[c], softmax_factor((float)(mb[c] - st.m), p.k_lambda), acc);
         }
       }
     }
@@ -1143,7 +1151,7 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
     const int i = lo + tid + kK2Threads * c;
     if (i >= K) continue;
     float w = 0.f;
-    if (ok && isfinite(sv[c])) w = expf(-(float)(sv[c] - st.m) * p.inv_lambda) * invZ;
+    if (ok && isfinite(sv[c])) w = softmax_factor((float)(sv[c] - st.m), p.k_lambda) * invZ;
     weights_out[i] = w;
   }
 }

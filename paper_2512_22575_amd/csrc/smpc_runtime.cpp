@@ -265,7 +265,7 @@ StepParams make_params(const smpc_ctx* ctx, const smpc_plan_args* a, const Launc
   p.R = lc.R;
   p.P = lc.P;
   p.dt = a->dt;
-  p.inv_lambda = (float)(1.0 / (double)a->lambda);
+  p.k_lambda = (float)(1.4426950408889634 / (double)a->lambda);
   return p;
 }
 
