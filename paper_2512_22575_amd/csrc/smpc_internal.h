@@ -90,7 +90,8 @@ struct Workspace {
   double* part_m;   // [P]   per-block minimum of S (+inf when the block has none finite)
   float* part_Z;    // [P]   sum_m exp(-(S - part_m)/lambda)
   float* part_Z2;   // [P]   sum_m exp(-2 (S - part_m)/lambda)
-  float* part_N;    // [P][HO4] sum_m exp(-(S - part_m)/lambda) eps^(m), HO4 = 7H padded to 4
+  float* part_N;    // [HO8 / 8][P][8] sum_m exp(-(S - part_m)/lambda) eps^(m) per output
+                    // chunk of 8 (HO8 = 7H padded to 8), chunk-major
   float* c0;        // [1]   state terms of state 0 (when computed by the rollout launch)
 };
 

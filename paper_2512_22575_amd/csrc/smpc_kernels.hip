@@ -849,10 +849,11 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
     }
   }
   __syncthreads();
-  // N_b[o] = sum_r e_r eps_r[o], one contiguous row per block (padded to 4 floats), two
-  // consecutive outputs per thread.
-  const int HO = H * kNdof, HO4 = (HO + 3) & ~3;
-  for (int o = 2 * tid; o < HO4; o += 2 * nthreads) {
+  // N_b[o] = sum_r e_r eps_r[o], two consecutive outputs per thread, stored by output
+  // chunk: the kOutPerBlock outputs of chunk o / kOutPerBlock of all blocks are
+  // contiguous ([chunk][block][kOutPerBlock]), so a merge block reads whole lines.
+  const int HO = H * kNdof, HO8 = (HO + kOutPerBlock - 1) & ~(kOutPerBlock - 1);
+  for (int o = 2 * tid; o < HO8; o += 2 * nthreads) {
     float acc0 = 0.f, acc1 = 0.f;
     const int o1 = min(o + 1, HO - 1);
     if (o < HO) {
@@ -874,8 +875,10 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
         }
       }
     }
-    ws.part_N[(size_t)b * HO4 + o] = acc0;
-    ws.part_N[(size_t)b * HO4 + o + 1] = o + 1 < HO ? acc1 : 0.f;
+    float* dst = ws.part_N + ((size_t)(o / kOutPerBlock) * p.P + b) * kOutPerBlock +
+                 o % kOutPerBlock;
+    dst[0] = acc0;
+    dst[1] = o + 1 < HO ? acc1 : 0.f;
   }
 }
 
@@ -1014,7 +1017,7 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
   __shared__ float red[kK2Threads];
   const int lane = threadIdx.x & (kWave - 1);
   const int tid = threadIdx.x;
-  const int K = p.K, P = p.P, HO = p.H * kNdof, HO4 = (HO + 3) & ~3;
+  const int K = p.K, P = p.P, HO = p.H * kNdof;
   const int n_out_blocks = (HO + kOutPerBlock - 1) / kOutPerBlock;
 
   if (kb == 0) {
@@ -1068,8 +1071,9 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
   // statistics, which they do not depend on, so both memory rounds overlap.
   const int oi = tid % kOutPerBlock, g = tid / kOutPerBlock;
   const int o = ob * kOutPerBlock + oi;
-  const int o_rd = min(o, HO4 - 1);
   const bool is_out = ob < n_out_blocks;
+  // This block's chunk of the block partials: [block][kOutPerBlock], contiguous.
+  const float* chunk = ws.part_N + (size_t)min(ob, n_out_blocks - 1) * P * kOutPerBlock + oi;
   float nv[kRowsAhead];
   double mv[kRowsAhead];
   const int lo = (ob - n_out_blocks) * kWeightsPerBlock;
@@ -1078,7 +1082,7 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
 #pragma unroll
     for (int c = 0; c < kRowsAhead; ++c) {
       const int b = min(g + kRowGroups * c, P - 1);
-      nv[c] = ws.part_N[(size_t)b * HO4 + o_rd];
+      nv[c] = chunk[(size_t)b * kOutPerBlock];
       mv[c] = ws.part_m[b];
     }
   } else {
@@ -1104,7 +1108,7 @@ __device__ __forceinline__ void merge_block(const DevRobot* __restrict__ rob, co
 #pragma unroll
         for (int c = 0; c < kBatch; ++c) {
           const int b = min(b0 + kRowGroups * c, P - 1);
-          nb[c] = ws.part_N[(size_t)b * HO4 + o];
+          nb[c] = chunk[(size_t)b * kOutPerBlock];
           mb[c] = ws.part_m[b];
         }
 #pragma unroll
@@ -1856,7 +1860,10 @@ LaunchConfig plan_launch_config(int K, int H) {
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-static size_t padded_outputs(int H) { return ((size_t)H * kNdof + 3) & ~size_t(3); }
+// Outputs 7H padded to whole merge chunks.
+static size_t padded_outputs(int H) {
+  return ((size_t)H * kNdof + kOutPerBlock - 1) / kOutPerBlock * kOutPerBlock;
+}
 
 size_t workspace_bytes(int K, int H, int P) {
   return align256((size_t)K * 8) + align256((size_t)P * 8) + 2 * align256((size_t)P * 4) +
