@@ -50,8 +50,8 @@ PEAK_FP32_TFLOPS = 157.3
 # reads half the bytes copied: x2; WRITE_SIZE reads them all: x1).  Valid only for
 # the kernel sources it was taken on: bench.py reports null traffic when their
 # hash differs.
-ROLLOUT_TRAFFIC = {"sources_sha256": "bae53bf2a305027707095d7a443b09260b1703d26ba90559f5c981fae6d78ef9",
-                   "fetch_kib": 2826.9, "fetch_scale": 2.0,
+ROLLOUT_TRAFFIC = {"sources_sha256": "de00b7d726e4447c9a267260306a530246ca986660893c74087731b8e182237a",
+                   "fetch_kib": 2814.1, "fetch_scale": 2.0,
                    "write_kib": 853.8, "write_scale": 1.0}
 # The same for one occupancy update (pixel and voxel pass together) at 200^3, 640x480.
 OGM_TRAFFIC = {"sources_sha256": "578bcf58ccf36d0e8adf0b931f77c1100deab1a3f38558deced67601a38b34e2",
@@ -63,7 +63,7 @@ OGM_TRAFFIC = {"sources_sha256": "578bcf58ccf36d0e8adf0b931f77c1100deab1a3f38558
 # TCC_REQ_sum, per dispatch), taken on the kernel sources named by the hash.  The L2
 # side of the roofline counts 128 B per request against the L2 peak of
 # PEAK_L2_GBPS: 8 XCDs x 16 channels x 128 B per clock x 2.4 GHz.
-ROLLOUT_L2 = {"sources_sha256": "bae53bf2a305027707095d7a443b09260b1703d26ba90559f5c981fae6d78ef9", "tcc_req": 221218.9}
+ROLLOUT_L2 = {"sources_sha256": "de00b7d726e4447c9a267260306a530246ca986660893c74087731b8e182237a", "tcc_req": 229407.0}
 PEAK_L2_GBPS = 8 * 16 * 128 * 2.4
 
 
