@@ -994,8 +994,9 @@ __device__ __forceinline__ GlobalStats wave_stats(const Workspace& ws, int P, fl
 //
 // Grid of K2: block 0 as above (costs and statistics); then one block per
 // kOutPerBlock outputs o in [0, 7H) merges the block partials into U*[o]: thread t
-// folds partial rows b = t / kOutPerBlock (mod kRowGroups) of output t % kOutPerBlock,
-// so one load instruction of a wave reads 8 rows x 32 contiguous bytes; then one
+// folds partial rows b = t / kOutPerBlock (mod kRowGroups) of output t % kOutPerBlock;
+// the partials are stored chunk-major, so one load instruction of a wave reads 256
+// contiguous bytes (8 rows x 8 outputs); then one
 // block per kWeightsPerBlock rollouts writes the weights.
 constexpr int kCostsPerThread = 32;   // costs per thread per later pass
 constexpr int kCostsAhead = 16;       // costs per thread loaded before c0 (K <= 4096)
