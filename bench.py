@@ -361,7 +361,7 @@ def edt_bench(args) -> None:
         "config": {"workload": f"reactive scene occupancy {n}^3 at 0.01 m, 20 boxes and 20 "
                                f"spheres drifting at 0.2 m/s, {pool} consecutive periods",
                    "grid": [n] * 3},
-        "roofline": {"bound": "hbm", "kernel": "smpc_edt (3 kernels)",
+        "roofline": {"bound": "hbm", "kernel": "smpc_edt (4 kernels)",
                      "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None,
                      "bytes_per_voxel": EDT_BYTES_PER_VOXEL},

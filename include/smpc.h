@@ -379,7 +379,8 @@ size_t smpc_edt_workspace_bytes(int32_t nx, int32_t ny, int32_t nz);
  * At least one of phi_out and d2_out is non-NULL; no two of occ, phi_out, d2_out
  * and work overlap.  Each side must lie in [1, SMPC_EDT_MAX_SIDE];
  * SMPC_E_UNSUPPORTED when the device cannot give one block the LDS the longer of
- * ny and nz needs (about 264 bytes per voxel of that side).
+ * ny and nz needs (about 270 bytes per voxel of that side, 200 when both are at
+ * most 255).
  * Runs on the device current to the calling thread, asynchronously on `stream`;
  * the caller owns every buffer.
  */

@@ -12,19 +12,21 @@
 //
 //   pass x  (binary input): one wave per row; ballots of the sources of each
 //           64-voxel chunk give the nearest source on either side by bit scans;
-//   pass y  FH over 16 (x, z) lines per block, staged in LDS tiles;
-//   pass z  FH over 16 (x, y) lines per block, one field per block;
-//   phi     the signed distance phi = voxel * (sqrt(D_out) - sqrt(D_in)).
+//   pass y  16 (x, z) lines of one field per block, staged in an LDS tile: D_out by
+//           FH, D_in by a bounded search around each occupied voxel (FH when an
+//           obstacle is too thick for it);
+//   pass z  the same over 16 (x, y) lines per block;
+//   finish  phi = voxel * (sqrt(D_out) - sqrt(D_in)) and/or the two squared fields.
 //
-// Compact intermediates: after the x and y passes a voxel's value in its own
-// field is 0 (a free voxel is a source of D_in, an occupied one of D_out), so one
-// value per voxel plus its occupancy bit carries both fields: 16 bits after the x
-// pass, 32 after the y pass.
+// Compact intermediates: after every pass a voxel's value in its own field is 0 (a
+// free voxel is a source of D_in, an occupied one of D_out), so one value per voxel
+// plus its occupancy bit carries both fields: 16 bits after the x pass, 32 after the
+// y and z passes.
 //
 // FH with 16 lanes per line.  Each lane builds the lower envelope of the samples of
 // its band of the line (FH's stack, kept as a linked list in LDS); four rounds of
-// pairwise merges join adjacent bands.  In the dual picture the envelope is the
-// lower convex hull of the points (q, F_q), F_q = f(q) + q^2, so merging the hulls
+// pairwise merges join adjacent bands.  In the dual picture the envelope is the lower
+// convex hull of the points (q, F_q), F_q = f(q) + q^2, so merging the hulls
 // of two index-separated bands only removes points near the junction: pop the left
 // tail and the right head until both turns there are strictly convex (the bridge).
 // The read-off walks the merged list; along it the cost (p - q)^2 + f(q) is
@@ -41,33 +43,16 @@ namespace smpc {
 namespace {
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;  // "no source on this line (yet)"
-constexpr uint16_t kNil = 0xFFFFu;       // end of a linked list
 constexpr int kLines = 16;               // lines per FH block
 constexpr int kG = 16;                   // lanes per line
 constexpr int kFhThreads = kLines * kG;  // 256
 constexpr int kTs = kLines + 1;          // LDS tile row stride (words), padded
-constexpr int kMaxChunks = kEdtMaxSide / 64;
 
 // Compact per-voxel records.
 //   after x: bit 15 occupied, bit 14 "no source in the row", bits 0..13 distance
 //   after y: bit 31 occupied, bit 30 "no source in the plane", bits 0..29 D
 constexpr uint16_t kXOcc = 0x8000u, kXNone = 0x4000u;
 constexpr uint32_t kYOcc = 0x80000000u, kYNone = 0x40000000u, kYVal = 0x3FFFFFFFu;
-
-// Squared-distance sample of field `fld` (0: to occupied, 1: to free) from a record.
-__device__ __forceinline__ uint32_t field_of_x(uint16_t r, int fld) {
-  const bool occ = r & kXOcc;
-  if (occ != (fld == 1)) return 0u;  // the voxel is a source of this field
-  if (r & kXNone) return kNone;
-  const uint32_t d = r & 0x3FFFu;
-  return d * d;
-}
-
-__device__ __forceinline__ uint32_t field_of_y(uint32_t r, int fld) {
-  const bool occ = r & kYOcc;
-  if (occ != (fld == 1)) return 0u;
-  return (r & kYNone) ? kNone : (r & kYVal);
-}
 
 // ---------------------------------------------------------------------------
 // Pass x: per voxel, the distance along its row to the nearest voxel of the other
@@ -76,6 +61,8 @@ __device__ __forceinline__ uint32_t field_of_y(uint32_t r, int fld) {
 constexpr int kRowWaves = 4;
 constexpr int kRowsPerWave = 4;
 
+// kChunks: 64-voxel chunks a row may hold (nx <= 64 kChunks).
+template <int kChunks>
 __global__ __launch_bounds__(64 * kRowWaves) void edt_pass_x_kernel(
     const uint8_t* __restrict__ occ, int nx, long long rows, uint16_t* __restrict__ xrec) {
   const int lane = threadIdx.x & 63;
@@ -84,13 +71,13 @@ __global__ __launch_bounds__(64 * kRowWaves) void edt_pass_x_kernel(
   if (row0 >= rows) return;  // whole wave leaves together
   const int nch = (nx + 63) >> 6;
   // All loads of the wave's rows first, so their latencies overlap.
-  uint8_t v[kRowsPerWave][kMaxChunks];
+  uint8_t v[kRowsPerWave][kChunks];
 #pragma unroll
   for (int w = 0; w < kRowsPerWave; ++w) {
     const long long row = row0 + w;
     const uint8_t* src = occ + row * nx;
 #pragma unroll
-    for (int c = 0; c < kMaxChunks; ++c) {
+    for (int c = 0; c < kChunks; ++c) {
       const int p = c * 64 + lane;
       v[w][c] = (row < rows && c < nch && p < nx) ? src[p] : 0;
     }
@@ -99,18 +86,18 @@ __global__ __launch_bounds__(64 * kRowWaves) void edt_pass_x_kernel(
   for (int w = 0; w < kRowsPerWave; ++w) {
     const long long row = row0 + w;
     if (row >= rows) break;
-    uint64_t m_occ[kMaxChunks], m_free[kMaxChunks];
+    uint64_t m_occ[kChunks], m_free[kChunks];
 #pragma unroll
-    for (int c = 0; c < kMaxChunks; ++c) {
+    for (int c = 0; c < kChunks; ++c) {
       const int p = c * 64 + lane;
       m_occ[c] = __ballot(p < nx && v[w][c] != 0);
       m_free[c] = __ballot(p < nx && v[w][c] == 0);
     }
     // Nearest source strictly left of chunk c / strictly right of it (-1 / 2^30: none).
-    int left_o[kMaxChunks], left_f[kMaxChunks], right_o[kMaxChunks], right_f[kMaxChunks];
+    int left_o[kChunks], left_f[kChunks], right_o[kChunks], right_f[kChunks];
     int lo = -1, lf = -1;
 #pragma unroll
-    for (int c = 0; c < kMaxChunks; ++c) {
+    for (int c = 0; c < kChunks; ++c) {
       left_o[c] = lo;
       left_f[c] = lf;
       if (m_occ[c]) lo = c * 64 + 63 - __clzll(m_occ[c]);
@@ -118,7 +105,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void edt_pass_x_kernel(
     }
     int ro = 1 << 30, rf = 1 << 30;
 #pragma unroll
-    for (int c = kMaxChunks - 1; c >= 0; --c) {
+    for (int c = kChunks - 1; c >= 0; --c) {
       right_o[c] = ro;
       right_f[c] = rf;
       if (m_occ[c]) ro = c * 64 + __ffsll((unsigned long long)m_occ[c]) - 1;
@@ -128,7 +115,7 @@ __global__ __launch_bounds__(64 * kRowWaves) void edt_pass_x_kernel(
     const uint64_t at_or_above = ~0ull << lane;
     uint16_t* out = xrec + row * nx;
 #pragma unroll
-    for (int c = 0; c < kMaxChunks; ++c) {
+    for (int c = 0; c < kChunks; ++c) {
       const int p = c * 64 + lane;
       if (c < nch && p < nx) {
         const bool o = v[w][c] != 0;
@@ -147,22 +134,32 @@ __global__ __launch_bounds__(64 * kRowWaves) void edt_pass_x_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// FH on a tile of kLines lines held in LDS, kG lanes per line.
+// FH on a tile of kLines lines held in LDS, kG lanes per line.  Samples are of type
+// Val (uint16_t when every finite sample is below 0xFFFF, else uint32_t; the
+// all-ones value marks "no sample" and dropped points) and list links are sample
+// indices of type Link (uint8_t for lines of at most 255 samples, index 255 ending a
+// list, else uint16_t), so that more tiles fit in a CU's LDS.
 // ---------------------------------------------------------------------------
+template <class Val, class Link>
 struct Tile {
-  uint32_t* f;    // [n][kTs]: f(q); kNone for no sample and for points dropped
-  uint16_t* prv;  // [n][kTs]: previous kept point of the list
-  uint16_t* nxt;  // [n][kTs]: next kept point of the list
+  static constexpr int kNil = (int)(Link)(-1);  // end of a linked list
+  static constexpr uint32_t kNoVal = (Val)(-1);
+  Val* f;     // [n][kTs]: f(q); kNoVal for no sample and for points dropped
+  Link* prv;  // [n][kTs]: previous kept point of the list
+  Link* nxt;  // [n][kTs]: next kept point of the list
 };
 
+// LDS bytes of a tile of n samples per line, rounded up to whole words.
+template <class Val, class Link>
 constexpr size_t tile_bytes(int n) {
-  return (size_t)n * kTs * (sizeof(uint32_t) + 2 * sizeof(uint16_t));
+  return ((size_t)n * kTs * (sizeof(Val) + 2 * sizeof(Link)) + 3) & ~size_t(3);
 }
 
-__device__ __forceinline__ Tile carve_tile(uint32_t* lds, int n) {
-  Tile t;
-  t.f = lds;
-  t.prv = reinterpret_cast<uint16_t*>(lds + n * kTs);
+template <class Val, class Link>
+__device__ __forceinline__ Tile<Val, Link> carve_tile(uint32_t* lds, int n) {
+  Tile<Val, Link> t;
+  t.f = reinterpret_cast<Val*>(lds);
+  t.prv = reinterpret_cast<Link*>(t.f + n * kTs);
   t.nxt = t.prv + n * kTs;
   return t;
 }
@@ -172,53 +169,85 @@ __device__ __forceinline__ bool below(int x, int Fx, int y, int Fy, int z, int F
   return (Fy - Fx) * (z - y) < (Fz - Fy) * (y - x);
 }
 
+// Band [lo, hi) of the calling thread's line: kG bands of ceil(n / kG) samples.
+struct Band {
+  int line, band, lo, hi;
+};
+__device__ __forceinline__ Band my_band(int n) {
+  Band b;
+  b.line = threadIdx.x / kG;
+  b.band = threadIdx.x % kG;
+  const int len = (n + kG - 1) / kG;
+  b.lo = min(n, b.band * len);
+  b.hi = min(n, b.lo + len);
+  return b;
+}
+static_assert((kEdtMaxSide + kG - 1) / kG <= 64, "a band's occupancy fits 64 bits");
+
+// Occupancy of the thread's band, bit q - lo (occ_bits[q] holds bit `line`).
+__device__ __forceinline__ uint64_t band_occupancy(const uint32_t* occ_bits, const Band& B) {
+  uint64_t m = 0;
+  for (int q = B.lo; q < B.hi; ++q) m |= (uint64_t)((occ_bits[q] >> B.line) & 1u) << (q - B.lo);
+  return m;
+}
+
 // Every thread of the block calls this (it holds block barriers).  The thread
 // works on line threadIdx.x / kG, band threadIdx.x % kG; `active` is false for
-// lines past the end of the grid.  emit(p, D) receives each output of the band
-// (kNone when the line holds no sample).
-template <class Emit>
-__device__ __forceinline__ void tile_fh(const Tile& T, int n, bool active, Emit&& emit) {
+// lines past the end of the grid and for lines with no output to write (a wave
+// whose lines are all inactive skips the work).  emit(p, D, occupied) receives
+// each output of the band (D = kNone when the line holds no sample).
+template <class Val, class Link, class Emit>
+__device__ __forceinline__ void tile_fh(const Tile<Val, Link>& T, int n, bool active,
+                                        const uint32_t* occ_bits, Emit&& emit) {
+  constexpr int kNil = Tile<Val, Link>::kNil;
+  constexpr uint32_t kNoVal = Tile<Val, Link>::kNoVal;
   const int lane = threadIdx.x & 63;
-  const int line = threadIdx.x / kG;
-  const int band = threadIdx.x % kG;
-  const int b = (n + kG - 1) / kG;
-  const int lo = min(n, band * b), hi = min(n, lo + b);
-  uint32_t* f = T.f + line;
-  uint16_t* prv = T.prv + line;
-  uint16_t* nxt = T.nxt + line;
+  const Band B = my_band(n);
+  const int band = B.band, lo = B.lo, hi = B.hi;
+  Val* f = T.f + B.line;
+  Link* prv = T.prv + B.line;
+  Link* nxt = T.nxt + B.line;
   auto F = [&](int q) { return (int)f[q * kTs] + q * q; };
 
-  // Phase A: lower envelope of the band, as a list head..tail.
+  // Phase A: lower envelope of the band, as a list head..tail.  The samples are
+  // read kAhead at a time (the pops only overwrite samples already read).
+  constexpr int kAhead = 8;
   int head = kNil, tail = kNil;
   if (active) {
     int k = 0, t = 0, Ft = 0, r = 0, Fr = 0;
-    for (int q = lo; q < hi; ++q) {
-      const uint32_t fq = f[q * kTs];
-      if (fq == kNone) continue;
-      const int Fq = (int)fq + q * q;
-      while (k >= 2 && !below(r, Fr, t, Ft, q, Fq)) {
-        f[t * kTs] = kNone;
-        t = r;
-        Ft = Fr;
-        --k;
-        if (k >= 2) {
-          r = prv[t * kTs];
-          Fr = F(r);
+    for (int q0 = lo; q0 < hi; q0 += kAhead) {
+      uint32_t fv[kAhead];
+#pragma unroll
+      for (int j = 0; j < kAhead; ++j) fv[j] = f[min(q0 + j, hi - 1) * kTs];
+#pragma unroll
+      for (int j = 0; j < kAhead; ++j) {
+        const int q = q0 + j;
+        if (q >= hi || fv[j] == kNoVal) continue;
+        const int Fq = (int)fv[j] + q * q;
+        while (k >= 2 && !below(r, Fr, t, Ft, q, Fq)) {
+          f[t * kTs] = (Val)kNoVal;
+          t = r;
+          Ft = Fr;
+          --k;
+          if (k >= 2) {
+            r = prv[t * kTs];
+            Fr = F(r);
+          }
         }
+        prv[q * kTs] = (Link)(k ? t : kNil);
+        if (k)
+          nxt[t * kTs] = (Link)q;
+        else
+          head = q;
+        r = t;
+        Fr = Ft;
+        t = q;
+        Ft = Fq;
+        ++k;
       }
-      prv[q * kTs] = (uint16_t)(k ? t : kNil);
-      if (k)
-        nxt[t * kTs] = (uint16_t)q;
-      else
-        head = q;
-      r = t;
-      Fr = Ft;
-      t = q;
-      Ft = Fq;
-      ++k;
     }
     if (k) {
-      nxt[t * kTs] = kNil;
+      nxt[t * kTs] = (Link)kNil;
       tail = t;
     }
   }
@@ -243,7 +272,7 @@ __device__ __forceinline__ void tile_fh(const Tile& T, int n, bool active, Emit&
             if (pa == kNil) break;
             const int Fpa = F(pa);
             if (below(pa, Fpa, a, Fa, c, Fc)) break;
-            f[a * kTs] = kNone;
+            f[a * kTs] = (Val)kNoVal;
             a = pa;
             Fa = Fpa;
             moved = true;
@@ -253,15 +282,15 @@ __device__ __forceinline__ void tile_fh(const Tile& T, int n, bool active, Emit&
             if (nc == kNil) break;
             const int Fnc = F(nc);
             if (below(a, Fa, c, Fc, nc, Fnc)) break;
-            f[c * kTs] = kNone;
+            f[c * kTs] = (Val)kNoVal;
             c = nc;
             Fc = Fnc;
             moved = true;
           }
           if (!moved) break;
         }
-        nxt[a * kTs] = (uint16_t)c;
-        prv[c * kTs] = (uint16_t)a;
+        nxt[a * kTs] = (Link)c;
+        prv[c * kTs] = (Link)a;
         nt = rt;  // the extreme points of a group are never dropped
       }
     }
@@ -275,7 +304,7 @@ __device__ __forceinline__ void tile_fh(const Tile& T, int n, bool active, Emit&
   int fm = kNil, lm = kNil;
   if (active) {
     for (int q = lo; q < hi; ++q) {
-      if (f[q * kTs] != kNone) {
+      if (f[q * kTs] != kNoVal) {
         if (fm == kNil) fm = q;
         lm = q;
       }
@@ -293,21 +322,24 @@ __device__ __forceinline__ void tile_fh(const Tile& T, int n, bool active, Emit&
     if (start == kNil && band + d < kG) start = v;
   }
   if (!active) return;
+  const uint64_t occ = band_occupancy(occ_bits, B);
   if (start == kNil) {
-    for (int p = lo; p < hi; ++p) emit(p, kNone);
+    for (int p = lo; p < hi; ++p) emit(p, kNone, (occ >> (p - lo)) & 1u);
     return;
   }
+  // The winner c and its successor nc (with their F) stay in registers, so an output
+  // whose winner does not change reads no LDS.
   int c = start, Fc = F(c);
+  int nc = nxt[c * kTs], Fn = nc == kNil ? 0 : F(nc);
   for (int p = lo; p < hi; ++p) {
-    for (;;) {
-      const int nc = nxt[c * kTs];
-      if (nc == kNil) break;
-      const int Fn = F(nc);
-      if (Fn + p * (p - 2 * nc) > Fc + p * (p - 2 * c)) break;
+    while (nc != kNil && Fn + p * (p - 2 * nc) <= Fc + p * (p - 2 * c)) {
       c = nc;
       Fc = Fn;
+      nc = nxt[c * kTs];
+      if (nc != kNil) Fn = F(nc);
     }
     if (p == lo) {
+      bool moved = false;
       for (;;) {
         const int pc = prv[c * kTs];
         if (pc == kNil) break;
@@ -315,131 +347,274 @@ __device__ __forceinline__ void tile_fh(const Tile& T, int n, bool active, Emit&
         if (Fp + p * (p - 2 * pc) >= Fc + p * (p - 2 * c)) break;
         c = pc;
         Fc = Fp;
+        moved = true;
+      }
+      if (moved) {
+        nc = nxt[c * kTs];
+        Fn = nc == kNil ? 0 : F(nc);
       }
     }
-    emit(p, (uint32_t)(Fc + p * (p - 2 * c)));
+    emit(p, (uint32_t)(Fc + p * (p - 2 * c)), (occ >> (p - lo)) & 1u);
   }
 }
 
-// Stage samples q = 0..n-1 of the block's lines into the f tile: thread t takes
-// line t % kLines at q = t / kLines + (kFhThreads / kLines) k.  Eight loads are
-// issued before any is used (indices clamped into range, so no load sits behind a
-// branch); decode(raw, q) turns a record into the sample.  Threads of lines past the grid pass ok = false
-// and a valid base; their samples become kNone.
-template <class Rec, class Decode>
-__device__ __forceinline__ void stage_tile(uint32_t* f, int n, const Rec* base, long long stride,
-                                           bool ok, Decode&& decode) {
-  constexpr int kRowsPerPass = kFhThreads / kLines;  // 8
-  constexpr int kBatch = 8;
-  const int l = threadIdx.x % kLines;
-  for (int q0 = threadIdx.x / kLines; q0 < n; q0 += kRowsPerPass * kBatch) {
-    Rec v[kBatch];
+// One field of kLines lines, one block (fld 0: D_out, 1: D_in).  A voxel's record
+// after the previous pass holds its occupancy and one value v: the sample of the
+// field it is not a source of (D_out's for a free voxel, D_in's for an occupied one;
+// its own field is 0 there).
+//   1. Stage the samples into the tile (thread t: line t % kLines, q = t / kLines +
+//      (kFhThreads / kLines) k, kBatch loads in flight) and the occupancy into
+//      occ_bits[q] (bit = line).  decode(raw, occ) returns v as a 32-bit value
+//      (kNone: no sample).
+//   2. D_out: FH over the lines that hold a free voxel, written at the free voxels.
+//   3. D_in: at each occupied voxel p a search outward from p: candidates q = p +- d
+//      for d = 1, 2, ... (f_in(q) = 0 on free q, v(q) on occupied q), stopping once d^2
+//      reaches the best value found, which is then exact since every farther q costs
+//      at least d^2.  Obstacles are thin against a line, so the search ends after a
+//      few steps.  The occupied voxels of the tile are listed during staging and
+//      shared out evenly over the block's threads; a tile with more than kInList of
+//      them, or a search that would pass kInReach, is transformed by FH instead.
+// write(p, D) stores the result of the thread's line and write_at(line, p, D) that of
+// line `line` of the block (D = kNone: no source of the field on the line).
+constexpr int kInReach = 64;
+constexpr int kInList = 2048;  // occupied voxels listed per tile, (q << 4) | line
+static_assert(kLines <= 16 && kEdtMaxSide <= 4096, "a list entry fits 16 bits");
+
+template <class Val, class Link, class Rec, class Decode, class Write, class WriteAt>
+__device__ __forceinline__ void fh_lines(uint32_t* lds, int n, const Rec* base, long long stride,
+                                         bool stage_ok, bool line_ok, int fld,
+                                         Decode&& decode, Write&& write, WriteAt&& write_at) {
+  constexpr uint32_t kNoVal = Tile<Val, Link>::kNoVal;
+  Tile<Val, Link> T = carve_tile<Val, Link>(lds, n);
+  uint32_t* occ_bits = lds + tile_bytes<Val, Link>(n) / sizeof(uint32_t);  // [n], bit = line
+  // Lines with an output (a voxel that is not a source of the field), voxels listed.
+  uint32_t* flags = occ_bits + n;
+  uint16_t* list = reinterpret_cast<uint16_t*>(flags + 2);  // [kInList]
+  for (int i = threadIdx.x; i < n + 2; i += kFhThreads) occ_bits[i] = 0u;
+  __syncthreads();
+
+  constexpr int kRowsPerPass = kFhThreads / kLines;  // 16
+  constexpr int kBatch = 16;
+  const int sl = threadIdx.x % kLines;
+  const uint32_t sbit = 1u << sl;
+  {
+    bool has_output = false;
+    for (int q0 = threadIdx.x / kLines; q0 < n; q0 += kRowsPerPass * kBatch) {
+      Rec v[kBatch];
 #pragma unroll
-    for (int j = 0; j < kBatch; ++j) {
-      const int q = min(q0 + j * kRowsPerPass, n - 1);
-      v[j] = base[q * stride];
-    }
+      for (int j = 0; j < kBatch; ++j) v[j] = base[min(q0 + j * kRowsPerPass, n - 1) * stride];
 #pragma unroll
-    for (int j = 0; j < kBatch; ++j) {
-      const int q = q0 + j * kRowsPerPass;
-      if (q < n) f[q * kTs + l] = ok ? decode(v[j], q) : kNone;
+      for (int j = 0; j < kBatch; ++j) {
+        const int q = q0 + j * kRowsPerPass;
+        if (q < n) {
+          bool occ = false;
+          const uint32_t x = decode(v[j], occ);
+          // D_out's sample is 0 on occupied voxels; D_in keeps v and tells the
+          // sources (free voxels, sample 0) by their occupancy bit.
+          const uint32_t sample = (fld == 0 && occ) ? 0u : x;
+          T.f[q * kTs + sl] = (Val)(stage_ok && sample != kNone ? sample : kNoVal);
+          if (stage_ok && occ) {
+            atomicOr(&occ_bits[q], sbit);
+            if (fld == 1) {
+              const uint32_t at = atomicAdd(&flags[1], 1u);
+              if (at < (uint32_t)kInList) list[at] = (uint16_t)((q << 4) | sl);
+            }
+          }
+          has_output |= stage_ok && (occ == (fld == 1));
+        }
+      }
     }
+    if (has_output) atomicOr(&flags[0], sbit);
   }
+  __syncthreads();
+  const Band B = my_band(n);
+  const uint32_t with_output = flags[0];
+  if (with_output == 0u) return;  // uniform across the block
+  const bool active = line_ok && ((with_output >> B.line) & 1u);
+  if (fld == 0) {
+    tile_fh(T, n, active, occ_bits, [&](int p, uint32_t d, bool o) {
+      if (!o) write(p, d);
+    });
+    return;
+  }
+
+  // D_in by the bounded search, listed voxel i on thread i mod kFhThreads.
+  const uint32_t n_occ = flags[1];
+  bool unresolved = n_occ > (uint32_t)kInList;
+  for (int i = threadIdx.x; !unresolved && i < (int)n_occ; i += kFhThreads) {
+    const int e = list[i];
+    const int line = e & 15, p = e >> 4;
+    const Val* f = T.f + line;
+    const uint32_t fp = f[p * kTs];
+    uint32_t best = fp == kNoVal ? kNone : fp;
+    const int dmax = max(p, n - 1 - p);  // beyond it no candidate is left
+    // kStep distances per round, all loads of a round issued together; after a
+    // round every candidate left costs at least (d0 + kStep)^2.
+    constexpr int kStep = 4;
+    bool done = false;
+    for (int d0 = 1; d0 <= kInReach; d0 += kStep) {
+      uint32_t ob[2 * kStep], fb[2 * kStep];
+#pragma unroll
+      for (int c = 0; c < kStep; ++c) {
+        const int qa = max(p - d0 - c, 0), qb = min(p + d0 + c, n - 1);
+        ob[2 * c] = occ_bits[qa];
+        fb[2 * c] = f[qa * kTs];
+        ob[2 * c + 1] = occ_bits[qb];
+        fb[2 * c + 1] = f[qb * kTs];
+      }
+#pragma unroll
+      for (int c = 0; c < 2 * kStep; ++c) {
+        const int d = d0 + c / 2;
+        const int q = (c & 1) ? p + d : p - d;
+        const uint32_t fq = ((ob[c] >> line) & 1u) ? fb[c] : 0u;
+        if (q >= 0 && q < n && fq != kNoVal) best = min(best, (uint32_t)(d * d) + fq);
+      }
+      const int dn = d0 + kStep;  // nearest distance not yet searched
+      if (dn > dmax || (uint32_t)(dn * dn) >= best) {
+        done = true;
+        break;
+      }
+    }
+    if (done)
+      write_at(line, p, best);
+    else
+      unresolved = true;  // the search would pass kInReach
+  }
+  if (!__syncthreads_or(unresolved)) return;
+  // FH on f_in: the free voxels' samples become 0 (each thread rewrites the entries
+  // it staged).
+  for (int q = threadIdx.x / kLines; q < n; q += kRowsPerPass)
+    if (!((occ_bits[q] >> sl) & 1u)) T.f[q * kTs + sl] = (Val)0;
+  __syncthreads();
+  tile_fh(T, n, active, occ_bits, [&](int p, uint32_t d, bool o) {
+    if (o) write(p, d);
+  });
 }
 
 // Pass y: block = 16 consecutive lines (x, z) of one field (blockIdx.y).
+template <class Val, class Link>
 __global__ __launch_bounds__(kFhThreads) void edt_pass_y_kernel(
     const uint16_t* __restrict__ xrec, uint32_t* __restrict__ yrec, int nx, int ny, int nz) {
   extern __shared__ uint32_t lds[];
   const int fld = blockIdx.y;
   const int line0 = blockIdx.x * kLines;  // flattened (z, x) < 2^18
-  Tile T = carve_tile(lds, ny);
-  uint32_t* occ_bits = lds + tile_bytes(ny) / sizeof(uint32_t);  // [ny], bit = line
   const int lines = nx * nz;
   const long long plane = (long long)nx * ny;
-  for (int i = threadIdx.x; i < ny; i += kFhThreads) occ_bits[i] = 0u;
-  __syncthreads();
-  {
-    const int li = line0 + (int)(threadIdx.x % kLines);
-    const bool ok = li < lines;
-    const int z = ok ? li / nx : 0, x = ok ? li - z * nx : 0;
-    const uint32_t bit = 1u << (threadIdx.x % kLines);
-    stage_tile(T.f, ny, xrec + z * plane + x, nx, ok, [&](uint16_t r, int y) -> uint32_t {
-      if (r & kXOcc) atomicOr(&occ_bits[y], bit);
-      return field_of_x(r, fld);
-    });
-  }
-  __syncthreads();
-  const int line = threadIdx.x / kG;
-  const int li = line0 + line;
-  const bool active = li < lines;
-  const int z = active ? li / nx : 0, x = active ? li - z * nx : 0;
-  uint32_t* out = yrec + z * plane + x;
-  tile_fh(T, ny, active, [&](int p, uint32_t d) {
-    const bool o = (occ_bits[p] >> line) & 1u;
-    if (o != (fld == 1)) return;  // a source of this field: the other field's block writes it
-    out[(long long)p * nx] = (o ? kYOcc : 0u) | (d == kNone ? kYNone : d);
-  });
+  auto line_out = [&](int l) {  // records of block line l (clamped into the grid)
+    const int i = min(line0 + l, lines - 1);
+    const int z = i / nx;
+    return yrec + z * plane + (i - z * nx);
+  };
+  const int si = line0 + (int)(threadIdx.x % kLines);
+  const bool stage_ok = si < lines;
+  const int sz = stage_ok ? si / nx : 0, sx = stage_ok ? si - sz * nx : 0;
+  const int line = (int)(threadIdx.x / kG);
+  uint32_t* out = line_out(line);
+  const uint32_t occ_flag = fld == 1 ? kYOcc : 0u;
+  fh_lines<Val, Link>(
+      lds, ny, xrec + sz * plane + sx, nx, stage_ok, line0 + line < lines, fld,
+      [](uint16_t r, bool& occ) -> uint32_t {
+        occ = r & kXOcc;
+        if (r & kXNone) return kNone;
+        const uint32_t d = r & 0x3FFFu;
+        return d * d;
+      },
+      [&](int p, uint32_t d) { out[(long long)p * nx] = occ_flag | (d == kNone ? kYNone : d); },
+      [&](int l, int p, uint32_t d) {
+        line_out(l)[(long long)p * nx] = occ_flag | (d == kNone ? kYNone : d);
+      });
 }
 
-// Pass z: block = 16 consecutive lines (x, y) of one field (blockIdx.y).  Without
-// d2, D_out is parked in the phi buffer (as bits) and D_in in the workspace region
-// of the x-pass records, which is dead once the y pass has finished; the y records
-// are only read (the blocks of the two fields run concurrently).
+// Pass z: block = 16 consecutive lines (x, y) of one field (blockIdx.y).  Output:
+// one record per voxel, kZOcc | D_in for an occupied voxel (written by the D_in
+// block) and D_out for a free one (by the D_out block); the other field is 0 there.
+// none_value stands for "no source in the grid".
+constexpr uint32_t kZOcc = 0x80000000u;
+
+template <class Link>
 __global__ __launch_bounds__(kFhThreads) void edt_pass_z_kernel(
-    const uint32_t* __restrict__ yrec, int nx, int ny, int nz, uint32_t none_value, float* phi,
-    uint32_t* d2, uint32_t* d_in_scratch) {
+    const uint32_t* __restrict__ yrec, int nx, int ny, int nz, uint32_t none_value,
+    uint32_t* __restrict__ zrec) {
   extern __shared__ uint32_t lds[];
   const int fld = blockIdx.y;
   const long long plane = (long long)nx * ny;
-  const long long nvox = plane * nz;
   const long long line0 = (long long)blockIdx.x * kLines;  // flattened (y, x)
-  Tile T = carve_tile(lds, nz);
-  const int line = threadIdx.x / kG;
-  const long long li = line0 + line;
-  const bool active = li < plane;
-  uint32_t* dst =
-      fld == 0 ? (d2 ? d2 : reinterpret_cast<uint32_t*>(phi)) : (d2 ? d2 + nvox : d_in_scratch);
-  {
-    const long long i = line0 + (long long)(threadIdx.x % kLines);
-    stage_tile(T.f, nz, yrec + (i < plane ? i : 0), plane, i < plane,
-               [&](uint32_t r, int) { return field_of_y(r, fld); });
-  }
-  __syncthreads();
-  uint32_t* out = dst + li;
-  tile_fh(T, nz, active, [&](int p, uint32_t d) {
-    out[p * plane] = d == kNone ? none_value : d;
-  });
+  const long long si = line0 + (long long)(threadIdx.x % kLines);
+  const long long li = line0 + (long long)(threadIdx.x / kG);
+  uint32_t* out = zrec + (li < plane ? li : 0);
+  const uint32_t occ_flag = fld == 1 ? kZOcc : 0u;
+  fh_lines<uint32_t, Link>(
+      lds, nz, yrec + (si < plane ? si : 0), plane, si < plane, li < plane, fld,
+      [](uint32_t r, bool& occ) -> uint32_t {
+        occ = r & kYOcc;
+        return (r & kYNone) ? kNone : (r & kYVal);
+      },
+      [&](int p, uint32_t d) { out[p * plane] = occ_flag | (d == kNone ? none_value : d); },
+      [&](int l, int p, uint32_t d) {
+        const long long i = line0 + l < plane ? line0 + l : plane - 1;
+        zrec[i + p * plane] = occ_flag | (d == kNone ? none_value : d);
+      });
 }
 
-// phi = voxel * (sqrt(D_out) - sqrt(D_in)), in float64, rounded to float32 once.  At
-// most one of the two is nonzero (a voxel is a source of one field), and then the
-// formula is exactly +-voxel * sqrt(D) (subtracting sqrt(0) = 0 and negating are
-// exact), so one square root suffices.
-__global__ __launch_bounds__(256) void edt_phi_kernel(const uint32_t* d_out,
-                                                      const uint32_t* d_in, long long nvox,
-                                                      double voxel, float* phi) {
+// From the z records: phi = voxel * (sqrt(D_out) - sqrt(D_in)), in float64, rounded
+// to float32 once, and/or the two squared fields.  One of the two is 0 (a voxel is a
+// source of one field), so the formula is exactly +-voxel * sqrt(D) (subtracting
+// sqrt(0) = 0 and negating are exact).  zrec may be phi (as bits) or d2: each
+// element is read before its own outputs are written.
+__global__ __launch_bounds__(256) void edt_finish_kernel(const uint32_t* zrec, long long nvox,
+                                                         double voxel, float* phi,
+                                                         uint32_t* d2) {
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
   if (i >= nvox) return;
-  const uint32_t a = d_out[i], b = d_in[i];
-  double v;
-  if (a == 0u)
-    v = -(voxel * __builtin_sqrt((double)b));
-  else if (b == 0u)
-    v = voxel * __builtin_sqrt((double)a);
+  const uint32_t r = zrec[i];
+  const bool occ = r & kZOcc;
+  const uint32_t D = r & ~kZOcc;
+  if (d2) {
+    d2[i] = occ ? 0u : D;
+    d2[nvox + i] = occ ? D : 0u;
+  }
+  if (phi) {
+    const double v = voxel * __builtin_sqrt((double)D);
+    phi[i] = (float)(occ ? -v : v);
+  }
+}
+
+template <class Val, class Link>
+size_t fh_lds_bytes(int n) {
+  return tile_bytes<Val, Link>(n) + (size_t)(n + 2) * sizeof(uint32_t) +
+         (size_t)kInList * sizeof(uint16_t);
+}
+
+template <class Link>
+void launch_fh_passes(const uint16_t* xrec, uint32_t* yrec, int nx, int ny, int nz,
+                      uint32_t none_value, uint32_t* zrec, hipStream_t stream) {
+  const long long plane = (long long)nx * ny;
+  const long long ly = (long long)nx * nz;
+  const dim3 ygrid((unsigned)((ly + kLines - 1) / kLines), 2);
+  // x-pass distances are at most nx - 1: their squares fit 16 bits below 0xFFFF
+  // when nx <= 256.
+  if (nx <= 256)
+    edt_pass_y_kernel<uint16_t, Link><<<ygrid, kFhThreads, fh_lds_bytes<uint16_t, Link>(ny),
+                                        stream>>>(xrec, yrec, nx, ny, nz);
   else
-    v = voxel * (__builtin_sqrt((double)a) - __builtin_sqrt((double)b));
-  phi[i] = (float)v;
+    edt_pass_y_kernel<uint32_t, Link><<<ygrid, kFhThreads, fh_lds_bytes<uint32_t, Link>(ny),
+                                        stream>>>(xrec, yrec, nx, ny, nz);
+  edt_pass_z_kernel<Link><<<dim3((unsigned)((plane + kLines - 1) / kLines), 2), kFhThreads,
+                            fh_lds_bytes<uint32_t, Link>(nz), stream>>>(yrec, nx, ny, nz,
+                                                                        none_value, zrec);
 }
 
 }  // namespace
 
 size_t edt_workspace_bytes(long long nvox) {
-  // y-pass records, then the x-pass records (u16) later reused for D_in (u32).
+  // y-pass records (u32), then the x-pass records (u16).
   return (size_t)nvox * (2 * sizeof(uint32_t));
 }
 
-size_t edt_lds_bytes(int n_line) { return tile_bytes(n_line) + (size_t)n_line * sizeof(uint32_t); }
+size_t edt_lds_bytes(int n_line) {
+  return n_line <= 255 ? fh_lds_bytes<uint32_t, uint8_t>(n_line)
+                       : fh_lds_bytes<uint32_t, uint16_t>(n_line);
+}
 
 int launch_edt(const uint8_t* occ, int nx, int ny, int nz, float voxel, float* phi,
                uint32_t* d2, void* work, hipStream_t stream) {
@@ -450,22 +625,22 @@ int launch_edt(const uint8_t* occ, int nx, int ny, int nz, float voxel, float* p
   const long long rows = (long long)ny * nz;
   const uint32_t none_value = (uint32_t)nx * nx + (uint32_t)ny * ny + (uint32_t)nz * nz;
   const long long rows_per_block = (long long)kRowWaves * kRowsPerWave;
-  hipLaunchKernelGGL(edt_pass_x_kernel,
-                     dim3((unsigned)((rows + rows_per_block - 1) / rows_per_block)),
-                     dim3(64 * kRowWaves), 0, stream, occ, nx, rows, xrec);
-  const long long ly = (long long)nx * nz;
-  hipLaunchKernelGGL(edt_pass_y_kernel, dim3((unsigned)((ly + kLines - 1) / kLines), 2),
-                     dim3(kFhThreads), edt_lds_bytes(ny), stream, xrec, yrec, nx, ny, nz);
-  uint32_t* d_in_scratch = yrec + nvox;  // over the x-pass records, dead after pass y
-  hipLaunchKernelGGL(edt_pass_z_kernel, dim3((unsigned)((plane + kLines - 1) / kLines), 2),
-                     dim3(kFhThreads), tile_bytes(nz), stream, yrec, nx, ny, nz, none_value, phi,
-                     d2, d_in_scratch);
-  if (phi) {
-    const uint32_t* d_out = d2 ? d2 : reinterpret_cast<const uint32_t*>(phi);
-    const uint32_t* d_in = d2 ? d2 + nvox : d_in_scratch;
-    hipLaunchKernelGGL(edt_phi_kernel, dim3((unsigned)((nvox + 255) / 256)), dim3(256), 0, stream,
-                       d_out, d_in, nvox, (double)voxel, phi);
-  }
+  const dim3 xgrid((unsigned)((rows + rows_per_block - 1) / rows_per_block));
+  if (nx <= 256)
+    hipLaunchKernelGGL(edt_pass_x_kernel<4>, xgrid, dim3(64 * kRowWaves), 0, stream, occ, nx,
+                       rows, xrec);
+  else
+    hipLaunchKernelGGL(edt_pass_x_kernel<kEdtMaxSide / 64>, xgrid, dim3(64 * kRowWaves), 0,
+                       stream, occ, nx, rows, xrec);
+  // The z records go where the caller's outputs are (D_out's half of d2, else phi as
+  // bits) and are expanded in place.
+  uint32_t* zrec = d2 ? d2 : reinterpret_cast<uint32_t*>(phi);
+  if (ny <= 255 && nz <= 255)
+    launch_fh_passes<uint8_t>(xrec, yrec, nx, ny, nz, none_value, zrec, stream);
+  else
+    launch_fh_passes<uint16_t>(xrec, yrec, nx, ny, nz, none_value, zrec, stream);
+  hipLaunchKernelGGL(edt_finish_kernel, dim3((unsigned)((nvox + 255) / 256)), dim3(256), 0,
+                     stream, zrec, nvox, (double)voxel, phi, d2);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -4,8 +4,10 @@ Squared index distances are integers and must match bit for bit; phi is one
 float64 formula rounded once to float32 on both sides (correctly rounded square
 roots), so it must match bit for bit too.  Cases: ragged grids spanning several
 64-voxel chunks and 64-lane line groups with partial tails, a single source,
-empty and full grids, sides of 1, the longest side along each axis, the
-workloads' scene grids, and the 200^3 reactive-scene grid.
+empty and full grids, sides of 1, the longest side along each axis, lines on
+either side of the 8-/16-bit link switch (255 and 256 samples), obstacles thicker
+than the D_in search reaches, the workloads' scene grids, and the 200^3
+reactive-scene grid.
 """
 import numpy as np
 import pytest
@@ -75,6 +77,34 @@ def test_longest_side_along_each_axis(axis):
     shape[axis] = 512
     rng = np.random.default_rng(axis)
     occ = rng.uniform(size=shape) < 0.004
+    check(occ, 0.01, transform=E.edt_separable_minplus)
+
+
+@pytest.mark.parametrize("shape", [(255, 4, 9), (4, 255, 9), (256, 4, 9), (4, 256, 9)])
+def test_line_lengths_around_the_link_width_switch(shape):
+    """Lines of 255 samples keep their lists in 8-bit links, 256 in 16-bit ones: both
+    sides of the switch, along y and along z, with sparse far-apart sources."""
+    rng = np.random.default_rng(sum(shape))
+    occ = rng.uniform(size=shape) < 0.01
+    check(occ, 0.01, transform=E.edt_separable_minplus)
+    check(~occ, 0.01, transform=E.edt_separable_minplus)
+
+
+def test_thick_obstacles():
+    """D_in inside obstacles: tiles with more occupied voxels than the search lists (a
+    slab filling whole rows, a box with a cavity), and a plane whose y lines hold no
+    free voxel, so the search runs past its reach: all of them take FH."""
+    occ = np.zeros((150, 150, 20), bool)
+    occ[5:145, 5:145, :] = True
+    check(occ, 0.01, transform=E.edt_separable_minplus)
+    occ = np.zeros((150, 150, 40), bool)
+    occ[3:147, 2:148, 4:36] = True
+    occ[70:80, 60:90, 10:20] = False
+    check(occ, 0.01, transform=E.edt_separable_minplus)
+    # One full plane: few occupied voxels per tile, but along y their search finds no
+    # free voxel within its reach.
+    occ = np.zeros((100, 140, 3), bool)
+    occ[50] = True
     check(occ, 0.01, transform=E.edt_separable_minplus)
 
 
