@@ -561,6 +561,11 @@ __global__ __launch_bounds__(kFhThreads) void edt_pass_z_kernel(
 // source of one field), so the formula is exactly +-voxel * sqrt(D) (subtracting
 // sqrt(0) = 0 and negating are exact).  zrec may be phi (as bits) or d2: each
 // element is read before its own outputs are written.
+__device__ __forceinline__ float finish_phi(uint32_t r, double voxel) {
+  const double v = voxel * __builtin_sqrt((double)(r & ~kZOcc));
+  return (float)((r & kZOcc) ? -v : v);
+}
+
 __global__ __launch_bounds__(256) void edt_finish_kernel(const uint32_t* zrec, long long nvox,
                                                          double voxel, float* phi,
                                                          uint32_t* d2) {
@@ -573,10 +578,22 @@ __global__ __launch_bounds__(256) void edt_finish_kernel(const uint32_t* zrec, l
     d2[i] = occ ? 0u : D;
     d2[nvox + i] = occ ? D : 0u;
   }
-  if (phi) {
-    const double v = voxel * __builtin_sqrt((double)D);
-    phi[i] = (float)(occ ? -v : v);
-  }
+  if (phi) phi[i] = finish_phi(r, voxel);
+}
+
+// The same for phi alone, four voxels per thread (zrec is phi: 16-byte aligned, nvox a
+// multiple of 4).
+__global__ __launch_bounds__(256) void edt_finish_phi4_kernel(float* phi, long long n4,
+                                                              double voxel) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n4) return;
+  const uint4 r = reinterpret_cast<const uint4*>(phi)[i];
+  float4 o;
+  o.x = finish_phi(r.x, voxel);
+  o.y = finish_phi(r.y, voxel);
+  o.z = finish_phi(r.z, voxel);
+  o.w = finish_phi(r.w, voxel);
+  reinterpret_cast<float4*>(phi)[i] = o;
 }
 
 template <class Val, class Link>
@@ -639,8 +656,12 @@ int launch_edt(const uint8_t* occ, int nx, int ny, int nz, float voxel, float* p
     launch_fh_passes<uint8_t>(xrec, yrec, nx, ny, nz, none_value, zrec, stream);
   else
     launch_fh_passes<uint16_t>(xrec, yrec, nx, ny, nz, none_value, zrec, stream);
-  hipLaunchKernelGGL(edt_finish_kernel, dim3((unsigned)((nvox + 255) / 256)), dim3(256), 0,
-                     stream, zrec, nvox, (double)voxel, phi, d2);
+  if (!d2 && (reinterpret_cast<uintptr_t>(phi) & 15u) == 0 && nvox % 4 == 0)
+    hipLaunchKernelGGL(edt_finish_phi4_kernel, dim3((unsigned)((nvox / 4 + 255) / 256)), dim3(256),
+                       0, stream, phi, nvox / 4, (double)voxel);
+  else
+    hipLaunchKernelGGL(edt_finish_kernel, dim3((unsigned)((nvox + 255) / 256)), dim3(256), 0,
+                       stream, zrec, nvox, (double)voxel, phi, d2);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -119,6 +119,11 @@ def test_distances_only_and_field_only():
     np.testing.assert_array_equal(d_in, ref_in)
     phi, _, _ = gpu_edt(occ, voxel, with_d2=False)
     np.testing.assert_array_equal(phi.view(np.uint32), ref_phi.view(np.uint32))
+    # The field alone on a voxel count that is not a multiple of 4 (element-wise tail).
+    occ = rng.uniform(size=(7, 9, 11)) < 0.05
+    ref_phi, _, _ = E.signed_distance(occ, voxel)
+    phi, _, _ = gpu_edt(occ, voxel, with_d2=False)
+    np.testing.assert_array_equal(phi.view(np.uint32), ref_phi.view(np.uint32))
 
 
 def test_long_sparse_lines_and_dense_stripes():
