@@ -491,14 +491,43 @@ __device__ __forceinline__ void fh_lines(uint32_t* lds, int n, const Rec* base, 
   });
 }
 
-// Pass y: block = 16 consecutive lines (x, z) of one field (blockIdx.y).
+// Work item (tile, field) of block b.  All D_out items come first (they take longest,
+// so the short D_in blocks fill the end of the launch).  Within a field, blocks are
+// dispatched to XCD b mod 8; the G neighbouring tiles that share 128-byte lines of the
+// records form a group that runs on one XCD, so each line is fetched into one L2 once,
+// and consecutive groups go to consecutive XCDs, so that every XCD gets a share of
+// every region of the grid (a contiguous run per XCD leaves the XCDs holding the
+// obstacle-dense regions to finish last).  Returns false for the padding blocks.
+template <int G>
+__host__ __device__ __forceinline__ long long xcd_half(long long tiles) {
+  return 8 * (((tiles + G - 1) / G + 7) / 8) * G;  // blocks per field, a multiple of 8
+}
+template <int G>
+__device__ __forceinline__ bool xcd_item(long long tiles, long long& tile, int& fld) {
+  const long long half = xcd_half<G>(tiles);
+  fld = blockIdx.x >= half;
+  const long long b = blockIdx.x - (fld ? half : 0);
+  const long long k = b / 8;  // k-th item of this XCD
+  tile = ((b % 8) + 8 * (k / G)) * G + k % G;
+  return tile < tiles;
+}
+template <int G>
+unsigned xcd_grid(long long tiles) {
+  return (unsigned)(2 * xcd_half<G>(tiles));
+}
+// Tiles per 128-byte line: 16 lines x 2-byte x-records, 16 lines x 4-byte y-records.
+constexpr int kGroupY = 4, kGroupZ = 2;
+
+// Pass y: block = 16 consecutive lines (x, z) of one field.
 template <class Val, class Link>
 __global__ __launch_bounds__(kFhThreads) void edt_pass_y_kernel(
     const uint16_t* __restrict__ xrec, uint32_t* __restrict__ yrec, int nx, int ny, int nz) {
   extern __shared__ uint32_t lds[];
-  const int fld = blockIdx.y;
-  const int line0 = blockIdx.x * kLines;  // flattened (z, x) < 2^18
   const int lines = nx * nz;
+  long long tile;
+  int fld;
+  if (!xcd_item<kGroupY>((lines + kLines - 1) / kLines, tile, fld)) return;  // whole block
+  const int line0 = (int)tile * kLines;  // flattened (z, x) < 2^18
   const long long plane = (long long)nx * ny;
   auto line_out = [&](int l) {  // records of block line l (clamped into the grid)
     const int i = min(line0 + l, lines - 1);
@@ -525,7 +554,7 @@ __global__ __launch_bounds__(kFhThreads) void edt_pass_y_kernel(
       });
 }
 
-// Pass z: block = 16 consecutive lines (x, y) of one field (blockIdx.y).  Output:
+// Pass z: block = 16 consecutive lines (x, y) of one field.  Output:
 // one record per voxel, kZOcc | D_in for an occupied voxel (written by the D_in
 // block) and D_out for a free one (by the D_out block); the other field is 0 there.
 // none_value stands for "no source in the grid".
@@ -536,9 +565,11 @@ __global__ __launch_bounds__(kFhThreads) void edt_pass_z_kernel(
     const uint32_t* __restrict__ yrec, int nx, int ny, int nz, uint32_t none_value,
     uint32_t* __restrict__ zrec) {
   extern __shared__ uint32_t lds[];
-  const int fld = blockIdx.y;
   const long long plane = (long long)nx * ny;
-  const long long line0 = (long long)blockIdx.x * kLines;  // flattened (y, x)
+  long long tile;
+  int fld;
+  if (!xcd_item<kGroupZ>((plane + kLines - 1) / kLines, tile, fld)) return;  // whole block
+  const long long line0 = tile * kLines;  // flattened (y, x)
   const long long si = line0 + (long long)(threadIdx.x % kLines);
   const long long li = line0 + (long long)(threadIdx.x / kG);
   uint32_t* out = zrec + (li < plane ? li : 0);
@@ -607,7 +638,7 @@ void launch_fh_passes(const uint16_t* xrec, uint32_t* yrec, int nx, int ny, int 
                       uint32_t none_value, uint32_t* zrec, hipStream_t stream) {
   const long long plane = (long long)nx * ny;
   const long long ly = (long long)nx * nz;
-  const dim3 ygrid((unsigned)((ly + kLines - 1) / kLines), 2);
+  const dim3 ygrid(xcd_grid<kGroupY>((ly + kLines - 1) / kLines));
   // x-pass distances are at most nx - 1: their squares fit 16 bits below 0xFFFF
   // when nx <= 256.
   if (nx <= 256)
@@ -616,7 +647,7 @@ void launch_fh_passes(const uint16_t* xrec, uint32_t* yrec, int nx, int ny, int 
   else
     edt_pass_y_kernel<uint32_t, Link><<<ygrid, kFhThreads, fh_lds_bytes<uint32_t, Link>(ny),
                                         stream>>>(xrec, yrec, nx, ny, nz);
-  edt_pass_z_kernel<Link><<<dim3((unsigned)((plane + kLines - 1) / kLines), 2), kFhThreads,
+  edt_pass_z_kernel<Link><<<dim3(xcd_grid<kGroupZ>((plane + kLines - 1) / kLines)), kFhThreads,
                             fh_lds_bytes<uint32_t, Link>(nz), stream>>>(yrec, nx, ny, nz,
                                                                         none_value, zrec);
 }
