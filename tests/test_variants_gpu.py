@@ -161,6 +161,19 @@ def test_f16_grid_matches_oracle_on_decoded_grid():
     assert_controls_close(got["U_star"], ref["U_star"])
 
 
+def test_f16_grid_odd_element_count_upper_corner():
+    """A float16 grid with an odd element count (31 x 29 x 27) placed so that most
+    lookups clamp to its upper faces and corner, the grid's last elements included."""
+    inp = W.tiny()
+    grid = np.ascontiguousarray(inp.grid[:31, :29, :27])
+    inp = dataclasses.replace(inp, grid=grid, origin=inp.origin - 0.5)
+    g16 = f16_grid(inp.grid)
+    got = run_f16(inp, g16)
+    ref = oracle(inp, grid=g16.astype(np.float64))
+    assert_costs_close(got["S"], ref["S"])
+    assert_controls_close(got["U_star"], ref["U_star"])
+
+
 def test_precision_variant_workload_reports_error_against_fp32_grid(capsys):
     """Mid workload, float16 grid clamped to +-2 m, on-device sampling (seed 4, sigma 0.5)."""
     inp = W.mid()
