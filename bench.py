@@ -54,7 +54,7 @@ ROLLOUT_TRAFFIC = {"sources_sha256": "70f6eb51b83ea0bedf570939bbafa8da9f02bbef68
                    "fetch_kib": 2814.1, "fetch_scale": 2.0,
                    "write_kib": 853.8, "write_scale": 1.0}
 # The same for one occupancy update (pixel and voxel pass together) at 200^3, 640x480.
-OGM_TRAFFIC = {"sources_sha256": "578bcf58ccf36d0e8adf0b931f77c1100deab1a3f38558deced67601a38b34e2",
+OGM_TRAFFIC = {"sources_sha256": "70f6eb51b83ea0bedf570939bbafa8da9f02bbef6880e5baed00b7be241a95bb",
                "fetch_kib": 674.54 + 20301.44, "fetch_scale": 2.0,
                "write_kib": 1200.5 + 39062.5, "write_scale": 1.0}
 
@@ -76,17 +76,19 @@ def rollout_l2(k1_ms):
             "bytes_per_request": 128}
 
 
-def kernel_sources_sha256() -> str:
+def kernel_sources_sha256(names=("smpc_kernels.hip", "smpc_internal.h")) -> str:
     import hashlib
     h = hashlib.sha256()
-    for name in ("smpc_kernels.hip", "smpc_internal.h"):
+    for name in names:
         with open(os.path.join(ROOT, "paper_2512_22575_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
 def traffic_bytes(t):
-    if t is None or t["sources_sha256"] != kernel_sources_sha256():
+    if t is None or t["sources_sha256"] != kernel_sources_sha256(t.get("sources",
+                                                                       ("smpc_kernels.hip",
+                                                                        "smpc_internal.h"))):
         return None
     return round(1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]))
 
@@ -249,6 +251,12 @@ def serving_bench(args) -> dict:
 # Compulsory traffic of the distance-field construction per voxel: the occupancy
 # byte read and the float32 field written.
 EDT_BYTES_PER_VOXEL = 5.0
+# HBM traffic of one construction at 200^3 (reactive scene; the four kernels together),
+# counted and scaled as ROLLOUT_TRAFFIC, valid for the sources named.
+EDT_TRAFFIC = {"sources": ("smpc_edt.hip", "smpc_internal.h"),
+               "sources_sha256": "728c4adcd63f560aaf70e3924c9138d2d07f69b5e56f9e3f31114ce7685cdc66",
+               "fetch_kib": 3973.2 + 33224.7 + 31085.7 + 15633.5, "fetch_scale": 2.0,
+               "write_kib": 15626.0 + 33067.6 + 33964.3 + 31250.0, "write_scale": 1.0}
 PEAK_HBM_GBPS = 8000.0
 
 
@@ -366,7 +374,8 @@ def edt_bench(args) -> dict:
                    "grid": [n] * 3},
         "roofline": {"bound": "hbm", "kernel": "smpc_edt (4 kernels)",
                      "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBPS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_HBM_GBPS, 4),
+                     "traffic": traffic_bytes(EDT_TRAFFIC) if n == 200 else None,
                      "bytes_per_voxel": EDT_BYTES_PER_VOXEL},
         "occupancy_h2d_ms": round(h2d_ms, 5),
         "pipeline_ms_per_step": round(pipe_ms, 5),
