@@ -67,6 +67,7 @@ struct StepParams {
   float w_env, w_self, w_q, w_qd, w_qdd, w_smooth, w_ns;
   float inv_voxel;             // 1 / voxel
   float gcx, gcy, gcz;         // -origin / voxel - 1/2 per axis (continuous-index offset)
+  float inv_voxel8, gc8[3];    // the same divided by 8 (exactly: coarse-cell coordinates)
   int32_t nx, ny, nz;
   uint32_t grid_bytes;
   int32_t ncx, ncy, ncz;       // coarse bound cells per axis

@@ -333,14 +333,16 @@ __device__ __forceinline__ float esdf_lookup(__amdgpu_buffer_rsrc_t rsrc, const 
 // esdf_locate), and its cell i0 >> 3 equals floor(u / 8) clamped to [0, nc - 1]:
 // u / 8 is exact, floor(u / 8) = floor(floor(u) / 8) for u >= 0, and the clamped ends
 // agree because nc - 1 = floor((n - 2) / 8) <= floor((n - 1) / 8).  The cell index is
-// formed in float (exact below 2^24).
+// formed in float (exact below 2^24).  u / 8 is taken as fma(p, inv_voxel / 8,
+// gc / 8), which equals fma(p, inv_voxel, gc) / 8 exactly (a power-of-two scaling
+// commutes with rounding; away from the subnormal range, where floor only sees the sign).
 __device__ __forceinline__ float coarse_bound(__amdgpu_buffer_rsrc_t crsrc, const StepParams& p,
                                               float px, float py, float pz) {
-  const float cx = __builtin_amdgcn_fmed3f(floorf(fmaf(px, p.inv_voxel, p.gcx) * 0.125f), 0.f,
+  const float cx = __builtin_amdgcn_fmed3f(floorf(fmaf(px, p.inv_voxel8, p.gc8[0])), 0.f,
                                            p.cmax[0]);
-  const float cy = __builtin_amdgcn_fmed3f(floorf(fmaf(py, p.inv_voxel, p.gcy) * 0.125f), 0.f,
+  const float cy = __builtin_amdgcn_fmed3f(floorf(fmaf(py, p.inv_voxel8, p.gc8[1])), 0.f,
                                            p.cmax[1]);
-  const float cz = __builtin_amdgcn_fmed3f(floorf(fmaf(pz, p.inv_voxel, p.gcz) * 0.125f), 0.f,
+  const float cz = __builtin_amdgcn_fmed3f(floorf(fmaf(pz, p.inv_voxel8, p.gc8[2])), 0.f,
                                            p.cmax[2]);
   const uint32_t cell = (uint32_t)fmaf(cz, p.cstride[1], fmaf(cy, p.cstride[0], cx));
   return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(crsrc, cell * 4u, 0, 0));

@@ -242,6 +242,12 @@ StepParams make_params(const smpc_ctx* ctx, const smpc_plan_args* a, const Launc
   p.gcx = (float)(-(double)a->esdf.origin[0] * inv_voxel - 0.5);
   p.gcy = (float)(-(double)a->esdf.origin[1] * inv_voxel - 0.5);
   p.gcz = (float)(-(double)a->esdf.origin[2] * inv_voxel - 0.5);
+  // Scaling by 1/8 is exact and commutes with rounding, so fma(x, inv_voxel8, gc8) is
+  // fma(x, inv_voxel, gc) / 8 bit for bit.
+  p.inv_voxel8 = p.inv_voxel * 0.125f;
+  p.gc8[0] = p.gcx * 0.125f;
+  p.gc8[1] = p.gcy * 0.125f;
+  p.gc8[2] = p.gcz * 0.125f;
   p.nx = a->esdf.nx;
   p.ny = a->esdf.ny;
   p.nz = a->esdf.nz;
