@@ -50,11 +50,11 @@ PEAK_FP32_TFLOPS = 157.3
 # reads half the bytes copied: x2; WRITE_SIZE reads them all: x1).  Valid only for
 # the kernel sources it was taken on: bench.py reports null traffic when their
 # hash differs.
-ROLLOUT_TRAFFIC = {"sources_sha256": "70f6eb51b83ea0bedf570939bbafa8da9f02bbef6880e5baed00b7be241a95bb",
-                   "fetch_kib": 2814.1, "fetch_scale": 2.0,
+ROLLOUT_TRAFFIC = {"sources_sha256": "eca5643ce7a3d22319db6b34b703521910fe5853741621f8c9c7077bed9027d3",
+                   "fetch_kib": 2830.5, "fetch_scale": 2.0,
                    "write_kib": 853.8, "write_scale": 1.0}
 # The same for one occupancy update (pixel and voxel pass together) at 200^3, 640x480.
-OGM_TRAFFIC = {"sources_sha256": "70f6eb51b83ea0bedf570939bbafa8da9f02bbef6880e5baed00b7be241a95bb",
+OGM_TRAFFIC = {"sources_sha256": "eca5643ce7a3d22319db6b34b703521910fe5853741621f8c9c7077bed9027d3",
                "fetch_kib": 674.54 + 20301.44, "fetch_scale": 2.0,
                "write_kib": 1200.5 + 39062.5, "write_scale": 1.0}
 
@@ -63,7 +63,7 @@ OGM_TRAFFIC = {"sources_sha256": "70f6eb51b83ea0bedf570939bbafa8da9f02bbef6880e5
 # TCC_REQ_sum, per dispatch), taken on the kernel sources named by the hash.  The L2
 # side of the roofline counts 128 B per request against the L2 peak of
 # PEAK_L2_GBPS: 8 XCDs x 16 channels x 128 B per clock x 2.4 GHz.
-ROLLOUT_L2 = {"sources_sha256": "70f6eb51b83ea0bedf570939bbafa8da9f02bbef6880e5baed00b7be241a95bb", "tcc_req": 229407.0}
+ROLLOUT_L2 = {"sources_sha256": "eca5643ce7a3d22319db6b34b703521910fe5853741621f8c9c7077bed9027d3", "tcc_req": 232095.5}
 PEAK_L2_GBPS = 8 * 16 * 128 * 2.4
 
 
