@@ -254,9 +254,9 @@ EDT_BYTES_PER_VOXEL = 5.0
 # HBM traffic of one construction at 200^3 (reactive scene; the four kernels together),
 # counted and scaled as ROLLOUT_TRAFFIC, valid for the sources named.
 EDT_TRAFFIC = {"sources": ("smpc_edt.hip", "smpc_internal.h"),
-               "sources_sha256": "728c4adcd63f560aaf70e3924c9138d2d07f69b5e56f9e3f31114ce7685cdc66",
-               "fetch_kib": 3973.2 + 33224.7 + 31085.7 + 15633.5, "fetch_scale": 2.0,
-               "write_kib": 15626.0 + 33067.6 + 33964.3 + 31250.0, "write_scale": 1.0}
+               "sources_sha256": "41a141ac90c2cf1b2e4ff265507d8e5455fcedd5208a2c6149159f5fe92a27e7",
+               "fetch_kib": 3973.1 + 33225.1 + 31085.0 + 15633.5, "fetch_scale": 2.0,
+               "write_kib": 15626.0 + 33075.6 + 33957.7 + 31250.0, "write_scale": 1.0}
 PEAK_HBM_GBPS = 8000.0
 
 
