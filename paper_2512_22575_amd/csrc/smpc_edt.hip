@@ -15,13 +15,13 @@
 //   pass y  16 (x, z) lines of one field per block, staged in an LDS tile: D_out by
 //           FH, D_in by a bounded search around each occupied voxel (FH when an
 //           obstacle is too thick for it);
-//   pass z  the same over 16 (x, y) lines per block;
-//   finish  phi = voxel * (sqrt(D_out) - sqrt(D_in)) and/or the two squared fields.
+//   pass z  the same over 16 (x, y) lines per block, writing the outputs: phi =
+//           voxel * (sqrt(D_out) - sqrt(D_in)) and/or the two squared fields.
 //
 // Compact intermediates: after every pass a voxel's value in its own field is 0 (a
 // free voxel is a source of D_in, an occupied one of D_out), so one value per voxel
 // plus its occupancy bit carries both fields: 16 bits after the x pass, 32 after the
-// y and z passes.
+// y pass.
 //
 // FH with 16 lanes per line.  Each lane builds the lower envelope of the samples of
 // its band of the line (FH's stack, kept as a linked list in LDS); four rounds of
@@ -554,16 +554,35 @@ __global__ __launch_bounds__(kFhThreads) void edt_pass_y_kernel(
       });
 }
 
-// Pass z: block = 16 consecutive lines (x, y) of one field.  Output:
-// one record per voxel, kZOcc | D_in for an occupied voxel (written by the D_in
-// block) and D_out for a free one (by the D_out block); the other field is 0 there.
-// none_value stands for "no source in the grid".
-constexpr uint32_t kZOcc = 0x80000000u;
+// The outputs of voxel i, which is occupied or not and has squared distance D to the
+// nearest voxel of the other kind (none_value: none in the grid): phi = voxel *
+// (sqrt(D_out) - sqrt(D_in)), in float64 and rounded to float32 once, and/or the two
+// squared fields.  One of D_out, D_in is 0 (a voxel is a source of one field), so phi
+// is exactly +-voxel * sqrt(D) (subtracting sqrt(0) = 0 and negating are exact).
+struct FieldOut {
+  float* phi;     // [nvox] or null
+  uint32_t* d2;   // [2][nvox] or null
+  long long nvox;
+  double voxel;
+  uint32_t none_value;
+  __device__ __forceinline__ void put(long long i, bool occ, uint32_t d) const {
+    const uint32_t D = d == kNone ? none_value : d;
+    if (d2) {
+      d2[i] = occ ? 0u : D;
+      d2[nvox + i] = occ ? D : 0u;
+    }
+    if (phi) {
+      const double v = voxel * __builtin_sqrt((double)D);
+      phi[i] = (float)(occ ? -v : v);
+    }
+  }
+};
 
+// Pass z: block = 16 consecutive lines (x, y) of one field; the D_out block writes the
+// outputs of the free voxels, the D_in block those of the occupied ones.
 template <class Link>
 __global__ __launch_bounds__(kFhThreads) void edt_pass_z_kernel(
-    const uint32_t* __restrict__ yrec, int nx, int ny, int nz, uint32_t none_value,
-    uint32_t* __restrict__ zrec) {
+    const uint32_t* __restrict__ yrec, int nx, int ny, int nz, FieldOut fo) {
   extern __shared__ uint32_t lds[];
   const long long plane = (long long)nx * ny;
   long long tile;
@@ -572,59 +591,19 @@ __global__ __launch_bounds__(kFhThreads) void edt_pass_z_kernel(
   const long long line0 = tile * kLines;  // flattened (y, x)
   const long long si = line0 + (long long)(threadIdx.x % kLines);
   const long long li = line0 + (long long)(threadIdx.x / kG);
-  uint32_t* out = zrec + (li < plane ? li : 0);
-  const uint32_t occ_flag = fld == 1 ? kZOcc : 0u;
+  const long long out0 = li < plane ? li : 0;
+  const bool occ = fld == 1;
   fh_lines<uint32_t, Link>(
       lds, nz, yrec + (si < plane ? si : 0), plane, si < plane, li < plane, fld,
-      [](uint32_t r, bool& occ) -> uint32_t {
-        occ = r & kYOcc;
+      [](uint32_t r, bool& o) -> uint32_t {
+        o = r & kYOcc;
         return (r & kYNone) ? kNone : (r & kYVal);
       },
-      [&](int p, uint32_t d) { out[p * plane] = occ_flag | (d == kNone ? none_value : d); },
+      [&](int p, uint32_t d) { fo.put(out0 + p * plane, occ, d); },
       [&](int l, int p, uint32_t d) {
         const long long i = line0 + l < plane ? line0 + l : plane - 1;
-        zrec[i + p * plane] = occ_flag | (d == kNone ? none_value : d);
+        fo.put(i + p * plane, occ, d);
       });
-}
-
-// From the z records: phi = voxel * (sqrt(D_out) - sqrt(D_in)), in float64, rounded
-// to float32 once, and/or the two squared fields.  One of the two is 0 (a voxel is a
-// source of one field), so the formula is exactly +-voxel * sqrt(D) (subtracting
-// sqrt(0) = 0 and negating are exact).  zrec may be phi (as bits) or d2: each
-// element is read before its own outputs are written.
-__device__ __forceinline__ float finish_phi(uint32_t r, double voxel) {
-  const double v = voxel * __builtin_sqrt((double)(r & ~kZOcc));
-  return (float)((r & kZOcc) ? -v : v);
-}
-
-__global__ __launch_bounds__(256) void edt_finish_kernel(const uint32_t* zrec, long long nvox,
-                                                         double voxel, float* phi,
-                                                         uint32_t* d2) {
-  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (i >= nvox) return;
-  const uint32_t r = zrec[i];
-  const bool occ = r & kZOcc;
-  const uint32_t D = r & ~kZOcc;
-  if (d2) {
-    d2[i] = occ ? 0u : D;
-    d2[nvox + i] = occ ? D : 0u;
-  }
-  if (phi) phi[i] = finish_phi(r, voxel);
-}
-
-// The same for phi alone, four voxels per thread (zrec is phi: 16-byte aligned, nvox a
-// multiple of 4).
-__global__ __launch_bounds__(256) void edt_finish_phi4_kernel(float* phi, long long n4,
-                                                              double voxel) {
-  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n4) return;
-  const uint4 r = reinterpret_cast<const uint4*>(phi)[i];
-  float4 o;
-  o.x = finish_phi(r.x, voxel);
-  o.y = finish_phi(r.y, voxel);
-  o.z = finish_phi(r.z, voxel);
-  o.w = finish_phi(r.w, voxel);
-  reinterpret_cast<float4*>(phi)[i] = o;
 }
 
 template <class Val, class Link>
@@ -635,7 +614,7 @@ size_t fh_lds_bytes(int n) {
 
 template <class Link>
 void launch_fh_passes(const uint16_t* xrec, uint32_t* yrec, int nx, int ny, int nz,
-                      uint32_t none_value, uint32_t* zrec, hipStream_t stream) {
+                      const FieldOut& fo, hipStream_t stream) {
   const long long plane = (long long)nx * ny;
   const long long ly = (long long)nx * nz;
   const dim3 ygrid(xcd_grid<kGroupY>((ly + kLines - 1) / kLines));
@@ -648,8 +627,7 @@ void launch_fh_passes(const uint16_t* xrec, uint32_t* yrec, int nx, int ny, int 
     edt_pass_y_kernel<uint32_t, Link><<<ygrid, kFhThreads, fh_lds_bytes<uint32_t, Link>(ny),
                                         stream>>>(xrec, yrec, nx, ny, nz);
   edt_pass_z_kernel<Link><<<dim3(xcd_grid<kGroupZ>((plane + kLines - 1) / kLines)), kFhThreads,
-                            fh_lds_bytes<uint32_t, Link>(nz), stream>>>(yrec, nx, ny, nz,
-                                                                        none_value, zrec);
+                            fh_lds_bytes<uint32_t, Link>(nz), stream>>>(yrec, nx, ny, nz, fo);
 }
 
 }  // namespace
@@ -680,19 +658,11 @@ int launch_edt(const uint8_t* occ, int nx, int ny, int nz, float voxel, float* p
   else
     hipLaunchKernelGGL(edt_pass_x_kernel<kEdtMaxSide / 64>, xgrid, dim3(64 * kRowWaves), 0,
                        stream, occ, nx, rows, xrec);
-  // The z records go where the caller's outputs are (D_out's half of d2, else phi as
-  // bits) and are expanded in place.
-  uint32_t* zrec = d2 ? d2 : reinterpret_cast<uint32_t*>(phi);
+  const FieldOut fo{phi, d2, nvox, (double)voxel, none_value};
   if (ny <= 255 && nz <= 255)
-    launch_fh_passes<uint8_t>(xrec, yrec, nx, ny, nz, none_value, zrec, stream);
+    launch_fh_passes<uint8_t>(xrec, yrec, nx, ny, nz, fo, stream);
   else
-    launch_fh_passes<uint16_t>(xrec, yrec, nx, ny, nz, none_value, zrec, stream);
-  if (!d2 && (reinterpret_cast<uintptr_t>(phi) & 15u) == 0 && nvox % 4 == 0)
-    hipLaunchKernelGGL(edt_finish_phi4_kernel, dim3((unsigned)((nvox / 4 + 255) / 256)), dim3(256),
-                       0, stream, phi, nvox / 4, (double)voxel);
-  else
-    hipLaunchKernelGGL(edt_finish_kernel, dim3((unsigned)((nvox + 255) / 256)), dim3(256), 0,
-                       stream, zrec, nvox, (double)voxel, phi, d2);
+    launch_fh_passes<uint16_t>(xrec, yrec, nx, ny, nz, fo, stream);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
