@@ -251,12 +251,12 @@ def serving_bench(args) -> dict:
 # Compulsory traffic of the distance-field construction per voxel: the occupancy
 # byte read and the float32 field written.
 EDT_BYTES_PER_VOXEL = 5.0
-# HBM traffic of one construction at 200^3 (reactive scene; the four kernels together),
+# HBM traffic of one construction at 200^3 (reactive scene; the three kernels together),
 # counted and scaled as ROLLOUT_TRAFFIC, valid for the sources named.
 EDT_TRAFFIC = {"sources": ("smpc_edt.hip", "smpc_internal.h"),
-               "sources_sha256": "41a141ac90c2cf1b2e4ff265507d8e5455fcedd5208a2c6149159f5fe92a27e7",
-               "fetch_kib": 3973.1 + 33225.1 + 31085.0 + 15633.5, "fetch_scale": 2.0,
-               "write_kib": 15626.0 + 33075.6 + 33957.7 + 31250.0, "write_scale": 1.0}
+               "sources_sha256": "0dc726b1fef442598e0dfb9e711bc2690ef4034362b7c9608a28c1059d7990ba",
+               "fetch_kib": 3974.6 + 33220.7 + 31094.5, "fetch_scale": 2.0,
+               "write_kib": 15625.8 + 33063.2 + 33883.7, "write_scale": 1.0}
 PEAK_HBM_GBPS = 8000.0
 
 
@@ -372,7 +372,7 @@ def edt_bench(args) -> dict:
         "config": {"workload": f"reactive scene occupancy {n}^3 at 0.01 m, 20 boxes and 20 "
                                f"spheres drifting at 0.2 m/s, {pool} consecutive periods",
                    "grid": [n] * 3},
-        "roofline": {"bound": "hbm", "kernel": "smpc_edt (4 kernels)",
+        "roofline": {"bound": "hbm", "kernel": "smpc_edt (3 kernels)",
                      "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBPS, 4),
                      "traffic": traffic_bytes(EDT_TRAFFIC) if n == 200 else None,
