@@ -148,6 +148,28 @@ def mid(seed: int = 2) -> PlanInputs:
     return make_inputs(seed, K=1024, H=32, dt=0.02, n=64, voxel=0.03, n_boxes=10, n_spheres=10)
 
 
+def paper_shaped(seed: int = 6, H: int = 40) -> PlanInputs:
+    """The paper's own setting as far as it states it: M = 512 samples at 50 Hz (dt =
+    0.02 s) on its integrated map of 0.02 m voxels over 3 x 3 x 0.5 m (150 x 150 x 25,
+    x and y centred on the base, floor at z = 0), here from 10 boxes and 10 spheres in
+    that slab.  The horizon is not stated; H = 40 as in the reactive workload.  Links
+    above the slab read its top layer (edge extension)."""
+    rng = np.random.default_rng(seed)
+    rob = robot_mod.make_robot(seed)
+    n, voxel, K = (150, 150, 25), 0.02, 512
+    side = np.array(n, np.float64) * voxel
+    origin = np.array([-0.5 * side[0], -0.5 * side[1], 0.0])
+    prims = scene_mod.random_primitives(rng, origin + 0.05 * side, origin + 0.95 * side, 10, 10)
+    grid = scene_mod.signed_distance_grid(scene_mod.occupancy(prims, n, origin, voxel), voxel)
+    q0 = f32(robot_mod.random_joint_config(rng, rob))
+    T_goal = f32(random_target_pose(rng))
+    noise = sample_noise(rng, K, H)
+    return PlanInputs(robot=rob, q0=q0, qd0=f32(np.zeros(robot_mod.N_DOF)), T_goal=T_goal,
+                      grid=grid, origin=f32(origin), voxel=f32s(voxel), noise=noise,
+                      U_bar=f32(np.zeros((H, robot_mod.N_DOF))), dt=f32s(0.02), lam=f32s(1.0),
+                      weights={k: f32s(v) for k, v in DEFAULT_WEIGHTS.items()})
+
+
 class ReactiveScenario:
     """K=4096, H=40, dt=0.02 closed-loop scene: drifting primitives, circling target.
 

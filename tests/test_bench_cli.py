@@ -9,7 +9,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-@pytest.mark.parametrize("mode", [[], ["--edt"], ["--ogm"], ["--serving"], ["--variants"]])
+@pytest.mark.parametrize("mode", [[], ["--edt"], ["--ogm"], ["--serving"], ["--variants"],
+                                  ["--paper-shaped"]])
 def test_more_than_one_gpu_is_refused(mode):
     res = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"] + mode,
                          capture_output=True, text=True, timeout=120)

@@ -66,6 +66,14 @@ def test_mid_workload_parity():
     check_full(W.mid())
 
 
+def test_paper_shaped_workload_parity():
+    """M = 512 on the paper's 150 x 150 x 25 map at 0.02 m (links above the slab read its
+    top layer)."""
+    inp = W.paper_shaped()
+    assert inp.grid.shape == (25, 150, 150) and inp.noise.shape[0] == 512
+    check_full(inp)
+
+
 def test_reactive_workload_full_size_parity():
     """K=4096, H=40, 200^3 grid: the benchmark's launch configuration."""
     check_full(W.ReactiveScenario(seed=3).inputs())
