@@ -117,6 +117,9 @@ def parse_args():
                          "occupancy summaries appended to the line")
     ap.add_argument("--no-coarse", action="store_true",
                     help="plan without the coarse lower bounds of the grid")
+    ap.add_argument("--no-fuse-bounds", action="store_true",
+                    help="build each period's bounds by a launch of their own before its plan "
+                         "step instead of in the previous period's merge launch")
     ap.add_argument("--K", type=int, default=4096)
     ap.add_argument("--H", type=int, default=40)
     ap.add_argument("--n", type=int, default=200, help="grid side in voxels")
@@ -820,7 +823,7 @@ def main():
     u0 = torch.zeros((7,), device=dev)
     u0_host = torch.zeros((7,), pin_memory=True)
 
-    total = args.warmup + args.steps + args.latency_steps + args.profile_steps
+    total = args.warmup + args.steps + args.latency_steps + 2 * args.profile_steps
     plans, grid_structs = [], []
     for i in range(total):
         g = grids[i % n_grids]
@@ -839,18 +842,36 @@ def main():
     coarse_ptr = ctypes.c_void_p(coarse.data_ptr() if use_coarse else 0)
     sp = ctypes.c_void_p(stream)
 
-    def period(i):
+    fuse = use_coarse and not args.no_fuse_bounds
+
+    def bounds(i):
+        st = lib.smpc_grid_coarse_min_ball(grid_ptrs[i % n_grids], reach_cp, reach_r,
+                                           coarse_ptr, sp)
+        if st != S.SMPC_OK:
+            raise S.SMPCError(st, "smpc_grid_coarse_min_ball")
+
+    def serial_period(i):
         """One control period on a fresh grid: bounds of the new grid, then the plan step
         (which executes u*_0 and shifts the nominal sequence on the device)."""
         if use_coarse:
-            st = lib.smpc_grid_coarse_min_ball(grid_ptrs[i % n_grids], reach_cp, reach_r,
-                                               coarse_ptr, sp)
-            if st != S.SMPC_OK:
-                raise S.SMPCError(st, "smpc_grid_coarse_min_ball")
+            bounds(i)
         st = lib.smpc_plan_step(ctx, plan_ptrs[i], sp)
         if st != S.SMPC_OK:
             raise S.SMPCError(st, S.smpc_last_error(ctx))
 
+    def period(i):
+        """One control period; fused, the plan step's merge launch also builds the bounds
+        of the next period's grid, into the table this step's rollouts have read."""
+        if not fuse:
+            serial_period(i)
+            return
+        st = lib.smpc_plan_step_then_bounds(ctx, plan_ptrs[i], grid_ptrs[(i + 1) % n_grids],
+                                            reach_cp, reach_r, coarse_ptr, sp)
+        if st != S.SMPC_OK:
+            raise S.SMPCError(st, S.smpc_last_error(ctx))
+
+    if fuse:
+        bounds(0)  # the first period's bounds; each period then builds the next one's
     # Warm-up (untimed).
     for i in range(args.warmup):
         period(i)
@@ -877,8 +898,9 @@ def main():
     if not np.all(np.isfinite(x_end)):
         raise RuntimeError("closed-loop state is not finite")
 
-    # Latency: each period alone, with u*_0 copied to pinned host memory (device time
-    # between events; host time from the first call to u*_0 on the host).
+    # Latency: each period alone, bounds then plan step (the map of a period is not
+    # known a period ahead), with u*_0 copied to pinned host memory (device time between
+    # events; host time from the first call to u*_0 on the host).
     base += args.steps
     lat_dev, lat_host = [], []
     for i in range(base, base + args.latency_steps):
@@ -886,7 +908,7 @@ def main():
         b = torch.cuda.Event(enable_timing=True)
         h0 = time.perf_counter()
         a.record()
-        period(i)
+        serial_period(i)
         u0_host.copy_(u0, non_blocking=True)
         b.record()
         b.synchronize()
@@ -913,6 +935,15 @@ def main():
             raise S.SMPCError(st, S.smpc_last_error(ctx))
     torch.cuda.synchronize()
     k1_ms, k2_ms = planner.profile_read(args.profile_steps)
+    k2f_ms = None
+    if fuse:  # the merge launch that also builds the next period's bounds
+        base += args.profile_steps
+        bounds(base)
+        planner.profile_enable(args.profile_steps)
+        for i in range(base, base + args.profile_steps):
+            period(i)
+        torch.cuda.synchronize()
+        _, k2f_ms = planner.profile_read(args.profile_steps)
     planner.profile_enable(0)
     coarse_ms = float(np.mean([a.elapsed_time(b) for a, b in cb])) if cb else 0.0
     k1_avg = float(np.mean(k1_ms))
@@ -972,7 +1003,10 @@ def main():
                         f"primitives drifting 0.2 m/s, target on a 0.3 m circle, 7-DoF arm, "
                         f"28 spheres, {sc.robot.n_pairs} self pairs",
             "K": K, "H": H, "grid": [n] * 3, "voxel_m": 0.01, "lambda": 1.0,
-            "period": ("coarse bounds of the period's grid (cells within the arm's reach) + "
+            "period": ("plan step that executes u*_0 and shifts the nominal sequence on "
+                       "the device, its merge launch also building the coarse bounds (cells "
+                       "within the arm's reach) of the next period's grid" if fuse else
+                       "coarse bounds of the period's grid (cells within the arm's reach) + "
                        "plan step that executes u*_0 and shifts the nominal sequence on the "
                        "device" if use_coarse else
                        "plan step that executes u*_0 and shifts the nominal sequence on the "
@@ -989,13 +1023,15 @@ def main():
             "host_p50": round(float(np.percentile(lat_host, 50)), 5),
             "host_p99": round(float(np.percentile(lat_host, 99)), 5),
             "steps": int(args.latency_steps),
-            "what": "one period alone on the device (events), and on the host until u*_0 "
-                    "is in host memory",
+            "what": "one period alone, coarse bounds of its grid then the plan step, on "
+                    "the device (events), and on the host until u*_0 is in host memory",
         },
         "host_ms_per_step": round(wall * 1e3 / args.steps, 5),
         "kernels_ms": {"coarse_bounds": round(coarse_ms, 6),
                        "rollout_cost": round(k1_avg, 6),
-                       "merge": round(float(np.mean(k2_ms)), 6)},
+                       "merge": round(float(np.mean(k2_ms)), 6),
+                       "merge_with_next_bounds": (round(float(np.mean(k2f_ms)), 6)
+                                                  if k2f_ms is not None else None)},
         "roofline": {
             "bound": "alu",
             "kernel": "rollout_cost_kernel",

@@ -285,6 +285,25 @@ smpc_status smpc_grid_coarse_min_ball(const smpc_grid* grid, const float center[
                                       float radius, float* coarse_out, void* stream);
 
 /*
+ * smpc_plan_step (Alg. 1 for args `a`), and smpc_grid_coarse_min_ball of `next_grid`
+ * (the map of the next control period in a receding-horizon loop, Sec. IV-C) into
+ * `coarse_out`: the bounds blocks run in the same launch as the plan step's merge of
+ * the rollouts (eqs. 29-30), beside it.  The results are those of the two calls made
+ * one after the other.
+ *   next_grid, center, radius, coarse_out: as smpc_grid_coarse_min_ball.
+ *   coarse_out may be the table `a` reads (a->esdf.coarse): the merge starts after the
+ *   rollouts have read it, and never reads it.  It must not overlap the step's other
+ *   outputs.
+ * When next_grid's dtype differs from a->esdf's, or its rows are not a multiple of 16
+ * bytes in a 16-byte-aligned grid, the bounds are built by a launch of their own after
+ * the step.  Argument errors return SMPC_E_INVALID_ARG before anything is enqueued.
+ * Runs on the context's device, asynchronously on `stream`.
+ */
+smpc_status smpc_plan_step_then_bounds(smpc_ctx* ctx, const smpc_plan_args* a,
+                                       const smpc_grid* next_grid, const float center[3],
+                                       float radius, float* coarse_out, void* stream);
+
+/*
  * A ball holding every sphere centre of the context's robot at any joint values: the
  * base (the world origin, R3) and radius max over spheres s on link l of
  * sum_{i <= l} sqrt(a_i^2 + d_i^2) + |c_s|, plus 1 mm (with modified DH each joint moves

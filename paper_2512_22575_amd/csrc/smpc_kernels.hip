@@ -1293,12 +1293,12 @@ __global__ __launch_bounds__(kCoarseThreads) void grid_coarse_min_kernel(
 // 16-byte-aligned grid.  A block covers one row (cy, cz) of cells and a chunk of
 // kCoarseChunkGroups - 1 sixteen-byte groups of columns (31 cells of float32, 63 of
 // float16) plus the next group, whose first column closes the chunk's last window.
-// Wave s of the block loads group g (its lane) of the 9 rows of planes s and s + 5 of
-// the cell row's window (all loads issued at once, at wave-uniform row starts; plane,
-// row and group indices are clamped instead of masked, since a repeated value changes
-// neither a minimum nor a maximum) and folds, per group, the minimum and the largest
-// |phi| (with non-finite values flagged) of all its columns and of its first column
-// alone.  The five waves' partial results meet in LDS, then
+// Wave s of a block of kWaves waves loads group g (its lane) of the 9 rows of planes
+// s, s + kWaves, ... of the cell row's window (all loads issued at once, at
+// wave-uniform row starts; plane, row and group indices are clamped instead of masked,
+// since a repeated value changes neither a minimum nor a maximum) and folds, per group,
+// the minimum and the largest |phi| (with non-finite values flagged) of all its columns
+// and of its first column alone.  The waves' partial results meet in LDS, then
 // each cell combines its groups: the window [8 cx, 8 cx + 8] is two whole groups of
 // float32 (one of float16) plus the first column of the next one, or ends at the
 // last column of the row.  Blocks are laid out by XCD (block b runs on XCD b mod 8,
@@ -1307,23 +1307,33 @@ __global__ __launch_bounds__(kCoarseThreads) void grid_coarse_min_kernel(
 constexpr int kCoarseChunkGroups = 64;
 constexpr int kCoarseSubsets = 5;
 constexpr int kCoarseWideThreads = kCoarseChunkGroups * kCoarseSubsets;  // 320
-static_assert(2 * kCoarseSubsets >= kCoarseCell + 1, "two planes per wave cover a window");
 constexpr int kXcds = 8;
 typedef uint32_t U32x4 __attribute__((ext_vector_type(4)));
 
-template <int kElemBytes>
-__global__ __launch_bounds__(kCoarseWideThreads) void grid_coarse_min_wide_kernel(
-    const unsigned char* __restrict__ grid, int nx, int ny, int nz, int ncx, int ncy,
-    int ncz, int nchunks, int nwork, CoarseBall ball, float* __restrict__ out) {
+// One wide-path bounds job: the grid, its cell counts, the work items (chunks x cell
+// rows) and the ball the bounds are restricted to.
+struct CoarseJob {
+  const unsigned char* grid;
+  int nx, ny, nz, ncx, ncy, ncz, nchunks, nwork;
+  CoarseBall ball;
+  float* out;
+};
+
+// Block b (b mod 8 = the XCD it runs on) of a wide-path job, with kWaves waves.
+template <int kElemBytes, int kWaves>
+__device__ __forceinline__ void coarse_wide_block(const CoarseJob& J, int b) {
   constexpr int kCols = 16 / kElemBytes;                               // columns per group
   constexpr int kCells = (kCoarseChunkGroups - 1) * kCols / kCoarseCell;  // cells per chunk
-  __shared__ float s_mn[kCoarseSubsets][kCoarseChunkGroups];
-  __shared__ uint32_t s_mx[kCoarseSubsets][kCoarseChunkGroups];
-  __shared__ float s_fmn[kCoarseSubsets][kCoarseChunkGroups];
-  __shared__ uint32_t s_fmx[kCoarseSubsets][kCoarseChunkGroups];
-  const int per = (nwork + kXcds - 1) / kXcds;
-  const int w = (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
-  if (w >= nwork) return;
+  constexpr int kPlanes = (kCoarseCell + kWaves) / kWaves;             // planes per wave
+  static_assert(kPlanes * kWaves >= kCoarseCell + 1, "the waves' planes cover a window");
+  __shared__ float s_mn[kWaves][kCoarseChunkGroups];
+  __shared__ uint32_t s_mx[kWaves][kCoarseChunkGroups];
+  __shared__ float s_fmn[kWaves][kCoarseChunkGroups];
+  __shared__ uint32_t s_fmx[kWaves][kCoarseChunkGroups];
+  const int nx = J.nx, ny = J.ny, nz = J.nz, ncx = J.ncx, ncy = J.ncy, nchunks = J.nchunks;
+  const int per = (J.nwork + kXcds - 1) / kXcds;
+  const int w = (b % kXcds) * per + b / kXcds;
+  if (w >= J.nwork) return;
   const int cyz = w / nchunks, ch = w - cyz * nchunks;
   const int cz = cyz / ncy, cy = cyz - cz * ncy;
   const int y0 = cy * kCoarseCell, z0 = cz * kCoarseCell;
@@ -1333,17 +1343,18 @@ __global__ __launch_bounds__(kCoarseWideThreads) void grid_coarse_min_wide_kerne
   const int n_groups = nx / kCols;                              // groups per grid row
   const int tid = threadIdx.x;
   const int cx_last = min(ch * kCells + kCells, ncx) - 1;
-  if (coarse_axis_gap(ball.c[0], ch * kCells, cx_last, ncx) +
-          coarse_axis_gap(ball.c[1], cy, cy, ncy) + coarse_axis_gap(ball.c[2], cz, cz, ncz) >
-      ball.r2) {
+  if (coarse_axis_gap(J.ball.c[0], ch * kCells, cx_last, ncx) +
+          coarse_axis_gap(J.ball.c[1], cy, cy, ncy) +
+          coarse_axis_gap(J.ball.c[2], cz, cz, J.ncz) >
+      J.ball.r2) {
     // No lookup from the ball reaches these cells: no bound (never skips), no loads.
     if (tid <= cx_last - ch * kCells)
-      out[((size_t)cz * ncy + cy) * ncx + ch * kCells + tid] = -__builtin_inff();
+      J.out[((size_t)cz * ncy + cy) * ncx + ch * kCells + tid] = -__builtin_inff();
     return;
   }
-  // Wave s takes planes s and s + 5 of the cell row's window and all 9 of its rows (plane
-  // and row clamped to the window: a repeated row changes nothing), so every address is a
-  // wave-uniform row start plus the lane's 16-byte group.
+  // Wave s takes planes s, s + kWaves, ... of the cell row's window and all 9 of its rows
+  // (plane and row clamped to the window: a repeated row changes nothing), so every
+  // address is a wave-uniform row start plus the lane's 16-byte group.
   const int s = __builtin_amdgcn_readfirstlane(tid / kCoarseChunkGroups);
   const int g = tid & (kCoarseChunkGroups - 1);
   const int gg = min(x0 / kCols + g, n_groups - 1);             // clamped group of the row
@@ -1351,14 +1362,14 @@ __global__ __launch_bounds__(kCoarseWideThreads) void grid_coarse_min_wide_kerne
   const size_t row_bytes = (size_t)nx * kElemBytes, plane_bytes = row_bytes * (size_t)ny;
   // Non-temporal loads: the grid streams through once and does not displace what the
   // plan step that follows keeps in L2 (robot constants, instructions).
-  U32x4 v[2][kCoarseCell + 1];
+  U32x4 v[kPlanes][kCoarseCell + 1];
 #pragma unroll
-  for (int zi = 0; zi < 2; ++zi) {
-    const int z = z0 + min(s + kCoarseSubsets * zi, wz - 1);
+  for (int zi = 0; zi < kPlanes; ++zi) {
+    const int z = z0 + min(s + kWaves * zi, wz - 1);
 #pragma unroll
     for (int yy = 0; yy <= kCoarseCell; ++yy) {
       const int y = y0 + min(yy, wy - 1);
-      const unsigned char* row = grid + (size_t)z * plane_bytes + (size_t)y * row_bytes;
+      const unsigned char* row = J.grid + (size_t)z * plane_bytes + (size_t)y * row_bytes;
       v[zi][yy] = __builtin_nontemporal_load(reinterpret_cast<const U32x4*>(row + lane_off));
     }
   }
@@ -1368,7 +1379,7 @@ __global__ __launch_bounds__(kCoarseWideThreads) void grid_coarse_min_wide_kerne
   float mn = __builtin_inff(), fmn = __builtin_inff();
   uint32_t mxb = 0u, fmxb = 0u;
 #pragma unroll
-  for (int j = 0; j < 2 * (kCoarseCell + 1); ++j) {
+  for (int j = 0; j < kPlanes * (kCoarseCell + 1); ++j) {
     const U32x4& vj = v[j / (kCoarseCell + 1)][j % (kCoarseCell + 1)];
     const uint32_t wd[4] = {vj[0], vj[1], vj[2], vj[3]};
 #pragma unroll
@@ -1406,22 +1417,43 @@ __global__ __launch_bounds__(kCoarseWideThreads) void grid_coarse_min_wide_kerne
     uint32_t cmxb = 0u;
     for (int gi = c_lo / kCols; gi < g_end; ++gi) {
 #pragma unroll
-      for (int t = 0; t < kCoarseSubsets; ++t) {
+      for (int t = 0; t < kWaves; ++t) {
         cmn = fminf(cmn, s_mn[t][gi]);
         cmxb = max(cmxb, s_mx[t][gi]);
       }
     }
     if (first_only) {
 #pragma unroll
-      for (int t = 0; t < kCoarseSubsets; ++t) {
+      for (int t = 0; t < kWaves; ++t) {
         cmn = fminf(cmn, s_fmn[t][g_end]);
         cmxb = max(cmxb, s_fmx[t][g_end]);
       }
     }
-    out[((size_t)cz * ncy + cy) * ncx + cx] =
+    J.out[((size_t)cz * ncy + cy) * ncx + cx] =
         cmxb >= 0x7f800000u ? -__builtin_inff()
                             : cmn - (1e-5f + __uint_as_float(cmxb) * 0x1p-18f);
   }
+}
+
+template <int kElemBytes>
+__global__ __launch_bounds__(kCoarseWideThreads) void grid_coarse_min_wide_kernel(CoarseJob J) {
+  coarse_wide_block<kElemBytes, kCoarseSubsets>(J, (int)blockIdx.x);
+}
+
+// A plan step's merge blocks (the first n_k2 blocks) and the wide-path bounds of another
+// grid (from block n_k2p on; n_k2p is n_k2 rounded up to a multiple of 8, so that the
+// bounds blocks keep their XCD layout) in one launch.  The merge blocks leave most of
+// the device idle, and neither part reads what the other writes (the merge never reads
+// bounds).
+template <int kElemBytes>
+__global__ __launch_bounds__(kK2Threads) void merge_bounds_kernel(const DevRobot* __restrict__ rob,
+                                                                  const Request q, int n_k2,
+                                                                  int n_k2p, CoarseJob J) {
+  const int b = (int)blockIdx.x;
+  if (b < n_k2)
+    merge_block<kElemBytes>(rob, q, b);
+  else if (b >= n_k2p)
+    coarse_wide_block<kElemBytes, kK2Threads / kCoarseChunkGroups>(J, b - n_k2p);
 }
 
 // ---------------------------------------------------------------------------
@@ -2038,6 +2070,28 @@ int launch_ogm(const DevRobot* robot, const OgmArgs& a, const float* depth, floa
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// The wide-path job for a grid, or false when its rows are not a multiple of 16 bytes
+// in a 16-byte-aligned grid.
+static bool wide_coarse_job(const void* grid, bool f16, int nx, int ny, int nz,
+                            const CoarseBall& ball, float* out, CoarseJob& job) {
+  const int elem = f16 ? 2 : 4;
+  if (((long long)nx * elem) % 16 != 0 || reinterpret_cast<uintptr_t>(grid) % 16 != 0)
+    return false;
+  job.grid = static_cast<const unsigned char*>(grid);
+  job.nx = nx;
+  job.ny = ny;
+  job.nz = nz;
+  job.ncx = coarse_cells_1d(nx);
+  job.ncy = coarse_cells_1d(ny);
+  job.ncz = coarse_cells_1d(nz);
+  const int cells_per_chunk = (kCoarseChunkGroups - 1) * (16 / elem) / kCoarseCell;
+  job.nchunks = (job.ncx + cells_per_chunk - 1) / cells_per_chunk;
+  job.nwork = (int)((long long)job.nchunks * job.ncy * job.ncz);
+  job.ball = ball;
+  job.out = out;
+  return true;
+}
+
 int launch_grid_coarse_min(const void* grid, bool f16, int nx, int ny, int nz,
                            const float* ball_c, float ball_r2, float* out, void* stream) {
   const int ncx = coarse_cells_1d(nx), ncy = coarse_cells_1d(ny), ncz = coarse_cells_1d(nz);
@@ -2047,15 +2101,12 @@ int launch_grid_coarse_min(const void* grid, bool f16, int nx, int ny, int nz,
   CoarseBall ball;
   for (int a = 0; a < 3; ++a) ball.c[a] = ball_c ? ball_c[a] : 0.f;
   ball.r2 = ball_c ? ball_r2 : __builtin_inff();
-  if (((long long)nx * elem) % 16 == 0 && reinterpret_cast<uintptr_t>(grid) % 16 == 0) {
-    const int cells_per_chunk = (kCoarseChunkGroups - 1) * (16 / elem) / kCoarseCell;
-    const int nchunks = (ncx + cells_per_chunk - 1) / cells_per_chunk;
-    const long long nwork = (long long)nchunks * ncy * ncz;
-    const long long blocks = (nwork + kXcds - 1) / kXcds * kXcds;
+  CoarseJob job;
+  if (wide_coarse_job(grid, f16, nx, ny, nz, ball, out, job)) {
+    const long long blocks = (job.nwork + kXcds - 1) / kXcds * kXcds;
     auto k = f16 ? grid_coarse_min_wide_kernel<2> : grid_coarse_min_wide_kernel<4>;
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kCoarseWideThreads), 0,
-                       (hipStream_t)stream, static_cast<const unsigned char*>(grid), nx, ny, nz,
-                       ncx, ncy, ncz, nchunks, (int)nwork, ball, out);
+                       (hipStream_t)stream, job);
   } else {
     const uint32_t bytes = (uint32_t)((long long)nx * ny * nz * elem);
     auto k = f16 ? grid_coarse_min_kernel<2> : grid_coarse_min_kernel<4>;
@@ -2063,6 +2114,39 @@ int launch_grid_coarse_min(const void* grid, bool f16, int nx, int ny, int nz,
                        (hipStream_t)stream, grid, bytes, nx, ny, nz, ncx, ncy, ncz, ball, out);
   }
   return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+int launch_plan_step_bounds(const DevRobot* robot, const Request& q, const LaunchConfig& lc,
+                            bool f16, const void* grid, bool grid_f16, int nx, int ny, int nz,
+                            const float* ball_c, float ball_r2, float* out, void* stream,
+                            void* events) {
+  CoarseBall ball;
+  for (int a = 0; a < 3; ++a) ball.c[a] = ball_c[a];
+  ball.r2 = ball_r2;
+  CoarseJob job;
+  if (grid_f16 != f16 || !wide_coarse_job(grid, grid_f16, nx, ny, nz, ball, out, job)) {
+    // Not fusable: the plan step, then the bounds by their own launch (same results).
+    const int e = launch_plan_step(robot, q, lc, f16, stream, events);
+    if (e != 0) return e;
+    return launch_grid_coarse_min(grid, grid_f16, nx, ny, nz, ball_c, ball_r2, out, stream);
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t* ev = static_cast<hipEvent_t*>(events);
+  hipError_t e;
+  if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return (int)e;
+  auto k1 = f16 ? rollout_cost_kernel<2> : rollout_cost_kernel<4>;
+  hipLaunchKernelGGL(k1, dim3(lc.P + (q.c0_in_ws ? 1 : 0)), dim3(lc.k1_threads), lc.k1_lds, s,
+                     robot, q);
+  if ((e = hipGetLastError()) != hipSuccess) return (int)e;
+  if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return (int)e;
+  const int n_k2 = lc.k2_blocks, n_k2p = (n_k2 + kXcds - 1) / kXcds * kXcds;
+  const int n_bounds = (job.nwork + kXcds - 1) / kXcds * kXcds;
+  auto k2 = f16 ? merge_bounds_kernel<2> : merge_bounds_kernel<4>;
+  hipLaunchKernelGGL(k2, dim3((unsigned)(n_k2p + n_bounds)), dim3(kK2Threads), 0, s, robot, q,
+                     n_k2, n_k2p, job);
+  if ((e = hipGetLastError()) != hipSuccess) return (int)e;
+  if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return (int)e;
+  return 0;
 }
 
 int launch_grid_to_f16(const float* src, void* dst, long long n, float clamp, void* stream) {

@@ -469,10 +469,40 @@ smpc_status smpc_set_robot(smpc_ctx* ctx, const smpc_robot_desc* d) {
   return SMPC_OK;
 }
 
-smpc_status smpc_plan_step(smpc_ctx* ctx, const smpc_plan_args* a, void* stream) {
-  if (!ctx) return SMPC_E_INVALID_ARG;
-  if (!a) return fail(ctx, SMPC_E_INVALID_ARG, "args is NULL");
-  ctx->last_error.clear();
+// Bounds of another grid restricted to a ball (smpc_grid_coarse_min_ball's arguments, the
+// ball in continuous-index units).
+struct BallBounds {
+  const smpc_grid* g;
+  float c[3];
+  float r2;
+  float* out;
+};
+
+// Checks smpc_grid_coarse_min_ball's arguments and puts the ball in index units: its
+// radius widened by one voxel, which covers the float32 rounding of the sphere
+// positions and of the cell test.
+static smpc_status ball_bounds(const smpc_grid* g, const float* center, float radius,
+                               float* coarse_out, BallBounds& b) {
+  if (!g || !g->data || !coarse_out || !center || g->nx < 2 || g->ny < 2 || g->nz < 2 ||
+      (g->dtype != SMPC_GRID_F32 && g->dtype != SMPC_GRID_F16))
+    return SMPC_E_INVALID_ARG;
+  const long long elem = g->dtype == SMPC_GRID_F16 ? 2 : 4;
+  if ((long long)g->nx * g->ny * g->nz * elem >= (1LL << 31)) return SMPC_E_INVALID_ARG;
+  if (!finite_all(center, 3) || !finite_all(g->origin, 3) || !std::isfinite(g->voxel) ||
+      !(g->voxel > 0.f) || std::isnan(radius) || radius < 0.f)
+    return SMPC_E_INVALID_ARG;
+  for (int a = 0; a < 3; ++a)
+    b.c[a] = (float)(((double)center[a] - (double)g->origin[a]) / (double)g->voxel - 0.5);
+  const double r = std::isinf(radius) ? HUGE_VAL : (double)radius / (double)g->voxel + 1.0;
+  b.r2 = std::isinf(r) ? HUGE_VALF : (float)(r * r);
+  b.g = g;
+  b.out = coarse_out;
+  return SMPC_OK;
+}
+
+// smpc_plan_step, and with `next` the bounds of another grid built by the merge launch.
+static smpc_status plan_step_impl(smpc_ctx* ctx, const smpc_plan_args* a, void* stream,
+                                  const BallBounds* next) {
   const smpc_status st = validate_args(ctx, a);
   if (st != SMPC_OK) return st;
 
@@ -498,12 +528,36 @@ smpc_status smpc_plan_step(smpc_ctx* ctx, const smpc_plan_args* a, void* stream)
   const Workspace ws = carve_workspace(ctx->workspace, a->K, a->H, lc.P);
   hipEvent_t* ev = nullptr;
   if (ctx->prof_recorded < ctx->prof_capacity) ev = &ctx->prof_events[3 * ctx->prof_recorded++];
-  const int e = launch_plan_step(ctx->dev_robot, single_request(a, p, ws), lc,
-                                 a->esdf.dtype == SMPC_GRID_F16, stream, ev);
+  const bool f16 = a->esdf.dtype == SMPC_GRID_F16;
+  const int e =
+      next ? launch_plan_step_bounds(ctx->dev_robot, single_request(a, p, ws), lc, f16,
+                                     next->g->data, next->g->dtype == SMPC_GRID_F16, next->g->nx,
+                                     next->g->ny, next->g->nz, next->c, next->r2, next->out,
+                                     stream, ev)
+           : launch_plan_step(ctx->dev_robot, single_request(a, p, ws), lc, f16, stream, ev);
   if (e != 0)
     return fail(ctx, SMPC_E_DEVICE, "kernel launch failed: %s",
                 hipGetErrorString(static_cast<hipError_t>(e)));
   return SMPC_OK;
+}
+
+smpc_status smpc_plan_step(smpc_ctx* ctx, const smpc_plan_args* a, void* stream) {
+  if (!ctx) return SMPC_E_INVALID_ARG;
+  if (!a) return fail(ctx, SMPC_E_INVALID_ARG, "args is NULL");
+  ctx->last_error.clear();
+  return plan_step_impl(ctx, a, stream, nullptr);
+}
+
+smpc_status smpc_plan_step_then_bounds(smpc_ctx* ctx, const smpc_plan_args* a,
+                                       const smpc_grid* next_grid, const float* center,
+                                       float radius, float* coarse_out, void* stream) {
+  if (!ctx) return SMPC_E_INVALID_ARG;
+  if (!a) return fail(ctx, SMPC_E_INVALID_ARG, "args is NULL");
+  ctx->last_error.clear();
+  BallBounds nb;
+  if (ball_bounds(next_grid, center, radius, coarse_out, nb) != SMPC_OK)
+    return fail(ctx, SMPC_E_INVALID_ARG, "invalid next grid, ball or bounds buffer");
+  return plan_step_impl(ctx, a, stream, &nb);
 }
 
 smpc_status smpc_plan_step_noalloc(smpc_ctx* ctx, const smpc_plan_args* a, void* stream) {
@@ -569,23 +623,11 @@ smpc_status smpc_grid_coarse_min(const smpc_grid* g, float* coarse_out, void* st
 
 smpc_status smpc_grid_coarse_min_ball(const smpc_grid* g, const float* center, float radius,
                                       float* coarse_out, void* stream) {
-  if (!g || !g->data || !coarse_out || !center || g->nx < 2 || g->ny < 2 || g->nz < 2 ||
-      (g->dtype != SMPC_GRID_F32 && g->dtype != SMPC_GRID_F16))
-    return SMPC_E_INVALID_ARG;
-  const long long elem = g->dtype == SMPC_GRID_F16 ? 2 : 4;
-  if ((long long)g->nx * g->ny * g->nz * elem >= (1LL << 31)) return SMPC_E_INVALID_ARG;
-  if (!finite_all(center, 3) || !finite_all(g->origin, 3) || !std::isfinite(g->voxel) ||
-      !(g->voxel > 0.f) || std::isnan(radius) || radius < 0.f)
-    return SMPC_E_INVALID_ARG;
-  // The ball in continuous-index units, its radius widened by one voxel, which covers
-  // the float32 rounding of the sphere positions and of the cell test.
-  float c[3];
-  for (int a = 0; a < 3; ++a)
-    c[a] = (float)(((double)center[a] - (double)g->origin[a]) / (double)g->voxel - 0.5);
-  const double r = std::isinf(radius) ? HUGE_VAL : (double)radius / (double)g->voxel + 1.0;
-  const float r2 = std::isinf(r) ? HUGE_VALF : (float)(r * r);
-  return launch_grid_coarse_min(g->data, g->dtype == SMPC_GRID_F16, g->nx, g->ny, g->nz, c, r2,
-                                coarse_out, stream) == 0
+  BallBounds b;
+  const smpc_status st = ball_bounds(g, center, radius, coarse_out, b);
+  if (st != SMPC_OK) return st;
+  return launch_grid_coarse_min(g->data, g->dtype == SMPC_GRID_F16, g->nx, g->ny, g->nz, b.c,
+                                b.r2, coarse_out, stream) == 0
              ? SMPC_OK
              : SMPC_E_DEVICE;
 }

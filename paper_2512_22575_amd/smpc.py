@@ -160,6 +160,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.smpc_plan_step.restype = c_int32
     lib.smpc_plan_step_noalloc.argtypes = [c_void_p, POINTER(smpc_plan_args), c_void_p]
     lib.smpc_plan_step_noalloc.restype = c_int32
+    lib.smpc_plan_step_then_bounds.argtypes = [c_void_p, POINTER(smpc_plan_args),
+                                               POINTER(smpc_grid), POINTER(c_float), c_float,
+                                               c_void_p, c_void_p]
+    lib.smpc_plan_step_then_bounds.restype = c_int32
     lib.smpc_status_string.argtypes = [c_int32]
     lib.smpc_status_string.restype = c_char_p
     lib.smpc_last_error.argtypes = [c_void_p]
@@ -246,6 +250,21 @@ def smpc_plan_step(ctx: c_void_p, args: smpc_plan_args, stream: int | None) -> i
 
 def smpc_plan_step_noalloc(ctx: c_void_p, args: smpc_plan_args, stream: int | None) -> int:
     return load_library().smpc_plan_step_noalloc(ctx, ctypes.byref(args), c_void_p(stream or 0))
+
+
+def smpc_plan_step_then_bounds(ctx: c_void_p, args: smpc_plan_args, next_grid, dtype: int,
+                               origin, voxel: float, center, radius: float, coarse_out: int,
+                               stream: int | None) -> int:
+    """Plan step, and the ball-restricted bounds of next_grid (device tensor [nz][ny][nx]
+    at origin / voxel) built by the step's merge launch into coarse_out."""
+    nz, ny, nx = (int(x) for x in next_grid.shape)
+    g = smpc_grid(c_void_p(_ptr(next_grid)), nx, ny, nz, int(dtype),
+                  (c_float * 3)(*[float(x) for x in np.asarray(origin, np.float32)]),
+                  float(voxel), None)
+    c = (c_float * 3)(*[float(x) for x in np.asarray(center, np.float32)])
+    return load_library().smpc_plan_step_then_bounds(ctx, ctypes.byref(args), ctypes.byref(g),
+                                                     c, float(radius), c_void_p(coarse_out or 0),
+                                                     c_void_p(stream or 0))
 
 
 def smpc_status_string(status: int) -> str:

@@ -295,6 +295,29 @@ def test_noalloc_rejects_a_workspace_beyond_the_static_scratch(ctx):
     _expect_noalloc(ctx, _args(**fits), S.SMPC_E_INVALID_ARG, "not on the device")
 
 
+def test_plan_step_then_bounds_validates_before_enqueueing(ctx):
+    """Bad bounds arguments, then bad plan-step arguments, are refused on the host."""
+    args = _args()
+    grid = _FakeTensor((16, 16, 16), ptr=0x2000)
+    good = dict(next_grid=grid, dtype=S.GRID_F32, origin=(0.0, 0.0, 0.0), voxel=0.05,
+                center=(0.0, 0.0, 0.0), radius=1.0, coarse_out=0x3000)
+    for bad in (dict(next_grid=_FakeTensor((16, 16, 16), ptr=0)), dict(radius=-1.0),
+                dict(radius=float("nan")), dict(coarse_out=0), dict(voxel=0.0),
+                dict(center=(float("inf"), 0.0, 0.0)), dict(dtype=7),
+                dict(next_grid=_FakeTensor((16, 16, 1), ptr=0x2000))):
+        kw = dict(good, **bad)
+        st = S.smpc_plan_step_then_bounds(ctx, args, kw["next_grid"], kw["dtype"], kw["origin"],
+                                          kw["voxel"], kw["center"], kw["radius"],
+                                          kw["coarse_out"], None)
+        assert st == S.SMPC_E_INVALID_ARG, bad
+        assert "next grid" in S.smpc_last_error(ctx)
+    # Valid bounds arguments: the plan step's own checks come next (no robot set).
+    st = S.smpc_plan_step_then_bounds(ctx, args, grid, S.GRID_F32, (0.0, 0.0, 0.0), 0.05,
+                                      (0.0, 0.0, 0.0), 1.0, 0x3000, None)
+    assert st == S.SMPC_E_INVALID_ARG
+    assert "robot" in S.smpc_last_error(ctx)
+
+
 def test_noalloc_requires_the_robot_on_the_device(ctx):
     # Setting a robot makes no device call, so nothing is resident until a plan step.
     assert S.smpc_set_robot(ctx, S.robot_desc(R.make_robot(0))) == S.SMPC_OK
