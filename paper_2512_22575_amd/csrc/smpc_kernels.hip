@@ -1319,13 +1319,69 @@ struct CoarseJob {
   float* out;
 };
 
+// Wave s of a bounds block: loads group `lane_off` of the 9 rows of the kP planes s,
+// s + kWaves, ... of the window (plane and row indices clamped to it: a repeated row
+// changes nothing), all issued at once at wave-uniform row starts, and folds them into
+// the minimum and the largest |phi| as the bits of |phi|, over all columns of the group
+// and over its first column alone.  For a float the bits with the sign cleared order like
+// |phi| when finite and are >= 0x7f800000 for +-inf and NaN, so one unsigned maximum
+// gives max |phi| and flags any non-finite value.
+struct CoarseFold {
+  float mn, fmn;
+  uint32_t mxb, fmxb;
+};
+
+template <int kElemBytes, int kP>
+__device__ __forceinline__ CoarseFold coarse_fold(const unsigned char* __restrict__ grid,
+                                                  size_t plane_bytes, size_t row_bytes, int z0,
+                                                  int wz, int y0, int wy, int s, int kWaves,
+                                                  uint32_t lane_off) {
+  constexpr int kCols = 16 / kElemBytes;
+  // Non-temporal loads: the grid streams through once and does not displace what the
+  // plan step that follows keeps in L2 (robot constants, instructions).
+  U32x4 v[kP][kCoarseCell + 1];
+#pragma unroll
+  for (int zi = 0; zi < kP; ++zi) {
+    const int z = z0 + min(s + kWaves * zi, wz - 1);
+#pragma unroll
+    for (int yy = 0; yy <= kCoarseCell; ++yy) {
+      const int y = y0 + min(yy, wy - 1);
+      const unsigned char* row = grid + (size_t)z * plane_bytes + (size_t)y * row_bytes;
+      v[zi][yy] = __builtin_nontemporal_load(reinterpret_cast<const U32x4*>(row + lane_off));
+    }
+  }
+  CoarseFold f{__builtin_inff(), __builtin_inff(), 0u, 0u};
+#pragma unroll
+  for (int j = 0; j < kP * (kCoarseCell + 1); ++j) {
+    const U32x4& vj = v[j / (kCoarseCell + 1)][j % (kCoarseCell + 1)];
+    const uint32_t wd[4] = {vj[0], vj[1], vj[2], vj[3]};
+#pragma unroll
+    for (int c = 0; c < kCols; ++c) {
+      float x;
+      if constexpr (kElemBytes == 4) {
+        x = __uint_as_float(wd[c]);
+      } else {
+        const unsigned short h = (unsigned short)(wd[c >> 1] >> ((c & 1) * 16));
+        x = (float)__builtin_bit_cast(_Float16, h);
+      }
+      const uint32_t ab = __float_as_uint(x) & 0x7fffffffu;
+      f.mn = fminf(f.mn, x);
+      f.mxb = max(f.mxb, ab);
+      if (c == 0) {
+        f.fmn = fminf(f.fmn, x);
+        f.fmxb = max(f.fmxb, ab);
+      }
+    }
+  }
+  return f;
+}
+
 // Block b (b mod 8 = the XCD it runs on) of a wide-path job, with kWaves waves.
 template <int kElemBytes, int kWaves>
 __device__ __forceinline__ void coarse_wide_block(const CoarseJob& J, int b) {
   constexpr int kCols = 16 / kElemBytes;                               // columns per group
   constexpr int kCells = (kCoarseChunkGroups - 1) * kCols / kCoarseCell;  // cells per chunk
-  constexpr int kPlanes = (kCoarseCell + kWaves) / kWaves;             // planes per wave
-  static_assert(kPlanes * kWaves >= kCoarseCell + 1, "the waves' planes cover a window");
+  static_assert(kWaves >= 2 && kWaves <= kCoarseCell + 1, "2 to 9 waves per block");
   __shared__ float s_mn[kWaves][kCoarseChunkGroups];
   __shared__ uint32_t s_mx[kWaves][kCoarseChunkGroups];
   __shared__ float s_fmn[kWaves][kCoarseChunkGroups];
@@ -1352,54 +1408,23 @@ __device__ __forceinline__ void coarse_wide_block(const CoarseJob& J, int b) {
       J.out[((size_t)cz * ncy + cy) * ncx + ch * kCells + tid] = -__builtin_inff();
     return;
   }
-  // Wave s takes planes s, s + kWaves, ... of the cell row's window and all 9 of its rows
-  // (plane and row clamped to the window: a repeated row changes nothing), so every
-  // address is a wave-uniform row start plus the lane's 16-byte group.
+  // Wave s takes planes s, s + kWaves, ... of the cell row's window and all 9 of its rows,
+  // so every address is a wave-uniform row start plus the lane's 16-byte group.
   const int s = __builtin_amdgcn_readfirstlane(tid / kCoarseChunkGroups);
   const int g = tid & (kCoarseChunkGroups - 1);
   const int gg = min(x0 / kCols + g, n_groups - 1);             // clamped group of the row
   const uint32_t lane_off = (uint32_t)gg * 16u;
   const size_t row_bytes = (size_t)nx * kElemBytes, plane_bytes = row_bytes * (size_t)ny;
-  // Non-temporal loads: the grid streams through once and does not displace what the
-  // plan step that follows keeps in L2 (robot constants, instructions).
-  U32x4 v[kPlanes][kCoarseCell + 1];
-#pragma unroll
-  for (int zi = 0; zi < kPlanes; ++zi) {
-    const int z = z0 + min(s + kWaves * zi, wz - 1);
-#pragma unroll
-    for (int yy = 0; yy <= kCoarseCell; ++yy) {
-      const int y = y0 + min(yy, wy - 1);
-      const unsigned char* row = J.grid + (size_t)z * plane_bytes + (size_t)y * row_bytes;
-      v[zi][yy] = __builtin_nontemporal_load(reinterpret_cast<const U32x4*>(row + lane_off));
-    }
-  }
-  // The minimum, and the largest |phi| as the bits of |phi|: for a float the bits with the
-  // sign cleared order like |phi| when finite and are >= 0x7f800000 for +-inf and NaN, so
-  // one unsigned maximum gives max |phi| and flags any non-finite value.
-  float mn = __builtin_inff(), fmn = __builtin_inff();
-  uint32_t mxb = 0u, fmxb = 0u;
-#pragma unroll
-  for (int j = 0; j < kPlanes * (kCoarseCell + 1); ++j) {
-    const U32x4& vj = v[j / (kCoarseCell + 1)][j % (kCoarseCell + 1)];
-    const uint32_t wd[4] = {vj[0], vj[1], vj[2], vj[3]};
-#pragma unroll
-    for (int c = 0; c < kCols; ++c) {
-      float x;
-      if constexpr (kElemBytes == 4) {
-        x = __uint_as_float(wd[c]);
-      } else {
-        const unsigned short h = (unsigned short)(wd[c >> 1] >> ((c & 1) * 16));
-        x = (float)__builtin_bit_cast(_Float16, h);
-      }
-      const uint32_t ab = __float_as_uint(x) & 0x7fffffffu;
-      mn = fminf(mn, x);
-      mxb = max(mxb, ab);
-      if (c == 0) {
-        fmn = fminf(fmn, x);
-        fmxb = max(fmxb, ab);
-      }
-    }
-  }
+  // The 9 planes of the window are dealt to the waves in turn: the first 9 mod kWaves
+  // waves take one plane more than the others, so no plane is loaded twice.
+  constexpr int kLo = (kCoarseCell + 1) / kWaves, kExtra = (kCoarseCell + 1) % kWaves;
+  const CoarseFold f =
+      s < kExtra ? coarse_fold<kElemBytes, kLo + 1>(J.grid, plane_bytes, row_bytes, z0, wz, y0,
+                                                    wy, s, kWaves, lane_off)
+                 : coarse_fold<kElemBytes, kLo>(J.grid, plane_bytes, row_bytes, z0, wz, y0, wy,
+                                                s, kWaves, lane_off);
+  const float mn = f.mn, fmn = f.fmn;
+  const uint32_t mxb = f.mxb, fmxb = f.fmxb;
   s_mn[s][g] = mn;
   s_mx[s][g] = mxb;
   s_fmn[s][g] = fmn;
