@@ -50,12 +50,12 @@ PEAK_FP32_TFLOPS = 157.3
 # reads half the bytes copied: x2; WRITE_SIZE reads them all: x1).  Valid only for
 # the kernel sources it was taken on: bench.py reports null traffic when their
 # hash differs.
-ROLLOUT_TRAFFIC = {"sources_sha256": "eca5643ce7a3d22319db6b34b703521910fe5853741621f8c9c7077bed9027d3",
-                   "fetch_kib": 2830.5, "fetch_scale": 2.0,
+ROLLOUT_TRAFFIC = {"sources_sha256": "04121460b14287b10501148696a70f49c9ca0143378798876f3732a37fe454fa",
+                   "fetch_kib": 2823.1, "fetch_scale": 2.0,
                    "write_kib": 853.8, "write_scale": 1.0}
 # The same for one occupancy update (pixel and voxel pass together) at 200^3, 640x480.
-OGM_TRAFFIC = {"sources_sha256": "eca5643ce7a3d22319db6b34b703521910fe5853741621f8c9c7077bed9027d3",
-               "fetch_kib": 674.54 + 20301.44, "fetch_scale": 2.0,
+OGM_TRAFFIC = {"sources_sha256": "04121460b14287b10501148696a70f49c9ca0143378798876f3732a37fe454fa",
+               "fetch_kib": 671.5 + 20301.4, "fetch_scale": 2.0,
                "write_kib": 1200.5 + 39062.5, "write_scale": 1.0}
 
 
@@ -63,7 +63,7 @@ OGM_TRAFFIC = {"sources_sha256": "eca5643ce7a3d22319db6b34b703521910fe5853741621
 # TCC_REQ_sum, per dispatch), taken on the kernel sources named by the hash.  The L2
 # side of the roofline counts 128 B per request against the L2 peak of
 # PEAK_L2_GBPS: 8 XCDs x 16 channels x 128 B per clock x 2.4 GHz.
-ROLLOUT_L2 = {"sources_sha256": "eca5643ce7a3d22319db6b34b703521910fe5853741621f8c9c7077bed9027d3", "tcc_req": 232095.5}
+ROLLOUT_L2 = {"sources_sha256": "04121460b14287b10501148696a70f49c9ca0143378798876f3732a37fe454fa", "tcc_req": 233313.7}
 PEAK_L2_GBPS = 8 * 16 * 128 * 2.4
 
 
@@ -259,9 +259,9 @@ EDT_BYTES_PER_VOXEL = 5.0
 # HBM traffic of one construction at 200^3 (reactive scene; the three kernels together),
 # counted and scaled as ROLLOUT_TRAFFIC, valid for the sources named.
 EDT_TRAFFIC = {"sources": ("smpc_edt.hip", "smpc_internal.h"),
-               "sources_sha256": "0dc726b1fef442598e0dfb9e711bc2690ef4034362b7c9608a28c1059d7990ba",
-               "fetch_kib": 3974.6 + 33220.7 + 31094.5, "fetch_scale": 2.0,
-               "write_kib": 15625.8 + 33063.2 + 33883.7, "write_scale": 1.0}
+               "sources_sha256": "8e04f1660cca487e284f79a0510ffe51b664cf3d9aefc2666f622e39b816c1ac",
+               "fetch_kib": 3974.6 + 33219.9 + 28807.0, "fetch_scale": 2.0,
+               "write_kib": 15626.0 + 33064.7 + 33876.2, "write_scale": 1.0}
 PEAK_HBM_GBPS = 8000.0
 
 
