@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <cstddef>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -641,6 +642,20 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
   const int m0 = b * R;
   const int nroll = min(R, p.K - m0);
 
+  // The robot constants the cost phase reads through chains of dependent scalar loads
+  // (DH parameters, sphere slots, link-pair records) are touched once here with vector
+  // loads, in parallel and beside the disturbances: after a kernel that streamed other
+  // data through L2 (a new distance field) they would otherwise come from HBM one chain
+  // link at a time.  The words are folded into a value the cost phase overwrites.
+  constexpr int kWarm16 = (int)(offsetof(DevRobot, lbound) / 16);
+  constexpr int kWarmLoads = (kWarm16 + kK1Threads - 1) / kK1Threads;
+  uint4 warm[kWarmLoads];
+  {
+    const uint4* rw = reinterpret_cast<const uint4*>(rob);
+#pragma unroll
+    for (int i = 0; i < kWarmLoads; ++i) warm[i] = rw[min(tid + i * kK1Threads, kWarm16 - 1)];
+  }
+
   // Stage this block's disturbances (contiguous [nroll][H][7]) and the nominal sequence:
   // read them, or sample them here (one (rollout, step) item per thread).
   if (noise == nullptr) {
@@ -683,6 +698,12 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
       L.sc0[tid] = s;
       L.sc0[kNdof + tid] = c;
     }
+  }
+  {
+    uint32_t x = 0u;
+#pragma unroll
+    for (int i = 0; i < kWarmLoads; ++i) x ^= warm[i].x ^ warm[i].y ^ warm[i].z ^ warm[i].w;
+    L.cost[min(tid, RH - 1)] = __uint_as_float(x);
   }
   __syncthreads();
 
