@@ -8,17 +8,20 @@ boxes and 20 spheres drifting at 0.2 m/s, a target moving on a 0.3 m circle, the
 All inputs are seeded synthetic data and are resident in device memory before
 timing starts.
 
-One step = one control period of the closed loop on a fresh grid: the coarse
-lower bounds of that period's grid over the cells the arm can reach
-(smpc_grid_coarse_min_ball with smpc_robot_reach) and one plan step
-(smpc_plan_step, both kernels) that reads the joint state and nominal sequence the
+One step = one control period of the closed loop on a fresh grid: one plan step
+(smpc_plan_step_then_bounds) that reads the joint state and nominal sequence the
 previous period left on the device, executes u*_0 for one period and shifts the
-nominal sequence (receding horizon).  The grids of consecutive periods (built on
-the device from the scene's occupancy) and the disturbances cycle through pools of
-distinct device buffers.
+nominal sequence (receding horizon), and whose rollout launch also builds the coarse
+lower bounds of the next period's grid over the cells the arm can reach (as
+smpc_grid_coarse_min_ball with smpc_robot_reach) into the second of two tables
+(--no-fuse-bounds: each period builds its own grid's bounds by a launch of their
+own before its plan step).  The grids of consecutive periods (built on the device
+from the scene's occupancy) and the disturbances cycle through pools of distinct
+device buffers.
 
 Printed: one JSON line with rollout-steps/s (K*H per second) from back-to-back
-periods, per-period latency percentiles (each period synchronised on its own), the
+periods, per-period latency percentiles (each period synchronised on its own: the
+bounds of its own grid, then smpc_plan_step), the
 rollout-cost kernel's duration against the FP32 VALU peak (and the L2 side when its
 counters match the sources), the same plan steps on one static grid, and the FP64
 oracle's closed loop on one host thread.
@@ -807,7 +810,10 @@ def main():
     noise = [torch.from_numpy(x).to(dev) for x in noise_np]
     t_setup = time.perf_counter() - t_setup
     use_coarse = not args.no_coarse
-    coarse = torch.empty(S.smpc_grid_coarse_cells(n, n, n), device=dev) if use_coarse else None
+    # Two bounds tables: period i reads table i mod 2 while its launches build the next
+    # period's bounds into the other one.
+    tables = [torch.empty(S.smpc_grid_coarse_cells(n, n, n), device=dev) for _ in range(2)]
+    coarse = tables[0] if use_coarse else None
     costs = torch.empty((K,), device=dev)
     stats = torch.empty((4,), device=dev)
     planner = S.Planner(sc.robot, device=0)
@@ -829,7 +835,8 @@ def main():
         g = grids[i % n_grids]
         plans.append(S.plan_args(sc.q0, sc.qd0, sc.target(), g, sc.origin, sc.VOXEL,
                                  noise[i % n_pool], U[i % 2], U[(i + 1) % 2], K, H, sc.DT, 1.0,
-                                 sc.weights, costs_out=costs, stats_out=stats, coarse=coarse,
+                                 sc.weights, costs_out=costs, stats_out=stats,
+                                 coarse=tables[i % 2] if use_coarse else None,
                                  receding=True, u0_out=u0, state_in=X[i % 2],
                                  state_out=X[(i + 1) % 2]))
         sc.t += sc.DT
@@ -839,14 +846,14 @@ def main():
                                         float(sc.VOXEL), None))
     plan_ptrs = [ctypes.byref(a) for a in plans]
     grid_ptrs = [ctypes.byref(g) for g in grid_structs]
-    coarse_ptr = ctypes.c_void_p(coarse.data_ptr() if use_coarse else 0)
+    table_ptrs = [ctypes.c_void_p(t.data_ptr()) for t in tables]
     sp = ctypes.c_void_p(stream)
 
     fuse = use_coarse and not args.no_fuse_bounds
 
     def bounds(i):
         st = lib.smpc_grid_coarse_min_ball(grid_ptrs[i % n_grids], reach_cp, reach_r,
-                                           coarse_ptr, sp)
+                                           table_ptrs[i % 2], sp)
         if st != S.SMPC_OK:
             raise S.SMPCError(st, "smpc_grid_coarse_min_ball")
 
@@ -860,13 +867,13 @@ def main():
             raise S.SMPCError(st, S.smpc_last_error(ctx))
 
     def period(i):
-        """One control period; fused, the plan step's merge launch also builds the bounds
-        of the next period's grid, into the table this step's rollouts have read."""
+        """One control period; fused, the plan step's rollout launch also builds the bounds
+        of the next period's grid, into the table this step does not read."""
         if not fuse:
             serial_period(i)
             return
         st = lib.smpc_plan_step_then_bounds(ctx, plan_ptrs[i], grid_ptrs[(i + 1) % n_grids],
-                                            reach_cp, reach_r, coarse_ptr, sp)
+                                            reach_cp, reach_r, table_ptrs[(i + 1) % 2], sp)
         if st != S.SMPC_OK:
             raise S.SMPCError(st, S.smpc_last_error(ctx))
 
@@ -927,7 +934,7 @@ def main():
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
             st = lib.smpc_grid_coarse_min_ball(grid_ptrs[i % n_grids], reach_cp, reach_r,
-                                               coarse_ptr, sp)
+                                               table_ptrs[i % 2], sp)
             e1.record()
             cb.append((e0, e1))
         st = lib.smpc_plan_step(ctx, plan_ptrs[i], sp)
@@ -935,15 +942,15 @@ def main():
             raise S.SMPCError(st, S.smpc_last_error(ctx))
     torch.cuda.synchronize()
     k1_ms, k2_ms = planner.profile_read(args.profile_steps)
-    k2f_ms = None
-    if fuse:  # the merge launch that also builds the next period's bounds
+    k1f_ms = k2f_ms = None
+    if fuse:  # the rollout launch that also builds the next period's bounds
         base += args.profile_steps
         bounds(base)
         planner.profile_enable(args.profile_steps)
         for i in range(base, base + args.profile_steps):
             period(i)
         torch.cuda.synchronize()
-        _, k2f_ms = planner.profile_read(args.profile_steps)
+        k1f_ms, k2f_ms = planner.profile_read(args.profile_steps)
     planner.profile_enable(0)
     coarse_ms = float(np.mean([a.elapsed_time(b) for a, b in cb])) if cb else 0.0
     k1_avg = float(np.mean(k1_ms))
@@ -1004,8 +1011,9 @@ def main():
                         f"28 spheres, {sc.robot.n_pairs} self pairs",
             "K": K, "H": H, "grid": [n] * 3, "voxel_m": 0.01, "lambda": 1.0,
             "period": ("plan step that executes u*_0 and shifts the nominal sequence on "
-                       "the device, its merge launch also building the coarse bounds (cells "
-                       "within the arm's reach) of the next period's grid" if fuse else
+                       "the device, its rollout launch also building the coarse bounds "
+                       "(cells within the arm's reach) of the next period's grid into the "
+                       "other of two tables" if fuse else
                        "coarse bounds of the period's grid (cells within the arm's reach) + "
                        "plan step that executes u*_0 and shifts the nominal sequence on the "
                        "device" if use_coarse else
@@ -1030,8 +1038,10 @@ def main():
         "kernels_ms": {"coarse_bounds": round(coarse_ms, 6),
                        "rollout_cost": round(k1_avg, 6),
                        "merge": round(float(np.mean(k2_ms)), 6),
-                       "merge_with_next_bounds": (round(float(np.mean(k2f_ms)), 6)
-                                                  if k2f_ms is not None else None)},
+                       "fused_period": (
+                           {"rollout_with_next_bounds": round(float(np.mean(k1f_ms)), 6),
+                            "merge": round(float(np.mean(k2f_ms)), 6)}
+                           if k1f_ms is not None else None)},
         "roofline": {
             "bound": "alu",
             "kernel": "rollout_cost_kernel",

@@ -287,13 +287,14 @@ smpc_status smpc_grid_coarse_min_ball(const smpc_grid* grid, const float center[
 /*
  * smpc_plan_step (Alg. 1 for args `a`), and smpc_grid_coarse_min_ball of `next_grid`
  * (the map of the next control period in a receding-horizon loop, Sec. IV-C) into
- * `coarse_out`: the bounds blocks run in the same launch as the plan step's merge of
- * the rollouts (eqs. 29-30), beside it.  The results are those of the two calls made
- * one after the other.
+ * `coarse_out`, built by the step's own launches: the results are those of the two
+ * calls made one after the other.
  *   next_grid, center, radius, coarse_out: as smpc_grid_coarse_min_ball.
- *   coarse_out may be the table `a` reads (a->esdf.coarse): the merge starts after the
- *   rollouts have read it, and never reads it.  It must not overlap the step's other
- *   outputs.
+ *   coarse_out is either the table `a` reads (a->esdf.coarse) or does not overlap it
+ *   (else SMPC_E_INVALID_ARG).  Apart from it, the bounds blocks run beside the rollouts
+ *   (eqs. 17-28) in their launch; as that table, they run beside the merge of the
+ *   rollouts (eqs. 29-30), which starts after the rollouts have read it and never reads
+ *   it.  coarse_out must not overlap the step's other outputs.
  * When next_grid's dtype differs from a->esdf's, or its rows are not a multiple of 16
  * bytes in a 16-byte-aligned grid, the bounds are built by a launch of their own after
  * the step.  Argument errors return SMPC_E_INVALID_ARG before anything is enqueued.

@@ -144,10 +144,12 @@ int scratch_address(int device, void** out);
 int launch_plan_step(const DevRobot* robot, const Request& q, const LaunchConfig& lc, bool f16,
                      void* stream, void* events);
 
-// launch_plan_step whose merge launch also builds the coarse bounds of another grid,
-// restricted to a ball (as launch_grid_coarse_min with ball_c non-null); when the grid
-// is not fit for the fused launch (another element type, rows not a multiple of 16
-// bytes, unaligned) the bounds follow the plan step in a launch of their own.
+// launch_plan_step whose launches also build the coarse bounds of another grid,
+// restricted to a ball (as launch_grid_coarse_min with ball_c non-null): in the rollout
+// launch when `out` is not the table the step reads (the two must not overlap), else in
+// the merge launch; when the grid is not fit for either (another element type, rows not
+// a multiple of 16 bytes, unaligned) the bounds follow the plan step in a launch of
+// their own.
 int launch_plan_step_bounds(const DevRobot* robot, const Request& q, const LaunchConfig& lc,
                             bool f16, const void* grid, bool grid_f16, int nx, int ny, int nz,
                             const float* ball_c, float ball_r2, float* out, void* stream,

@@ -557,6 +557,20 @@ smpc_status smpc_plan_step_then_bounds(smpc_ctx* ctx, const smpc_plan_args* a,
   BallBounds nb;
   if (ball_bounds(next_grid, center, radius, coarse_out, nb) != SMPC_OK)
     return fail(ctx, SMPC_E_INVALID_ARG, "invalid next grid, ball or bounds buffer");
+  // The table written is the one the step reads, or lies apart from it: the rollouts
+  // read theirs while the bounds blocks of the same launch write another.
+  const float* rd = a->esdf.coarse;
+  if (rd && coarse_out != rd) {
+    const uintptr_t r0 = reinterpret_cast<uintptr_t>(rd);
+    const uintptr_t w0 = reinterpret_cast<uintptr_t>(coarse_out);
+    const uintptr_t r1 = r0 + (uintptr_t)smpc_grid_coarse_cells(a->esdf.nx, a->esdf.ny,
+                                                                  a->esdf.nz) * 4u;
+    const uintptr_t w1 = w0 + (uintptr_t)smpc_grid_coarse_cells(next_grid->nx, next_grid->ny,
+                                                                  next_grid->nz) * 4u;
+    if (w0 < r1 && r0 < w1)
+      return fail(ctx, SMPC_E_INVALID_ARG,
+                  "coarse_out overlaps the table the step reads without being it");
+  }
   return plan_step_impl(ctx, a, stream, &nb);
 }
 

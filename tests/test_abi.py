@@ -311,6 +311,14 @@ def test_plan_step_then_bounds_validates_before_enqueueing(ctx):
                                           kw["coarse_out"], None)
         assert st == S.SMPC_E_INVALID_ARG, bad
         assert "next grid" in S.smpc_last_error(ctx)
+    # A table that overlaps the one the step reads without being it.
+    import ctypes as C
+    a_over = _args()
+    a_over.esdf.coarse = C.c_void_p(0x3000)
+    st = S.smpc_plan_step_then_bounds(ctx, a_over, grid, S.GRID_F32, (0.0, 0.0, 0.0), 0.05,
+                                      (0.0, 0.0, 0.0), 1.0, 0x3004, None)
+    assert st == S.SMPC_E_INVALID_ARG
+    assert "overlaps" in S.smpc_last_error(ctx)
     # Valid bounds arguments: the plan step's own checks come next (no robot set).
     st = S.smpc_plan_step_then_bounds(ctx, args, grid, S.GRID_F32, (0.0, 0.0, 0.0), 0.05,
                                       (0.0, 0.0, 0.0), 1.0, 0x3000, None)

@@ -1,11 +1,12 @@
 """GPU tests of smpc_plan_step_then_bounds: a receding-horizon loop in which each plan
-step's merge launch also builds the bounds of the next period's grid gives, period by
+step's launches also build the bounds of the next period's grid gives, period by
 period, bitwise the plan-step outputs (U_out, costs, weights, statistics, u*_0, next
 state) and bounds tables of the same loop run as smpc_grid_coarse_min_ball followed by
-smpc_plan_step -- with the bounds written to the table the step reads, or to a second
-one; on float32 and float16 grids; and on grids the fused launch cannot take (another
-element type than the step's grid, rows that are not a multiple of 16 bytes), which get
-the bounds from a launch of their own.
+smpc_plan_step -- with the bounds written to a second table (built by the rollout
+launch) or to the table the step reads (built by the merge launch); on float32 and
+float16 grids; and on grids neither launch can take (another element type than the
+step's grid, rows that are not a multiple of 16 bytes), which get the bounds from a
+launch of their own.
 """
 import numpy as np
 import pytest
