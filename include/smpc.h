@@ -416,7 +416,9 @@ smpc_status smpc_edt(const uint8_t* occ, int32_t nx, int32_t ny, int32_t nz, flo
  * step, the durations in milliseconds of the rollout-cost kernel (rollout_ms[i])
  * and of the merge kernel (merge_ms[i]); *n_steps receives the count written
  * (at most `capacity`).  Reading resets the record.  Events are created by
- * smpc_profile_enable; both calls return SMPC_E_DEVICE on HIP failures.
+ * smpc_profile_enable, for timing only: they carry no system-scope memory fence, so
+ * waiting for them does not make the step's outputs visible to the host (synchronise
+ * the stream for that).  Both calls return SMPC_E_DEVICE on HIP failures.
  */
 smpc_status smpc_profile_enable(smpc_ctx* ctx, int32_t n_steps);
 smpc_status smpc_profile_read(smpc_ctx* ctx, float* rollout_ms, float* merge_ms,

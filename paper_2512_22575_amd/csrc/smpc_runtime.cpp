@@ -863,8 +863,12 @@ smpc_status smpc_profile_enable(smpc_ctx* ctx, int32_t n_steps) {
   (void)hipDeviceSynchronize();
   destroy_events(ctx);
   ctx->prof_events.resize((size_t)3 * n_steps);
+  // Timing-only events: without the system-scope fence (an L2 write-back and
+  // invalidate) that a default event performs when it is recorded, which would add to
+  // the measured kernel and slow the one after it.
   for (size_t i = 0; i < ctx->prof_events.size(); ++i) {
-    if (hipEventCreate(&ctx->prof_events[i]) != hipSuccess) {
+    if (hipEventCreateWithFlags(&ctx->prof_events[i], hipEventDisableSystemFence) !=
+        hipSuccess) {
       ctx->prof_events.resize(i);
       destroy_events(ctx);
       return fail(ctx, SMPC_E_DEVICE, "hipEventCreate failed");
