@@ -456,9 +456,11 @@ class Planner:
                   weights, costs_out=None, weights_out=None, stats_out=None, stream=None,
                   seed: int = 0, sigma=None, grid_dtype: int = GRID_F32, K=None, H=None,
                   coarse=None, receding: bool = False, u0_out=None, state_in=None,
-                  state_out=None, noalloc: bool = False) -> None:
+                  state_out=None, noalloc: bool = False, next_bounds=None) -> None:
         """Enqueue one plan step on ``stream`` (default: torch's current stream);
-        ``noalloc`` takes the workspace from the library's static device scratch."""
+        ``noalloc`` takes the workspace from the library's static device scratch;
+        ``next_bounds`` = (grid, dtype, origin, voxel, coarse_out) also builds that grid's
+        bounds within the robot's reach into coarse_out (smpc_plan_step_then_bounds)."""
         import torch
         if noise is not None:
             K, H = int(noise.shape[0]), int(noise.shape[1])
@@ -469,7 +471,15 @@ class Planner:
         a = plan_args(q0, qd0, T_goal, grid, origin, voxel, noise, U_in, U_out, K, H, dt, lam,
                       weights, costs_out, weights_out, stats_out, seed, sigma, grid_dtype,
                       coarse, receding, u0_out, state_in, state_out)
-        st = (smpc_plan_step_noalloc if noalloc else smpc_plan_step)(self._ctx, a, stream)
+        if next_bounds is not None:
+            if noalloc:
+                raise ValueError("next_bounds has no allocation-free form")
+            g, dt_g, org, vox, out = next_bounds
+            c, r = self.robot_reach()
+            st = smpc_plan_step_then_bounds(self._ctx, a, g, dt_g, org, vox, c, r, _ptr(out),
+                                            stream)
+        else:
+            st = (smpc_plan_step_noalloc if noalloc else smpc_plan_step)(self._ctx, a, stream)
         if st != SMPC_OK:
             raise SMPCError(st, smpc_last_error(self._ctx))
 
@@ -533,8 +543,9 @@ class RecedingHorizon:
 
     def step(self, *, T_goal, grid, origin, voxel, dt, lam, weights, noise=None, seed: int = 0,
              sigma=None, K=None, coarse=None, costs_out=None, weights_out=None, stats_out=None,
-             grid_dtype: int = GRID_F32, stream=None) -> None:
-        """Enqueue one control period on ``stream`` (default: torch's current stream)."""
+             grid_dtype: int = GRID_F32, stream=None, next_bounds=None) -> None:
+        """Enqueue one control period on ``stream`` (default: torch's current stream);
+        ``next_bounds`` as for Planner.plan_step (the next period's map, when known)."""
         nxt = 1 - self._cur
         self.planner.plan_step(q0=self._q0, qd0=self._qd0, T_goal=T_goal, grid=grid,
                                origin=origin, voxel=voxel, noise=noise, U_in=self._U[self._cur],
@@ -542,7 +553,8 @@ class RecedingHorizon:
                                costs_out=costs_out, weights_out=weights_out, stats_out=stats_out,
                                stream=stream, seed=seed, sigma=sigma, grid_dtype=grid_dtype, K=K,
                                H=self.H, coarse=coarse, receding=True, u0_out=self.u0,
-                               state_in=self._X[self._cur], state_out=self._X[nxt])
+                               state_in=self._X[self._cur], state_out=self._X[nxt],
+                               next_bounds=next_bounds)
         self._cur = nxt
 
 

@@ -28,7 +28,8 @@ def _grids(base: np.ndarray, n: int, seed: int, dtype) -> list[np.ndarray]:
     return [np.ascontiguousarray(g, np.float32) for g in out]
 
 
-def _loop(inp, grids_np, dtype, next_dtype, K, H, fused, alias, next_grids_np=None):
+def _loop(inp, grids_np, dtype, next_dtype, K, H, fused, alias, next_grids_np=None,
+          step_reads_bounds=True):
     """Run len(grids_np) periods; return per-period outputs and the tables."""
     import torch
 
@@ -55,7 +56,7 @@ def _loop(inp, grids_np, dtype, next_dtype, K, H, fused, alias, next_grids_np=No
     n = len(grids)
     tab = lambda i: tabs[i % len(tabs)]  # noqa: E731
     # When the step's grid differs in type from the bounded one, the step reads no table.
-    reads_table = next_grids_np is None
+    reads_table = next_grids_np is None and step_reads_bounds
     results = []
     if fused:
         st = S.smpc_grid_coarse_min_ball(bgrids[0], next_dtype, inp.origin, inp.voxel, reach_c,
@@ -95,10 +96,13 @@ def _loop(inp, grids_np, dtype, next_dtype, K, H, fused, alias, next_grids_np=No
     return results, final
 
 
-def _check(inp, grids_np, dtype, K, H, alias, next_dtype=None, next_grids_np=None):
+def _check(inp, grids_np, dtype, K, H, alias, next_dtype=None, next_grids_np=None,
+           step_reads_bounds=True):
     nd = dtype if next_dtype is None else next_dtype
-    a, fa = _loop(inp, grids_np, dtype, nd, K, H, False, alias, next_grids_np)
-    b, fb = _loop(inp, grids_np, dtype, nd, K, H, True, alias, next_grids_np)
+    a, fa = _loop(inp, grids_np, dtype, nd, K, H, False, alias, next_grids_np,
+                  step_reads_bounds)
+    b, fb = _loop(inp, grids_np, dtype, nd, K, H, True, alias, next_grids_np,
+                  step_reads_bounds)
     names = ("U_out", "costs", "weights", "stats", "u0", "state", "table")
     for i, (ra, rb) in enumerate(zip(a, b)):
         for name, x, y in zip(names, ra, rb):
@@ -130,11 +134,22 @@ def test_fused_matches_separate_reactive_full_size(alias):
         _check(inp, grids, S.GRID_F32, K, sc.H, alias)
 
 
-def test_fused_matches_separate_f16():
+@pytest.mark.parametrize("alias", [False, True])
+def test_fused_matches_separate_f16(alias):
     inp = W.mid()
     from paper_2512_22575_amd import smpc as S
-    print("mid f16", flush=True)
-    _check(inp, _grids(inp.grid, 3, 7, S.GRID_F16), S.GRID_F16, 512, 24, True)
+    print(f"mid f16 alias={alias}", flush=True)
+    _check(inp, _grids(inp.grid, 3, 7, S.GRID_F16), S.GRID_F16, 512, 24, alias)
+
+
+def test_fused_step_without_bounds_of_its_own():
+    """A step that reads no table (its grid's bounds not built) still builds the next
+    grid's bounds in its rollout launch."""
+    inp = W.mid()
+    from paper_2512_22575_amd import smpc as S
+    print("mid f32, step without bounds", flush=True)
+    _check(inp, _grids(inp.grid, 3, 12, S.GRID_F32), S.GRID_F32, 700, 20, False,
+           step_reads_bounds=False)
 
 
 def test_unfusable_grids_get_their_own_launch():
@@ -178,3 +193,53 @@ def test_fused_call_keeps_the_profile_events():
     k1, k2 = planner.profile_read(4)
     assert len(k1) == 2 and np.all(k1 > 0) and np.all(k2 > 0)
     planner.close()
+
+
+def test_receding_horizon_next_bounds():
+    """RecedingHorizon.step with next_bounds (the next period's bounds built by the step,
+    into the other of two tables) runs the same closed loop as steps that each build
+    their own grid's bounds first."""
+    import torch
+
+    from paper_2512_22575_amd import smpc as S
+    inp = W.mid()
+    grids_np = _grids(inp.grid, 4, 13, S.GRID_F32)
+    dev = torch.device("cuda:0")
+    grids = [torch.from_numpy(g).to(dev) for g in grids_np]
+    nz, ny, nx = grids_np[0].shape
+    K, H = 512, inp.H
+
+    def run(fused):
+        planner = S.Planner(inp.robot)
+        c, r = planner.robot_reach()
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        tabs = [torch.empty((S.smpc_grid_coarse_cells(nx, ny, nz),), device=dev)
+                for _ in range(2)]
+        loop = S.RecedingHorizon(planner, H, inp.q0, inp.qd0)
+        rng = np.random.default_rng(21)
+        out = []
+        if fused:
+            assert S.smpc_grid_coarse_min_ball(grids[0], S.GRID_F32, inp.origin, inp.voxel, c, r,
+                                               tabs[0].data_ptr(), stream) == S.SMPC_OK
+        for i in range(len(grids)):
+            if not fused:
+                assert S.smpc_grid_coarse_min_ball(grids[i], S.GRID_F32, inp.origin, inp.voxel,
+                                                   c, r, tabs[i % 2].data_ptr(),
+                                                   stream) == S.SMPC_OK
+            nb = None
+            if fused and i + 1 < len(grids):
+                nb = (grids[i + 1], S.GRID_F32, inp.origin, inp.voxel, tabs[(i + 1) % 2])
+            noise = torch.from_numpy(W.sample_noise(rng, K, H)).to(dev)
+            loop.step(T_goal=inp.T_goal, grid=grids[i], origin=inp.origin, voxel=inp.voxel,
+                      dt=inp.dt, lam=inp.lam, weights=inp.weights, noise=noise,
+                      coarse=tabs[i % 2], next_bounds=nb)
+            torch.cuda.synchronize()
+            out.append([t.cpu().numpy().copy() for t in (loop.U, loop.state, loop.u0)])
+        planner.close()
+        return out
+
+    a, b = run(False), run(True)
+    for i, (x, y) in enumerate(zip(a, b)):
+        for name, u, v in zip(("U", "state", "u0"), x, y):
+            np.testing.assert_array_equal(u.view(np.uint32), v.view(np.uint32),
+                                          err_msg=f"period {i}: {name}")
