@@ -414,7 +414,9 @@ smpc_status smpc_edt(const uint8_t* occ, int32_t nx, int32_t ny, int32_t nz, flo
  * between the two kernels and after the merge kernel; n = 0 disables recording.
  * smpc_profile_read waits for the recorded events and returns, per recorded
  * step, the durations in milliseconds of the rollout-cost kernel (rollout_ms[i])
- * and of the merge kernel (merge_ms[i]); *n_steps receives the count written
+ * and of the merge kernel (merge_ms[i]) -- for smpc_plan_step_then_bounds, of the
+ * launch among the two that also held the next grid's bounds, or of the bounds'
+ * own launch after the merge when neither could; *n_steps receives the count written
  * (at most `capacity`).  Reading resets the record.  Events are created by
  * smpc_profile_enable, for timing only: they carry no system-scope memory fence, so
  * waiting for them does not make the step's outputs visible to the host (synchronise
