@@ -829,7 +829,7 @@ def main():
     u0 = torch.zeros((7,), device=dev)
     u0_host = torch.zeros((7,), pin_memory=True)
 
-    total = args.warmup + args.steps + args.latency_steps + 2 * args.profile_steps
+    total = args.warmup + args.steps + 2 * args.latency_steps + 2 * args.profile_steps
     plans, grid_structs = [], []
     for i in range(total):
         g = grids[i % n_grids]
@@ -923,6 +923,29 @@ def main():
         lat_dev.append(a.elapsed_time(b))
     lat_dev = np.array(lat_dev)
     lat_host = np.array(lat_host)
+
+    # The plan step alone, the bounds of its grid built beforehand (a map that arrived
+    # before the period started): the same measurement around smpc_plan_step only.
+    base += args.latency_steps
+    ps_dev, ps_host = [], []
+    for i in range(base, base + args.latency_steps):
+        if use_coarse:
+            bounds(i)
+            torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        h0 = time.perf_counter()
+        a.record()
+        st = lib.smpc_plan_step(ctx, plan_ptrs[i], sp)
+        if st != S.SMPC_OK:
+            raise S.SMPCError(st, S.smpc_last_error(ctx))
+        u0_host.copy_(u0, non_blocking=True)
+        b.record()
+        b.synchronize()
+        ps_host.append((time.perf_counter() - h0) * 1e3)
+        ps_dev.append(a.elapsed_time(b))
+    ps_dev = np.array(ps_dev)
+    ps_host = np.array(ps_host)
 
     # Per-kernel durations from events recorded by the library on the launch stream;
     # the bounds build between events of its own.
@@ -1033,6 +1056,14 @@ def main():
             "steps": int(args.latency_steps),
             "what": "one period alone, coarse bounds of its grid then the plan step, on "
                     "the device (events), and on the host until u*_0 is in host memory",
+            "plan_step": {
+                "p50": round(float(np.percentile(ps_dev, 50)), 5),
+                "p99": round(float(np.percentile(ps_dev, 99)), 5),
+                "host_p50": round(float(np.percentile(ps_host, 50)), 5),
+                "host_p99": round(float(np.percentile(ps_host, 99)), 5),
+                "what": "the plan step alone (smpc_plan_step, u*_0 to host memory), the "
+                        "bounds of its grid built before the call",
+            },
         },
         "host_ms_per_step": round(wall * 1e3 / args.steps, 5),
         "kernels_ms": {"coarse_bounds": round(coarse_ms, 6),
