@@ -125,7 +125,17 @@ struct LaunchConfig {
   int P;            // number of K1 blocks
   size_t k1_lds;    // dynamic LDS bytes of K1
   int k2_blocks;    // K2 grid
+  bool far_pairs = false;  // every self-collision pair joins links two or more apart
 };
+
+// Whether every self-collision pair of the robot joins links two or more apart (the
+// link-pair groups of a link with itself and with its neighbour are empty).
+inline bool robot_far_pairs(const DevRobot& r) {
+  for (int la = 0; la < kNdof; ++la)
+    for (int lb = la; lb < kNdof && lb <= la + 1; ++lb)
+      if (r.lp[la * kNdof + lb].mask != 0u) return false;
+  return true;
+}
 
 LaunchConfig plan_launch_config(int K, int H);
 size_t workspace_bytes(int K, int H, int P);
@@ -160,12 +170,14 @@ int launch_plan_step_bounds(const DevRobot* robot, const Request& q, const Launc
 // both batch kernels, result download),
 // created at the first launch and re-parameterised for every later one.  `*graph` is
 // the slot's handle (null before the first launch); the caller relaunches it only after
-// the previous launch has completed.  up: host -> device bytes (descriptors and maps);
+// the previous launch has completed (a launch for a robot of the other pair kind, `far`,
+// rebuilds the graph).  up: host -> device bytes (descriptors and maps);
 // res: device -> host result bytes.  Returns a hipError_t value.
 int launch_batch_graph(void** graph, const DevRobot* robot, void* d_up, const void* h_up,
                        size_t up_bytes, const Request* reqs, const int32_t* k1_map,
                        int k1_blocks, const int32_t* k2_map, int k2_blocks, size_t k1_lds,
-                       bool f16, void* h_res, const void* d_res, size_t res_bytes, void* stream);
+                       bool f16, bool far, void* h_res, const void* d_res, size_t res_bytes,
+                       void* stream);
 void destroy_batch_graph(void* graph);
 
 // Disturbances of the sampling mode written to memory (eps [K][H][7], words [K][H][8];

@@ -395,7 +395,11 @@ __device__ __forceinline__ float state_limit_cost(const StepParams& p, const flo
 // Cost charged by thread (m, k): control terms of u_k and state terms of state k+1.
 //   q0 : start positions (wave-uniform);  dq, qd : q_{k+1} - q0 and qd_{k+1};  u : u_k;
 //   sc0 : sin(q0) then cos(q0) (LDS).
-template <int kElemBytes>
+//   kFar: the robot's self-collision pairs all join links two or more apart (the usual
+//   sphere model), so the groups of a link with itself and with its neighbour, which
+//   then hold no pair, are left out of the code (a smaller kernel, fewer instruction
+//   fetches); otherwise every group is tested at run time.
+template <int kElemBytes, bool kFar>
 __device__ __forceinline__ float step_cost(const DevRobot* __restrict__ rob, const StepParams& p,
                                            __amdgpu_buffer_rsrc_t rsrc,
                                            __amdgpu_buffer_rsrc_t crsrc, const float* sc0,
@@ -442,7 +446,7 @@ __device__ __forceinline__ float step_cost(const DevRobot* __restrict__ rob, con
 #pragma unroll
   for (int la = 0; la < kNdof; ++la) {
 #pragma unroll
-    for (int lb = la; lb < kNdof; ++lb) {
+    for (int lb = kFar ? la + 2 : la; lb < kNdof; ++lb) {
       const LinkPair& G = rob->lp[la * kNdof + lb];
       const uint32_t mask = G.mask;
       if (mask == 0u) continue;
@@ -627,7 +631,7 @@ __device__ __forceinline__ int div_small(int q, float inv_d) {
 }
 
 // Rollout-cost work of block b (counted within its request) of request q.
-template <int kElemBytes>
+template <int kElemBytes, bool kFar>
 __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ rob,
                                                    const Request& q, int b) {
   extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -804,7 +808,7 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
             float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, L.x0[j])));
       const __amdgpu_buffer_rsrc_t rsrc = grid_resource(q.grid, p.grid_bytes);
       const __amdgpu_buffer_rsrc_t crsrc = grid_resource(q.coarse, p.coarse_bytes);
-      cost = step_cost<kElemBytes>(rob, p, rsrc, crsrc, L.sc0, q0, dq, qd, u, k == H - 1);
+      cost = step_cost<kElemBytes, kFar>(rob, p, rsrc, crsrc, L.sc0, q0, dq, qd, u, k == H - 1);
     }
     L.cost[tid] = cost;
   }
@@ -914,7 +918,7 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
 // With the state-0 terms requested, block 0 evaluates them and the rollout blocks
 // follow: the dispatcher places blocks in index order and fills each CU with two
 // rollout blocks, so an extra block at the end would only start when one of them ends.
-template <int kElemBytes>
+template <int kElemBytes, bool kFar>
 __device__ __forceinline__ void plan_rollout_block(const DevRobot* __restrict__ rob,
                                                    const Request& q, int bi) {
   const int b = bi - q.c0_in_ws;
@@ -923,22 +927,22 @@ __device__ __forceinline__ void plan_rollout_block(const DevRobot* __restrict__ 
     if (threadIdx.x == 0) q.ws.c0[0] = c0;
     return;
   }
-  rollout_cost_block<kElemBytes>(rob, q, b);
+  rollout_cost_block<kElemBytes, kFar>(rob, q, b);
 }
 
-template <int kElemBytes>
+template <int kElemBytes, bool kFar>
 __global__ __launch_bounds__(kK1Threads) __attribute__((amdgpu_waves_per_eu(4))) void
 rollout_cost_kernel(const DevRobot* __restrict__ rob, const Request q) {
-  plan_rollout_block<kElemBytes>(rob, q, (int)blockIdx.x);
+  plan_rollout_block<kElemBytes, kFar>(rob, q, (int)blockIdx.x);
 }
 
 // A batch of plan steps: block_req maps each block to its request.
-template <int kElemBytes>
+template <int kElemBytes, bool kFar>
 __global__ __launch_bounds__(kK1Threads) __attribute__((amdgpu_waves_per_eu(4))) void
 rollout_cost_batch_kernel(const DevRobot* __restrict__ rob, const Request* __restrict__ reqs,
                           const int32_t* __restrict__ block_req) {
   const Request& q = reqs[block_req[blockIdx.x]];
-  rollout_cost_block<kElemBytes>(rob, q, (int)blockIdx.x - q.k1_begin);
+  rollout_cost_block<kElemBytes, kFar>(rob, q, (int)blockIdx.x - q.k1_begin);
 }
 
 // ---------------------------------------------------------------------------
@@ -1514,13 +1518,13 @@ __global__ __launch_bounds__(kK2Threads) void merge_bounds_kernel(const DevRobot
 // multiple of 8, for the bounds blocks' XCD layout) in one launch: the bounds load while
 // the rollouts, which leave HBM mostly idle, compute.  The table written must not be the
 // one the rollouts read.
-template <int kElemBytes>
+template <int kElemBytes, bool kFar>
 __global__ __launch_bounds__(kK1Threads) __attribute__((amdgpu_waves_per_eu(4))) void
 rollout_bounds_kernel(const DevRobot* __restrict__ rob, const Request q, int n_k1, int n_k1p,
                       CoarseJob J) {
   const int b = (int)blockIdx.x;
   if (b < n_k1)
-    plan_rollout_block<kElemBytes>(rob, q, b);
+    plan_rollout_block<kElemBytes, kFar>(rob, q, b);
   else if (b >= n_k1p)
     coarse_wide_block<kElemBytes, kK1Threads / kCoarseChunkGroups>(J, b - n_k1p);
 }
@@ -2019,7 +2023,8 @@ int launch_plan_step(const DevRobot* robot, const Request& q, const LaunchConfig
   hipEvent_t* ev = static_cast<hipEvent_t*>(events);
   hipError_t e;
   if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return (int)e;
-  auto k1 = f16 ? rollout_cost_kernel<2> : rollout_cost_kernel<4>;
+  auto k1 = f16 ? (lc.far_pairs ? rollout_cost_kernel<2, true> : rollout_cost_kernel<2, false>)
+                 : (lc.far_pairs ? rollout_cost_kernel<4, true> : rollout_cost_kernel<4, false>);
   hipLaunchKernelGGL(k1, dim3(lc.P + (q.c0_in_ws ? 1 : 0)), dim3(lc.k1_threads), lc.k1_lds, s,
                      robot, q);
   if ((e = hipGetLastError()) != hipSuccess) return (int)e;
@@ -2036,7 +2041,7 @@ struct BatchGraph {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipGraphNode_t up = nullptr, k1 = nullptr, k2 = nullptr, down = nullptr;
-  bool f16 = false;
+  bool f16 = false, far = false;
 };
 
 hipKernelNodeParams kernel_node(void* func, int blocks, int threads, size_t lds, void** args) {
@@ -2063,9 +2068,12 @@ void destroy_batch_graph(void* handle) {
 int launch_batch_graph(void** handle, const DevRobot* robot, void* d_up, const void* h_up,
                        size_t up_bytes, const Request* reqs, const int32_t* k1_map,
                        int k1_blocks, const int32_t* k2_map, int k2_blocks, size_t k1_lds,
-                       bool f16, void* h_res, const void* d_res, size_t res_bytes, void* stream) {
-  void* f1 = f16 ? reinterpret_cast<void*>(rollout_cost_batch_kernel<2>)
-                 : reinterpret_cast<void*>(rollout_cost_batch_kernel<4>);
+                       bool f16, bool far, void* h_res, const void* d_res, size_t res_bytes,
+                       void* stream) {
+  void* f1 = f16 ? (far ? reinterpret_cast<void*>(rollout_cost_batch_kernel<2, true>)
+                       : reinterpret_cast<void*>(rollout_cost_batch_kernel<2, false>))
+                 : (far ? reinterpret_cast<void*>(rollout_cost_batch_kernel<4, true>)
+                       : reinterpret_cast<void*>(rollout_cost_batch_kernel<4, false>));
   void* f2 = f16 ? reinterpret_cast<void*>(merge_batch_kernel<2>)
                  : reinterpret_cast<void*>(merge_batch_kernel<4>);
   const DevRobot* rob = robot;
@@ -2078,10 +2086,16 @@ int launch_batch_graph(void** handle, const DevRobot* robot, void* d_up, const v
   const hipKernelNodeParams p2 = kernel_node(f2, k2_blocks, kK2Threads, 0, a2);
   BatchGraph* g = static_cast<BatchGraph*>(*handle);
   hipError_t e;
+  if (g && g->far != far) {  // a robot of the other pair kind: the kernel node changes
+    destroy_batch_graph(g);
+    *handle = nullptr;
+    g = nullptr;
+  }
   if (!g) {
     g = new (std::nothrow) BatchGraph();
     if (!g) return (int)hipErrorOutOfMemory;
     g->f16 = f16;
+    g->far = far;
     if ((e = hipGraphCreate(&g->graph, 0)) != hipSuccess ||
         (e = hipGraphAddMemcpyNode1D(&g->up, g->graph, nullptr, 0, d_up, h_up, up_bytes,
                                      hipMemcpyHostToDevice)) != hipSuccess ||
@@ -2209,7 +2223,8 @@ int launch_plan_step_bounds(const DevRobot* robot, const Request& q, const Launc
     // launch, whose blocks leave HBM mostly idle (1.5 us added to it at 200^3, against
     // 3.6 us added to the merge launch).
     const int n_k1 = lc.P + (q.c0_in_ws ? 1 : 0), n_k1p = (n_k1 + kXcds - 1) / kXcds * kXcds;
-    auto k1 = f16 ? rollout_bounds_kernel<2> : rollout_bounds_kernel<4>;
+    auto k1 = f16 ? (lc.far_pairs ? rollout_bounds_kernel<2, true> : rollout_bounds_kernel<2, false>)
+                   : (lc.far_pairs ? rollout_bounds_kernel<4, true> : rollout_bounds_kernel<4, false>);
     hipLaunchKernelGGL(k1, dim3((unsigned)(n_k1p + n_bounds)), dim3(lc.k1_threads), lc.k1_lds, s,
                        robot, q, n_k1, n_k1p, job);
     if ((e = hipGetLastError()) != hipSuccess) return (int)e;
@@ -2220,7 +2235,8 @@ int launch_plan_step_bounds(const DevRobot* robot, const Request& q, const Launc
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return (int)e;
     return 0;
   }
-  auto k1 = f16 ? rollout_cost_kernel<2> : rollout_cost_kernel<4>;
+  auto k1 = f16 ? (lc.far_pairs ? rollout_cost_kernel<2, true> : rollout_cost_kernel<2, false>)
+                 : (lc.far_pairs ? rollout_cost_kernel<4, true> : rollout_cost_kernel<4, false>);
   hipLaunchKernelGGL(k1, dim3(lc.P + (q.c0_in_ws ? 1 : 0)), dim3(lc.k1_threads), lc.k1_lds, s,
                      robot, q);
   if ((e = hipGetLastError()) != hipSuccess) return (int)e;

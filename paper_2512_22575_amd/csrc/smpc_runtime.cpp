@@ -506,7 +506,8 @@ static smpc_status plan_step_impl(smpc_ctx* ctx, const smpc_plan_args* a, void* 
   const smpc_status st = validate_args(ctx, a);
   if (st != SMPC_OK) return st;
 
-  const LaunchConfig lc = plan_launch_config(a->K, a->H);
+  LaunchConfig lc = plan_launch_config(a->K, a->H);
+  lc.far_pairs = robot_far_pairs(ctx->host_robot);
   const StepParams p = make_params(ctx, a, lc);
 
   DeviceGuard g(ctx->device);
@@ -580,7 +581,8 @@ smpc_status smpc_plan_step_noalloc(smpc_ctx* ctx, const smpc_plan_args* a, void*
   ctx->last_error.clear();
   const smpc_status st = validate_args(ctx, a);
   if (st != SMPC_OK) return st;
-  const LaunchConfig lc = plan_launch_config(a->K, a->H);
+  LaunchConfig lc = plan_launch_config(a->K, a->H);
+  lc.far_pairs = robot_far_pairs(ctx->host_robot);
   const size_t need = workspace_bytes(a->K, a->H, lc.P);
   if (need > kScratchBytes)
     return fail(ctx, SMPC_E_INVALID_ARG,
@@ -1117,7 +1119,8 @@ smpc_status launch_next(smpc_server* s, void* stream, int* launched) {
   // One graph launch: descriptors and maps up, both batch kernels, results down.
   const int e = launch_batch_graph(&b.graph, s->ctx->dev_robot, b.d_up, b.h_up, up_bytes, d_reqs,
                                    d_maps, (int)k1_total, d_maps + k1_total, (int)k2_total, lds,
-                                   s->elem_dtype == SMPC_GRID_F16, b.h_res, b.d_res,
+                                   s->elem_dtype == SMPC_GRID_F16,
+                                   robot_far_pairs(s->ctx->host_robot), b.h_res, b.d_res,
                                    take.size() * kResultStride * 4, stream);
   if (e != 0) return sfail(s, SMPC_E_DEVICE, std::string("batch launch failed: ") +
                                                  hipGetErrorString(static_cast<hipError_t>(e)));
