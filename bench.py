@@ -53,12 +53,12 @@ PEAK_FP32_TFLOPS = 157.3
 # reads half the bytes copied: x2; WRITE_SIZE reads them all: x1).  Valid only for
 # the kernel sources it was taken on: bench.py reports null traffic when their
 # hash differs.
-ROLLOUT_TRAFFIC = {"sources_sha256": "1d88d25f7eaff3ef5dd192bfec2d82687f4d7e90573157b6cd83d70c2268f2a3",
-                   "fetch_kib": 2839.3, "fetch_scale": 2.0,
+ROLLOUT_TRAFFIC = {"sources_sha256": "83c67efe43d585088f34bcde8a897bb6523af3b8920946894f656c331edf5f21",
+                   "fetch_kib": 2734.1, "fetch_scale": 2.0,
                    "write_kib": 853.8, "write_scale": 1.0}
 # The same for one occupancy update (pixel and voxel pass together) at 200^3, 640x480.
-OGM_TRAFFIC = {"sources_sha256": "1d88d25f7eaff3ef5dd192bfec2d82687f4d7e90573157b6cd83d70c2268f2a3",
-               "fetch_kib": 673.5 + 20301.4, "fetch_scale": 2.0,
+OGM_TRAFFIC = {"sources_sha256": "83c67efe43d585088f34bcde8a897bb6523af3b8920946894f656c331edf5f21",
+               "fetch_kib": 673.8 + 20301.4, "fetch_scale": 2.0,
                "write_kib": 1200.5 + 39062.5, "write_scale": 1.0}
 
 
@@ -66,7 +66,7 @@ OGM_TRAFFIC = {"sources_sha256": "1d88d25f7eaff3ef5dd192bfec2d82687f4d7e90573157
 # TCC_REQ_sum, per dispatch), taken on the kernel sources named by the hash.  The L2
 # side of the roofline counts 128 B per request against the L2 peak of
 # PEAK_L2_GBPS: 8 XCDs x 16 channels x 128 B per clock x 2.4 GHz.
-ROLLOUT_L2 = {"sources_sha256": "1d88d25f7eaff3ef5dd192bfec2d82687f4d7e90573157b6cd83d70c2268f2a3", "tcc_req": 251833.5}
+ROLLOUT_L2 = {"sources_sha256": "83c67efe43d585088f34bcde8a897bb6523af3b8920946894f656c331edf5f21", "tcc_req": 219159.0}
 PEAK_L2_GBPS = 8 * 16 * 128 * 2.4
 
 
@@ -262,9 +262,9 @@ EDT_BYTES_PER_VOXEL = 5.0
 # HBM traffic of one construction at 200^3 (reactive scene; the three kernels together),
 # counted and scaled as ROLLOUT_TRAFFIC, valid for the sources named.
 EDT_TRAFFIC = {"sources": ("smpc_edt.hip", "smpc_internal.h"),
-               "sources_sha256": "0c67dadbac6c34d2b200e5df78bf364941a9aba3e411ace700a96048e81ab329",
-               "fetch_kib": 3974.6 + 33221.0 + 31094.4, "fetch_scale": 2.0,
-               "write_kib": 15625.8 + 33062.9 + 33883.9, "write_scale": 1.0}
+               "sources_sha256": "7e7224061528b206bf0b6cffed380f974ae2f97cbe65f529de7169ea7450eb50",
+               "fetch_kib": 3974.6 + 33227.6 + 31092.4, "fetch_scale": 2.0,
+               "write_kib": 15625.8 + 33061.3 + 33879.2, "write_scale": 1.0}
 PEAK_HBM_GBPS = 8000.0
 
 
