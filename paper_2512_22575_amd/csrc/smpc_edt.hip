@@ -133,6 +133,80 @@ __global__ __launch_bounds__(64 * kRowWaves) void edt_pass_x_kernel(
   }
 }
 
+// Rows whose length is a multiple of 4, at most 256 voxels, in a 4-byte-aligned grid
+// (records 8-byte aligned): lane l holds voxels 4l .. 4l + 3 of a row, read as one
+// 32-bit word and written as one 8-byte record group.  The nearest voxel of the other
+// kind is found in the lane's own four voxels, else in the nearest lane on that side
+// holding one (a ballot of the lanes holding each kind, then a lane shuffle of that
+// lane's first or last such voxel).
+__device__ __forceinline__ int last_bit4(uint32_t m) { return 31 - __clz(m); }  // m != 0
+__device__ __forceinline__ int first_bit4(uint32_t m) { return __ffs(m) - 1; }  // m != 0
+
+constexpr int kWordRows = 2;  // rows per wave of the word-per-lane kernel
+
+__global__ __launch_bounds__(64 * kRowWaves) void edt_pass_x_words_kernel(
+    const uint8_t* __restrict__ occ, int nx, long long rows, uint16_t* __restrict__ xrec) {
+  const int lane = threadIdx.x & 63;
+  const long long row0 =
+      ((long long)blockIdx.x * kRowWaves + (threadIdx.x >> 6)) * kWordRows;
+  if (row0 >= rows) return;  // whole wave leaves together
+  const int nw = nx >> 2;    // 32-bit words per row
+  const bool has = lane < nw;
+  uint32_t word[kWordRows];
+#pragma unroll
+  for (int w = 0; w < kWordRows; ++w) {
+    const long long row = row0 + w;
+    word[w] = (row < rows && has)
+                  ? *reinterpret_cast<const uint32_t*>(occ + row * nx + 4 * lane)
+                  : 0u;
+  }
+  const uint64_t below = (1ull << lane) - 1ull;               // lanes left of this one
+  const uint64_t above = lane == 63 ? 0ull : ~0ull << (lane + 1);
+  // "None" on the left / right: p - kNoLeft and kNoRight - p are >= 2^20 for every p.
+  constexpr int kNoLeft = -(1 << 20), kNoRight = 1 << 21;
+#pragma unroll
+  for (int w = 0; w < kWordRows; ++w) {
+    const long long row = row0 + w;
+    if (row >= rows) break;
+    uint32_t mo = 0u;  // bit k: voxel 4 lane + k occupied
+#pragma unroll
+    for (int k = 0; k < 4; ++k) mo |= (((word[w] >> (8 * k)) & 0xFFu) != 0u ? 1u : 0u) << k;
+    const uint32_t mf = has ? (~mo & 0xFu) : 0u;              // free voxels
+    const uint64_t lanes_o = __ballot(mo != 0u), lanes_f = __ballot(mf != 0u);
+    // This lane's first and last voxel of each kind (absolute indices).
+    const int fo = mo ? 4 * lane + first_bit4(mo) : 0, lo = mo ? 4 * lane + last_bit4(mo) : 0;
+    const int ff = mf ? 4 * lane + first_bit4(mf) : 0, lf = mf ? 4 * lane + last_bit4(mf) : 0;
+    // Nearest lane on each side holding each kind, and its nearest voxel of that kind.
+    const uint64_t lo_m = lanes_o & below, ro_m = lanes_o & above;
+    const uint64_t lf_m = lanes_f & below, rf_m = lanes_f & above;
+    const int lo_src = lo_m ? 63 - __clzll(lo_m) : lane;
+    const int ro_src = ro_m ? __ffsll((unsigned long long)ro_m) - 1 : lane;
+    const int lf_src = lf_m ? 63 - __clzll(lf_m) : lane;
+    const int rf_src = rf_m ? __ffsll((unsigned long long)rf_m) - 1 : lane;
+    const int sh_lo = __shfl(lo, lo_src), sh_fo = __shfl(fo, ro_src);
+    const int sh_lf = __shfl(lf, lf_src), sh_ff = __shfl(ff, rf_src);
+    const int left_o = lo_m ? sh_lo : kNoLeft, right_o = ro_m ? sh_fo : kNoRight;
+    const int left_f = lf_m ? sh_lf : kNoLeft, right_f = rf_m ? sh_ff : kNoRight;
+    if (!has) continue;
+    uint16_t rec[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int p = 4 * lane + k;
+      const bool o = (mo >> k) & 1u;
+      const uint32_t m = o ? mf : mo;                          // sources of the other kind
+      const uint32_t ml = m & ((1u << k) - 1u), mr = m & (0xEu << k) & 0xFu;
+      const int l = ml ? 4 * lane + last_bit4(ml) : (o ? left_f : left_o);
+      const int r = mr ? 4 * lane + first_bit4(mr) : (o ? right_f : right_o);
+      const int dist = min(p - l, r - p);
+      rec[k] = (uint16_t)((o ? kXOcc : 0u) | (dist < (1 << 20) ? (uint32_t)dist : kXNone));
+    }
+    uint2 out;
+    out.x = (uint32_t)rec[0] | ((uint32_t)rec[1] << 16);
+    out.y = (uint32_t)rec[2] | ((uint32_t)rec[3] << 16);
+    *reinterpret_cast<uint2*>(xrec + row * nx + 4 * lane) = out;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // FH on a tile of kLines lines held in LDS, kG lanes per line.  Samples are of type
 // Val (uint16_t when every finite sample is below 0xFFFF, else uint32_t; the
@@ -652,7 +726,13 @@ int launch_edt(const uint8_t* occ, int nx, int ny, int nz, float voxel, float* p
   const uint32_t none_value = (uint32_t)nx * nx + (uint32_t)ny * ny + (uint32_t)nz * nz;
   const long long rows_per_block = (long long)kRowWaves * kRowsPerWave;
   const dim3 xgrid((unsigned)((rows + rows_per_block - 1) / rows_per_block));
-  if (nx <= 256)
+  const long long word_rows_per_block = (long long)kRowWaves * kWordRows;
+  if (nx <= 256 && nx % 4 == 0 && reinterpret_cast<uintptr_t>(occ) % 4 == 0 &&
+      reinterpret_cast<uintptr_t>(xrec) % 8 == 0)
+    hipLaunchKernelGGL(edt_pass_x_words_kernel,
+                       dim3((unsigned)((rows + word_rows_per_block - 1) / word_rows_per_block)),
+                       dim3(64 * kRowWaves), 0, stream, occ, nx, rows, xrec);
+  else if (nx <= 256)
     hipLaunchKernelGGL(edt_pass_x_kernel<4>, xgrid, dim3(64 * kRowWaves), 0, stream, occ, nx,
                        rows, xrec);
   else
