@@ -53,11 +53,11 @@ PEAK_FP32_TFLOPS = 157.3
 # reads half the bytes copied: x2; WRITE_SIZE reads them all: x1).  Valid only for
 # the kernel sources it was taken on: bench.py reports null traffic when their
 # hash differs.
-ROLLOUT_TRAFFIC = {"sources_sha256": "83c67efe43d585088f34bcde8a897bb6523af3b8920946894f656c331edf5f21",
-                   "fetch_kib": 2734.1, "fetch_scale": 2.0,
+ROLLOUT_TRAFFIC = {"sources_sha256": "43582789e6126943d4d8693afb96846aa5ca8a351bf627d51ed033fd6b8b3cbf",
+                   "fetch_kib": 2726.0, "fetch_scale": 2.0,
                    "write_kib": 853.8, "write_scale": 1.0}
 # The same for one occupancy update (pixel and voxel pass together) at 200^3, 640x480.
-OGM_TRAFFIC = {"sources_sha256": "83c67efe43d585088f34bcde8a897bb6523af3b8920946894f656c331edf5f21",
+OGM_TRAFFIC = {"sources_sha256": "43582789e6126943d4d8693afb96846aa5ca8a351bf627d51ed033fd6b8b3cbf",
                "fetch_kib": 673.8 + 20301.4, "fetch_scale": 2.0,
                "write_kib": 1200.5 + 39062.5, "write_scale": 1.0}
 
@@ -66,7 +66,7 @@ OGM_TRAFFIC = {"sources_sha256": "83c67efe43d585088f34bcde8a897bb6523af3b8920946
 # TCC_REQ_sum, per dispatch), taken on the kernel sources named by the hash.  The L2
 # side of the roofline counts 128 B per request against the L2 peak of
 # PEAK_L2_GBPS: 8 XCDs x 16 channels x 128 B per clock x 2.4 GHz.
-ROLLOUT_L2 = {"sources_sha256": "83c67efe43d585088f34bcde8a897bb6523af3b8920946894f656c331edf5f21", "tcc_req": 219159.0}
+ROLLOUT_L2 = {"sources_sha256": "43582789e6126943d4d8693afb96846aa5ca8a351bf627d51ed033fd6b8b3cbf", "tcc_req": 222327.1}
 PEAK_L2_GBPS = 8 * 16 * 128 * 2.4
 
 
@@ -262,9 +262,9 @@ EDT_BYTES_PER_VOXEL = 5.0
 # HBM traffic of one construction at 200^3 (reactive scene; the three kernels together),
 # counted and scaled as ROLLOUT_TRAFFIC, valid for the sources named.
 EDT_TRAFFIC = {"sources": ("smpc_edt.hip", "smpc_internal.h"),
-               "sources_sha256": "7e7224061528b206bf0b6cffed380f974ae2f97cbe65f529de7169ea7450eb50",
-               "fetch_kib": 3974.6 + 33227.6 + 31092.4, "fetch_scale": 2.0,
-               "write_kib": 15625.8 + 33061.3 + 33879.2, "write_scale": 1.0}
+               "sources_sha256": "119e5d909baa710898ce1b79cae4da3b9b58fdbe07621595edc881dfe20977b3",
+               "fetch_kib": 4090.6 + 33223.0 + 31089.6, "fetch_scale": 2.0,
+               "write_kib": 15625.0 + 33071.8 + 33859.8, "write_scale": 1.0}
 PEAK_HBM_GBPS = 8000.0
 
 
