@@ -1527,8 +1527,14 @@ rollout_bounds_kernel(const DevRobot* __restrict__ rob, const Request q, int n_k
   const int b = (int)blockIdx.x;
   if (b < n_k1)
     plan_rollout_block<kElemBytes, kFar>(rob, q, b);
-  else if (b >= n_k1p)
+  else if (b >= n_k1p) {
+    // Hold the bounds loads back for about 2.7 us (100 x 64 clocks): every rollout block
+    // first waits on its disturbances from HBM, and those loads go first (29.0 against
+    // 30.2 us per period at K = 4096, H = 40 on 200^3; waiting twice as long lets the
+    // bounds blocks dispatched later finish after the rollouts).
+    __builtin_amdgcn_s_sleep(100);
     coarse_wide_block<kElemBytes, kK1Threads / kCoarseChunkGroups>(J, b - n_k1p);
+  }
 }
 
 // ---------------------------------------------------------------------------
