@@ -163,3 +163,37 @@ def test_reactive_scene_full_size():
     sc = W.ReactiveScenario()
     occ = sc.occupancy()
     check(occ, sc.VOXEL, transform=E.edt_separable_minplus)
+
+
+def test_unaligned_occupancy_and_workspace_take_the_byte_kernel():
+    """Rows of a multiple of 4 voxels in a 4-byte-aligned grid take the x pass that reads
+    four voxels per lane; an occupancy grid starting one byte into its buffer, or a
+    workspace whose x records are not 8-byte aligned, takes the per-voxel x pass: the
+    same fields either way."""
+    import torch
+
+    from paper_2512_22575_amd import smpc as S
+    rng = np.random.default_rng(17)
+    occ = rng.uniform(size=(6, 9, 64)) < 0.05
+    nz, ny, nx = occ.shape
+    voxel = float(np.float32(0.02))
+    ref_phi, ref_out, ref_in = E.signed_distance(occ, voxel)
+    dev = torch.device("cuda:0")
+    need = S.smpc_edt_workspace_bytes(nx, ny, nz)
+    flat = np.ascontiguousarray(occ, dtype=np.uint8).reshape(-1)
+    for occ_off, work_off in ((0, 0), (1, 0), (0, 4)):
+        buf = torch.zeros(flat.size + 8, dtype=torch.uint8, device=dev)
+        buf[occ_off:occ_off + flat.size] = torch.from_numpy(flat).to(dev)
+        work = torch.zeros(need + 16, dtype=torch.uint8, device=dev)
+        phi = torch.full(occ.shape, float("nan"), device=dev)
+        d2 = torch.full((2,) + occ.shape, -1, dtype=torch.int32, device=dev)
+        print(f"occupancy offset {occ_off}, workspace offset {work_off}", flush=True)
+        st = S.smpc_edt(buf.data_ptr() + occ_off, nx, ny, nz, voxel, phi.data_ptr(),
+                        d2.data_ptr(), work.data_ptr() + work_off, need,
+                        torch.cuda.current_stream().cuda_stream)
+        assert st == S.SMPC_OK, S.smpc_status_string(st)
+        torch.cuda.synchronize()
+        w = d2.cpu().numpy().view(np.uint32).astype(np.int64)
+        np.testing.assert_array_equal(w[0], ref_out)
+        np.testing.assert_array_equal(w[1], ref_in)
+        np.testing.assert_array_equal(phi.cpu().numpy().view(np.uint32), ref_phi.view(np.uint32))
