@@ -154,7 +154,9 @@ typedef struct {
  * starts the nominal sequence from zero, so the control shifted in last is 0):
  *   receding  : 0: U_out receives U*.  1: U_out receives [u*_1 .. u*_{H-1}, 0], the
  *               nominal sequence of the next period; U_out must then not overlap U_in.
- *   u0_out    : device float [7] receiving u*_0, or NULL.
+ *   u0_out    : device-accessible float [7] receiving u*_0, or NULL: device memory,
+ *               or pinned host memory (hipHostMalloc), which the merge kernel then
+ *               writes directly, so u*_0 is on the host once the step has completed.
  *   state_in  : device float [14] holding (q0, qd0), or NULL to use q0 and qd0 above.
  *               Lets a loop keep its state on the device with no host round trip.
  *   state_out : device float [14] receiving the state one period dt later when u*_0

@@ -182,3 +182,37 @@ def test_receding_horizon_one_step():
     assert np.max(np.abs(x[7:] - qd1)) <= U_ATOL * inp.dt + 1e-6
     assert np.max(np.abs(x[:7] - q1)) <= 1e-6
     planner.close()
+
+
+def test_u0_written_to_pinned_host_memory():
+    """u0_out in pinned host memory: after the step's stream has synchronised, the host
+    array holds u*_0, bitwise the value written to device memory by the same step, on the
+    reactive workload's size (K = 4096, H = 40) and in a short loop of periods."""
+    import torch
+
+    from paper_2512_22575_amd import smpc as S
+    sc = W.ReactiveScenario(seed=3)
+    inp = sc.inputs()
+    dev = torch.device("cuda:0")
+    grid = torch.from_numpy(inp.grid).to(dev)
+    planner = S.Planner(inp.robot, device=0)
+    U = [torch.from_numpy(inp.U_bar).to(dev), torch.zeros((sc.H, 7), device=dev)]
+    host = torch.full((7,), float("nan"), pin_memory=True)
+    rng = np.random.default_rng(8)
+    for i in range(3):
+        noise = torch.from_numpy(W.sample_noise(rng, sc.K, sc.H)).to(dev)
+        outs = []
+        for u0 in (torch.full((7,), float("nan"), device=dev), host):
+            u0.fill_(float("nan"))
+            U_out = torch.full_like(U[0], float("nan"))
+            planner.plan_step(q0=inp.q0, qd0=inp.qd0, T_goal=inp.T_goal, grid=grid,
+                              origin=inp.origin, voxel=inp.voxel, noise=noise, U_in=U[i % 2],
+                              U_out=U_out, dt=inp.dt, lam=inp.lam, weights=inp.weights,
+                              receding=True, u0_out=u0)
+            torch.cuda.current_stream(dev).synchronize()
+            outs.append((u0.cpu().numpy().copy(), U_out.cpu().numpy()))
+        np.testing.assert_array_equal(outs[0][0].view(np.uint32), outs[1][0].view(np.uint32))
+        np.testing.assert_array_equal(outs[0][1].view(np.uint32), outs[1][1].view(np.uint32))
+        assert np.all(np.isfinite(outs[1][0]))
+        U[(i + 1) % 2].copy_(torch.from_numpy(outs[0][1]).to(dev))
+    planner.close()
