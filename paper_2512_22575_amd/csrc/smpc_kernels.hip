@@ -678,18 +678,38 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
     }
   } else {
     // All loads of a thread are issued before any is stored (indices clamped into
-    // range, so no load sits behind a branch).
+    // range, so no load sits behind a branch); 16 bytes per load when the block's
+    // disturbances start on a 16-byte boundary and both counts are multiples of 4
+    // (at H = 40 every block), else 4.
     const float* src = noise + (size_t)m0 * H * kNdof;
     const int n_eps = nroll * H * kNdof;
-    constexpr int kLoads = 8;
-    for (int i0 = tid; i0 < RH * kNdof; i0 += nthreads * kLoads) {
-      float v[kLoads];
+    if ((reinterpret_cast<uintptr_t>(src) & 15u) == 0 && (n_eps & 3) == 0 &&
+        ((RH * kNdof) & 3) == 0) {
+      const float4* src4 = reinterpret_cast<const float4*>(src);
+      float4* dst4 = reinterpret_cast<float4*>(L.eps);
+      const int n4 = n_eps >> 2, t4 = (RH * kNdof) >> 2;
+      constexpr int kLoads4 = 2;
+      for (int i0 = tid; i0 < t4; i0 += nthreads * kLoads4) {
+        float4 v[kLoads4];
 #pragma unroll
-      for (int c = 0; c < kLoads; ++c) v[c] = src[min(i0 + c * nthreads, n_eps - 1)];
+        for (int c = 0; c < kLoads4; ++c) v[c] = src4[min(i0 + c * nthreads, n4 - 1)];
 #pragma unroll
-      for (int c = 0; c < kLoads; ++c) {
-        const int i = i0 + c * nthreads;
-        if (i < RH * kNdof) L.eps[i] = i < n_eps ? v[c] : 0.f;
+        for (int c = 0; c < kLoads4; ++c) {
+          const int i = i0 + c * nthreads;
+          if (i < t4) dst4[i] = i < n4 ? v[c] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+      }
+    } else {
+      constexpr int kLoads = 8;
+      for (int i0 = tid; i0 < RH * kNdof; i0 += nthreads * kLoads) {
+        float v[kLoads];
+#pragma unroll
+        for (int c = 0; c < kLoads; ++c) v[c] = src[min(i0 + c * nthreads, n_eps - 1)];
+#pragma unroll
+        for (int c = 0; c < kLoads; ++c) {
+          const int i = i0 + c * nthreads;
+          if (i < RH * kNdof) L.eps[i] = i < n_eps ? v[c] : 0.f;
+        }
       }
     }
   }
