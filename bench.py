@@ -53,11 +53,11 @@ PEAK_FP32_TFLOPS = 157.3
 # reads half the bytes copied: x2; WRITE_SIZE reads them all: x1).  Valid only for
 # the kernel sources it was taken on: bench.py reports null traffic when their
 # hash differs.
-ROLLOUT_TRAFFIC = {"sources_sha256": "ea5e046e0c05acb1a9860f138cc79e9c2f31f53f110e46b05a7ab4af89861954",
-                   "fetch_kib": 2726.0, "fetch_scale": 2.0,
+ROLLOUT_TRAFFIC = {"sources_sha256": "7729e50e3514578734c4f3e9c77ff92ba2773fda411f4ff3e0768cc58c52d536",
+                   "fetch_kib": 2736.0, "fetch_scale": 2.0,
                    "write_kib": 853.8, "write_scale": 1.0}
 # The same for one occupancy update (pixel and voxel pass together) at 200^3, 640x480.
-OGM_TRAFFIC = {"sources_sha256": "ea5e046e0c05acb1a9860f138cc79e9c2f31f53f110e46b05a7ab4af89861954",
+OGM_TRAFFIC = {"sources_sha256": "7729e50e3514578734c4f3e9c77ff92ba2773fda411f4ff3e0768cc58c52d536",
                "fetch_kib": 673.8 + 20301.4, "fetch_scale": 2.0,
                "write_kib": 1200.5 + 39062.5, "write_scale": 1.0}
 
@@ -66,7 +66,7 @@ OGM_TRAFFIC = {"sources_sha256": "ea5e046e0c05acb1a9860f138cc79e9c2f31f53f110e46
 # TCC_REQ_sum, per dispatch), taken on the kernel sources named by the hash.  The L2
 # side of the roofline counts 128 B per request against the L2 peak of
 # PEAK_L2_GBPS: 8 XCDs x 16 channels x 128 B per clock x 2.4 GHz.
-ROLLOUT_L2 = {"sources_sha256": "ea5e046e0c05acb1a9860f138cc79e9c2f31f53f110e46b05a7ab4af89861954", "tcc_req": 219196.4}
+ROLLOUT_L2 = {"sources_sha256": "7729e50e3514578734c4f3e9c77ff92ba2773fda411f4ff3e0768cc58c52d536", "tcc_req": 219736.8}
 PEAK_L2_GBPS = 8 * 16 * 128 * 2.4
 
 
