@@ -975,14 +975,67 @@ rollout_cost_batch_kernel(const DevRobot* __restrict__ rob, const Request* __res
 // Global statistics of the block partials, computed by one whole wave:
 // m = min_b m_b over finite m_b, then with c_b = exp(-(m_b - m)/lambda),
 // Z = sum_b Z_b c_b and Z2 = sum_b Z2_b c_b^2 (eqs. 29-30 regrouped).  Lane l folds
-// rows b = l + 64 c in order and the lanes combine through a fixed butterfly, so
-// every wave that calls this (in any block) gets bitwise the same result, with no
-// barrier.  The first kStatRows rows per lane are loaded in one round and kept;
-// larger P reloads the rest.  m = +inf when no cost is finite.
+// rows b = l + 64 c in order and the lanes combine in a fixed order (DPP moves, then
+// readlanes), so every wave that calls this (in any block) gets bitwise the same
+// result, with no barrier; all 64 lanes of the wave take part.  The first kStatRows
+// rows per lane are loaded in one round and kept; larger P reloads the rest.
+// m = +inf when no cost is finite.
 struct GlobalStats {
   double m;
   float Z, Z2;
 };
+
+// Cross-lane combines of the statistics without the LDS: xor 1 and xor 2 by quad
+// permutations (DPP), then the half-row and row mirrors -- once the lanes of each quad
+// (then of each half-row) agree, a mirror pairs the same groups as xor 4 (xor 8)
+// would -- and the four row values combined in scalar registers in a fixed order.
+// Every lane returns the same value.  All 64 lanes must be active.
+template <int kCtrl>
+__device__ __forceinline__ int dpp_move(int x) {
+  return __builtin_amdgcn_update_dpp(x, x, kCtrl, 0xF, 0xF, false);
+}
+constexpr int kDppSwap1 = 0xB1;         // quad_perm [1, 0, 3, 2]
+constexpr int kDppSwap2 = 0x4E;         // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;   // lane i <-> 7 - i within each 8
+constexpr int kDppMirror = 0x140;       // lane i <-> 15 - i within each row of 16
+
+template <int kCtrl>
+__device__ __forceinline__ float dpp_f32(float x) {
+  return __int_as_float(dpp_move<kCtrl>(__float_as_int(x)));
+}
+template <int kCtrl>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = dpp_move<kCtrl>((int)v), hi = dpp_move<kCtrl>((int)(v >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                          (unsigned)lo));
+}
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)v, l);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                          (unsigned)lo));
+}
+__device__ __forceinline__ float readlane_f32(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
+__device__ __forceinline__ double wave_min_f64(double x) {
+  x = fmin(x, dpp_f64<kDppSwap1>(x));
+  x = fmin(x, dpp_f64<kDppSwap2>(x));
+  x = fmin(x, dpp_f64<kDppHalfMirror>(x));
+  x = fmin(x, dpp_f64<kDppMirror>(x));
+  return fmin(fmin(readlane_f64(x, 0), readlane_f64(x, 16)),
+              fmin(readlane_f64(x, 32), readlane_f64(x, 48)));
+}
+__device__ __forceinline__ float wave_sum_f32(float x) {
+  x += dpp_f32<kDppSwap1>(x);
+  x += dpp_f32<kDppSwap2>(x);
+  x += dpp_f32<kDppHalfMirror>(x);
+  x += dpp_f32<kDppMirror>(x);
+  return (readlane_f32(x, 0) + readlane_f32(x, 16)) + (readlane_f32(x, 32) + readlane_f32(x, 48));
+}
 constexpr int kStatRows = 12;
 
 // Rows of the first round, loaded by stats_load and folded by stats_finish (so a
@@ -1009,8 +1062,7 @@ __device__ __forceinline__ GlobalStats stats_finish(const Workspace& ws, int P, 
   for (int c = 0; c < kStatRows; ++c)
     if (lane + kWave * c < P) mn = fmin(mn, r.m[c]);
   for (int b = lane + kWave * kStatRows; b < P; b += kWave) mn = fmin(mn, ws.part_m[b]);
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) mn = fmin(mn, __shfl_xor(mn, off, kWave));
+  mn = wave_min_f64(mn);
   float Z = 0.f, Z2 = 0.f;
   if (isfinite(mn)) {
 #pragma unroll
@@ -1028,12 +1080,7 @@ __device__ __forceinline__ GlobalStats stats_finish(const Workspace& ws, int P, 
       Z2 = fmaf(ws.part_Z2[b], e * e, Z2);
     }
   }
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) {
-    Z += __shfl_xor(Z, off, kWave);
-    Z2 += __shfl_xor(Z2, off, kWave);
-  }
-  return {mn, Z, Z2};
+  return {mn, wave_sum_f32(Z), wave_sum_f32(Z2)};
 }
 
 __device__ __forceinline__ GlobalStats wave_stats(const Workspace& ws, int P, float k_lambda,
