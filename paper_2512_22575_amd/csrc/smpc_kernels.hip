@@ -192,6 +192,58 @@ __device__ __forceinline__ float softmax_factor(float d, float k) {
   return __builtin_amdgcn_exp2f(-d * k);
 }
 
+// Cross-lane combines without the LDS: xor 1 and xor 2 by quad permutations (DPP),
+// then the half-row and row mirrors -- once the lanes of each quad (then of each
+// half-row) agree, a mirror pairs the same groups as xor 4 (xor 8) would -- and the
+// four row values combined in scalar registers in a fixed order, so every lane of
+// wave_min_f64 / wave_sum_f32 returns the same value.  All 64 lanes must be active.
+template <int kCtrl>
+__device__ __forceinline__ int dpp_move(int x) {
+  return __builtin_amdgcn_update_dpp(x, x, kCtrl, 0xF, 0xF, false);
+}
+constexpr int kDppSwap1 = 0xB1;         // quad_perm [1, 0, 3, 2]
+constexpr int kDppSwap2 = 0x4E;         // quad_perm [2, 3, 0, 1]
+constexpr int kDppHalfMirror = 0x141;   // lane i <-> 7 - i within each 8
+constexpr int kDppMirror = 0x140;       // lane i <-> 15 - i within each row of 16
+
+template <int kCtrl>
+__device__ __forceinline__ float dpp_f32(float x) {
+  return __int_as_float(dpp_move<kCtrl>(__float_as_int(x)));
+}
+template <int kCtrl>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = dpp_move<kCtrl>((int)v), hi = dpp_move<kCtrl>((int)(v >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                          (unsigned)lo));
+}
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)v, l);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                          (unsigned)lo));
+}
+__device__ __forceinline__ float readlane_f32(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+
+__device__ __forceinline__ double wave_min_f64(double x) {
+  x = fmin(x, dpp_f64<kDppSwap1>(x));
+  x = fmin(x, dpp_f64<kDppSwap2>(x));
+  x = fmin(x, dpp_f64<kDppHalfMirror>(x));
+  x = fmin(x, dpp_f64<kDppMirror>(x));
+  return fmin(fmin(readlane_f64(x, 0), readlane_f64(x, 16)),
+              fmin(readlane_f64(x, 32), readlane_f64(x, 48)));
+}
+__device__ __forceinline__ float wave_sum_f32(float x) {
+  x += dpp_f32<kDppSwap1>(x);
+  x += dpp_f32<kDppSwap2>(x);
+  x += dpp_f32<kDppHalfMirror>(x);
+  x += dpp_f32<kDppMirror>(x);
+  return (readlane_f32(x, 0) + readlane_f32(x, 16)) + (readlane_f32(x, 32) + readlane_f32(x, 48));
+}
+
 // g(theta) = (x^2 - sin^2 x) / (2 sin^4 x), x = theta / 2, for theta in [0, pi].
 // With it |v|^2 = |t|^2 + g(theta) t^T (I - R) t for the translational part v of
 // log(T) (eqs. 12-14): V(theta) acts as the identity along the rotation axis and
@@ -860,7 +912,9 @@ __device__ __forceinline__ void rollout_cost_block(const DevRobot* __restrict__ 
           if (j + (c0 + c) * G < H) s += (double)cv[c];
       }
     }
-    for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, kWave);
+    for (int off = G / 2; off > 2; off >>= 1) s += __shfl_xor(s, off, kWave);
+    if (G >= 4) s += dpp_f64<kDppSwap2>(s);  // the same pairs as xor 2 and xor 1
+    if (G >= 2) s += dpp_f64<kDppSwap1>(s);
     if (r < nroll && j == 0) L.sr[r] = s;
     __builtin_amdgcn_wave_barrier();
     constexpr int kBatch = 8;  // LDS reads in flight at once
@@ -984,58 +1038,6 @@ struct GlobalStats {
   double m;
   float Z, Z2;
 };
-
-// Cross-lane combines of the statistics without the LDS: xor 1 and xor 2 by quad
-// permutations (DPP), then the half-row and row mirrors -- once the lanes of each quad
-// (then of each half-row) agree, a mirror pairs the same groups as xor 4 (xor 8)
-// would -- and the four row values combined in scalar registers in a fixed order.
-// Every lane returns the same value.  All 64 lanes must be active.
-template <int kCtrl>
-__device__ __forceinline__ int dpp_move(int x) {
-  return __builtin_amdgcn_update_dpp(x, x, kCtrl, 0xF, 0xF, false);
-}
-constexpr int kDppSwap1 = 0xB1;         // quad_perm [1, 0, 3, 2]
-constexpr int kDppSwap2 = 0x4E;         // quad_perm [2, 3, 0, 1]
-constexpr int kDppHalfMirror = 0x141;   // lane i <-> 7 - i within each 8
-constexpr int kDppMirror = 0x140;       // lane i <-> 15 - i within each row of 16
-
-template <int kCtrl>
-__device__ __forceinline__ float dpp_f32(float x) {
-  return __int_as_float(dpp_move<kCtrl>(__float_as_int(x)));
-}
-template <int kCtrl>
-__device__ __forceinline__ double dpp_f64(double x) {
-  const long long v = __double_as_longlong(x);
-  const int lo = dpp_move<kCtrl>((int)v), hi = dpp_move<kCtrl>((int)(v >> 32));
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
-                                          (unsigned)lo));
-}
-__device__ __forceinline__ double readlane_f64(double x, int l) {
-  const long long v = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_readlane((int)v, l);
-  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
-                                          (unsigned)lo));
-}
-__device__ __forceinline__ float readlane_f32(float x, int l) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
-}
-
-__device__ __forceinline__ double wave_min_f64(double x) {
-  x = fmin(x, dpp_f64<kDppSwap1>(x));
-  x = fmin(x, dpp_f64<kDppSwap2>(x));
-  x = fmin(x, dpp_f64<kDppHalfMirror>(x));
-  x = fmin(x, dpp_f64<kDppMirror>(x));
-  return fmin(fmin(readlane_f64(x, 0), readlane_f64(x, 16)),
-              fmin(readlane_f64(x, 32), readlane_f64(x, 48)));
-}
-__device__ __forceinline__ float wave_sum_f32(float x) {
-  x += dpp_f32<kDppSwap1>(x);
-  x += dpp_f32<kDppSwap2>(x);
-  x += dpp_f32<kDppHalfMirror>(x);
-  x += dpp_f32<kDppMirror>(x);
-  return (readlane_f32(x, 0) + readlane_f32(x, 16)) + (readlane_f32(x, 32) + readlane_f32(x, 48));
-}
 constexpr int kStatRows = 12;
 
 // Rows of the first round, loaded by stats_load and folded by stats_finish (so a
