@@ -53,11 +53,11 @@ PEAK_FP32_TFLOPS = 157.3
 # reads half the bytes copied: x2; WRITE_SIZE reads them all: x1).  Valid only for
 # the kernel sources it was taken on: bench.py reports null traffic when their
 # hash differs.
-ROLLOUT_TRAFFIC = {"sources_sha256": "d09b7c1ab05ff1c542f63009fa9ad53df17eee5492fe9a5074785a0d175066c8",
-                   "fetch_kib": 2736.0, "fetch_scale": 2.0,
+ROLLOUT_TRAFFIC = {"sources_sha256": "188e26cae7c3a2936ac4d546c21edf32063817c72ba26a689ab890931367897c",
+                   "fetch_kib": 2740.7, "fetch_scale": 2.0,
                    "write_kib": 853.8, "write_scale": 1.0}
 # The same for one occupancy update (pixel and voxel pass together) at 200^3, 640x480.
-OGM_TRAFFIC = {"sources_sha256": "d09b7c1ab05ff1c542f63009fa9ad53df17eee5492fe9a5074785a0d175066c8",
+OGM_TRAFFIC = {"sources_sha256": "188e26cae7c3a2936ac4d546c21edf32063817c72ba26a689ab890931367897c",
                "fetch_kib": 673.8 + 20301.4, "fetch_scale": 2.0,
                "write_kib": 1200.5 + 39062.5, "write_scale": 1.0}
 
@@ -66,7 +66,7 @@ OGM_TRAFFIC = {"sources_sha256": "d09b7c1ab05ff1c542f63009fa9ad53df17eee5492fe9a
 # TCC_REQ_sum, per dispatch), taken on the kernel sources named by the hash.  The L2
 # side of the roofline counts 128 B per request against the L2 peak of
 # PEAK_L2_GBPS: 8 XCDs x 16 channels x 128 B per clock x 2.4 GHz.
-ROLLOUT_L2 = {"sources_sha256": "d09b7c1ab05ff1c542f63009fa9ad53df17eee5492fe9a5074785a0d175066c8", "tcc_req": 219737.2}
+ROLLOUT_L2 = {"sources_sha256": "188e26cae7c3a2936ac4d546c21edf32063817c72ba26a689ab890931367897c", "tcc_req": 226746.3}
 PEAK_L2_GBPS = 8 * 16 * 128 * 2.4
 
 
